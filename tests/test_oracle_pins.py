@@ -1,0 +1,383 @@
+"""Pins of the FP64 oracle against closed forms, textbook routines, brute
+force and invariants.  CPU only.
+
+Each test states which part of the oracle it fixes and which mistake it
+would catch.  None of them re-types the oracle's own formula: the checks
+come from special functions (Bessel), eigen-solvers of the one-particle
+problem (scipy's tridiagonal solver), Pade-based matrix exponentials, an
+independent second-quantised construction of H, and symmetries.
+"""
+
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.special as ss
+
+from oracle import basis as B
+from oracle import hamiltonian as Hm
+from oracle import observables as O
+from oracle import propagate as P
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------- 1 particle
+
+@pytest.mark.parametrize("t", [2.5, 10.0, 20.0])
+def test_bessel_closed_form_single_walker(t):
+    """Uniform open chain, walker on node s: psi_{s+n}(t) = (-i)^n J_n(2t)
+    before the front reaches the ends (pins the hopping sign, the -i of the
+    evolution and the tridiagonal layout)."""
+    N, s = 256, 128
+    H = Hm.hamiltonian(N, 1, np.ones(N - 1), np.zeros(N), 0.0)
+    psi0 = B.product_state(N, [s])
+    psi = P.EDPropagator(H).evolve(psi0, t)
+    n = np.arange(N) - s
+    # For negative n, (-i)^n J_n = i^|n| (-1)^|n| J_|n| = (-i)^|n| J_|n|.
+    expect = (-1j) ** np.abs(n) * ss.jv(np.abs(n), 2 * t)
+    assert np.max(np.abs(psi - expect)) < 1e-12
+
+
+def test_bessel_reference_values_against_mpmath():
+    """scipy's jv is the reference above; cross-check it at high precision."""
+    for n, z in [(0, 5.0), (3, 20.0), (17, 40.0), (60, 40.0)]:
+        assert abs(ss.jv(n, z) - float(mpmath.besselj(n, z))) < 1e-14
+
+
+def test_bessel_taylor_and_rk4_routes():
+    """Alg. 3 with a tolerance and Alg. 2 with a small step reach the same
+    closed form (pins the Taylor recursion Phi_j = -(i dt/j) H Phi_{j-1})."""
+    N, s, dt, steps = 128, 64, 0.05, 200
+    H = Hm.hamiltonian(N, 1, np.ones(N - 1), np.zeros(N), 0.0)
+    psi0 = B.product_state(N, [s])
+    n = np.abs(np.arange(N) - s)
+    expect = (-1j) ** n * ss.jv(n, 2 * dt * steps)
+    psi_t, _, orders = P.evolve_taylor(H, psi0, dt, steps, tol=1e-15)
+    assert np.max(np.abs(psi_t - expect)) < 1e-12
+    assert min(orders) >= 8
+    psi_rk = P.evolve_rk4(H, psi0, 0.01, 1000)
+    assert np.max(np.abs(psi_rk - expect)) < 1e-6
+
+
+def test_periodic_ring_fourier_closed_form():
+    """Uniform ring: psi_x(t) = (1/N) sum_k exp(2 pi i k (x-s)/N) exp(-2 i J t cos(2 pi k/N))
+    (pins the wrap-around bond)."""
+    N, s, J, t = 11, 3, 0.7, 3.3
+    H = Hm.hamiltonian(N, 1, np.full(N, J), np.zeros(N), 0.0, boundary=Hm.PERIODIC)
+    psi = P.EDPropagator(H).evolve(B.product_state(N, [s]), t)
+    k = np.arange(N)
+    x = np.arange(N)[:, None]
+    expect = (np.exp(2j * np.pi * k * (x - s) / N) * np.exp(-2j * J * t * np.cos(2 * np.pi * k / N))).sum(1) / N
+    assert np.max(np.abs(psi - expect)) < 1e-13
+
+
+# --------------------------------------------------- non-interacting m > 1
+
+def one_particle_orbitals(J, eps, t):
+    """exp(-i H1 t) from scipy's tridiagonal eigen-solver (textbook routine)."""
+    E, V = sla.eigh_tridiagonal(np.asarray(eps, float), np.asarray(J, float))
+    return (V * np.exp(-1j * E * t)) @ V.T
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_product_form_distinguishable(m):
+    """U = 0: psi(x_1..x_m) = prod_a phi_{s_a}(x_a) with phi = exp(-i H1 t)|s>
+    (pins the Kronecker-sum order, and that all particles share one set of
+    noisy parameters)."""
+    g = rng(1)
+    N = 9 if m == 2 else 6
+    J = 1 + g.uniform(-0.3, 0.3, N - 1)
+    eps = g.uniform(-0.5, 0.5, N)
+    sites = [1, 6] if m == 2 else [0, 2, 5]
+    t = 1.7
+    psi = P.EDPropagator(Hm.hamiltonian(N, m, J, eps, 0.0)).evolve(B.product_state(N, sites), t)
+    U1 = one_particle_orbitals(J, eps, t)
+    expect = U1[:, sites[0]]
+    for s in sites[1:]:
+        expect = np.multiply.outer(expect, U1[:, s])
+    assert np.max(np.abs(psi - expect.reshape(-1))) < 1e-12
+
+
+def test_product_form_bosons():
+    """U = 0 bosons: the normalised symmetric combination of the orbitals;
+    in the symmetric basis c_{x<y} = sqrt(2) psi_full(x,y), c_{xx} = psi_full(x,x)."""
+    g = rng(2)
+    N = 10
+    J = 1 + g.uniform(-0.3, 0.3, N - 1)
+    eps = g.uniform(-0.5, 0.5, N)
+    a, b, t = 3, 4, 2.3
+    U1 = one_particle_orbitals(J, eps, t)
+    full = (np.outer(U1[:, a], U1[:, b]) + np.outer(U1[:, b], U1[:, a])) / math.sqrt(2)
+    psi = P.EDPropagator(Hm.hamiltonian(N, 2, J, eps, 0.0, B.BOSON)).evolve(
+        B.product_state(N, [a, b], B.BOSON), t)
+    states = B.basis_states(N, 2, B.BOSON)
+    expect = np.where(states[:, 0] < states[:, 1], math.sqrt(2), 1.0) * full[states[:, 0], states[:, 1]]
+    assert np.max(np.abs(psi - expect)) < 1e-12
+
+
+def test_two_site_boson_closed_form():
+    """N = 2, two bosons: basis (0,0), (0,1), (1,1) and
+    H = [[2e0+U, sqrt2 J, 0], [sqrt2 J, e0+e1, sqrt2 J], [0, sqrt2 J, 2e1+U]]."""
+    J, e0, e1, U = 0.83, -0.2, 0.35, 1.7
+    H = Hm.hamiltonian(2, 2, [J], [e0, e1], U, B.BOSON).toarray()
+    r2 = math.sqrt(2)
+    expect = np.array([[2 * e0 + U, r2 * J, 0], [r2 * J, e0 + e1, r2 * J], [0, r2 * J, 2 * e1 + U]])
+    assert np.max(np.abs(H - expect)) < 1e-15
+
+
+# ------------------------------------------ brute force, second quantised
+
+def second_quantised(N, m, J, eps, U, statistics, boundary, interaction):
+    """H built from occupation numbers, independent of the Kronecker route:
+    H = sum_i eps_i n_i + sum_bonds J_b (a+_i a_j + h.c.) + V, where for
+    bosons a+_i a_j |..n_i..n_j..> = sqrt((n_i+1) n_j) |..n_i+1..n_j-1..>,
+    on-site V = U/2 sum_i n_i (n_i - 1) and nearest V = U sum_bonds n_i n_j."""
+    states = [tuple(s) for s in B.basis_states(N, m, statistics)]
+    index = {s: k for k, s in enumerate(states)}
+    bonds = [(i, i + 1) for i in range(N - 1)]
+    if boundary == Hm.PERIODIC:
+        bonds.append((N - 1, 0))
+    H = np.zeros((len(states), len(states)))
+    for k, s in enumerate(states):
+        occ = np.bincount(s, minlength=N)
+        diag = float(np.dot(eps, occ))
+        if interaction == Hm.ONSITE:
+            diag += U * 0.5 * float(np.sum(occ * (occ - 1)))
+        else:
+            diag += U * float(sum(occ[i] * occ[j] for i, j in bonds))
+        H[k, k] += diag
+        for bi, (i, j) in enumerate(bonds):
+            for src, dst in ((i, j), (j, i)):
+                if statistics == B.DISTINGUISHABLE:
+                    for a in range(m):
+                        if s[a] == src:
+                            t = list(s)
+                            t[a] = dst
+                            H[index[tuple(t)], k] += J[bi]
+                else:
+                    if occ[src] == 0:
+                        continue
+                    new = occ.copy()
+                    amp = math.sqrt(occ[src] * (occ[dst] + 1))
+                    new[src] -= 1
+                    new[dst] += 1
+                    t = tuple(sorted(np.repeat(np.arange(N), new)))
+                    H[index[t], k] += J[bi] * amp
+    return H
+
+
+@pytest.mark.parametrize("m,statistics,boundary,interaction", [
+    (2, B.DISTINGUISHABLE, Hm.OPEN, Hm.ONSITE),
+    (3, B.DISTINGUISHABLE, Hm.OPEN, Hm.NEAREST),
+    (2, B.BOSON, Hm.OPEN, Hm.ONSITE),
+    (3, B.BOSON, Hm.OPEN, Hm.ONSITE),
+    (2, B.DISTINGUISHABLE, Hm.PERIODIC, Hm.NEAREST),
+    (2, B.BOSON, Hm.PERIODIC, Hm.ONSITE),
+])
+def test_hamiltonian_matches_second_quantised(m, statistics, boundary, interaction):
+    g = rng(3)
+    N = 4
+    nb = Hm.n_bonds(N, boundary)
+    J = 1 + g.uniform(-0.4, 0.4, nb)
+    eps = g.uniform(-1, 1, N)
+    U = 1.3
+    H = Hm.hamiltonian(N, m, J, eps, U, statistics, boundary, interaction).toarray()
+    Href = second_quantised(N, m, J, eps, U, statistics, boundary, interaction)
+    assert np.max(np.abs(H - Href)) < 1e-14
+
+
+@pytest.mark.parametrize("m,statistics", [(2, B.DISTINGUISHABLE), (3, B.DISTINGUISHABLE), (2, B.BOSON)])
+def test_ed_matches_pade_expm(m, statistics):
+    """ED (Eq. 4) against scipy's scaling-and-squaring Pade exp(-iHt)."""
+    g = rng(4)
+    N = 4
+    H = Hm.hamiltonian(N, m, 1 + g.uniform(-0.2, 0.2, N - 1), g.uniform(-1, 1, N), 0.9, statistics)
+    psi0 = B.product_state(N, list(range(m)), statistics)
+    t = 3.1
+    a = P.EDPropagator(H).evolve(psi0, t)
+    b = sla.expm(-1j * t * H.toarray()) @ psi0
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+# ------------------------------------------------------ propagator routes
+
+def small_case(seed=5, N=8, statistics=B.DISTINGUISHABLE, U=1.5):
+    g = rng(seed)
+    J = 1 + g.normal(0, 0.2, N - 1)
+    eps = g.uniform(-0.5, 0.5, N)
+    H = Hm.hamiltonian(N, 2, J, eps, U, statistics)
+    psi0 = B.product_state(N, [N // 2 - 1, N // 2], statistics)
+    return H, psi0
+
+
+@pytest.mark.parametrize("statistics", [B.DISTINGUISHABLE, B.BOSON])
+def test_taylor_tolerance_matches_ed(statistics):
+    H, psi0 = small_case(statistics=statistics)
+    dt, steps = 0.05, 400
+    psi, snaps, _ = P.evolve_taylor(H, psi0, dt, steps, tol=1e-14, output_every=100)
+    ed = P.EDPropagator(H)
+    for k, snap in enumerate(snaps):
+        assert np.max(np.abs(snap - ed.evolve(psi0, k * 100 * dt))) < 1e-11
+
+
+def test_rk4_step_equals_fourth_order_taylor_step():
+    """For a linear autonomous system one RK4 step is the degree-4 Taylor
+    polynomial of exp(-i H dt) (Sec. 2.3)."""
+    H, psi0 = small_case()
+    psi = P.EDPropagator(H).evolve(psi0, 0.7)
+    a = P.rk4_step(H, psi, 0.08)
+    b, j, _ = P.taylor_step(H, psi, 0.08, order=4)
+    assert j == 4
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_rk4_global_error_is_fourth_order():
+    H, psi0 = small_case()
+    T = 2.0
+    exact = P.EDPropagator(H).evolve(psi0, T)
+    errs = []
+    for steps in (40, 80, 160):
+        errs.append(np.max(np.abs(P.evolve_rk4(H, psi0, T / steps, steps) - exact)))
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(slopes - 4.0) < 0.3)
+    # RK4 does not conserve the norm exactly (Sec. 2.2).
+    psi = P.evolve_rk4(H, psi0, T / 40, 40)
+    assert abs(np.linalg.norm(psi) - 1) > 1e-9
+
+
+def test_fixed_order_truncation_error_scales_as_next_power():
+    """Dropping terms j > n costs O(dt^(n+1)) per step: halving dt at fixed n
+    cuts the one-step error by about 2^(n+1)."""
+    H, psi0 = small_case()
+    exact = P.EDPropagator(H)
+    for n in (3, 5):
+        e1 = np.linalg.norm(P.taylor_step(H, psi0, 0.1, order=n)[0] - exact.evolve(psi0, 0.1))
+        e2 = np.linalg.norm(P.taylor_step(H, psi0, 0.05, order=n)[0] - exact.evolve(psi0, 0.05))
+        assert abs(math.log2(e1 / e2) - (n + 1)) < 0.35
+
+
+# ------------------------------------------------------------- invariants
+
+def test_norm_and_energy_conservation():
+    H, psi0 = small_case(U=2.0)
+    dt = 0.05
+    e0 = P.energy(H, psi0)
+    psi = psi0
+    for _ in range(300):
+        psi, _, _ = P.taylor_step(H, psi, dt, tol=1e-15)
+    assert abs(np.linalg.norm(psi) - 1) < 1e-12
+    assert abs(P.energy(H, psi) - e0) < 1e-11
+
+
+def test_boson_exchange_symmetry_and_sector_agreement():
+    """Distinguishable evolution of a symmetrised start stays symmetric and
+    equals the boson-sector evolution mapped back to the full grid."""
+    g = rng(6)
+    N, U, t = 7, 1.1, 2.9
+    J = 1 + g.normal(0, 0.2, N - 1)
+    eps = g.uniform(-0.5, 0.5, N)
+    a, b = 2, 5
+    full0 = np.zeros((N, N), complex)
+    full0[a, b] = full0[b, a] = 1 / math.sqrt(2)
+    full = P.EDPropagator(Hm.hamiltonian(N, 2, J, eps, U)).evolve(full0.reshape(-1), t).reshape(N, N)
+    assert np.max(np.abs(full - full.T)) < 1e-13
+    sym = P.EDPropagator(Hm.hamiltonian(N, 2, J, eps, U, B.BOSON)).evolve(
+        B.product_state(N, [a, b], B.BOSON), t)
+    states = B.basis_states(N, 2, B.BOSON)
+    from_full = np.where(states[:, 0] < states[:, 1], math.sqrt(2), 1.0) * full[states[:, 0], states[:, 1]]
+    assert np.max(np.abs(sym - from_full)) < 1e-13
+
+
+def test_time_reversal_of_probabilities():
+    """Real H and real psi0: psi(-t) = conj(psi(t)), so |psi(t)|^2 = |psi(-t)|^2."""
+    H, psi0 = small_case(U=0.7)
+    ed = P.EDPropagator(H)
+    p = O.probabilities(ed.evolve(psi0, 1.9))
+    q = O.probabilities(ed.evolve(psi0, -1.9))
+    assert np.max(np.abs(p - q)) < 1e-14
+    assert np.max(np.abs(ed.evolve(psi0, 1.9) - np.conj(ed.evolve(psi0, -1.9)))) < 1e-13
+
+
+def test_mirror_symmetry_of_occupations():
+    """Mirror-symmetric parameters and mirrored starts give mirrored
+    occupations (pins bond-index orientation)."""
+    g = rng(7)
+    N = 9
+    half = 1 + g.uniform(-0.3, 0.3, (N - 1) // 2)
+    J = np.concatenate([half, half[::-1]])
+    eh = g.uniform(-0.5, 0.5, N // 2 + 1)
+    eps = np.concatenate([eh, eh[:-1][::-1]])
+    H = Hm.hamiltonian(N, 2, J, eps, 1.0)
+    st = B.basis_states(N, 2)
+    ed = P.EDPropagator(H)
+    n1 = O.occupation(ed.evolve(B.product_state(N, [1, 3]), 2.2), st, N)
+    n2 = O.occupation(ed.evolve(B.product_state(N, [N - 2, N - 4]), 2.2), st, N)
+    assert np.max(np.abs(n1 - n2[::-1])) < 1e-13
+    # and a non-symmetric J breaks it (the check has teeth)
+    J2 = J.copy()
+    J2[0] += 0.3
+    ed2 = P.EDPropagator(Hm.hamiltonian(N, 2, J2, eps, 1.0))
+    m1 = O.occupation(ed2.evolve(B.product_state(N, [1, 3]), 2.2), st, N)
+    m2 = O.occupation(ed2.evolve(B.product_state(N, [N - 2, N - 4]), 2.2), st, N)
+    assert np.max(np.abs(m1 - m2[::-1])) > 1e-4
+
+
+# ------------------------------------------------------------- observables
+
+@pytest.mark.parametrize("m,statistics", [(2, B.DISTINGUISHABLE), (3, B.DISTINGUISHABLE), (2, B.BOSON), (3, B.BOSON)])
+def test_occupation_and_pair_correlation_sum_rules(m, statistics):
+    g = rng(8)
+    N = 5
+    states = B.basis_states(N, m, statistics)
+    psi = g.normal(size=states.shape[0]) + 1j * g.normal(size=states.shape[0])
+    n = O.occupation(psi, states, N)
+    G = O.pair_correlation(psi, states, N)
+    nrm = O.norm2(psi)
+    assert abs(n.sum() - m * nrm) < 1e-12 * nrm
+    assert np.max(np.abs(G.sum(axis=1) - (m - 1) * n)) < 1e-12 * nrm
+    assert np.max(np.abs(G - G.T)) < 1e-14 * nrm
+
+
+def test_occupation_brute_force_loops():
+    g = rng(9)
+    N = 4
+    states = B.basis_states(N, 3, B.DISTINGUISHABLE)
+    psi = g.normal(size=states.shape[0]) + 1j * g.normal(size=states.shape[0])
+    n = np.zeros(N)
+    G = np.zeros((N, N))
+    for k, s in enumerate(states):
+        p = abs(psi[k]) ** 2
+        for a in range(3):
+            n[s[a]] += p
+            for b in range(3):
+                if a != b:
+                    G[s[a], s[b]] += p
+    assert np.allclose(O.occupation(psi, states, N), n, rtol=0, atol=1e-13)
+    assert np.allclose(O.pair_correlation(psi, states, N), G, rtol=0, atol=1e-13)
+    for a in range(3):
+        marg = np.array([sum(abs(psi[k]) ** 2 for k, s in enumerate(states) if s[a] == i) for i in range(N)])
+        assert np.allclose(O.marginal(psi, states, N, a), marg, rtol=0, atol=1e-13)
+
+
+def test_boson_occupation_counts_double_occupancy():
+    """|x x>_S holds two particles on node x; |x y>_S one on each."""
+    N = 4
+    states = B.basis_states(N, 2, B.BOSON)
+    for k, s in enumerate(states):
+        psi = np.zeros(states.shape[0], complex)
+        psi[k] = 1
+        n = O.occupation(psi, states, N)
+        assert n[s[0]] + (n[s[1]] if s[1] != s[0] else 0) == 2
+
+
+def test_ensemble_mean_against_fsum():
+    g = rng(10)
+    vals = g.normal(size=(1000, 3)) * 10.0 ** g.integers(-8, 8, size=(1000, 1))
+    mean = O.ensemble_mean(vals)
+    for c in range(3):
+        assert abs(mean[c] - O.exact_mean(vals[:, c])) <= 1e-14 * np.max(np.abs(vals[:, c]))
