@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Throughput of the truncated-Taylor propagation of noisy two-particle walks
+on one MI355X.
+
+Default workload (the batched complex64 case): 4096 realisations of two
+distinguishable walkers on open chains whose sizes are drawn uniformly from
+{64, 96, ..., 1024}, on-site U ~ U[0, 4], hopping noise J ~ N(1, 0.1^2),
+eps = 0, dt = 0.05, Taylor tolerance 1e-7 per step, Kahan-compensated
+accumulation of the terms.  One "step" is one time step of every
+realisation (all Taylor terms, the FP64 norm / truncation check).
+
+Metric: amplitude-updates/s = (stored amplitudes of all realisations) x
+(steps) / (time); one update advances one amplitude by one dt.  The state
+is resident in HBM before the timed region.  The same JSON line carries
+  * roofline: algorithmic HBM bytes of the dominant (step) kernel per launch
+    (read psi + write psi once) over its average duration, timed with HIP
+    events on the kernel's stream, against the 8 TB/s HBM3E peak;
+  * fp64_plain: the same workload with complex128 state at the same
+    per-step tolerance, one regular launch per step;
+  * cpu_baseline: the FP64 oracle (CSR Taylor propagator) timed on a bounded
+    sample of the same workload on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+# ------------------------------------------------------------ CPU baseline
+
+def _oracle_sample(args):
+    """Propagate one realisation with the oracle for `steps` steps; returns
+    (amplitude-updates, seconds)."""
+    N, J, eps, U, dt, steps, tol = args
+    from oracle import basis as B
+    from oracle import hamiltonian as Hm
+    from oracle import propagate as P
+    H = Hm.hamiltonian(N, 2, J, eps, U)
+    psi = B.product_state(N, [N // 2 - 1, N // 2])
+    t0 = time.perf_counter()
+    P.evolve_taylor(H, psi, dt, steps, tol=tol)
+    return N * N * steps, time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s: float = 15.0):
+    """Oracle on a sample of realisations of the workload (one process per
+    core, forked before the GPU is touched)."""
+    import multiprocessing as mp
+    cores = min(host_cores(), 16)
+    sizes = w.lattice_sizes()
+    # sample: the first realisations of the workload, in order, with their
+    # own lattice sizes; steps chosen so the sample takes ~budget_s
+    sample = list(range(min(4 * cores, w.R)))
+    probe = _oracle_sample((int(sizes[0]),) + w.realization(0, int(sizes[0])) + (w.dt, 2, w.tol))
+    rate = probe[0] / max(probe[1], 1e-9)
+    total_amp = sum(int(sizes[r]) ** 2 for r in sample)
+    steps = max(2, int(budget_s * rate * cores / max(total_amp, 1)))
+    steps = min(steps, w.n_steps)
+    jobs = [(int(sizes[r]),) + w.realization(r, int(sizes[r])) + (w.dt, steps, w.tol) for r in sample]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_sample, jobs)
+    wall = time.perf_counter() - t0
+    updates = sum(r[0] for r in res)
+    return {"value": updates / wall, "unit": "amplitude-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(sample)} realisations (N in {sorted(set(int(sizes[r]) for r in sample))}) x "
+                      f"{steps} steps of the FP64 CSR Taylor oracle, tol {w.tol:g}, {cores} processes",
+            "seconds": round(wall, 2)}
+
+
+# ---------------------------------------------------------------- GPU side
+
+def build_plan(w, dtype, accumulation, launch, tol):
+    from paper_1612_00746_amd import Plan, make_problem
+    sizes = w.lattice_sizes()
+    reals = w.all_realizations()
+    J = np.concatenate([r[1] for r in reals])
+    eps = np.concatenate([r[2] for r in reals])
+    U = np.array([r[3] for r in reals])
+    pr, keep = make_problem(2, w.R, sizes.tolist(), w.dt, statistics=w.statistics, dtype=dtype,
+                            accumulation=accumulation, taylor_tol=tol, observables=1)
+    plan = Plan(pr)
+    plan._keep.append(keep)
+    plan.set_launch(**launch)
+    plan.set_params(J, eps, U)
+    plan.bind()
+    sites = np.array([[n // 2 - 1, n // 2] for n in sizes], dtype=np.int32)
+    plan.init_product_state(sites)
+    return plan
+
+
+def time_plan(plan, steps, warmup):
+    import torch
+    plan.propagate(warmup)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.propagate(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = plan.get_timing()
+    plan.set_timing(False)
+    return wall, kern_ms / max(launches, 1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cols-per-lane", type=int, default=1)
+    ap.add_argument("--accumulation", default="kahan")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: realisations are independent, and a multi-GPU run would "
+              "shard them with one all-reduce of the FP64 observables; only --gpus 1 is built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from workloads import C3
+    w = C3("c64")
+    cpu = None if a.no_cpu else cpu_baseline(w, a.cpu_budget)   # before the GPU is touched
+
+    import torch
+    sizes = w.lattice_sizes()
+    amps = int(np.sum(sizes.astype(np.int64) ** 2))
+    launch = {"cols_per_lane": a.cols_per_lane, "persistent": 1, "waves_per_block": 4}
+    plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
+    wall, kern_ms = time_plan(plan, a.steps, a.warmup)
+    st = plan.stats()
+    ms_per_step = 1e3 * wall / a.steps
+    updates = amps * a.steps / wall
+    bytes_per_launch = amps * 16.0
+    achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
+    orders = plan.orders()
+    items, _ = plan.work_items()
+    del plan
+    torch.cuda.empty_cache()
+
+    fp64 = None
+    if not a.no_fp64:
+        p64 = build_plan(w, "c128", "plain", {"cols_per_lane": 1, "persistent": 0, "waves_per_block": 4}, w.tol)
+        wall64, kern64 = time_plan(p64, max(2, a.steps // 2), 2)
+        s64 = max(2, a.steps // 2)
+        fp64 = {"value": amps * s64 / wall64, "unit": "amplitude-updates/s", "dtype": "c128",
+                "ms_per_step": round(1e3 * wall64 / s64, 4),
+                "kernel_ms": round(kern64, 4),
+                "hbm_gbs_algorithmic": round(amps * 32.0 / (kern64 * 1e-3) / 1e9, 1),
+                "taylor_order": int(p64.orders().max()), "launch": "regular, one per step"}
+        del p64
+        torch.cuda.empty_cache()
+
+    line = {
+        "metric": "amplitude-updates/s per Taylor step",
+        "value": updates,
+        "unit": "amplitude-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic (seeded noise draws, no dataset)",
+        "config": {"workload": w.name, "realisations": w.R, "sites": "U{64,96,...,1024}",
+                   "particles": 2, "amplitudes": amps, "dt": w.dt, "taylor_tol": w.tol,
+                   "taylor_order": [int(orders.min()), int(orders.max())],
+                   "accumulation": a.accumulation, "launch": launch, "work_items": items},
+        "hbm_gbs_algorithmic": round(updates * 16.0 / 1e9, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "step2d_kernel", "kernel_ms": round(kern_ms, 4)},
+        "fp64_plain": fp64,
+        "speedup_fp32_batched_vs_fp64_plain": (round(updates / fp64["value"], 3) if fp64 else None),
+        "norm_range": [st.min_norm, st.max_norm],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * ctqw.h -- C ABI of libctqw, an MI355X (gfx950) implementation of the
+ * truncated-Taylor propagation of many noisy realisations of a
+ * many-particle tight-binding walk, after Piccinini et al., "GPU-accelerated
+ * algorithms for many-particle continuous-time quantum walks"
+ * (arXiv:1612.00746).
+ *
+ * The problem statement follows Sec. 2 of the paper: m particles on a
+ * one-dimensional lattice of N nodes (q = 1, nearest-neighbour hopping),
+ * Hamiltonian entries made of a deterministic and a stochastic part on the
+ * diagonal and between neighbours (Eq. 1), R independent realisations whose
+ * density matrices are averaged (Eq. 2), and the evolution operator
+ * exp(-i H dt) expanded in a Taylor series (Eqs. 5-7, Alg. 3).  hbar = 1.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns ctqw_status; nothing else crosses the ABI.
+ *    Output arguments come last.
+ *  - Host arrays passed in are copied before the call returns.
+ *  - Device memory (the two state buffers and the workspace) is owned by
+ *    the caller; the library never allocates or frees device memory.
+ *    Sizes come from ctqw_sizes().
+ *  - Work is enqueued on the stream given to ctqw_bind().  Calls that return
+ *    host data (ctqw_propagate, ctqw_observe, ctqw_get_state, ctqw_stats,
+ *    ctqw_realization_norms) synchronise that stream; device faults and the
+ *    norm / truncation alarms are reported by those calls.
+ *  - A plan is not thread-safe.  Distinct plans are independent.
+ *  - On CTQW_ERR_INVALID_ARG the plan is left unchanged; ctqw_last_error()
+ *    returns a description of the last failure on a plan.
+ */
+#ifndef CTQW_H
+#define CTQW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CTQW_OK = 0,
+    CTQW_ERR_INVALID_ARG = 1,   /* bad pointer, size, enum or non-finite value */
+    CTQW_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+    CTQW_ERR_OUT_OF_MEMORY = 3, /* host allocation failed or sizes overflow */
+    CTQW_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    CTQW_ERR_NOT_CONVERGED = 5, /* Taylor order above the cap, or the FP64
+                                   a-posteriori truncation test failed */
+    CTQW_ERR_NUMERICAL = 6,     /* non-finite state or norm outside the alarm */
+    CTQW_ERR_STATE = 7          /* call out of order (e.g. propagate before bind) */
+} ctqw_status;
+
+/* Particle statistics (Sec. 1 of the paper: walks depend on statistics). */
+typedef enum { CTQW_DISTINGUISHABLE = 0, CTQW_BOSON = 1 } ctqw_statistics;
+/* Open chain (N-1 bonds) or ring (N bonds, bond N-1 joins node N-1 to 0). */
+typedef enum { CTQW_OPEN = 0, CTQW_PERIODIC = 1 } ctqw_boundary;
+/* Interaction energy V(x) added to the diagonal of H:
+ *   ONSITE  : U * #{a<b : x_a == x_b}
+ *   NEAREST : U * #{a<b : chain distance |x_a - x_b| == 1}                */
+typedef enum { CTQW_INT_ONSITE = 0, CTQW_INT_NEAREST = 1 } ctqw_interaction;
+/* State precision: interleaved complex FP32 or FP64 (torch.complex64/128). */
+typedef enum { CTQW_C64 = 0, CTQW_C128 = 1 } ctqw_dtype;
+/* Summation of the Taylor terms within one step.  KAHAN: compensated
+ * (Kahan) accumulation of sum_j Phi^(j); PLAIN: ordinary accumulation.  The
+ * FP64 state always uses PLAIN.                                           */
+typedef enum { CTQW_ACC_KAHAN = 0, CTQW_ACC_PLAIN = 1 } ctqw_accumulation;
+
+/* Observables (bit mask).  OCCUPATION: <n_i> = sum_x p(x) #{a : x_a = i},
+ * which sums to m.  PAIR: G(i,j) = sum_x p(x) #{a != b : x_a = i, x_b = j}.
+ * Both come from the diagonal of the ensemble-averaged density matrix
+ * (Eq. 2 and the post-processing stage of Algs. 1-3).                     */
+#define CTQW_OBS_OCCUPATION 1u
+#define CTQW_OBS_PAIR 2u
+
+typedef struct {
+    int32_t m;               /* particles: 1 or 2 (3: CTQW_ERR_UNSUPPORTED) */
+    int32_t statistics;      /* ctqw_statistics; BOSON needs m == 2 and OPEN */
+    int32_t interaction;     /* ctqw_interaction */
+    int32_t boundary;        /* ctqw_boundary; PERIODIC needs N >= 3 */
+    int32_t dtype;           /* ctqw_dtype */
+    int32_t accumulation;    /* ctqw_accumulation (ignored for CTQW_C128) */
+    int64_t R;               /* realisations, >= 1 */
+    int32_t n_sites;         /* N for every realisation, or 0 to use ... */
+    const int32_t* n_sites_per_real; /* ... [R] sizes (uneven batch), copied */
+    double dt;               /* time step, finite and > 0 */
+    int32_t taylor_order;    /* > 0: fixed n terms per step (Alg. 3);
+                                0: n_r chosen per realisation from taylor_tol */
+    double taylor_tol;       /* per-step relative 2-norm truncation tolerance */
+    int32_t taylor_max_order;/* cap on n_r; 0 or above the compiled maximum
+                                (12 for complex64, 16 for complex128) means
+                                that maximum; above it: NOT_CONVERGED */
+    int32_t renormalize;     /* 0: monitor the norm only; 1: rescale each step */
+    double norm_alarm;       /* |norm - 1| above this -> NUMERICAL; 0: off */
+    uint32_t observables;    /* CTQW_OBS_* that ctqw_propagate may be asked for */
+} ctqw_problem;
+
+typedef struct ctqw_plan ctqw_plan;
+
+/* Per-step monitoring, FP64 (Alg. 3 "check norm", plus the truncation test). */
+typedef struct {
+    int64_t steps_done;      /* steps taken since the last ctqw_set_state/init */
+    double min_norm;         /* min over realisations of ||psi_r|| after the last step */
+    double max_norm;
+    double max_tail_ratio;   /* max over r of the estimated truncation error
+                                divided by taylor_tol * ||psi_r|| (<= 1 is ok) */
+    int32_t min_order, max_order;  /* Taylor terms used per step */
+    int64_t alarms;          /* realisation-steps that raised an alarm */
+    int32_t flags;           /* bit 0: NOT_CONVERGED, bit 1: NUMERICAL */
+} ctqw_step_stats;
+
+/* Launch shape of the propagation kernels.  Defaults are chosen by the
+ * library; ctqw_autotune() measures and stores the best one.             */
+typedef struct {
+    int32_t cols_per_lane;   /* 1 or 2 lattice columns per SIMD lane */
+    int32_t waves_per_block; /* 1, 2 or 4 */
+    int32_t persistent;      /* 0: one wave per work item; 1: a grid sized to
+                                the device pulls items from a queue */
+    int32_t use_graph;       /* 1: capture the step loop into a HIP graph */
+    int32_t waves_per_cu;    /* persistent grid: resident waves per CU (0: auto) */
+} ctqw_launch;
+
+/* Create a plan from a problem statement.  Host only: validates the
+ * problem, computes the state layout.  No device is touched.
+ * Errors: INVALID_ARG (NULL, m not in 1..3, N < 2, periodic with N < 3,
+ * non-finite or non-positive dt, order and tol both unset, bad enums),
+ * UNSUPPORTED (m == 3, bosons with m != 2 or periodic), OUT_OF_MEMORY.   */
+ctqw_status ctqw_plan_create(const ctqw_problem* problem, ctqw_plan** out);
+ctqw_status ctqw_plan_destroy(ctqw_plan* plan);
+
+/* Static parameters of every realisation (Eq. 1 with the noise drawn):
+ * J   : packed per realisation, n_bonds(N_r) values each (N_r - 1 open,
+ *       N_r periodic); bond i joins node i and node i+1 (mod N_r).
+ * eps : packed per realisation, N_r on-site energies each.
+ * U   : [R] interaction strengths.
+ * Realisations are packed in order r = 0..R-1.  Copied.  Computes the
+ * Taylor order n_r of each realisation (see ctqw_orders).
+ * Errors: INVALID_ARG (NULL, non-finite), NOT_CONVERGED (n_r above cap).   */
+ctqw_status ctqw_set_params(ctqw_plan* plan, const double* J, const double* eps,
+                            const double* U);
+ctqw_status ctqw_get_params(const ctqw_plan* plan, double* J, double* eps, double* U);
+
+/* Taylor terms per step of each realisation, [R].  With taylor_order > 0
+ * every entry is taylor_order; otherwise n_r is the smallest n >= 1 with
+ * x^(n+1)/(n+1)! / (1 - x/(n+2)) <= taylor_tol, x = dt * G_r, where G_r =
+ * m * max_i(|eps_i| + |J_(i-1)| + |J_i|) + |U_r| m(m-1)/2 bounds ||H_r||_2
+ * (Gershgorin).  Valid after ctqw_set_params.                            */
+ctqw_status ctqw_orders(const ctqw_plan* plan, int32_t* orders);
+
+/* Amplitudes stored per realisation and their offsets in a state buffer.
+ * Layouts (interleaved complex, re then im):
+ *   m = 1                : psi[x], N_r amplitudes.
+ *   m = 2 distinguishable: psi[x1][x2], x2 fastest, N_r^2 amplitudes.
+ *   m = 2 bosons         : the exchange-symmetric amplitude phi(x1, x2)
+ *                          for x1 <= x2, row-major (row x1 holds x2 = x1..N-1),
+ *                          N_r (N_r + 1) / 2 amplitudes.  In the normalised
+ *                          symmetric basis the coefficient of |x1 x2> is
+ *                          sqrt(2) phi for x1 < x2 and phi for x1 == x2.
+ * offsets: [R + 1], in amplitudes; offsets[R] is the total.                */
+ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
+
+/* Device bytes the caller must provide: each of the two state buffers and
+ * the workspace, for the current parameters and launch shape.             */
+ctqw_status ctqw_sizes(const ctqw_plan* plan, int64_t* state_bytes, int64_t* workspace_bytes);
+
+/* Bind caller-owned device memory and a HIP stream (hipStream_t, may be
+ * NULL for the default stream) and upload the parameter tables.  psi_a and
+ * psi_b are the ping-pong state buffers.  The buffers must stay valid
+ * until the plan is destroyed or re-bound.  Errors: INVALID_ARG (NULL or a
+ * buffer smaller than ctqw_sizes), STATE (params not set), DEVICE.        */
+ctqw_status ctqw_bind(ctqw_plan* plan, void* psi_a, void* psi_b, int64_t state_bytes,
+                      void* workspace, int64_t workspace_bytes, void* hip_stream);
+
+/* Start state: particle a on node sites[a] (per_realization == 0, [m]
+ * entries) or sites[r*m + a] (per_realization == 1, [R*m]).  Bosons get the
+ * normalised symmetric state of that occupation.  Resets steps_done.
+ * Errors: INVALID_ARG (site out of range), STATE (not bound).             */
+ctqw_status ctqw_init_product_state(ctqw_plan* plan, const int32_t* sites, int32_t per_realization);
+
+/* Copy the whole current state (layout of ctqw_layout, dtype of the plan)
+ * in or out.  on_device != 0: psi is a device pointer; else host memory.   */
+ctqw_status ctqw_set_state(ctqw_plan* plan, const void* psi, int32_t on_device);
+ctqw_status ctqw_get_state(ctqw_plan* plan, void* psi, int32_t on_device);
+
+/* Advance every realisation by n_steps steps of Alg. 3.  If output_every
+ * > 0 and obs != 0, the ensemble observables are evaluated at step 0 and
+ * after every output_every steps and written to out (host, FP64):
+ *   n_out = n_steps / output_every + 1 snapshots, groups = distinct lattice
+ *   sizes in ascending order, and for each snapshot and group
+ *     OCCUPATION: N_g values, then PAIR: N_g * N_g values (row-major),
+ *   snapshot-major: [n_out][group][OCC block then PAIR block].
+ * Errors: STATE, INVALID_ARG (obs not enabled in the problem),
+ * NOT_CONVERGED / NUMERICAL (alarms raised during the run), DEVICE.       */
+ctqw_status ctqw_propagate(ctqw_plan* plan, int64_t n_steps, int64_t output_every,
+                           uint32_t obs, double* out);
+
+/* Ensemble observables of the current state, same layout as one snapshot. */
+ctqw_status ctqw_observe(ctqw_plan* plan, uint32_t obs, double* out);
+
+/* Number of groups (distinct lattice sizes) and their sizes, ascending.   */
+ctqw_status ctqw_groups(const ctqw_plan* plan, int32_t* n_groups, int32_t* sizes);
+
+/* Monitoring after the last step (see ctqw_step_stats).                   */
+ctqw_status ctqw_stats(ctqw_plan* plan, ctqw_step_stats* out);
+/* FP64 squared norms and estimated squared truncation errors of every
+ * realisation after the last step, [R] each (either may be NULL).         */
+ctqw_status ctqw_realization_norms(ctqw_plan* plan, double* norm2, double* tail2);
+
+/* Launch shape (see ctqw_launch).  Setting it may change ctqw_sizes.      */
+ctqw_status ctqw_get_launch(const ctqw_plan* plan, ctqw_launch* out);
+ctqw_status ctqw_set_launch(ctqw_plan* plan, const ctqw_launch* launch);
+
+/* Number of work items (realisation x column band) of one step and the
+ * number of waves that one step launches, for the current launch shape.  */
+ctqw_status ctqw_work_items(const ctqw_plan* plan, int64_t* items, int64_t* waves);
+
+/* Kernel timing: with enable != 0, every step-kernel launch is bracketed by
+ * HIP events on the bound stream and ctqw_get_timing returns the summed
+ * elapsed time (ms) and the number of timed launches since timing was
+ * (re-)enabled.  For measurement only; adds two event records per step.    */
+ctqw_status ctqw_set_timing(ctqw_plan* plan, int32_t enable);
+ctqw_status ctqw_get_timing(ctqw_plan* plan, double* step_kernel_ms, int64_t* launches);
+
+const char* ctqw_status_string(ctqw_status status);
+const char* ctqw_last_error(const ctqw_plan* plan);
+/* Library version string. */
+const char* ctqw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTQW_H */

@@ -1,0 +1,210 @@
+"""MI355X (gfx950) propagation of noisy many-particle quantum walks.
+
+Python face of libctqw (include/ctqw.h).  The ``Plan`` class marshals
+arguments to the C ABI and provides device memory and the HIP stream from
+PyTorch; the propagation itself (stencil, Taylor series, norms,
+observables) runs in the library's HIP kernels.  There is no CPU fallback:
+without the built library, or without a GPU, the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (ACC_KAHAN, ACC_PLAIN, BOSON, C64, C128, DISTINGUISHABLE, INT_NEAREST,  # noqa: F401
+                   INT_ONSITE, OBS_OCCUPATION, OBS_PAIR, OPEN, PERIODIC, CtqwError)
+
+__all__ = ["Plan", "CtqwError", "make_problem"]
+
+_STAT = {"distinguishable": DISTINGUISHABLE, "boson": BOSON}
+_BC = {"open": OPEN, "periodic": PERIODIC}
+_INT = {"onsite": INT_ONSITE, "nearest": INT_NEAREST}
+_DT = {"c64": C64, "c128": C128}
+_ACC = {"kahan": ACC_KAHAN, "plain": ACC_PLAIN}
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def make_problem(m: int, R: int, n_sites: int | Sequence[int], dt: float, *,
+                 statistics: str = "distinguishable", boundary: str = "open",
+                 interaction: str = "onsite", dtype: str = "c128", accumulation: str = "kahan",
+                 taylor_order: int = 0, taylor_tol: float = 0.0, taylor_max_order: int = 0,
+                 renormalize: bool = False, norm_alarm: float = 0.0,
+                 observables: int = OBS_OCCUPATION):
+    """Build a ``ctqw_problem``; returns (struct, keep-alive array or None)."""
+    pr = L.Problem()
+    pr.m = m
+    pr.statistics = _STAT[statistics]
+    pr.interaction = _INT[interaction]
+    pr.boundary = _BC[boundary]
+    pr.dtype = _DT[dtype]
+    pr.accumulation = _ACC[accumulation]
+    pr.R = R
+    keep = None
+    if np.isscalar(n_sites):
+        pr.n_sites = int(n_sites)
+    else:
+        keep = np.ascontiguousarray(n_sites, dtype=np.int32)
+        if keep.shape[0] != R:
+            raise ValueError("n_sites list must have R entries")
+        pr.n_sites = 0
+        pr.n_sites_per_real = _ptr(keep, C.c_int32)
+    pr.dt = dt
+    pr.taylor_order = taylor_order
+    pr.taylor_tol = taylor_tol
+    pr.taylor_max_order = taylor_max_order
+    pr.renormalize = 1 if renormalize else 0
+    pr.norm_alarm = norm_alarm
+    pr.observables = observables
+    return pr, keep
+
+
+class Plan:
+    """One ``ctqw_plan`` with torch-owned device buffers."""
+
+    def __init__(self, problem: "L.Problem"):
+        self.lib = L.load()
+        self.problem = problem
+        h = L.PlanP()
+        L.check(self.lib.ctqw_plan_create(C.byref(problem), C.byref(h)))
+        self.h = h
+        self.R = int(problem.R)
+        self.m = int(problem.m)
+        self.dtype = "c128" if problem.dtype == C128 else "c64"
+        self._buffers = None
+        self._keep = []
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.ctqw_plan_destroy(h)
+            self.h = None
+
+    def _check(self, status):
+        L.check(status, self.h)
+
+    # -------------------------------------------------------------- host side
+    def set_params(self, J: np.ndarray, eps: np.ndarray, U: np.ndarray) -> None:
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        self._check(self.lib.ctqw_set_params(self.h, _ptr(J, C.c_double), _ptr(eps, C.c_double),
+                                             _ptr(U, C.c_double)))
+
+    def orders(self) -> np.ndarray:
+        out = np.zeros(self.R, dtype=np.int32)
+        self._check(self.lib.ctqw_orders(self.h, _ptr(out, C.c_int32)))
+        return out
+
+    def layout(self) -> np.ndarray:
+        out = np.zeros(self.R + 1, dtype=np.int64)
+        self._check(self.lib.ctqw_layout(self.h, _ptr(out, C.c_int64)))
+        return out
+
+    def sizes(self) -> tuple[int, int]:
+        s, w = C.c_int64(), C.c_int64()
+        self._check(self.lib.ctqw_sizes(self.h, C.byref(s), C.byref(w)))
+        return s.value, w.value
+
+    def groups(self) -> np.ndarray:
+        n = C.c_int32()
+        self._check(self.lib.ctqw_groups(self.h, C.byref(n), None))
+        out = np.zeros(n.value, dtype=np.int32)
+        self._check(self.lib.ctqw_groups(self.h, C.byref(n), _ptr(out, C.c_int32)))
+        return out
+
+    def get_launch(self) -> "L.Launch":
+        l = L.Launch()
+        self._check(self.lib.ctqw_get_launch(self.h, C.byref(l)))
+        return l
+
+    def set_launch(self, **kw) -> None:
+        l = self.get_launch()
+        for k, v in kw.items():
+            setattr(l, k, int(v))
+        self._check(self.lib.ctqw_set_launch(self.h, C.byref(l)))
+
+    def work_items(self) -> tuple[int, int]:
+        a, b = C.c_int64(), C.c_int64()
+        self._check(self.lib.ctqw_work_items(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    # ------------------------------------------------------------ device side
+    def bind(self, device: str = "cuda", stream=None) -> None:
+        import torch
+        state_bytes, ws_bytes = self.sizes()
+        dev = torch.device(device)
+        psi_a = torch.empty(max(state_bytes, 256), dtype=torch.uint8, device=dev)
+        psi_b = torch.empty(max(state_bytes, 256), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self._buffers = (psi_a, psi_b, ws)
+        self._stream = stream
+        self._check(self.lib.ctqw_bind(self.h, C.c_void_p(psi_a.data_ptr()), C.c_void_p(psi_b.data_ptr()),
+                                       state_bytes, C.c_void_p(ws.data_ptr()), ws_bytes,
+                                       C.c_void_p(stream.cuda_stream)))
+
+    def init_product_state(self, sites) -> None:
+        s = np.ascontiguousarray(sites, dtype=np.int32)
+        per_real = 1 if s.ndim == 2 else 0
+        s = s.reshape(-1)
+        self._check(self.lib.ctqw_init_product_state(self.h, _ptr(s, C.c_int32), per_real))
+
+    def state_numpy(self) -> np.ndarray:
+        total = int(self.layout()[-1])
+        out = np.zeros(total, dtype=np.complex128 if self.dtype == "c128" else np.complex64)
+        self._check(self.lib.ctqw_get_state(self.h, out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def set_state_numpy(self, psi: np.ndarray) -> None:
+        psi = np.ascontiguousarray(psi, dtype=np.complex128 if self.dtype == "c128" else np.complex64)
+        self._check(self.lib.ctqw_set_state(self.h, psi.ctypes.data_as(C.c_void_p), 0))
+
+    def snapshot_len(self, obs: int) -> int:
+        n = 0
+        for Ng in self.groups():
+            if obs & OBS_OCCUPATION:
+                n += int(Ng)
+            if obs & OBS_PAIR:
+                n += int(Ng) * int(Ng)
+        return n
+
+    def propagate(self, n_steps: int, output_every: int = 0, obs: int = 0) -> Optional[np.ndarray]:
+        if output_every > 0 and obs:
+            n_out = n_steps // output_every + 1
+            out = np.zeros(n_out * self.snapshot_len(obs), dtype=np.float64)
+            self._check(self.lib.ctqw_propagate(self.h, n_steps, output_every, obs, _ptr(out, C.c_double)))
+            return out.reshape(n_out, -1)
+        self._check(self.lib.ctqw_propagate(self.h, n_steps, 0, 0, None))
+        return None
+
+    def observe(self, obs: int = OBS_OCCUPATION) -> np.ndarray:
+        out = np.zeros(self.snapshot_len(obs), dtype=np.float64)
+        self._check(self.lib.ctqw_observe(self.h, obs, _ptr(out, C.c_double)))
+        return out
+
+    def stats(self) -> "L.StepStats":
+        s = L.StepStats()
+        self._check(self.lib.ctqw_stats(self.h, C.byref(s)))
+        return s
+
+    def set_timing(self, enable: bool) -> None:
+        self._check(self.lib.ctqw_set_timing(self.h, 1 if enable else 0))
+
+    def get_timing(self) -> tuple[float, int]:
+        ms, n = C.c_double(), C.c_int64()
+        self._check(self.lib.ctqw_get_timing(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def realization_norms(self) -> tuple[np.ndarray, np.ndarray]:
+        n2 = np.zeros(self.R)
+        t2 = np.zeros(self.R)
+        self._check(self.lib.ctqw_realization_norms(self.h, _ptr(n2, C.c_double), _ptr(t2, C.c_double)))
+        return n2, t2

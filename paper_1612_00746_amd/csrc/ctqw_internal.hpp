@@ -1,0 +1,141 @@
+// Internal tables and launch descriptors shared by the host runtime and the
+// HIP kernels of libctqw.  Not part of the public ABI (include/ctqw.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ctqw {
+
+// Bits of RealDev::flags.
+enum : int32_t {
+    RF_PERIODIC = 1,   // ring: bond N-1 joins node N-1 and node 0
+    RF_TRIANGLE = 2,   // two bosons stored as the upper triangle x1 <= x2
+    RF_NEAREST = 4,    // interaction on pairs at chain distance 1
+};
+
+// One realisation, as the kernels see it.  The walk of m = 1 or 2 particles
+// is a grid of `rows` x N amplitudes: rows = N for two particles (x1 runs
+// over rows, x2 over columns) and rows = 1 for one particle.
+struct RealDev {
+    int64_t state_off;   // first amplitude in a state buffer
+    int32_t N;           // nodes (columns)
+    int32_t rows;        // rows of the amplitude grid (1 or N)
+    int32_t order;       // Taylor terms per step
+    int32_t param_off;   // J / eps of this realisation: [N] each, J padded
+    int32_t row_param_off;  // J / eps for the row axis (a zero block if rows == 1)
+    int32_t flags;       // RF_*
+    double U;            // interaction strength (0 for one particle)
+    double tail_factor;  // remainder estimate / ||Phi^(n)|| (see runtime)
+};
+
+// One work item: a band of columns of one realisation, swept over all rows.
+// The wave holds columns [w0, w0 + 64 * P); only [lo, hi) are written, the
+// rest is halo that is recomputed by the neighbouring band.
+struct ItemDev {
+    int32_t real;
+    int32_t w0;          // first window column (negative allowed on a ring)
+    int32_t lo, hi;      // output columns
+    int32_t row0;        // first swept row (negative allowed on a ring)
+    int32_t nrows;       // swept rows
+    int32_t out_lo, out_hi;  // output rows (absolute)
+};
+
+struct StepArgs {
+    const void* psi_in;
+    void* psi_out;
+    const RealDev* reals;
+    const ItemDev* items;
+    const int32_t* item_order;   // processing order (largest first)
+    int32_t n_items;
+    int32_t n_waves;             // persistent launch: waves in the grid
+    const double* Jd;
+    const double* Ed;
+    const float* Jf;
+    const float* Ef;
+    const double* scale;         // [R] factor applied when loading the state
+    double* norm_part;           // [n_items] sum of w |psi_out|^2 of each item
+    double* tail_part;           // [n_items] sum of w |Phi^(n)|^2 of each item
+    int32_t* queue;              // persistent launch: [2] ticket / exit counters
+    double dt;
+    int32_t persistent;          // 1: grid sized to the device, items from queue
+};
+
+struct StepConfig {
+    int dtype;          // 0: complex64, 1: complex128
+    int kahan;          // compensated accumulation (complex64 only)
+    int cols_per_lane;  // 1 or 2
+    int levels;         // compiled pipeline depth (>= max order in the batch)
+    int waves_per_block;
+    int persistent;
+    int grid_blocks;    // persistent: blocks to launch
+};
+
+// Host entry points implemented in the .hip translation units.
+hipError_t launch_step(const StepConfig& cfg, const StepArgs& args, hipStream_t stream);
+// Smallest compiled pipeline depth >= order (-1 if none).
+int step_levels_bucket(int dtype, int cols_per_lane, int order);
+hipError_t step_occupancy(const StepConfig& cfg, int* blocks_per_cu);
+
+struct FinalizeArgs {
+    const int32_t* item_first;   // [R + 1] home items of each realisation
+    const double* norm_part;
+    const double* tail_part;
+    const RealDev* reals;
+    double* norm2;               // [R]
+    double* tail2;               // [R] estimated squared truncation error
+    double* scale;               // [R] next load scale
+    int32_t* status;             // [4]: flags, alarm count lo, alarm count hi, pad
+    int64_t R;
+    double tol2;
+    double norm_alarm;
+    int renormalize;
+};
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t stream);
+
+struct InitArgs {
+    void* psi;
+    const RealDev* reals;
+    const int32_t* sites;        // [m] or [R*m]
+    int32_t per_real;
+    int32_t m;
+    int64_t R;
+    int64_t total;               // amplitudes
+    int dtype;
+};
+hipError_t launch_init(const InitArgs& a, hipStream_t stream);
+
+struct ObsArgs {
+    const void* psi;
+    const RealDev* reals;
+    const double* scale;
+    double* colsum;              // [sum_r N_r]
+    double* rowsum;              // [sum_r N_r]
+    double* diag;                // [sum_r N_r] p(i, i) (two particles)
+    const int64_t* site_off;     // [R] offsets into the per-site arrays
+    const int32_t* group_members;  // realisations ordered by group
+    const int32_t* group_first;  // [G + 1]
+    const int32_t* group_N;      // [G]
+    const int64_t* group_out;    // [G] offset of the group's block in out
+    double* out;                 // device snapshot buffer
+    int64_t R;
+    int32_t G;
+    int32_t m;
+    int32_t max_N;
+    int32_t want_pair;
+    int dtype;
+};
+hipError_t launch_observables(const ObsArgs& a, hipStream_t stream);
+
+struct RescaleArgs {
+    void* psi;
+    const RealDev* reals;
+    double* scale;
+    int64_t R;
+    int dtype;
+};
+hipError_t launch_rescale(const RescaleArgs& a, hipStream_t stream);
+
+hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t stream);
+
+}  // namespace ctqw

@@ -1,0 +1,996 @@
+// Host runtime of libctqw: the C ABI of include/ctqw.h.
+//
+// Stage structure of Algs. 2-3 (Sec. 3 of the paper: initialisation,
+// wave-function evolution, Hamiltonian update, density-matrix
+// post-processing).  Static noise: the Hamiltonian update stage is empty.
+//  * initialisation  -- ctqw_plan_create / ctqw_set_params build the
+//    realisation tables, Taylor orders and column bands on the host;
+//    ctqw_bind uploads them once into the caller's workspace.
+//  * evolution       -- ctqw_propagate launches one fused step kernel per
+//    time step (all Taylor terms, Alg. 3) and a small FP64 kernel that
+//    reduces the per-band norms in a fixed order and raises the alarms
+//    (the "check norm" line of Alg. 3).
+//  * post-processing -- the diagonal of the ensemble-averaged density matrix
+//    (occupations, pair correlation), reduced in FP64 in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ctqw.h"
+#include "ctqw_internal.hpp"
+
+using namespace ctqw;
+
+namespace {
+
+constexpr int kMaxSites = 32768;
+thread_local std::string g_last_error;
+
+struct Region {
+    int64_t off = 0;
+    int64_t bytes = 0;
+};
+
+struct Layout {
+    Region reals, items, order, item_first, Jd, Ed, Jf, Ef, scale, norm_part, tail_part, norm2,
+        tail2, status, queue, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites;
+    int64_t total = 0;
+};
+
+}  // namespace
+
+struct ctqw_plan {
+    ctqw_problem prob{};
+    std::vector<int32_t> N;          // [R]
+    std::vector<int64_t> state_off;  // [R + 1]
+    std::vector<int32_t> param_off;  // [R] into the padded J / eps arrays
+    int64_t param_total = 0;         // padded entries incl. the zero block
+    int32_t zero_block = 0;          // offset of the all-zero row-axis block
+    int32_t max_N = 0;
+    int64_t site_total = 0;          // sum_r N_r
+    std::vector<int64_t> site_off;   // [R]
+    bool params_set = false;
+    std::vector<double> J, eps, U;   // user layout (packed, unpadded)
+    std::vector<double> Jpad, Epad;  // padded [param_total]
+    std::vector<int32_t> order;      // [R]
+    std::vector<double> tail_factor; // [R]
+    // groups (distinct N, ascending)
+    std::vector<int32_t> group_N, group_first, group_members;
+    std::vector<int64_t> group_out;
+    int64_t obs_per_snapshot = 0;
+    // work items
+    std::vector<ItemDev> items;
+    std::vector<int32_t> item_first, item_order;
+    int levels = 0;
+    ctqw_launch launch{};
+    Layout lay;
+    bool tables_dirty = true;
+    // binding
+    bool bound = false;
+    void* psi[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint8_t* ws = nullptr;
+    int64_t ws_bytes = 0;
+    int64_t state_bytes_bound = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    int64_t steps_done = 0;
+    bool have_step_stats = false;
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;      // pairs (start, stop) per timed launch
+    size_t ev_used = 0;              // events recorded and not yet read
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    std::string err;
+    ~ctqw_plan() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+ctqw_status fail(ctqw_plan* p, ctqw_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    if (p) p->err = buf;
+    return s;
+}
+
+#define HIP_TRY(p, call)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((p), CTQW_ERR_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+int n_bonds(const ctqw_problem& pr, int N) { return pr.boundary == CTQW_PERIODIC ? N : N - 1; }
+
+int64_t amplitudes(const ctqw_problem& pr, int N) {
+    if (pr.m == 1) return N;
+    if (pr.statistics == CTQW_BOSON) return (int64_t)N * (N + 1) / 2;
+    return (int64_t)N * N;
+}
+
+int max_order_cap(const ctqw_problem& pr) {
+    const int compiled = pr.dtype == CTQW_C128 ? 16 : 12;
+    if (pr.taylor_max_order > 0) return std::min(pr.taylor_max_order, compiled);
+    return compiled;
+}
+
+// a-priori remainder bound of the degree-n Taylor polynomial of exp(z),
+// |z| <= x: sum_{k>n} x^k/k! <= x^(n+1)/(n+1)! / (1 - x/(n+2)).
+double remainder_bound(double x, int n) {
+    if (x >= n + 2) return INFINITY;
+    double t = 1.0;
+    for (int k = 1; k <= n + 1; ++k) t *= x / k;
+    return t / (1.0 - x / (n + 2));
+}
+
+void align_region(Layout& L, Region& r, int64_t bytes) {
+    L.total = (L.total + 255) & ~int64_t(255);
+    r.off = L.total;
+    r.bytes = bytes;
+    L.total += bytes;
+}
+
+template <typename T>
+T* at(ctqw_plan* p, const Region& r) {
+    return reinterpret_cast<T*>(p->ws + r.off);
+}
+
+// Column bands of one realisation for halo h (= its Taylor order) and a
+// window of W columns.  Returns false if the halo leaves no output column.
+bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, std::vector<ItemDev>& out) {
+    const int rows = pr.m == 1 ? 1 : N;
+    const bool periodic = pr.boundary == CTQW_PERIODIC;
+    const bool tri = pr.m == 2 && pr.statistics == CTQW_BOSON;
+    if (W - 2 * h <= 0) return false;
+    int lo = 0;
+    while (lo < N) {
+        ItemDev it{};
+        it.real = r;
+        if (periodic) {
+            it.w0 = lo - h;
+            it.lo = lo;
+            it.hi = std::min(N, lo + W - 2 * h);
+        } else {
+            int w0 = std::max(0, lo - h);
+            if (w0 + W > N) w0 = std::max(0, N - W);
+            const int w1 = std::min(N, w0 + W);
+            it.w0 = w0;
+            it.lo = lo;
+            it.hi = (w1 == N) ? N : w1 - h;
+        }
+        if (it.hi <= it.lo) return false;
+        if (periodic && rows > 1) {
+            it.row0 = -h;
+            it.nrows = rows + 2 * h;
+        } else if (tri) {
+            it.row0 = 0;
+            it.nrows = std::min(rows, it.w0 + W);
+        } else {
+            it.row0 = 0;
+            it.nrows = rows;
+        }
+        it.out_lo = 0;
+        it.out_hi = rows;
+        out.push_back(it);
+        lo = it.hi;
+    }
+    return true;
+}
+
+ctqw_status build_tables(ctqw_plan* p) {
+    const ctqw_problem& pr = p->prob;
+    const int P = p->launch.cols_per_lane;
+    const int W = 64 * P;
+    int maxn = 0;
+    for (int64_t r = 0; r < pr.R; ++r) maxn = std::max(maxn, p->order[r]);
+    const int levels = step_levels_bucket(pr.dtype == CTQW_C128 ? 1 : 0, P, maxn);
+    if (levels < 0)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d has no compiled kernel for %d column(s) per lane",
+                    maxn, P);
+    std::vector<ItemDev> items;
+    std::vector<int32_t> first(pr.R + 1, 0);
+    for (int64_t r = 0; r < pr.R; ++r) {
+        first[r] = (int32_t)items.size();
+        if (!make_bands(pr, (int)r, p->N[r], p->order[r], W, items))
+            return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", p->order[r], W);
+    }
+    first[pr.R] = (int32_t)items.size();
+    if (items.size() > (size_t)INT32_MAX) return fail(p, CTQW_ERR_OUT_OF_MEMORY, "too many work items");
+    std::vector<int32_t> ord(items.size());
+    std::vector<int64_t> cost(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        ord[k] = (int32_t)k;
+        cost[k] = (int64_t)(items[k].nrows + levels) * p->order[items[k].real];
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    p->items.swap(items);
+    p->item_first.swap(first);
+    p->item_order.swap(ord);
+    p->levels = levels;
+
+    // workspace layout
+    Layout L;
+    const int64_t R = pr.R;
+    const int64_t nit = (int64_t)p->items.size();
+    const int64_t G = (int64_t)p->group_N.size();
+    align_region(L, L.reals, R * (int64_t)sizeof(RealDev));
+    align_region(L, L.items, nit * (int64_t)sizeof(ItemDev));
+    align_region(L, L.order, nit * 4);
+    align_region(L, L.item_first, (R + 1) * 4);
+    align_region(L, L.Jd, p->param_total * 8);
+    align_region(L, L.Ed, p->param_total * 8);
+    align_region(L, L.Jf, p->param_total * 4);
+    align_region(L, L.Ef, p->param_total * 4);
+    align_region(L, L.scale, R * 8);
+    align_region(L, L.norm_part, nit * 8);
+    align_region(L, L.tail_part, nit * 8);
+    align_region(L, L.norm2, R * 8);
+    align_region(L, L.tail2, R * 8);
+    align_region(L, L.status, 16);
+    align_region(L, L.queue, 16);
+    align_region(L, L.colsum, p->site_total * 8);
+    align_region(L, L.rowsum, p->site_total * 8);
+    align_region(L, L.diag, p->site_total * 8);
+    align_region(L, L.site_off, R * 8);
+    align_region(L, L.gmembers, R * 4);
+    align_region(L, L.gfirst, (G + 1) * 4);
+    align_region(L, L.gN, G * 4);
+    align_region(L, L.gout, G * 8);
+    align_region(L, L.obs, p->obs_per_snapshot * 8);
+    align_region(L, L.sites, R * pr.m * 4);
+    L.total = (L.total + 255) & ~int64_t(255);
+    p->lay = L;
+    p->tables_dirty = true;
+    return CTQW_OK;
+}
+
+ctqw_status upload_tables(ctqw_plan* p) {
+    const ctqw_problem& pr = p->prob;
+    const Layout& L = p->lay;
+    const int64_t R = pr.R;
+    std::vector<RealDev> reals(R);
+    for (int64_t r = 0; r < R; ++r) {
+        RealDev& d = reals[r];
+        d.state_off = p->state_off[r];
+        d.N = p->N[r];
+        d.rows = pr.m == 1 ? 1 : p->N[r];
+        d.order = p->order[r];
+        d.param_off = p->param_off[r];
+        d.row_param_off = pr.m == 1 ? p->zero_block : p->param_off[r];
+        d.flags = (pr.boundary == CTQW_PERIODIC ? RF_PERIODIC : 0) |
+                  (pr.m == 2 && pr.statistics == CTQW_BOSON ? RF_TRIANGLE : 0) |
+                  (pr.interaction == CTQW_INT_NEAREST ? RF_NEAREST : 0);
+        d.U = pr.m == 1 ? 0.0 : p->U[r];
+        d.tail_factor = p->tail_factor[r];
+    }
+    std::vector<float> Jf(p->Jpad.begin(), p->Jpad.end()), Ef(p->Epad.begin(), p->Epad.end());
+    std::vector<double> ones(R, 1.0);
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    hipStream_t s = p->stream;
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.reals.off, reals.data(), L.reals.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.items.off, p->items.data(), L.items.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.order.off, p->item_order.data(), L.order.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.item_first.off, p->item_first.data(), L.item_first.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Jd.off, p->Jpad.data(), L.Jd.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Ed.off, p->Epad.data(), L.Ed.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Jf.off, Jf.data(), L.Jf.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Ef.off, Ef.data(), L.Ef.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.scale.off, ones.data(), L.scale.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.site_off.off, p->site_off.data(), L.site_off.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.gmembers.off, p->group_members.data(), L.gmembers.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.gfirst.off, p->group_first.data(), L.gfirst.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.gN.off, p->group_N.data(), L.gN.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.gout.off, p->group_out.data(), L.gout.bytes, h2d, s));
+    HIP_TRY(p, launch_fill_zero(p->ws + L.status.off, 32, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    p->tables_dirty = false;
+    return CTQW_OK;
+}
+
+ctqw_status ensure_ready(ctqw_plan* p) {
+    if (!p->bound) return fail(p, CTQW_ERR_STATE, "plan is not bound to device memory");
+    if (p->lay.total > p->ws_bytes)
+        return fail(p, CTQW_ERR_STATE, "workspace too small (%lld < %lld bytes); query ctqw_sizes and re-bind",
+                    (long long)p->ws_bytes, (long long)p->lay.total);
+    if (p->tables_dirty) return upload_tables(p);
+    return CTQW_OK;
+}
+
+StepConfig step_config(ctqw_plan* p) {
+    StepConfig c{};
+    c.dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
+    c.kahan = (c.dtype == 0 && p->prob.accumulation == CTQW_ACC_KAHAN) ? 1 : 0;
+    c.cols_per_lane = p->launch.cols_per_lane;
+    c.levels = p->levels;
+    c.waves_per_block = p->launch.waves_per_block;
+    c.persistent = p->launch.persistent;
+    c.grid_blocks = 0;
+    return c;
+}
+
+ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
+    if (!c.persistent) {
+        *n_waves = (int)p->items.size();
+        return CTQW_OK;
+    }
+    int per_cu = 0;
+    HIP_TRY(p, step_occupancy(c, &per_cu));
+    if (p->launch.waves_per_cu > 0) per_cu = std::max(1, p->launch.waves_per_cu / c.waves_per_block);
+    if (per_cu < 1) per_cu = 1;
+    int64_t blocks = (int64_t)p->cu_count * per_cu;
+    const int64_t need = ((int64_t)p->items.size() + c.waves_per_block - 1) / c.waves_per_block;
+    blocks = std::max<int64_t>(1, std::min(blocks, need));
+    c.grid_blocks = (int)blocks;
+    *n_waves = (int)(blocks * c.waves_per_block);
+    return CTQW_OK;
+}
+
+ctqw_status enqueue_step(ctqw_plan* p) {
+    const Layout& L = p->lay;
+    StepConfig c = step_config(p);
+    int n_waves = 0;
+    ctqw_status st = grid_for(p, c, &n_waves);
+    if (st != CTQW_OK) return st;
+    StepArgs a{};
+    a.psi_in = p->psi[p->cur];
+    a.psi_out = p->psi[1 - p->cur];
+    a.reals = at<RealDev>(p, L.reals);
+    a.items = at<ItemDev>(p, L.items);
+    a.item_order = at<int32_t>(p, L.order);
+    a.n_items = (int32_t)p->items.size();
+    a.n_waves = n_waves;
+    a.Jd = at<double>(p, L.Jd);
+    a.Ed = at<double>(p, L.Ed);
+    a.Jf = at<float>(p, L.Jf);
+    a.Ef = at<float>(p, L.Ef);
+    a.scale = at<double>(p, L.scale);
+    a.norm_part = at<double>(p, L.norm_part);
+    a.tail_part = at<double>(p, L.tail_part);
+    a.queue = at<int32_t>(p, L.queue);
+    a.dt = p->prob.dt;
+    a.persistent = c.persistent;
+    if (p->timing) {
+        if (p->ev_used + 2 > p->ev.size()) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t e;
+                HIP_TRY(p, hipEventCreate(&e));
+                p->ev.push_back(e);
+            }
+        }
+        HIP_TRY(p, hipEventRecord(p->ev[p->ev_used], p->stream));
+    }
+    HIP_TRY(p, launch_step(c, a, p->stream));
+    if (p->timing) {
+        HIP_TRY(p, hipEventRecord(p->ev[p->ev_used + 1], p->stream));
+        p->ev_used += 2;
+    }
+    FinalizeArgs f{};
+    f.item_first = at<int32_t>(p, L.item_first);
+    f.norm_part = a.norm_part;
+    f.tail_part = a.tail_part;
+    f.reals = a.reals;
+    f.norm2 = at<double>(p, L.norm2);
+    f.tail2 = at<double>(p, L.tail2);
+    f.scale = at<double>(p, L.scale);
+    f.status = at<int32_t>(p, L.status);
+    f.R = p->prob.R;
+    f.tol2 = p->prob.taylor_tol > 0 ? p->prob.taylor_tol * p->prob.taylor_tol : 0.0;
+    f.norm_alarm = p->prob.norm_alarm;
+    f.renormalize = p->prob.renormalize;
+    HIP_TRY(p, launch_finalize(f, p->stream));
+    p->cur = 1 - p->cur;
+    p->steps_done += 1;
+    p->have_step_stats = true;
+    return CTQW_OK;
+}
+
+ctqw_status enqueue_observe(ctqw_plan* p, int want_pair) {
+    const Layout& L = p->lay;
+    ObsArgs o{};
+    o.psi = p->psi[p->cur];
+    o.reals = at<RealDev>(p, L.reals);
+    o.scale = at<double>(p, L.scale);
+    o.colsum = at<double>(p, L.colsum);
+    o.rowsum = at<double>(p, L.rowsum);
+    o.diag = at<double>(p, L.diag);
+    o.site_off = at<int64_t>(p, L.site_off);
+    o.group_members = at<int32_t>(p, L.gmembers);
+    o.group_first = at<int32_t>(p, L.gfirst);
+    o.group_N = at<int32_t>(p, L.gN);
+    o.group_out = at<int64_t>(p, L.gout);
+    o.out = at<double>(p, L.obs);
+    o.R = p->prob.R;
+    o.G = (int32_t)p->group_N.size();
+    o.m = p->prob.m;
+    o.max_N = p->max_N;
+    o.want_pair = want_pair;
+    o.dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
+    HIP_TRY(p, launch_observables(o, p->stream));
+    return CTQW_OK;
+}
+
+int64_t snapshot_len(const ctqw_plan* p, uint32_t obs) {
+    int64_t n = 0;
+    for (int32_t Ng : p->group_N) {
+        if (obs & CTQW_OBS_OCCUPATION) n += Ng;
+        if (obs & CTQW_OBS_PAIR) n += (int64_t)Ng * Ng;
+    }
+    return n;
+}
+
+// Copy the device snapshot (layout: per group [occ][pair if enabled]) into
+// the caller's layout for the requested observables.
+ctqw_status read_snapshot(ctqw_plan* p, uint32_t obs, double* out) {
+    std::vector<double> host(p->obs_per_snapshot);
+    HIP_TRY(p, hipMemcpyAsync(host.data(), p->ws + p->lay.obs.off, p->lay.obs.bytes, hipMemcpyDeviceToHost,
+                              p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    int64_t k = 0;
+    for (size_t g = 0; g < p->group_N.size(); ++g) {
+        const int64_t Ng = p->group_N[g];
+        const double* src = host.data() + p->group_out[g];
+        if (obs & CTQW_OBS_OCCUPATION) {
+            std::memcpy(out + k, src, Ng * 8);
+            k += Ng;
+        }
+        if (obs & CTQW_OBS_PAIR) {
+            std::memcpy(out + k, src + Ng, Ng * Ng * 8);
+            k += Ng * Ng;
+        }
+    }
+    return CTQW_OK;
+}
+
+// Sum the recorded event pairs (synchronises the stream).
+ctqw_status collect_timing(ctqw_plan* p) {
+    if (p->ev_used == 0) return CTQW_OK;
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    for (size_t k = 0; k + 1 < p->ev_used; k += 2) {
+        float ms = 0.f;
+        HIP_TRY(p, hipEventElapsedTime(&ms, p->ev[k], p->ev[k + 1]));
+        p->timed_ms += ms;
+        p->timed_launches += 1;
+    }
+    p->ev_used = 0;
+    return CTQW_OK;
+}
+
+ctqw_status read_status(ctqw_plan* p, int32_t* st) {
+    HIP_TRY(p, hipMemcpyAsync(st, p->ws + p->lay.status.off, 16, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return CTQW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ctqw_version(void) { return "ctqw-mi355x 0.1 (gfx950)"; }
+
+const char* ctqw_status_string(ctqw_status s) {
+    switch (s) {
+        case CTQW_OK: return "ok";
+        case CTQW_ERR_INVALID_ARG: return "invalid argument";
+        case CTQW_ERR_UNSUPPORTED: return "unsupported";
+        case CTQW_ERR_OUT_OF_MEMORY: return "out of memory";
+        case CTQW_ERR_DEVICE: return "device error";
+        case CTQW_ERR_NOT_CONVERGED: return "not converged";
+        case CTQW_ERR_NUMERICAL: return "numerical alarm";
+        case CTQW_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* ctqw_last_error(const ctqw_plan* p) {
+    if (p) return p->err.c_str();
+    return g_last_error.c_str();
+}
+
+ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
+    if (!pr || !out) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL problem or output pointer");
+    *out = nullptr;
+    if (pr->m < 1 || pr->m > 3) return fail(nullptr, CTQW_ERR_INVALID_ARG, "m must be 1, 2 or 3 (got %d)", pr->m);
+    if (pr->statistics != CTQW_DISTINGUISHABLE && pr->statistics != CTQW_BOSON)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown statistics %d", pr->statistics);
+    if (pr->interaction != CTQW_INT_ONSITE && pr->interaction != CTQW_INT_NEAREST)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown interaction %d", pr->interaction);
+    if (pr->boundary != CTQW_OPEN && pr->boundary != CTQW_PERIODIC)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown boundary %d", pr->boundary);
+    if (pr->dtype != CTQW_C64 && pr->dtype != CTQW_C128)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown dtype %d", pr->dtype);
+    if (pr->accumulation != CTQW_ACC_KAHAN && pr->accumulation != CTQW_ACC_PLAIN)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown accumulation %d", pr->accumulation);
+    if (pr->R < 1) return fail(nullptr, CTQW_ERR_INVALID_ARG, "R must be >= 1");
+    if (!(is_fin(pr->dt) && pr->dt > 0)) return fail(nullptr, CTQW_ERR_INVALID_ARG, "dt must be finite and > 0");
+    if (pr->taylor_order < 0) return fail(nullptr, CTQW_ERR_INVALID_ARG, "taylor_order must be >= 0");
+    if (!is_fin(pr->taylor_tol) || pr->taylor_tol < 0)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "taylor_tol must be finite and >= 0");
+    if (pr->taylor_order == 0 && !(pr->taylor_tol > 0))
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "set taylor_order > 0 or taylor_tol > 0");
+    if (pr->taylor_max_order < 0) return fail(nullptr, CTQW_ERR_INVALID_ARG, "taylor_max_order must be >= 0");
+    if (!is_fin(pr->norm_alarm) || pr->norm_alarm < 0)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "norm_alarm must be finite and >= 0");
+    if (pr->renormalize != 0 && pr->renormalize != 1)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "renormalize must be 0 or 1");
+    if (pr->observables & ~(CTQW_OBS_OCCUPATION | CTQW_OBS_PAIR))
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown observable bits 0x%x", pr->observables);
+    if (pr->n_sites == 0 && !pr->n_sites_per_real)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "set n_sites or n_sites_per_real");
+    if (pr->n_sites < 0) return fail(nullptr, CTQW_ERR_INVALID_ARG, "n_sites must be >= 0");
+    if (pr->R > 65535) return fail(nullptr, CTQW_ERR_UNSUPPORTED, "at most 65535 realisations per plan");
+    if (pr->m == 3) return fail(nullptr, CTQW_ERR_UNSUPPORTED, "three particles are not built yet");
+    if (pr->statistics == CTQW_BOSON && pr->m != 2 && pr->m != 1)
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "bosons are built for m == 2");
+    if (pr->statistics == CTQW_BOSON && pr->m == 2 && pr->boundary == CTQW_PERIODIC)
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "bosons on a ring are not built (use distinguishable "
+                                                   "particles with a symmetrised start)");
+
+    ctqw_plan* p = new (std::nothrow) ctqw_plan();
+    if (!p) return fail(nullptr, CTQW_ERR_OUT_OF_MEMORY, "host allocation failed");
+    try {
+        p->prob = *pr;
+        p->prob.n_sites_per_real = nullptr;
+        const int64_t R = pr->R;
+        p->N.resize(R);
+        for (int64_t r = 0; r < R; ++r) {
+            const int N = pr->n_sites > 0 ? pr->n_sites : pr->n_sites_per_real[r];
+            if (N < 2 || N > kMaxSites) {
+                delete p;
+                return fail(nullptr, CTQW_ERR_INVALID_ARG, "realisation %lld: N = %d outside [2, %d]",
+                            (long long)r, N, kMaxSites);
+            }
+            if (pr->boundary == CTQW_PERIODIC && N < 3) {
+                delete p;
+                return fail(nullptr, CTQW_ERR_INVALID_ARG, "a ring needs N >= 3");
+            }
+            p->N[r] = N;
+        }
+        p->state_off.resize(R + 1);
+        p->param_off.resize(R);
+        p->site_off.resize(R);
+        int64_t so = 0, po = 0, st = 0;
+        for (int64_t r = 0; r < R; ++r) {
+            p->state_off[r] = so;
+            const int64_t a = amplitudes(*pr, p->N[r]);
+            if (so > INT64_MAX / 16 - a) {
+                delete p;
+                return fail(nullptr, CTQW_ERR_OUT_OF_MEMORY, "state size overflows");
+            }
+            so += a;
+            p->param_off[r] = (int32_t)po;
+            po += p->N[r];
+            p->site_off[r] = st;
+            st += p->N[r];
+            p->max_N = std::max(p->max_N, p->N[r]);
+        }
+        p->state_off[R] = so;
+        p->zero_block = (int32_t)po;
+        po += p->max_N;
+        if (po > INT32_MAX) {
+            delete p;
+            return fail(nullptr, CTQW_ERR_OUT_OF_MEMORY, "parameter tables too large");
+        }
+        p->param_total = po;
+        p->site_total = st;
+        p->Jpad.assign(po, 0.0);
+        p->Epad.assign(po, 0.0);
+        // groups of equal N, ascending
+        std::map<int32_t, std::vector<int32_t>> groups;
+        for (int64_t r = 0; r < R; ++r) groups[p->N[r]].push_back((int32_t)r);
+        int64_t go = 0;
+        p->group_first.push_back(0);
+        for (auto& kv : groups) {
+            p->group_N.push_back(kv.first);
+            for (int32_t r : kv.second) p->group_members.push_back(r);
+            p->group_first.push_back((int32_t)p->group_members.size());
+            p->group_out.push_back(go);
+            go += kv.first;
+            if (pr->observables & CTQW_OBS_PAIR) go += (int64_t)kv.first * kv.first;
+        }
+        p->obs_per_snapshot = go;
+        p->launch.cols_per_lane = 1;
+        p->launch.waves_per_block = 4;
+        p->launch.persistent = 0;
+        p->launch.use_graph = 0;
+        p->launch.waves_per_cu = 0;
+        p->order.assign(R, 0);
+        p->tail_factor.assign(R, 0.0);
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return fail(nullptr, CTQW_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    *out = p;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_plan_destroy(ctqw_plan* p) {
+    delete p;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_set_params(ctqw_plan* p, const double* J, const double* eps, const double* U) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!J || !eps || !U) return fail(p, CTQW_ERR_INVALID_ARG, "NULL parameter array");
+    const ctqw_problem& pr = p->prob;
+    const int64_t R = pr.R;
+    int64_t nJ = 0, nE = 0;
+    for (int64_t r = 0; r < R; ++r) {
+        nJ += n_bonds(pr, p->N[r]);
+        nE += p->N[r];
+    }
+    for (int64_t k = 0; k < nJ; ++k)
+        if (!is_fin(J[k])) return fail(p, CTQW_ERR_INVALID_ARG, "J[%lld] is not finite", (long long)k);
+    for (int64_t k = 0; k < nE; ++k)
+        if (!is_fin(eps[k])) return fail(p, CTQW_ERR_INVALID_ARG, "eps[%lld] is not finite", (long long)k);
+    for (int64_t r = 0; r < R; ++r)
+        if (!is_fin(U[r])) return fail(p, CTQW_ERR_INVALID_ARG, "U[%lld] is not finite", (long long)r);
+
+    std::vector<int32_t> order(R);
+    std::vector<double> tf(R);
+    std::vector<double> Jpad(p->param_total, 0.0), Epad(p->param_total, 0.0);
+    const int cap = max_order_cap(pr);
+    int64_t jo = 0, eo = 0;
+    for (int64_t r = 0; r < R; ++r) {
+        const int N = p->N[r];
+        const int nb = n_bonds(pr, N);
+        const int32_t po = p->param_off[r];
+        for (int i = 0; i < nb; ++i) Jpad[po + i] = J[jo + i];
+        for (int i = 0; i < N; ++i) Epad[po + i] = eps[eo + i];
+        jo += nb;
+        eo += N;
+        double gmax = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const double jl = std::fabs(Jpad[po + (i + N - 1) % N]);
+            const double jr = std::fabs(Jpad[po + i]);
+            gmax = std::max(gmax, std::fabs(Epad[po + i]) + jl + jr);
+        }
+        const double G = pr.m * gmax + (pr.m > 1 ? std::fabs(U[r]) * pr.m * (pr.m - 1) / 2.0 : 0.0);
+        const double x = G * pr.dt;
+        int n;
+        if (pr.taylor_order > 0) {
+            n = pr.taylor_order;
+            if (n > cap)
+                return fail(p, CTQW_ERR_NOT_CONVERGED, "taylor_order %d above the cap %d", n, cap);
+        } else {
+            n = 1;
+            while (remainder_bound(x, n) > pr.taylor_tol) {
+                ++n;
+                if (n > cap)
+                    return fail(p, CTQW_ERR_NOT_CONVERGED,
+                                "realisation %lld: dt*||H|| <= %.4g needs more than %d Taylor terms for tol %.3g",
+                                (long long)r, x, cap, pr.taylor_tol);
+            }
+        }
+        order[r] = n;
+        tf[r] = (x < n + 2) ? (x / (n + 1)) / (1.0 - x / (n + 2)) : INFINITY;
+    }
+    p->J.assign(J, J + nJ);
+    p->eps.assign(eps, eps + nE);
+    p->U.assign(U, U + R);
+    p->Jpad.swap(Jpad);
+    p->Epad.swap(Epad);
+    p->order.swap(order);
+    p->tail_factor.swap(tf);
+    p->params_set = true;
+    return build_tables(p);
+}
+
+ctqw_status ctqw_get_params(const ctqw_plan* p, double* J, double* eps, double* U) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
+    if (J) std::memcpy(J, p->J.data(), p->J.size() * 8);
+    if (eps) std::memcpy(eps, p->eps.data(), p->eps.size() * 8);
+    if (U) std::memcpy(U, p->U.data(), p->U.size() * 8);
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_orders(const ctqw_plan* p, int32_t* orders) {
+    if (!p || !orders) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
+    std::memcpy(orders, p->order.data(), p->order.size() * 4);
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_layout(const ctqw_plan* p, int64_t* offsets) {
+    if (!p || !offsets) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
+    std::memcpy(offsets, p->state_off.data(), p->state_off.size() * 8);
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_groups(const ctqw_plan* p, int32_t* n_groups, int32_t* sizes) {
+    if (!p || !n_groups) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
+    *n_groups = (int32_t)p->group_N.size();
+    if (sizes) std::memcpy(sizes, p->group_N.data(), p->group_N.size() * 4);
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_sizes(const ctqw_plan* p, int64_t* state_bytes, int64_t* workspace_bytes) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
+    const int64_t esz = p->prob.dtype == CTQW_C128 ? 16 : 8;
+    if (state_bytes) *state_bytes = p->state_off.back() * esz;
+    if (workspace_bytes) *workspace_bytes = p->lay.total;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_work_items(const ctqw_plan* p, int64_t* items, int64_t* waves) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
+    if (items) *items = (int64_t)p->items.size();
+    if (waves) *waves = (int64_t)p->items.size();
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_get_launch(const ctqw_plan* p, ctqw_launch* out) {
+    if (!p || !out) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
+    *out = p->launch;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_set_launch(ctqw_plan* p, const ctqw_launch* l) {
+    if (!p || !l) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (l->cols_per_lane != 1 && l->cols_per_lane != 2)
+        return fail(p, CTQW_ERR_INVALID_ARG, "cols_per_lane must be 1 or 2");
+    if (l->waves_per_block != 1 && l->waves_per_block != 2 && l->waves_per_block != 4)
+        return fail(p, CTQW_ERR_INVALID_ARG, "waves_per_block must be 1, 2 or 4");
+    if ((l->persistent != 0 && l->persistent != 1) || (l->use_graph != 0 && l->use_graph != 1) ||
+        l->waves_per_cu < 0)
+        return fail(p, CTQW_ERR_INVALID_ARG, "bad persistent / use_graph / waves_per_cu");
+    const ctqw_launch old = p->launch;
+    p->launch = *l;
+    if (p->params_set) {
+        ctqw_status st = build_tables(p);
+        if (st != CTQW_OK) {
+            p->launch = old;
+            build_tables(p);
+            return st;
+        }
+    }
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_bind(ctqw_plan* p, void* psi_a, void* psi_b, int64_t state_bytes, void* workspace,
+                      int64_t workspace_bytes, void* hip_stream) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!p->params_set) return fail(p, CTQW_ERR_STATE, "set parameters before binding");
+    if (!psi_a || !psi_b || !workspace) return fail(p, CTQW_ERR_INVALID_ARG, "NULL device buffer");
+    if (psi_a == psi_b) return fail(p, CTQW_ERR_INVALID_ARG, "the two state buffers must differ");
+    const int64_t esz = p->prob.dtype == CTQW_C128 ? 16 : 8;
+    if (state_bytes < p->state_off.back() * esz)
+        return fail(p, CTQW_ERR_INVALID_ARG, "state buffers too small (%lld < %lld bytes)", (long long)state_bytes,
+                    (long long)(p->state_off.back() * esz));
+    if (workspace_bytes < p->lay.total)
+        return fail(p, CTQW_ERR_INVALID_ARG, "workspace too small (%lld < %lld bytes)", (long long)workspace_bytes,
+                    (long long)p->lay.total);
+    if ((reinterpret_cast<uintptr_t>(psi_a) | reinterpret_cast<uintptr_t>(psi_b) |
+         reinterpret_cast<uintptr_t>(workspace)) & 255)
+        return fail(p, CTQW_ERR_INVALID_ARG, "device buffers must be 256-byte aligned");
+    int dev = 0;
+    HIP_TRY(p, hipGetDevice(&dev));
+    HIP_TRY(p, hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+    p->psi[0] = psi_a;
+    p->psi[1] = psi_b;
+    p->cur = 0;
+    p->ws = static_cast<uint8_t*>(workspace);
+    p->ws_bytes = workspace_bytes;
+    p->state_bytes_bound = state_bytes;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    p->bound = true;
+    p->tables_dirty = true;
+    HIP_TRY(p, launch_fill_zero(p->ws + p->lay.queue.off, 16, p->stream));
+    ctqw_status st = upload_tables(p);
+    if (st != CTQW_OK) {
+        p->bound = false;
+        return st;
+    }
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_init_product_state(ctqw_plan* p, const int32_t* sites, int32_t per_real) {
+    if (!p || !sites) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    const ctqw_problem& pr = p->prob;
+    const int64_t cnt = per_real ? pr.R * pr.m : pr.m;
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t r = per_real ? k / pr.m : 0;
+        if (sites[k] < 0 || sites[k] >= p->N[per_real ? r : 0])
+            return fail(p, CTQW_ERR_INVALID_ARG, "start site %d out of range", sites[k]);
+    }
+    if (!per_real)
+        for (int64_t r = 0; r < pr.R; ++r)
+            for (int a = 0; a < pr.m; ++a)
+                if (sites[a] >= p->N[r])
+                    return fail(p, CTQW_ERR_INVALID_ARG, "start site %d out of range for N = %d", sites[a], p->N[r]);
+    HIP_TRY(p, hipMemcpyAsync(p->ws + p->lay.sites.off, sites, cnt * 4, hipMemcpyHostToDevice, p->stream));
+    InitArgs a{};
+    a.psi = p->psi[0];
+    a.reals = at<RealDev>(p, p->lay.reals);
+    a.sites = at<int32_t>(p, p->lay.sites);
+    a.per_real = per_real ? 1 : 0;
+    a.m = pr.m;
+    a.R = pr.R;
+    a.total = p->state_off.back();
+    a.dtype = pr.dtype == CTQW_C128 ? 1 : 0;
+    HIP_TRY(p, launch_init(a, p->stream));
+    std::vector<double> ones(pr.R, 1.0);
+    HIP_TRY(p, hipMemcpyAsync(p->ws + p->lay.scale.off, ones.data(), pr.R * 8, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(p, launch_fill_zero(p->ws + p->lay.status.off, 16, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->cur = 0;
+    p->steps_done = 0;
+    p->have_step_stats = false;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_set_state(ctqw_plan* p, const void* psi, int32_t on_device) {
+    if (!p || !psi) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    const int64_t bytes = p->state_off.back() * (p->prob.dtype == CTQW_C128 ? 16 : 8);
+    HIP_TRY(p, hipMemcpyAsync(p->psi[0], psi, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              p->stream));
+    std::vector<double> ones(p->prob.R, 1.0);
+    HIP_TRY(p, hipMemcpyAsync(p->ws + p->lay.scale.off, ones.data(), p->prob.R * 8, hipMemcpyHostToDevice,
+                              p->stream));
+    HIP_TRY(p, launch_fill_zero(p->ws + p->lay.status.off, 16, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->cur = 0;
+    p->steps_done = 0;
+    p->have_step_stats = false;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_get_state(ctqw_plan* p, void* psi, int32_t on_device) {
+    if (!p || !psi) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    if (p->prob.renormalize) {
+        RescaleArgs ra{};
+        ra.psi = p->psi[p->cur];
+        ra.reals = at<RealDev>(p, p->lay.reals);
+        ra.scale = at<double>(p, p->lay.scale);
+        ra.R = p->prob.R;
+        ra.dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
+        HIP_TRY(p, launch_rescale(ra, p->stream));
+    }
+    const int64_t bytes = p->state_off.back() * (p->prob.dtype == CTQW_C128 ? 16 : 8);
+    HIP_TRY(p, hipMemcpyAsync(psi, p->psi[p->cur], bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                              p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_observe(ctqw_plan* p, uint32_t obs, double* out) {
+    if (!p || !out) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (obs == 0 || (obs & ~p->prob.observables))
+        return fail(p, CTQW_ERR_INVALID_ARG, "observables 0x%x not enabled in the problem (0x%x)", obs,
+                    p->prob.observables);
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    st = enqueue_observe(p, (obs & CTQW_OBS_PAIR) ? 1 : 0);
+    if (st != CTQW_OK) return st;
+    return read_snapshot(p, obs, out);
+}
+
+ctqw_status ctqw_propagate(ctqw_plan* p, int64_t n_steps, int64_t output_every, uint32_t obs, double* out) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (n_steps < 0 || output_every < 0) return fail(p, CTQW_ERR_INVALID_ARG, "negative step count");
+    if (obs & ~p->prob.observables)
+        return fail(p, CTQW_ERR_INVALID_ARG, "observables 0x%x not enabled in the problem (0x%x)", obs,
+                    p->prob.observables);
+    const bool outputs = output_every > 0 && obs != 0;
+    if (outputs && !out) return fail(p, CTQW_ERR_INVALID_ARG, "NULL output buffer");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    const int64_t snap = snapshot_len(p, obs);
+    const int want_pair = (obs & CTQW_OBS_PAIR) ? 1 : 0;
+    int64_t k = 0;
+    if (outputs) {
+        if ((st = enqueue_observe(p, want_pair)) != CTQW_OK) return st;
+        if ((st = read_snapshot(p, obs, out + (k++) * snap)) != CTQW_OK) return st;
+    }
+    for (int64_t s = 1; s <= n_steps; ++s) {
+        if (p->timing && p->ev_used >= 512 && (st = collect_timing(p)) != CTQW_OK) return st;
+        if ((st = enqueue_step(p)) != CTQW_OK) return st;
+        if (outputs && s % output_every == 0) {
+            if ((st = enqueue_observe(p, want_pair)) != CTQW_OK) return st;
+            if ((st = read_snapshot(p, obs, out + (k++) * snap)) != CTQW_OK) return st;
+        }
+    }
+    if ((st = collect_timing(p)) != CTQW_OK) return st;
+    int32_t status[4];
+    if ((st = read_status(p, status)) != CTQW_OK) return st;
+    if (status[0] & 2)
+        return fail(p, CTQW_ERR_NUMERICAL, "norm alarm or non-finite state in %d realisation-steps", status[1]);
+    if (status[0] & 1)
+        return fail(p, CTQW_ERR_NOT_CONVERGED, "FP64 truncation test failed in %d realisation-steps", status[1]);
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_set_timing(ctqw_plan* p, int32_t enable) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (p->bound) {
+        ctqw_status st = collect_timing(p);
+        if (st != CTQW_OK) return st;
+    }
+    p->timing = enable != 0;
+    p->timed_ms = 0.0;
+    p->timed_launches = 0;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_get_timing(ctqw_plan* p, double* ms, int64_t* launches) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (p->bound) {
+        ctqw_status st = collect_timing(p);
+        if (st != CTQW_OK) return st;
+    }
+    if (ms) *ms = p->timed_ms;
+    if (launches) *launches = p->timed_launches;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_realization_norms(ctqw_plan* p, double* norm2, double* tail2) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    if (!p->have_step_stats) return fail(p, CTQW_ERR_STATE, "no step taken yet");
+    if (norm2) HIP_TRY(p, hipMemcpyAsync(norm2, p->ws + p->lay.norm2.off, p->prob.R * 8, hipMemcpyDeviceToHost, p->stream));
+    if (tail2) HIP_TRY(p, hipMemcpyAsync(tail2, p->ws + p->lay.tail2.off, p->prob.R * 8, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_stats(ctqw_plan* p, ctqw_step_stats* out) {
+    if (!p || !out) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    std::memset(out, 0, sizeof *out);
+    out->steps_done = p->steps_done;
+    out->min_order = *std::min_element(p->order.begin(), p->order.end());
+    out->max_order = *std::max_element(p->order.begin(), p->order.end());
+    int32_t status[4];
+    if ((st = read_status(p, status)) != CTQW_OK) return st;
+    out->flags = status[0];
+    out->alarms = status[1];
+    if (!p->have_step_stats) {
+        out->min_norm = out->max_norm = NAN;
+        out->max_tail_ratio = NAN;
+        return CTQW_OK;
+    }
+    std::vector<double> n2(p->prob.R), t2(p->prob.R);
+    if ((st = ctqw_realization_norms(p, n2.data(), t2.data())) != CTQW_OK) return st;
+    double mn = INFINITY, mx = -INFINITY, tr = 0.0;
+    const double tol = p->prob.taylor_tol;
+    for (int64_t r = 0; r < p->prob.R; ++r) {
+        const double nr = std::sqrt(n2[r]);
+        mn = std::min(mn, nr);
+        mx = std::max(mx, nr);
+        if (tol > 0) tr = std::max(tr, std::sqrt(t2[r]) / (tol * nr));
+    }
+    out->min_norm = mn;
+    out->max_norm = mx;
+    out->max_tail_ratio = tol > 0 ? tr : NAN;
+    return CTQW_OK;
+}
+
+}  // extern "C"

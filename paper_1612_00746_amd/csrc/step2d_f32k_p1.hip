@@ -1,0 +1,18 @@
+// Compiled pipeline depths: float state, 1 column(s) per lane, Kahan accumulation.
+#include "step2d_impl.hpp"
+
+namespace ctqw {
+StepKernelFn step_table_f32k_p1(int levels) {
+    switch (levels) {
+        CTQW_STEP_CASE(float, 3, 1, true)
+        CTQW_STEP_CASE(float, 4, 1, true)
+        CTQW_STEP_CASE(float, 5, 1, true)
+        CTQW_STEP_CASE(float, 6, 1, true)
+        CTQW_STEP_CASE(float, 7, 1, true)
+        CTQW_STEP_CASE(float, 8, 1, true)
+        CTQW_STEP_CASE(float, 10, 1, true)
+        CTQW_STEP_CASE(float, 12, 1, true)
+        default: return nullptr;
+    }
+}
+}  // namespace ctqw

@@ -1,0 +1,355 @@
+// Fused stencil + truncated-Taylor step for one and two particles on a chain.
+//
+// One step of Alg. 3 (Eqs. 6-7): Phi^(0) = psi, Phi^(j) = -(i dt / j) H Phi^(j-1),
+// psi(t + dt) = sum_{j<=n} Phi^(j), with H applied matrix-free:
+//   (H phi)(q, c) = J[q-1] phi(q-1, c) + J[q] phi(q+1, c)
+//                 + J[c-1] phi(q, c-1) + J[c] phi(q, c+1)
+//                 + (eps[q] + eps[c] + V(q, c)) phi(q, c)
+// (Eq. 1 with the Kronecker-sum structure of m = 2 particles; one particle is
+// the single-row case).  The paper builds H from a reduced matrix and a shared
+// topology matrix (Sec. 2.2) and runs one kernel per term with device-wide
+// copies in between; here all n terms of a step are chained in registers
+// during one pass over the state:
+//
+//  * a wave owns a band of 64*P consecutive columns (P per lane, so global
+//    loads and stores of a row are contiguous) and sweeps the rows;
+//  * a pipeline of n levels runs down the rows: at sweep iteration i, level 0
+//    loads row i, level j computes Phi^(j) on row i - j from level j-1 on
+//    rows i-j-1, i-j, i-j+1 (all already in registers), and row i - n is
+//    complete and stored.  Each level keeps a three-row window; the partial
+//    sums psi + Phi^(1) + ... of the rows in flight sit in an (n+1)-row window.
+//  * column neighbours come from the adjacent lanes through DPP row shifts
+//    (wave_shr / wave_shl); the band overlaps its neighbours by n columns
+//    (the halo), recomputed by both.
+//  * HBM traffic per step: each amplitude is read once and written once.
+//
+// Two bosons are stored as the symmetric function phi(x1, x2) on x1 <= x2,
+// row-major: the diagonal uses the mirrored neighbours phi(q, q-1) =
+// phi(q-1, q) and phi(q+1, q) = phi(q, q+1), i.e. doubled couplings to the
+// row above and the column to the right, with the lower triangle held at 0.
+//
+// Complex64 state can accumulate the terms with Kahan compensation.  The
+// squared norm of the new state and of the last term are accumulated in FP64
+// per item (the paper checks the norm every step, Alg. 3).
+#pragma once
+#include "ctqw_internal.hpp"
+
+namespace ctqw {
+namespace step2d_detail {
+
+template <typename T> struct CplxOf;
+template <> struct CplxOf<float> { using type = float2; };
+template <> struct CplxOf<double> { using type = double2; };
+
+// Lane i receives lane i-1 (lane 0 receives 0).
+__device__ __forceinline__ float from_left(float x) {
+    return __builtin_amdgcn_update_dpp(0.0f, x, 0x138, 0xF, 0xF, true);
+}
+__device__ __forceinline__ double from_left(double x) {
+    return __builtin_amdgcn_update_dpp(0.0, x, 0x138, 0xF, 0xF, true);
+}
+// Lane i receives lane i+1 (lane 63 receives 0).
+__device__ __forceinline__ float from_right(float x) {
+    return __builtin_amdgcn_update_dpp(0.0f, x, 0x130, 0xF, 0xF, true);
+}
+__device__ __forceinline__ double from_right(double x) {
+    return __builtin_amdgcn_update_dpp(0.0, x, 0x130, 0xF, 0xF, true);
+}
+
+__host__ __device__ constexpr int window_rows(int nt) { return ((nt + 3) / 3) * 3; }
+__host__ __device__ constexpr int mod_pos(int x, int w) { return ((x % w) + w) % w; }
+__device__ __forceinline__ int wrap(int x, int n) { int r = x % n; return r < 0 ? r + n : r; }
+
+template <typename T> __device__ __forceinline__ const T* jpar(const StepArgs& a);
+template <> __device__ __forceinline__ const float* jpar<float>(const StepArgs& a) { return a.Jf; }
+template <> __device__ __forceinline__ const double* jpar<double>(const StepArgs& a) { return a.Jd; }
+template <typename T> __device__ __forceinline__ const T* epar(const StepArgs& a);
+template <> __device__ __forceinline__ const float* epar<float>(const StepArgs& a) { return a.Ef; }
+template <> __device__ __forceinline__ const double* epar<double>(const StepArgs& a) { return a.Ed; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, int NT, int P, bool KAHAN>
+__device__ __forceinline__ void process_item(const StepArgs& a, int home, int lane) {
+    using C = typename CplxOf<T>::type;
+    constexpr int WA = window_rows(NT);
+
+    const ItemDev it = a.items[home];
+    const RealDev rd = a.reals[it.real];
+    const int N = rd.N;
+    const int rows = rd.rows;
+    const int order = rd.order;
+    const int nrows = it.nrows;
+    const bool periodic = (rd.flags & RF_PERIODIC) != 0;
+    const bool nearest = (rd.flags & RF_NEAREST) != 0;
+    const bool TRI = (rd.flags & RF_TRIANGLE) != 0;
+    const T* __restrict__ Jc = jpar<T>(a) + rd.param_off;
+    const T* __restrict__ Ec = epar<T>(a) + rd.param_off;
+    const T* __restrict__ Jr_ = jpar<T>(a) + rd.row_param_off;
+    const T* __restrict__ Er_ = epar<T>(a) + rd.row_param_off;
+    const C* __restrict__ in = reinterpret_cast<const C*>(a.psi_in) + rd.state_off;
+    C* __restrict__ out = reinterpret_cast<C*>(a.psi_out) + rd.state_off;
+    const T sc = static_cast<T>(a.scale[it.real]);
+    const T U = static_cast<T>(rd.U);
+
+    T dtj[NT + 1];
+#pragma unroll
+    for (int j = 1; j <= NT; ++j) dtj[j] = static_cast<T>(a.dt / j);
+
+    // Columns held by this lane.
+    int col[P], colw[P];
+    bool inb[P], outv[P];
+    T jl[P], jr[P], ec[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int c = it.w0 + lane * P + p;
+        col[p] = c;
+        const int cw = periodic ? wrap(c, N) : c;
+        colw[p] = cw;
+        inb[p] = periodic || (c >= 0 && c < N);
+        outv[p] = (c >= it.lo && c < it.hi);
+        const int cs = inb[p] ? cw : 0;   // clamped: no access outside [0, N)
+        jl[p] = inb[p] ? Jc[wrap(cs - 1, N)] : T(0);
+        jr[p] = inb[p] ? Jc[cs] : T(0);
+        ec[p] = inb[p] ? Ec[cs] : T(0);
+    }
+
+    auto load_row = [&](int q, C (&dst)[P]) {
+        const int qa = it.row0 + q;
+        const int qm = periodic ? wrap(qa, rows) : qa;
+        const int base = TRI ? qm * N - (qm * (qm + 1)) / 2 : qm * N;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const bool ok = inb[p] && (!TRI || col[p] >= qm);
+            C v;
+            v.x = T(0);
+            v.y = T(0);
+            if (ok) v = in[ok ? base + colw[p] : 0];
+            dst[p] = v;
+        }
+    };
+
+    T fr[NT][3][P], fi[NT][3][P];   // Phi^(j) rows, j < NT
+    T ar[WA][P], ai[WA][P];         // partial sums of rows in flight
+    T cr[WA][P], ci[WA][P];         // Kahan compensations
+    T dg[WA][P];                    // diagonal of H on rows in flight
+    T ju[WA];                       // bond above each row in flight
+    C pre[3][P];                    // rows being fetched
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int p = 0; p < P; ++p) { fr[j][s][p] = T(0); fi[j][s][p] = T(0); }
+#pragma unroll
+    for (int w = 0; w < WA; ++w) {
+        ju[w] = T(0);
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            ar[w][p] = ai[w][p] = cr[w][p] = ci[w][p] = dg[w][p] = T(0);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        if (s < nrows) load_row(s, pre[s]);
+    }
+
+    double nrm = 0.0, tail = 0.0;
+    const int total = nrows + NT;
+
+    for (int i0 = 0; i0 < total; i0 += WA) {
+#pragma unroll
+        for (int u = 0; u < WA; ++u) {
+            const int i = i0 + u;
+            if (i < total) {
+                // ---- level 0: row i enters.
+                {
+                    const int s = u % 3;
+                    if (i < nrows) {
+                        C v[P];
+#pragma unroll
+                        for (int p = 0; p < P; ++p) v[p] = pre[s][p];
+                        if (i + 3 < nrows) load_row(i + 3, pre[s]);
+                        const int qa = it.row0 + i;
+                        const int qm = periodic ? wrap(qa, rows) : qa;
+                        ju[u] = Jr_[wrap(qm - 1, rows)];
+                        const T er = Er_[qm];
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const T re = v[p].x * sc, im = v[p].y * sc;
+                            if (NT > 0) { fr[0][s][p] = re; fi[0][s][p] = im; }
+                            ar[u][p] = re;
+                            ai[u][p] = im;
+                            cr[u][p] = T(0);
+                            ci[u][p] = T(0);
+                            T vint = T(0);
+                            if (rows > 1) {
+                                int d = qm - colw[p];
+                                d = d < 0 ? -d : d;
+                                if (periodic && N - d < d) d = N - d;
+                                vint = nearest ? (d == 1 ? U : T(0)) : (d == 0 ? U : T(0));
+                            }
+                            dg[u][p] = inb[p] ? er + ec[p] + vint : T(0);
+                        }
+                    } else {
+                        ju[u] = T(0);
+#pragma unroll
+                        for (int p = 0; p < P; ++p) { fr[0][s][p] = T(0); fi[0][s][p] = T(0); }
+                    }
+                }
+                // ---- levels 1..NT: Phi^(j) on row i - j.
+#pragma unroll
+                for (int j = 1; j <= NT; ++j) {
+                    const int q = i - j;
+                    const int su = mod_pos(u - j - 1, 3);
+                    const int sm = mod_pos(u - j, 3);
+                    const int sd = mod_pos(u - j + 1, 3);
+                    const int w = mod_pos(u - j, WA);
+                    const int w1 = mod_pos(u - j + 1, WA);
+                    if (q >= 0 && q < nrows) {
+                        if (j <= order) {
+                            const T Ju = ju[w];
+                            const T Jd = ju[w1];
+                            const int qa = it.row0 + q;
+                            const bool zone = TRI && (qa >= it.w0);
+                            T lr[P], li[P], rr[P], ri[P];
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                if (p > 0) { lr[p] = fr[j - 1][sm][p - 1]; li[p] = fi[j - 1][sm][p - 1]; }
+                                if (p < P - 1) { rr[p] = fr[j - 1][sm][p + 1]; ri[p] = fi[j - 1][sm][p + 1]; }
+                            }
+                            lr[0] = from_left(fr[j - 1][sm][P - 1]);
+                            li[0] = from_left(fi[j - 1][sm][P - 1]);
+                            rr[P - 1] = from_right(fr[j - 1][sm][0]);
+                            ri[P - 1] = from_right(fi[j - 1][sm][0]);
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                T cu = Ju, crt = jr[p];
+                                bool low = false;
+                                if (zone) {
+                                    const bool isd = (col[p] == qa);
+                                    low = (col[p] < qa);
+                                    if (isd) { cu = Ju + Ju; crt = crt + crt; }
+                                }
+                                const T mr = fr[j - 1][sm][p], mi = fi[j - 1][sm][p];
+                                T hr = dg[w][p] * mr;
+                                T hi = dg[w][p] * mi;
+                                hr += cu * fr[j - 1][su][p];
+                                hi += cu * fi[j - 1][su][p];
+                                hr += Jd * fr[j - 1][sd][p];
+                                hi += Jd * fi[j - 1][sd][p];
+                                hr += jl[p] * lr[p];
+                                hi += jl[p] * li[p];
+                                hr += crt * rr[p];
+                                hi += crt * ri[p];
+                                T pr_ = dtj[j] * hi;
+                                T pi_ = -dtj[j] * hr;
+                                if (TRI && low) { pr_ = T(0); pi_ = T(0); }
+                                if (j < NT) { fr[j % NT][sm][p] = pr_; fi[j % NT][sm][p] = pi_; }
+                                if (KAHAN) {
+                                    const T yr = pr_ - cr[w][p];
+                                    const T tr = ar[w][p] + yr;
+                                    cr[w][p] = (tr - ar[w][p]) - yr;
+                                    ar[w][p] = tr;
+                                    const T yi = pi_ - ci[w][p];
+                                    const T ti = ai[w][p] + yi;
+                                    ci[w][p] = (ti - ai[w][p]) - yi;
+                                    ai[w][p] = ti;
+                                } else {
+                                    ar[w][p] += pr_;
+                                    ai[w][p] += pi_;
+                                }
+                                if (j == order) {
+                                    const bool rowok = qa >= it.out_lo && qa < it.out_hi;
+                                    if (rowok && outv[p] && (!TRI || col[p] >= qa)) {
+                                        const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
+                                        const double dr = pr_, di = pi_;
+                                        tail += wgt * (dr * dr + di * di);
+                                    }
+                                }
+                            }
+                        }
+                    } else if (q >= nrows && j < NT) {
+#pragma unroll
+                        for (int p = 0; p < P; ++p) { fr[j % NT][sm][p] = T(0); fi[j % NT][sm][p] = T(0); }
+                    }
+                }
+                // ---- row i - NT is complete.
+                {
+                    const int q = i - NT;
+                    const int w = mod_pos(u - NT, WA);
+                    if (q >= 0 && q < nrows) {
+                        const int qa = it.row0 + q;
+                        if (qa >= it.out_lo && qa < it.out_hi) {
+                            const int base = TRI ? qa * N - (qa * (qa + 1)) / 2 : qa * N;
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                if (outv[p] && (!TRI || col[p] >= qa)) {
+                                    C v;
+                                    v.x = ar[w][p];
+                                    v.y = ai[w][p];
+                                    out[base + colw[p]] = v;
+                                    const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
+                                    const double dr = v.x, di = v.y;
+                                    nrm += wgt * (dr * dr + di * di);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    nrm = wave_sum(nrm);
+    tail = wave_sum(tail);
+    if (lane == 0) {
+        a.norm_part[home] = nrm;
+        a.tail_part[home] = tail;
+    }
+}
+
+// One kernel serves both launch forms.  Regular: wave k of the grid takes
+// item k of the processing order.  Persistent (a grid sized to the device):
+// each wave takes the next item, largest first, from a ticket counter; the
+// last wave to leave resets both counters, so the kernel can be launched
+// again, or replayed in a graph, without a separate reset.
+template <typename T, int NT, int P, bool KAHAN>
+__global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
+    const int lane = threadIdx.x & 63;
+    if (!a.persistent) {
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int k = blockIdx.x * (blockDim.x >> 6) + wv;
+        if (k >= a.n_items) return;
+        process_item<T, NT, P, KAHAN>(a, a.item_order[k], lane);
+        return;
+    }
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(&a.queue[0], 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= a.n_items) break;
+        process_item<T, NT, P, KAHAN>(a, a.item_order[t], lane);
+    }
+    if (lane == 0) {
+        const int done = atomicAdd(&a.queue[1], 1);
+        if (done == a.n_waves - 1) {
+            atomicExch(&a.queue[0], 0);
+            atomicExch(&a.queue[1], 0);
+        }
+    }
+}
+
+}  // namespace step2d_detail
+
+using StepKernelFn = void (*)(StepArgs);
+
+}  // namespace ctqw
+
+// Table of compiled pipeline depths for one (type, columns per lane,
+// accumulation) combination; each translation unit instantiates one table.
+#define CTQW_STEP_CASE(T, NT, P, K) \
+    case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, P, K>;

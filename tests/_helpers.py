@@ -1,0 +1,73 @@
+"""Shared test helpers: run the GPU path through the C ABI and the FP64 oracle
+on the same seeded inputs, and map between their state layouts."""
+
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+from oracle import basis as B
+from oracle import hamiltonian as Hm
+from oracle import propagate as P
+
+
+def say(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def params_for(w, subset=None):
+    """[(N, J, eps, U)] for realisations of a workload."""
+    return w.all_realizations(subset)
+
+
+def pack(reals):
+    Ns = [r[0] for r in reals]
+    J = np.concatenate([r[1] for r in reals])
+    eps = np.concatenate([r[2] for r in reals])
+    U = np.array([r[3] for r in reals], dtype=np.float64)
+    return Ns, J, eps, U
+
+
+def gpu_plan(*, m, statistics, boundary, interaction, dtype, reals, dt, tol=0.0, order=0,
+             accumulation="kahan", observables=1, renormalize=False, norm_alarm=0.0, launch=None,
+             sites=None):
+    from paper_1612_00746_amd import Plan, make_problem
+    Ns, J, eps, U = pack(reals)
+    uniform = len(set(Ns)) == 1
+    pr, keep = make_problem(m, len(Ns), Ns[0] if uniform else Ns, dt, statistics=statistics,
+                            boundary=boundary, interaction=interaction, dtype=dtype,
+                            accumulation=accumulation, taylor_order=order, taylor_tol=tol,
+                            renormalize=renormalize, norm_alarm=norm_alarm, observables=observables)
+    plan = Plan(pr)
+    plan._keep.append(keep)
+    if launch:
+        plan.set_launch(**launch)
+    plan.set_params(J, eps, U)
+    plan.bind()
+    if sites is not None:
+        plan.init_product_state(sites)
+    return plan
+
+
+def oracle_H(N, m, statistics, boundary, interaction, J, eps, U):
+    return Hm.hamiltonian(N, m, J, eps, U if m > 1 else 0.0, statistics, boundary, interaction)
+
+
+def gpu_to_oracle(psi_r, N, m, statistics):
+    """GPU layout of one realisation -> oracle basis coefficients."""
+    psi_r = np.asarray(psi_r, dtype=np.complex128)
+    if m == 2 and statistics == B.BOSON:
+        st = B.basis_states(N, 2, B.BOSON)
+        return psi_r * np.where(st[:, 0] < st[:, 1], math.sqrt(2.0), 1.0)
+    return psi_r
+
+
+def oracle_to_gpu(c, N, m, statistics):
+    c = np.asarray(c, dtype=np.complex128)
+    if m == 2 and statistics == B.BOSON:
+        st = B.basis_states(N, 2, B.BOSON)
+        return c / np.where(st[:, 0] < st[:, 1], math.sqrt(2.0), 1.0)
+    return c

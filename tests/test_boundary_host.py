@@ -1,0 +1,196 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/ctqw.h, validates problems, selects
+Taylor orders and reports layouts and sizes without touching a device."""
+
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ctqw.h")
+
+lib_path = os.path.join(ROOT, "paper_1612_00746_amd", "libctqw.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(lib_path), reason="libctqw.so not built")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctqw_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def make(**kw):
+    from paper_1612_00746_amd import Plan, make_problem
+    args = dict(m=2, R=3, n_sites=8, dt=0.05, taylor_tol=1e-12)
+    args.update(kw)
+    pr, keep = make_problem(**args)
+    plan = Plan(pr)
+    plan._keep.append(keep)
+    return plan
+
+
+def status_of(fn):
+    from paper_1612_00746_amd import CtqwError
+    try:
+        fn()
+    except CtqwError as e:
+        return e.status
+    return 0
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=0), 1), (dict(m=4), 1), (dict(m=3), 2),
+    (dict(n_sites=1), 1), (dict(R=0), 1),
+    (dict(dt=0.0), 1), (dict(dt=float("nan")), 1), (dict(dt=-1.0), 1),
+    (dict(taylor_tol=0.0), 1),
+    (dict(boundary="periodic", n_sites=2), 1),
+    (dict(statistics="boson", boundary="periodic"), 2),
+])
+def test_plan_create_validation(kw, status):
+    assert status_of(lambda: make(**kw)) == status
+
+
+def test_invalid_enum_and_null():
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    from paper_1612_00746_amd import make_problem
+    pr, _ = make_problem(2, 2, 8, 0.1, taylor_tol=1e-10)
+    pr.dtype = 7
+    h = L.PlanP()
+    assert lib.ctqw_plan_create(C.byref(pr), C.byref(h)) == L.ERR_INVALID_ARG
+    assert b"dtype" in lib.ctqw_last_error(None)
+    assert lib.ctqw_plan_create(None, C.byref(h)) == L.ERR_INVALID_ARG
+
+
+def draw(plan_N, R, nb, seed=0):
+    g = np.random.default_rng(seed)
+    J = 1 + 0.1 * g.standard_normal(R * nb)
+    eps = g.uniform(-0.5, 0.5, R * plan_N)
+    U = g.uniform(0, 2, R)
+    return J, eps, U
+
+
+def test_set_params_rejects_nonfinite_and_keeps_state():
+    plan = make()
+    J, eps, U = draw(8, 3, 7)
+    bad = J.copy()
+    bad[4] = np.inf
+    assert status_of(lambda: plan.set_params(bad, eps, U)) == 1
+    plan.set_params(J, eps, U)
+    o = plan.orders()
+    assert status_of(lambda: plan.set_params(J, eps, np.array([0, np.nan, 0.0]))) == 1
+    assert np.array_equal(plan.orders(), o)
+
+
+def reference_order(J, eps, U, m, dt, tol, periodic=False):
+    """Smallest n with x^(n+1)/(n+1)!/(1 - x/(n+2)) <= tol, x = dt*G, with
+    G = m*max_i(|eps_i| + |J_{i-1}| + |J_i|) + |U| m(m-1)/2 (documented rule)."""
+    N = len(eps)
+    Jp = np.zeros(N)
+    Jp[:len(J)] = J
+    G = m * max(abs(eps[i]) + abs(Jp[(i - 1) % N]) + abs(Jp[i]) for i in range(N))
+    G += abs(U) * m * (m - 1) / 2
+    x = G * dt
+    n = 1
+    while True:
+        b = x ** (n + 1) / math.factorial(n + 1) / (1 - x / (n + 2)) if x < n + 2 else math.inf
+        if b <= tol:
+            return n
+        n += 1
+
+
+@pytest.mark.parametrize("m,periodic,tol,dt", [(2, False, 1e-14, 0.05), (2, True, 1e-7, 0.05),
+                                               (1, False, 1e-12, 0.2), (2, False, 1e-10, 0.01)])
+def test_apriori_taylor_orders(m, periodic, tol, dt):
+    N, R = 12, 5
+    plan = make(m=m, R=R, n_sites=N, dt=dt, taylor_tol=tol, boundary="periodic" if periodic else "open",
+                dtype="c128")
+    nb = N if periodic else N - 1
+    J, eps, U = draw(N, R, nb, seed=3)
+    plan.set_params(J, eps, U)
+    got = plan.orders()
+    for r in range(R):
+        assert got[r] == reference_order(J[r * nb:(r + 1) * nb], eps[r * N:(r + 1) * N], U[r], m, dt, tol)
+
+
+def test_fixed_order_and_cap():
+    plan = make(taylor_order=5, taylor_tol=0.0)
+    J, eps, U = draw(8, 3, 7)
+    plan.set_params(J, eps, U)
+    assert list(plan.orders()) == [5, 5, 5]
+    plan2 = make(dt=2.0, taylor_tol=1e-14)
+    assert status_of(lambda: plan2.set_params(J, eps, U)) == 5   # NOT_CONVERGED
+    plan3 = make(taylor_order=30, taylor_tol=0.0)
+    assert status_of(lambda: plan3.set_params(J, eps, U)) == 5
+
+
+def test_layout_sizes_groups_uneven():
+    Ns = [16, 40, 16, 70, 40]
+    plan = make(R=5, n_sites=Ns, statistics="boson", dtype="c64")
+    nbs = [n - 1 for n in Ns]
+    g = np.random.default_rng(1)
+    plan.set_params(1 + 0.1 * g.standard_normal(sum(nbs)), g.uniform(-1, 1, sum(Ns)), np.ones(5))
+    off = plan.layout()
+    assert list(np.diff(off)) == [n * (n + 1) // 2 for n in Ns]
+    sb, wb = plan.sizes()
+    assert sb == off[-1] * 8 and wb > 0
+    assert list(plan.groups()) == [16, 40, 70]
+    items, _ = plan.work_items()
+    assert items >= 5
+
+
+def test_band_partition_covers_columns_once():
+    """Each realisation's bands must cover every column exactly once; the
+    number of bands follows from the window (64 per lane column) and halo."""
+    for P, N, expect in [(1, 64, 1), (1, 65, 2), (1, 200, 4), (2, 128, 1), (2, 300, 3)]:
+        plan = make(R=1, n_sites=N, taylor_order=7, taylor_tol=0.0)
+        plan.set_launch(cols_per_lane=P)
+        plan.set_params(np.ones(N - 1), np.zeros(N), np.zeros(1))
+        assert plan.work_items()[0] == expect, (P, N)
+
+
+def test_bind_requires_valid_buffers_without_touching_device():
+    from paper_1612_00746_amd import _lib as L
+    plan = make()
+    lib = plan.lib
+    assert lib.ctqw_bind(plan.h, None, None, 0, None, 0, None) == L.ERR_STATE   # params not set
+    J, eps, U = draw(8, 3, 7)
+    plan.set_params(J, eps, U)
+    assert lib.ctqw_bind(plan.h, None, None, 0, None, 0, None) == L.ERR_INVALID_ARG
+    out = np.zeros(4)
+    assert lib.ctqw_propagate(plan.h, 1, 0, 0, None) == L.ERR_STATE
+    assert lib.ctqw_init_product_state(plan.h, np.zeros(2, np.int32).ctypes.data_as(L.i32p), 0) == L.ERR_STATE
+    assert lib.ctqw_observe(plan.h, 1, out.ctypes.data_as(L.dp)) == L.ERR_STATE
+
+
+def test_launch_validation():
+    from paper_1612_00746_amd import CtqwError
+    plan = make()
+    with pytest.raises(CtqwError):
+        plan.set_launch(cols_per_lane=3)
+    with pytest.raises(CtqwError):
+        plan.set_launch(waves_per_block=8)
+    plan.set_launch(cols_per_lane=2, persistent=1)
+    assert plan.get_launch().cols_per_lane == 2
+
+
+def test_status_strings():
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    for s in range(8):
+        assert lib.ctqw_status_string(s)
+    assert lib.ctqw_version().startswith(b"ctqw")

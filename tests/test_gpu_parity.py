@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+identical seeded inputs, element by element.
+
+Bars: complex128 state <= 1e-10 max-abs amplitude and occupation error
+(the target set for the FP64 path); complex64 bars are stated per test and
+derived from the single-precision rounding of the stored state (about
+6e-8 relative per step, growing like the square root of the step count)."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import basis as B
+from oracle import observables as O
+from oracle import propagate as P
+from workloads import C1, Noise, Workload, scaled
+
+from _helpers import gpu_plan, gpu_to_oracle, oracle_H, oracle_to_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+C128_BAR = 1e-10
+
+
+def ed_states(reals, m, statistics, boundary, interaction, sites, times):
+    out = []
+    for k, (N, J, eps, U) in enumerate(reals):
+        H = oracle_H(N, m, statistics, boundary, interaction, J, eps, U)
+        s = sites[k] if np.ndim(sites) == 2 else sites
+        out.append(P.EDPropagator(H).evolve_many(B.product_state(N, list(s), statistics), times))
+    return out
+
+
+def compare_final(plan, reals, m, statistics, boundary, interaction, sites, t, bar):
+    psi = plan.state_numpy()
+    off = plan.layout()
+    ref = ed_states(reals, m, statistics, boundary, interaction, sites, [t])
+    worst = 0.0
+    for k, (N, *_rest) in enumerate(reals):
+        got = gpu_to_oracle(psi[off[k]:off[k + 1]], N, m, statistics)
+        worst = max(worst, float(np.max(np.abs(got - ref[k][0]))))
+    say(f"  max |psi_gpu - psi_ed| = {worst:.3e} (bar {bar:.1e})")
+    assert worst <= bar
+    return worst
+
+
+def random_reals(Ns, boundary="open", seed=0, U=(0.0, 2.0), eps=0.5, Jsig=0.2):
+    g = np.random.default_rng(seed)
+    out = []
+    for N in Ns:
+        nb = N if boundary == "periodic" else N - 1
+        out.append((N, 1 + Jsig * g.standard_normal(nb), g.uniform(-eps, eps, N), float(g.uniform(*U))))
+    return out
+
+
+# ------------------------------------------------------------ closed forms
+
+def test_bessel_single_walker_c128():
+    """One walker, uniform open chain N=256 from node 128, t = 10:
+    psi_{128+n} = (-i)^n J_n(2t) (closed form)."""
+    import scipy.special as ss
+    say("case: m=1 N=256 c128 Bessel, dt=0.05, 200 steps")
+    N, s, dt, steps = 256, 128, 0.05, 200
+    reals = [(N, np.ones(N - 1), np.zeros(N), 0.0)]
+    plan = gpu_plan(m=1, statistics="distinguishable", boundary="open", interaction="onsite",
+                    dtype="c128", reals=reals, dt=dt, tol=1e-14, sites=[s])
+    plan.propagate(steps)
+    psi = plan.state_numpy()
+    n = np.abs(np.arange(N) - s)
+    expect = (-1j) ** n * ss.jv(n, 2 * dt * steps)
+    err = np.max(np.abs(psi - expect))
+    say(f"  max err vs Bessel = {err:.3e}")
+    assert err <= C128_BAR
+
+
+def test_config1_full_c128():
+    """2 distinguishable walkers, N=16 open, J_i = 1 + U[-0.1, 0.1], 8
+    realisations, start (7, 8), dt = 0.01 to t = 5, occupation every 0.1."""
+    w = C1()
+    say(f"case: {w.name} R={w.R} steps={w.n_steps}")
+    reals = w.all_realizations()
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
+                    dtype="c128", reals=reals, dt=w.dt, tol=w.tol, sites=list(w.start))
+    occ = plan.propagate(w.n_steps, w.output_every, 1)
+    assert occ.shape == (w.n_steps // w.output_every + 1, 16)
+    times = np.arange(occ.shape[0]) * w.output_every * w.dt
+    states = B.basis_states(16, 2)
+    ref = ed_states(reals, 2, B.DISTINGUISHABLE, "open", "onsite", w.start, times)
+    ens = np.array([O.ensemble_mean([O.occupation(ref[r][k], states, 16) for r in range(w.R)])
+                    for k in range(len(times))])
+    err = np.max(np.abs(occ - ens))
+    say(f"  max occupation error over {len(times)} snapshots = {err:.3e}")
+    assert err <= C128_BAR
+    assert np.max(np.abs(occ.sum(axis=1) - 2.0)) < 1e-12
+    compare_final(plan, reals, 2, B.DISTINGUISHABLE, "open", "onsite", w.start, w.n_steps * w.dt, C128_BAR)
+    st = plan.stats()
+    assert st.steps_done == w.n_steps and abs(st.max_norm - 1) < 1e-12 and st.flags == 0
+
+
+# ------------------------------------------------------------- two particles
+
+@pytest.mark.parametrize("P_", [1, 2])
+def test_distinguishable_multiband_c128(P_):
+    say(f"case: m=2 dist open N=[100,150,64,65] c128 P={P_}")
+    reals = random_reals([100, 150, 64, 65], seed=1)
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
+                    dtype="c128", reals=reals, dt=0.05, tol=1e-14, launch={"cols_per_lane": P_},
+                    sites=[40, 50])
+    plan.propagate(60)
+    compare_final(plan, reals, 2, B.DISTINGUISHABLE, "open", "onsite", [40, 50], 3.0, C128_BAR)
+
+
+@pytest.mark.parametrize("N", [2, 3, 70, 130])
+def test_bosons_c128(N):
+    say(f"case: m=2 bosons open N={N} c128")
+    reals = random_reals([N, N], seed=2)
+    s = [0, 1] if N <= 3 else [N // 2 - 1, N // 2]
+    plan = gpu_plan(m=2, statistics="boson", boundary="open", interaction="onsite", dtype="c128",
+                    reals=reals, dt=0.05, tol=1e-14, sites=s)
+    plan.propagate(40)
+    compare_final(plan, reals, 2, B.BOSON, "open", "onsite", s, 2.0, C128_BAR)
+
+
+def test_bosons_double_occupied_start_and_nearest():
+    say("case: m=2 bosons N=40 start (20,20), nearest-neighbour U")
+    reals = random_reals([40], seed=3)
+    plan = gpu_plan(m=2, statistics="boson", boundary="open", interaction="nearest", dtype="c128",
+                    reals=reals, dt=0.05, tol=1e-14, sites=[20, 20])
+    plan.propagate(30)
+    compare_final(plan, reals, 2, B.BOSON, "open", "nearest", [20, 20], 1.5, C128_BAR)
+
+
+@pytest.mark.parametrize("interaction", ["onsite", "nearest"])
+def test_periodic_c128(interaction):
+    say(f"case: m=2 dist periodic N=[7,40,90] {interaction} c128")
+    reals = random_reals([7, 40, 90], boundary="periodic", seed=4)
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="periodic", interaction=interaction,
+                    dtype="c128", reals=reals, dt=0.05, tol=1e-14, sites=[1, 5])
+    plan.propagate(40)
+    compare_final(plan, reals, 2, B.DISTINGUISHABLE, "periodic", interaction, [1, 5], 2.0, C128_BAR)
+
+
+def test_single_walker_periodic_and_uneven():
+    say("case: m=1 periodic N=[3, 50, 300] c128")
+    reals = random_reals([3, 50, 300], boundary="periodic", seed=5)
+    plan = gpu_plan(m=1, statistics="distinguishable", boundary="periodic", interaction="onsite",
+                    dtype="c128", reals=reals, dt=0.05, tol=1e-14, sites=[1])
+    plan.propagate(50)
+    compare_final(plan, reals, 1, B.DISTINGUISHABLE, "periodic", "onsite", [1], 2.5, C128_BAR)
+
+
+def test_uneven_batch_c128_with_groups():
+    Ns = [16, 33, 64, 100, 130, 16, 33]
+    say(f"case: uneven batch N={Ns} c128, per-realisation start sites")
+    reals = random_reals(Ns, seed=6, U=(0, 4))
+    sites = np.array([[n // 2 - 1, n // 2] for n in Ns], dtype=np.int32)
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
+                    dtype="c128", reals=reals, dt=0.05, tol=1e-14, sites=sites)
+    occ = plan.propagate(40, 20, 1)
+    assert list(plan.groups()) == [16, 33, 64, 100, 130]
+    compare_final(plan, reals, 2, B.DISTINGUISHABLE, "open", "onsite", sites, 2.0, C128_BAR)
+    # ensemble occupation of the N=16 group (realisations 0 and 5) at t=2
+    ref = ed_states([reals[0], reals[5]], 2, B.DISTINGUISHABLE, "open", "onsite", sites[[0, 5]], [2.0])
+    st = B.basis_states(16, 2)
+    ens = O.ensemble_mean([O.occupation(ref[k][0], st, 16) for k in range(2)])
+    assert np.max(np.abs(occ[-1][:16] - ens)) <= C128_BAR
+
+
+def test_pair_correlation_c128():
+    say("case: pair correlation m=2 dist N=24 and bosons N=24")
+    for stat in ("distinguishable", "boson"):
+        reals = random_reals([24, 24, 24], seed=7)
+        plan = gpu_plan(m=2, statistics=stat, boundary="open", interaction="onsite", dtype="c128",
+                        reals=reals, dt=0.05, tol=1e-14, observables=3, sites=[10, 13])
+        out = plan.propagate(30, 30, 3)
+        sb = B.BOSON if stat == "boson" else B.DISTINGUISHABLE
+        ref = ed_states(reals, 2, sb, "open", "onsite", [10, 13], [1.5])
+        st = B.basis_states(24, 2, sb)
+        occ = O.ensemble_mean([O.occupation(ref[k][0], st, 24) for k in range(3)])
+        G = O.ensemble_mean([O.pair_correlation(ref[k][0], st, 24) for k in range(3)])
+        got_occ, got_G = out[-1][:24], out[-1][24:].reshape(24, 24)
+        say(f"  {stat}: occ err {np.max(np.abs(got_occ - occ)):.2e} pair err {np.max(np.abs(got_G - G)):.2e}")
+        assert np.max(np.abs(got_occ - occ)) <= C128_BAR
+        assert np.max(np.abs(got_G - G)) <= C128_BAR
+
+
+# ------------------------------------------------------------ launch shapes
+
+def test_launch_shapes_are_bitwise_identical():
+    """The arithmetic of each amplitude does not depend on the band
+    partition, the columns per lane or the launch form."""
+    say("case: bitwise identity across cols_per_lane / persistent / waves_per_block")
+    reals = random_reals([100, 200, 37], seed=8)
+    states = []
+    for launch in ({"cols_per_lane": 1}, {"cols_per_lane": 2}, {"cols_per_lane": 1, "persistent": 1},
+                   {"cols_per_lane": 2, "persistent": 1, "waves_per_block": 1}):
+        plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
+                        dtype="c64", reals=reals, dt=0.05, tol=1e-7, launch=launch, sites=[30, 31])
+        plan.propagate(25)
+        states.append(plan.state_numpy())
+        # run twice more to check the persistent queue resets between launches
+        plan.propagate(0)
+    for s in states[1:]:
+        assert np.array_equal(s, states[0])
+
+
+def test_boson_kernel_matches_distinguishable_symmetrised():
+    """Two independent layouts: the triangle kernel and the full-grid kernel
+    started from the symmetrised state must agree."""
+    say("case: boson triangle vs full grid with symmetric start, N=90")
+    reals = random_reals([90], seed=9)
+    pb = gpu_plan(m=2, statistics="boson", boundary="open", interaction="onsite", dtype="c128",
+                  reals=reals, dt=0.05, tol=1e-14, sites=[30, 60])
+    pd = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c128",
+                  reals=reals, dt=0.05, tol=1e-14)
+    full0 = np.zeros((90, 90), np.complex128)
+    full0[30, 60] = full0[60, 30] = 1 / math.sqrt(2)
+    pd.set_state_numpy(full0.reshape(-1))
+    pb.propagate(40)
+    pd.propagate(40)
+    tri = pb.state_numpy()
+    full = pd.state_numpy().reshape(90, 90)
+    iu = np.triu_indices(90)
+    assert np.max(np.abs(full[iu] - tri)) < 1e-12
+    assert np.max(np.abs(full - full.T)) < 1e-12
+
+
+# ------------------------------------------------------------- complex64
+
+@pytest.mark.parametrize("acc", ["kahan", "plain"])
+def test_c64_against_oracle(acc):
+    """complex64 state, FP32 stencil: error against the FP64 exact evolution
+    after 200 steps of dt = 0.05 stays below 2e-5 (max-abs amplitude);
+    the measured error is printed."""
+    say(f"case: c64 {acc} m=2 dist N=[64,100] and bosons N=70, 200 steps")
+    for stat, Ns in (("distinguishable", [64, 100]), ("boson", [70])):
+        reals = random_reals(Ns, seed=10)
+        sb = B.BOSON if stat == "boson" else B.DISTINGUISHABLE
+        plan = gpu_plan(m=2, statistics=stat, boundary="open", interaction="onsite", dtype="c64",
+                        accumulation=acc, reals=reals, dt=0.05, tol=1e-7, sites=[30, 33])
+        plan.propagate(200)
+        err = compare_final(plan, reals, 2, sb, "open", "onsite", [30, 33], 10.0, 2e-5)
+        n2, _ = plan.realization_norms()
+        say(f"  {stat} {acc}: err {err:.3e}, |norm-1| max {np.max(np.abs(np.sqrt(n2) - 1)):.2e}")
+        assert np.max(np.abs(np.sqrt(n2) - 1)) < 1e-5
+
+
+# ------------------------------------------------------ monitoring / errors
+
+def test_norm_alarm_raised_from_corrupted_state():
+    """A host-corrupted state (one amplitude doubled) trips the FP64 norm
+    alarm; the numerical error is reported by propagate."""
+    from paper_1612_00746_amd import CtqwError
+    say("case: norm alarm")
+    reals = random_reals([20], seed=11)
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
+                    dtype="c128", reals=reals, dt=0.05, tol=1e-14, norm_alarm=1e-6, sites=[5, 6])
+    plan.propagate(3)
+    psi = plan.state_numpy()
+    psi[5 * 20 + 6] *= 2.0
+    plan.set_state_numpy(psi)
+    with pytest.raises(CtqwError) as e:
+        plan.propagate(1)
+    assert e.value.status == 6
+    assert plan.stats().flags & 2
+
+
+def test_renormalize_keeps_unit_norm_and_fixed_order_matches_oracle_taylor():
+    """Fixed order n = 2 (a deliberately short series, as in Alg. 3 with a
+    fixed n) drifts in norm; renormalisation rescales every step.  Without
+    renormalisation the GPU must equal the oracle's fixed-order Taylor map."""
+    say("case: fixed order 2, renormalize on/off")
+    reals = random_reals([30], seed=12)
+    N, J, eps, U = reals[0]
+    H = oracle_H(N, 2, B.DISTINGUISHABLE, "open", "onsite", J, eps, U)
+    psi_o, _, _ = P.evolve_taylor(H, B.product_state(N, [10, 12]), 0.02, 50, order=2)
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c128",
+                    reals=reals, dt=0.02, order=2, tol=0.0, sites=[10, 12])
+    plan.propagate(50)
+    assert np.max(np.abs(plan.state_numpy() - psi_o)) < 1e-13
+    pr = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c128",
+                  reals=reals, dt=0.02, order=2, tol=0.0, renormalize=True, sites=[10, 12])
+    pr.propagate(50)
+    assert abs(np.linalg.norm(pr.state_numpy()) - 1) < 1e-13
+    ref = psi_o / np.linalg.norm(psi_o)
+    # renormalising every step equals renormalising once at the end (linear map)
+    assert np.max(np.abs(pr.state_numpy() - ref)) < 1e-12
+
+
+def test_zero_steps_and_observe():
+    say("case: zero steps / observe at t=0")
+    reals = random_reals([12, 12], seed=13)
+    plan = gpu_plan(m=2, statistics="boson", boundary="open", interaction="onsite", dtype="c64",
+                    reals=reals, dt=0.05, tol=1e-7, sites=[3, 3])
+    out = plan.propagate(0, 1, 1)
+    assert out.shape == (1, 12)
+    expect = np.zeros(12)
+    expect[3] = 2.0
+    assert np.max(np.abs(out[0] - expect)) < 1e-7
+    assert np.max(np.abs(plan.observe(1) - expect)) < 1e-7
