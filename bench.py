@@ -46,44 +46,50 @@ def host_cores() -> int:
 
 # ------------------------------------------------------------ CPU baseline
 
+def log(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def _oracle_sample(args):
-    """Propagate one realisation with the oracle for `steps` steps; returns
-    (amplitude-updates, seconds)."""
-    N, J, eps, U, dt, steps, tol = args
+    """Propagate one realisation with the oracle, one step at a time, until
+    `budget_s` seconds of propagation have passed; returns
+    (amplitude-updates, propagation seconds, steps)."""
+    N, J, eps, U, dt, tol, budget_s = args
     from oracle import basis as B
     from oracle import hamiltonian as Hm
     from oracle import propagate as P
     H = Hm.hamiltonian(N, 2, J, eps, U)
     psi = B.product_state(N, [N // 2 - 1, N // 2])
-    t0 = time.perf_counter()
-    P.evolve_taylor(H, psi, dt, steps, tol=tol)
-    return N * N * steps, time.perf_counter() - t0
+    steps, spent = 0, 0.0
+    while spent < budget_s:
+        t0 = time.perf_counter()
+        psi, _, _ = P.taylor_step(H, psi, dt, tol=tol)
+        spent += time.perf_counter() - t0
+        steps += 1
+    return N * N * steps, spent, steps
 
 
-def cpu_baseline(w, budget_s: float = 15.0):
-    """Oracle on a sample of realisations of the workload (one process per
-    core, forked before the GPU is touched)."""
+def cpu_baseline(w, budget_s: float = 10.0):
+    """The FP64 oracle on a bounded sample of the workload: one realisation
+    per process (one process per core, forked before the GPU is touched),
+    each propagated step by step for `budget_s` seconds; the rate is the
+    summed updates over the summed per-process seconds times the cores."""
     import multiprocessing as mp
     cores = min(host_cores(), 16)
     sizes = w.lattice_sizes()
-    # sample: the first realisations of the workload, in order, with their
-    # own lattice sizes; steps chosen so the sample takes ~budget_s
-    sample = list(range(min(4 * cores, w.R)))
-    probe = _oracle_sample((int(sizes[0]),) + w.realization(0, int(sizes[0])) + (w.dt, 2, w.tol))
-    rate = probe[0] / max(probe[1], 1e-9)
-    total_amp = sum(int(sizes[r]) ** 2 for r in sample)
-    steps = max(2, int(budget_s * rate * cores / max(total_amp, 1)))
-    steps = min(steps, w.n_steps)
-    jobs = [(int(sizes[r]),) + w.realization(r, int(sizes[r])) + (w.dt, steps, w.tol) for r in sample]
+    sample = list(range(min(cores, w.R)))
+    jobs = [(int(sizes[r]),) + w.realization(r, int(sizes[r])) + (w.dt, w.tol, budget_s) for r in sample]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         res = pool.map(_oracle_sample, jobs)
     wall = time.perf_counter() - t0
     updates = sum(r[0] for r in res)
-    return {"value": updates / wall, "unit": "amplitude-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(sample)} realisations (N in {sorted(set(int(sizes[r]) for r in sample))}) x "
-                      f"{steps} steps of the FP64 CSR Taylor oracle, tol {w.tol:g}, {cores} processes",
+    per_proc_rate = updates / sum(r[1] for r in res)
+    return {"value": per_proc_rate * cores, "unit": "amplitude-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"realisations 0..{len(sample) - 1} (N = {[int(sizes[r]) for r in sample]}), "
+                      f"{sum(r[2] for r in res)} steps in total of the FP64 CSR Taylor oracle (tol {w.tol:g}), "
+                      f"{budget_s:g} s of propagation per process, {cores} processes",
             "seconds": round(wall, 2)}
 
 
@@ -132,7 +138,7 @@ def main():
     ap.add_argument("--accumulation", default="kahan")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: realisations are independent, and a multi-GPU run would "
@@ -142,14 +148,20 @@ def main():
 
     from workloads import C3
     w = C3("c64")
+    log("cpu baseline (oracle) ..." if not a.no_cpu else "cpu baseline skipped")
     cpu = None if a.no_cpu else cpu_baseline(w, a.cpu_budget)   # before the GPU is touched
+    if cpu:
+        log(f"cpu baseline: {cpu['value']:.3e} updates/s on {cpu['cores']} cores ({cpu['seconds']} s)")
 
     import torch
     sizes = w.lattice_sizes()
     amps = int(np.sum(sizes.astype(np.int64) ** 2))
     launch = {"cols_per_lane": a.cols_per_lane, "persistent": 1, "waves_per_block": 4}
+    log("building the complex64 plan ...")
     plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
+    log("timing complex64 ...")
     wall, kern_ms = time_plan(plan, a.steps, a.warmup)
+    log(f"complex64: {1e3 * wall / a.steps:.3f} ms/step, kernel {kern_ms:.3f} ms")
     st = plan.stats()
     ms_per_step = 1e3 * wall / a.steps
     updates = amps * a.steps / wall
@@ -162,8 +174,10 @@ def main():
 
     fp64 = None
     if not a.no_fp64:
+        log("building the complex128 plan ...")
         p64 = build_plan(w, "c128", "plain", {"cols_per_lane": 1, "persistent": 0, "waves_per_block": 4}, w.tol)
         wall64, kern64 = time_plan(p64, max(2, a.steps // 2), 2)
+        log(f"complex128: kernel {kern64:.3f} ms")
         s64 = max(2, a.steps // 2)
         fp64 = {"value": amps * s64 / wall64, "unit": "amplitude-updates/s", "dtype": "c128",
                 "ms_per_step": round(1e3 * wall64 / s64, 4),

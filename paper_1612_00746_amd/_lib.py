@@ -111,6 +111,13 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libctqw.so is not built ({path}); run paper_1612_00746_amd/build.py")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading it
+    # first makes libctqw resolve to that runtime, so torch's device memory
+    # and streams and libctqw's kernels share one HIP context.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

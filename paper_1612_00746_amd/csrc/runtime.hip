@@ -90,8 +90,17 @@ struct ctqw_plan {
     size_t ev_used = 0;              // events recorded and not yet read
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
+    // captured step loops: (steps, starting buffer) -> executable graph
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
     std::string err;
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
     ~ctqw_plan() {
+        drop_graphs();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
 };
@@ -259,6 +268,7 @@ ctqw_status build_tables(ctqw_plan* p) {
     L.total = (L.total + 255) & ~int64_t(255);
     p->lay = L;
     p->tables_dirty = true;
+    p->drop_graphs();
     return CTQW_OK;
 }
 
@@ -399,6 +409,60 @@ ctqw_status enqueue_step(ctqw_plan* p) {
     p->cur = 1 - p->cur;
     p->steps_done += 1;
     p->have_step_stats = true;
+    return CTQW_OK;
+}
+
+// Advance `count` steps.  With use_graph the sequence of (step, finalize)
+// launches is captured once per (steps, starting buffer) on a private
+// capture stream and the executable graph is replayed on the bound stream.
+ctqw_status enqueue_steps(ctqw_plan* p, int64_t count) {
+    if (count <= 0) return CTQW_OK;
+    if (!p->launch.use_graph || p->timing || count < 2) {
+        for (int64_t s = 0; s < count; ++s) {
+            ctqw_status st = enqueue_step(p);
+            if (st != CTQW_OK) return st;
+        }
+        return CTQW_OK;
+    }
+    constexpr int64_t kMaxCaptured = 256;
+    if (!p->cap_stream) HIP_TRY(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    while (count > 0) {
+        const int64_t n = std::min(count, kMaxCaptured);
+        const auto key = std::make_pair(n, p->cur);
+        auto found = p->graphs.find(key);
+        if (found == p->graphs.end()) {
+            const int cur0 = p->cur;
+            const int64_t done0 = p->steps_done;
+            hipStream_t user = p->stream;
+            p->stream = p->cap_stream;
+            hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+            ctqw_status st = CTQW_OK;
+            if (e == hipSuccess)
+                for (int64_t s = 0; s < n && st == CTQW_OK; ++s) st = enqueue_step(p);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(p->stream, &g) : e;
+            p->stream = user;
+            p->cur = cur0;
+            p->steps_done = done0;
+            if (st != CTQW_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e2 != hipSuccess)
+                return fail(p, CTQW_ERR_DEVICE, "step-loop capture failed: %s", hipGetErrorString(e2));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e3 != hipSuccess)
+                return fail(p, CTQW_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e3));
+            found = p->graphs.emplace(key, ex).first;
+        }
+        HIP_TRY(p, hipGraphLaunch(found->second, p->stream));
+        p->cur ^= (int)(n & 1);
+        p->steps_done += n;
+        p->have_step_stats = true;
+        count -= n;
+    }
     return CTQW_OK;
 }
 
@@ -794,6 +858,7 @@ ctqw_status ctqw_bind(ctqw_plan* p, void* psi_a, void* psi_b, int64_t state_byte
     p->state_bytes_bound = state_bytes;
     p->stream = static_cast<hipStream_t>(hip_stream);
     p->bound = true;
+    p->drop_graphs();
     p->tables_dirty = true;
     HIP_TRY(p, launch_fill_zero(p->ws + p->lay.queue.off, 16, p->stream));
     ctqw_status st = upload_tables(p);
@@ -908,9 +973,14 @@ ctqw_status ctqw_propagate(ctqw_plan* p, int64_t n_steps, int64_t output_every, 
         if ((st = enqueue_observe(p, want_pair)) != CTQW_OK) return st;
         if ((st = read_snapshot(p, obs, out + (k++) * snap)) != CTQW_OK) return st;
     }
-    for (int64_t s = 1; s <= n_steps; ++s) {
-        if (p->timing && p->ev_used >= 512 && (st = collect_timing(p)) != CTQW_OK) return st;
-        if ((st = enqueue_step(p)) != CTQW_OK) return st;
+    // Steps between outputs form one segment (captured as one graph when
+    // use_graph is set); timing collects its events every 256 steps.
+    const int64_t seg = outputs ? output_every : (p->timing ? 256 : n_steps);
+    for (int64_t s = 0; s < n_steps;) {
+        const int64_t n = std::min(seg, n_steps - s);
+        if ((st = enqueue_steps(p, n)) != CTQW_OK) return st;
+        if (p->timing && (st = collect_timing(p)) != CTQW_OK) return st;
+        s += n;
         if (outputs && s % output_every == 0) {
             if ((st = enqueue_observe(p, want_pair)) != CTQW_OK) return st;
             if ((st = read_snapshot(p, obs, out + (k++) * snap)) != CTQW_OK) return st;
