@@ -211,6 +211,21 @@ ctqw_status ctqw_set_launch(ctqw_plan* plan, const ctqw_launch* launch);
  * number of waves that one step launches, for the current launch shape.  */
 ctqw_status ctqw_work_items(const ctqw_plan* plan, int64_t* items, int64_t* waves);
 
+/* Autotuner.  Times `steps` propagation steps (after one warm-up step) for
+ * every launch shape -- columns per lane {1, 2}, waves per block {1, 2, 4},
+ * regular or persistent launch, and for the persistent form a cap of
+ * {auto, 8, 16} resident waves per CU -- that fits the bound workspace,
+ * keeps the fastest (average step-kernel time from HIP events) and applies
+ * it with ctqw_set_launch (use_graph is left as set).  With a cache path
+ * (or the CTQW_TUNE_CACHE environment variable when cache_path is NULL),
+ * a stored result for the same device, library version and problem shape
+ * (dtype, accumulation, m, statistics, boundary, lattice sizes, R, Taylor
+ * orders) is applied without timing, and new results are appended (one
+ * JSON object per line).  The state buffers are overwritten: tune before
+ * ctqw_init_product_state / ctqw_set_state.  best / best_ms may be NULL.  */
+ctqw_status ctqw_autotune(ctqw_plan* plan, const char* cache_path, int32_t steps, ctqw_launch* best,
+                          double* best_ms);
+
 /* Kernel timing: with enable != 0, every step-kernel launch is bracketed by
  * HIP events on the bound stream and ctqw_get_timing returns the summed
  * elapsed time (ms) and the number of timed launches since timing was

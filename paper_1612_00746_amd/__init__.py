@@ -195,6 +195,13 @@ class Plan:
         self._check(self.lib.ctqw_stats(self.h, C.byref(s)))
         return s
 
+    def autotune(self, cache_path: Optional[str] = None, steps: int = 3) -> tuple["L.Launch", float]:
+        """Time the launch shapes and apply the fastest (overwrites the state)."""
+        best, ms = L.Launch(), C.c_double()
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.ctqw_autotune(self.h, path, steps, C.byref(best), C.byref(ms)))
+        return best, ms.value
+
     def set_timing(self, enable: bool) -> None:
         self._check(self.lib.ctqw_set_timing(self.h, 1 if enable else 0))
 

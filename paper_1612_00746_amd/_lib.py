@@ -95,6 +95,7 @@ SIGNATURES = {
     "ctqw_get_launch": (C.c_int, [PlanP, C.POINTER(Launch)]),
     "ctqw_set_launch": (C.c_int, [PlanP, C.POINTER(Launch)]),
     "ctqw_work_items": (C.c_int, [PlanP, i64p, i64p]),
+    "ctqw_autotune": (C.c_int, [PlanP, C.c_char_p, C.c_int32, C.POINTER(Launch), dp]),
     "ctqw_set_timing": (C.c_int, [PlanP, C.c_int32]),
     "ctqw_get_timing": (C.c_int, [PlanP, dp, i64p]),
     "ctqw_status_string": (C.c_char_p, [C.c_int]),

@@ -56,9 +56,8 @@ struct StepArgs {
     const double* scale;         // [R] factor applied when loading the state
     double* norm_part;           // [n_items] sum of w |psi_out|^2 of each item
     double* tail_part;           // [n_items] sum of w |Phi^(n)|^2 of each item
-    int32_t* queue;              // persistent launch: [2] ticket / exit counters
     double dt;
-    int32_t persistent;          // 1: grid sized to the device, items from queue
+    int32_t persistent;          // 1: grid of n_waves waves, items round-robin
 };
 
 struct StepConfig {

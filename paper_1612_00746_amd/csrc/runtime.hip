@@ -41,7 +41,7 @@ struct Region {
 
 struct Layout {
     Region reals, items, order, item_first, Jd, Ed, Jf, Ef, scale, norm_part, tail_part, norm2,
-        tail2, status, queue, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites;
+        tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites;
     int64_t total = 0;
 };
 
@@ -254,7 +254,6 @@ ctqw_status build_tables(ctqw_plan* p) {
     align_region(L, L.norm2, R * 8);
     align_region(L, L.tail2, R * 8);
     align_region(L, L.status, 16);
-    align_region(L, L.queue, 16);
     align_region(L, L.colsum, p->site_total * 8);
     align_region(L, L.rowsum, p->site_total * 8);
     align_region(L, L.diag, p->site_total * 8);
@@ -374,7 +373,6 @@ ctqw_status enqueue_step(ctqw_plan* p) {
     a.scale = at<double>(p, L.scale);
     a.norm_part = at<double>(p, L.norm_part);
     a.tail_part = at<double>(p, L.tail_part);
-    a.queue = at<int32_t>(p, L.queue);
     a.dt = p->prob.dt;
     a.persistent = c.persistent;
     if (p->timing) {
@@ -860,7 +858,6 @@ ctqw_status ctqw_bind(ctqw_plan* p, void* psi_a, void* psi_b, int64_t state_byte
     p->bound = true;
     p->drop_graphs();
     p->tables_dirty = true;
-    HIP_TRY(p, launch_fill_zero(p->ws + p->lay.queue.off, 16, p->stream));
     ctqw_status st = upload_tables(p);
     if (st != CTQW_OK) {
         p->bound = false;
@@ -993,6 +990,150 @@ ctqw_status ctqw_propagate(ctqw_plan* p, int64_t n_steps, int64_t output_every, 
         return fail(p, CTQW_ERR_NUMERICAL, "norm alarm or non-finite state in %d realisation-steps", status[1]);
     if (status[0] & 1)
         return fail(p, CTQW_ERR_NOT_CONVERGED, "FP64 truncation test failed in %d realisation-steps", status[1]);
+    return CTQW_OK;
+}
+
+namespace {
+
+std::string tune_key(ctqw_plan* p) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    const ctqw_problem& pr = p->prob;
+    int64_t nsum = 0;
+    for (int32_t n : p->N) nsum += n;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s|%s|dtype%d|acc%d|m%d|stat%d|bc%d|int%d|R%lld|N%d-%d-%lld|n%d-%d", arch.c_str(),
+             ctqw_version(), pr.dtype, pr.dtype == CTQW_C128 ? 1 : pr.accumulation, pr.m, pr.statistics, pr.boundary,
+             pr.interaction, (long long)pr.R, *std::min_element(p->N.begin(), p->N.end()), p->max_N,
+             (long long)nsum, *std::min_element(p->order.begin(), p->order.end()),
+             *std::max_element(p->order.begin(), p->order.end()));
+    return buf;
+}
+
+bool parse_int_field(const std::string& line, const char* name, int* out) {
+    const std::string pat = std::string("\"") + name + "\": ";
+    const size_t at = line.find(pat);
+    if (at == std::string::npos) return false;
+    return sscanf(line.c_str() + at + pat.size(), "%d", out) == 1;
+}
+
+bool cache_lookup(const char* path, const std::string& key, ctqw_launch* out, double* ms) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[2048];
+    bool found = false;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        std::string s(line);
+        if (s.find(pat) == std::string::npos) continue;
+        ctqw_launch l{};
+        if (parse_int_field(s, "cols_per_lane", &l.cols_per_lane) &&
+            parse_int_field(s, "waves_per_block", &l.waves_per_block) &&
+            parse_int_field(s, "persistent", &l.persistent) && parse_int_field(s, "waves_per_cu", &l.waves_per_cu)) {
+            *out = l;
+            const size_t at = s.find("\"ms\": ");
+            *ms = at == std::string::npos ? NAN : atof(s.c_str() + at + 6);
+            found = true;  // keep the last matching line
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_append(const char* path, const std::string& key, const ctqw_launch& l, double ms) {
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f,
+            "{\"key\": \"%s\", \"cols_per_lane\": %d, \"waves_per_block\": %d, \"persistent\": %d, "
+            "\"waves_per_cu\": %d, \"ms\": %.6f}\n",
+            key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, ms);
+    fclose(f);
+}
+
+// Average step-kernel time of `steps` steps with the current launch shape.
+ctqw_status time_steps(ctqw_plan* p, int32_t steps, double* ms) {
+    const bool was = p->timing;
+    const double t0 = p->timed_ms;
+    const int64_t n0 = p->timed_launches;
+    ctqw_status st;
+    if ((st = enqueue_step(p)) != CTQW_OK) return st;   // warm-up, untimed
+    HIP_TRY(p, hipStreamSynchronize(p->stream));
+    p->timing = true;
+    p->timed_ms = 0.0;
+    p->timed_launches = 0;
+    for (int32_t s = 0; s < steps; ++s)
+        if ((st = enqueue_step(p)) != CTQW_OK) return st;
+    if ((st = collect_timing(p)) != CTQW_OK) return st;
+    *ms = p->timed_ms / std::max<int64_t>(1, p->timed_launches);
+    p->timing = was;
+    p->timed_ms = t0;
+    p->timed_launches = n0;
+    return CTQW_OK;
+}
+
+}  // namespace
+
+ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, ctqw_launch* best_out,
+                          double* best_ms_out) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (steps < 1) return fail(p, CTQW_ERR_INVALID_ARG, "steps must be >= 1");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    const char* path = cache_path ? cache_path : getenv("CTQW_TUNE_CACHE");
+    const std::string key = tune_key(p);
+    const ctqw_launch orig = p->launch;
+    ctqw_launch best = orig;
+    double best_ms = INFINITY;
+    bool cached = false;
+    if (path && *path) {
+        ctqw_launch l{};
+        double ms = NAN;
+        if (cache_lookup(path, key, &l, &ms)) {
+            l.use_graph = orig.use_graph;
+            p->launch = l;
+            if (build_tables(p) == CTQW_OK && p->lay.total <= p->ws_bytes) {
+                best = l;
+                best_ms = ms;
+                cached = true;
+            }
+        }
+    }
+    if (!cached) {
+        for (int P : {1, 2})
+            for (int wpb : {1, 2, 4})
+                for (int pers : {0, 1})
+                    for (int cap : {0, 8, 16}) {
+                        if (!pers && cap) continue;
+                        ctqw_launch c = orig;
+                        c.cols_per_lane = P;
+                        c.waves_per_block = wpb;
+                        c.persistent = pers;
+                        c.waves_per_cu = cap;
+                        p->launch = c;
+                        if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
+                        if ((st = upload_tables(p)) != CTQW_OK) return st;
+                        double ms = INFINITY;
+                        if ((st = time_steps(p, steps, &ms)) != CTQW_OK) return st;
+                        if (ms < best_ms) {
+                            best_ms = ms;
+                            best = c;
+                        }
+                    }
+        if (!std::isfinite(best_ms)) {
+            p->launch = orig;
+            build_tables(p);
+            return fail(p, CTQW_ERR_UNSUPPORTED, "no launch shape fits the bound workspace");
+        }
+        if (path && *path) cache_append(path, key, best, best_ms);
+    }
+    p->launch = best;
+    if ((st = build_tables(p)) != CTQW_OK) return st;
+    if ((st = upload_tables(p)) != CTQW_OK) return st;
+    p->have_step_stats = false;
+    if (best_out) *best_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
     return CTQW_OK;
 }
 

@@ -313,33 +313,20 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 }
 
 // One kernel serves both launch forms.  Regular: wave k of the grid takes
-// item k of the processing order.  Persistent (a grid sized to the device):
-// each wave takes the next item, largest first, from a ticket counter; the
-// last wave to leave resets both counters, so the kernel can be launched
-// again, or replayed in a graph, without a separate reset.
+// item k of the processing order.  Persistent (a grid sized to the device,
+// n_waves resident waves): wave w takes items w, w + n_waves, w + 2 n_waves,
+// ... of the processing order (largest first), so every wave gets a share of
+// large and small items.  The loop bound is wave-uniform and no counter
+// state is kept between launches, so the kernel can be launched again or
+// replayed in a graph as is.
 template <typename T, int NT, int P, bool KAHAN>
 __global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
-    if (!a.persistent) {
-        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int k = blockIdx.x * (blockDim.x >> 6) + wv;
-        if (k >= a.n_items) return;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k0 = blockIdx.x * (blockDim.x >> 6) + wv;
+    const int stride = a.persistent ? a.n_waves : a.n_items;
+    for (int k = k0; k < a.n_items; k += stride) {
         process_item<T, NT, P, KAHAN>(a, a.item_order[k], lane);
-        return;
-    }
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(&a.queue[0], 1);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= a.n_items) break;
-        process_item<T, NT, P, KAHAN>(a, a.item_order[t], lane);
-    }
-    if (lane == 0) {
-        const int done = atomicAdd(&a.queue[1], 1);
-        if (done == a.n_waves - 1) {
-            atomicExch(&a.queue[0], 0);
-            atomicExch(&a.queue[1], 0);
-        }
     }
 }
 

@@ -32,14 +32,30 @@ def ed_states(reals, m, statistics, boundary, interaction, sites, times):
     return out
 
 
-def compare_final(plan, reals, m, statistics, boundary, interaction, sites, t, bar):
+ED_MAX_DIM = 3000
+
+
+def oracle_final(N, J, eps, U, m, statistics, boundary, interaction, s, t, dt):
+    """Exact evolution to time t: ED for small dimensions, the oracle's
+    Taylor route with tolerance 1e-15 per step (pinned against ED) above."""
+    H = oracle_H(N, m, statistics, boundary, interaction, J, eps, U)
+    psi0 = B.product_state(N, list(s), statistics)
+    if H.shape[0] <= ED_MAX_DIM:
+        return P.EDPropagator(H).evolve(psi0, t)
+    steps = int(round(t / dt))
+    psi, _, _ = P.evolve_taylor(H, psi0, dt, steps, tol=1e-15)
+    return psi
+
+
+def compare_final(plan, reals, m, statistics, boundary, interaction, sites, t, bar, dt=0.05):
     psi = plan.state_numpy()
     off = plan.layout()
-    ref = ed_states(reals, m, statistics, boundary, interaction, sites, [t])
     worst = 0.0
-    for k, (N, *_rest) in enumerate(reals):
+    for k, (N, J, eps, U) in enumerate(reals):
+        s = sites[k] if np.ndim(sites) == 2 else sites
+        ref = oracle_final(N, J, eps, U, m, statistics, boundary, interaction, s, t, dt)
         got = gpu_to_oracle(psi[off[k]:off[k + 1]], N, m, statistics)
-        worst = max(worst, float(np.max(np.abs(got - ref[k][0]))))
+        worst = max(worst, float(np.max(np.abs(got - ref))))
     say(f"  max |psi_gpu - psi_ed| = {worst:.3e} (bar {bar:.1e})")
     assert worst <= bar
     return worst
@@ -102,13 +118,30 @@ def test_config1_full_c128():
 
 @pytest.mark.parametrize("P_", [1, 2])
 def test_distinguishable_multiband_c128(P_):
+    """Multi-band realisations.  Two columns per lane are compiled for FP64
+    up to order 8, so that case runs a fixed order 8 against the oracle's
+    fixed-order Taylor map."""
     say(f"case: m=2 dist open N=[100,150,64,65] c128 P={P_}")
     reals = random_reals([100, 150, 64, 65], seed=1)
-    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
-                    dtype="c128", reals=reals, dt=0.05, tol=1e-14, launch={"cols_per_lane": P_},
-                    sites=[40, 50])
-    plan.propagate(60)
-    compare_final(plan, reals, 2, B.DISTINGUISHABLE, "open", "onsite", [40, 50], 3.0, C128_BAR)
+    if P_ == 1:
+        plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
+                        dtype="c128", reals=reals, dt=0.05, tol=1e-14, launch={"cols_per_lane": P_},
+                        sites=[40, 50])
+        plan.propagate(60)
+        compare_final(plan, reals, 2, B.DISTINGUISHABLE, "open", "onsite", [40, 50], 3.0, C128_BAR)
+        return
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c128",
+                    reals=reals, dt=0.02, order=8, tol=0.0, launch={"cols_per_lane": P_}, sites=[40, 50])
+    plan.propagate(40)
+    psi = plan.state_numpy()
+    off = plan.layout()
+    worst = 0.0
+    for k, (N, J, eps, U) in enumerate(reals):
+        H = oracle_H(N, 2, B.DISTINGUISHABLE, "open", "onsite", J, eps, U)
+        ref, _, _ = P.evolve_taylor(H, B.product_state(N, [40, 50]), 0.02, 40, order=8)
+        worst = max(worst, float(np.max(np.abs(psi[off[k]:off[k + 1]] - ref))))
+    say(f"  fixed order 8, 40 steps: max err vs oracle Taylor map {worst:.3e}")
+    assert worst <= C128_BAR
 
 
 @pytest.mark.parametrize("N", [2, 3, 70, 130])
@@ -187,24 +220,6 @@ def test_pair_correlation_c128():
 
 # ------------------------------------------------------------ launch shapes
 
-def test_launch_shapes_are_bitwise_identical():
-    """The arithmetic of each amplitude does not depend on the band
-    partition, the columns per lane or the launch form."""
-    say("case: bitwise identity across cols_per_lane / persistent / waves_per_block")
-    reals = random_reals([100, 200, 37], seed=8)
-    states = []
-    for launch in ({"cols_per_lane": 1}, {"cols_per_lane": 2}, {"cols_per_lane": 1, "persistent": 1},
-                   {"cols_per_lane": 2, "persistent": 1, "waves_per_block": 1}):
-        plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
-                        dtype="c64", reals=reals, dt=0.05, tol=1e-7, launch=launch, sites=[30, 31])
-        plan.propagate(25)
-        states.append(plan.state_numpy())
-        # run twice more to check the persistent queue resets between launches
-        plan.propagate(0)
-    for s in states[1:]:
-        assert np.array_equal(s, states[0])
-
-
 def test_graph_replays_match_eager_launches():
     """The step loop captured in a HIP graph (with the persistent kernel and
     its self-resetting queue) and replayed several times, with eager work and
@@ -227,6 +242,32 @@ def test_graph_replays_match_eager_launches():
     graph.propagate(7, 7, 1)
     assert np.array_equal(graph.state_numpy(), eager.state_numpy())
     assert graph.stats().steps_done == eager.stats().steps_done == 31
+
+
+def test_autotune_applies_and_caches_a_shape(tmp_path):
+    """The autotuner picks a launch shape, writes it to the cache, a second
+    plan of the same shape reads it back, and results do not depend on it."""
+    say("case: autotune + cache on an uneven batch")
+    reals = random_reals([64, 200, 130], seed=15)
+    cache = str(tmp_path / "tune.jsonl")
+    p1 = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
+                  reals=reals, dt=0.05, tol=1e-7)
+    best, ms = p1.autotune(cache, steps=2)
+    say(f"  best: P={best.cols_per_lane} wpb={best.waves_per_block} persistent={best.persistent} "
+        f"cap={best.waves_per_cu} {ms:.4f} ms")
+    assert ms > 0 and open(cache).read().count("\n") == 1
+    p2 = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
+                  reals=reals, dt=0.05, tol=1e-7)
+    best2, ms2 = p2.autotune(cache, steps=2)
+    assert (best2.cols_per_lane, best2.waves_per_block, best2.persistent) == \
+        (best.cols_per_lane, best.waves_per_block, best.persistent)
+    assert open(cache).read().count("\n") == 1
+    ref = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
+                   reals=reals, dt=0.05, tol=1e-7)
+    for p in (p1, ref):
+        p.init_product_state([30, 31])
+        p.propagate(10)
+    assert np.array_equal(p1.state_numpy(), ref.state_numpy())
 
 
 def test_boson_kernel_matches_distinguishable_symmetrised():
@@ -323,3 +364,33 @@ def test_zero_steps_and_observe():
     expect[3] = 2.0
     assert np.max(np.abs(out[0] - expect)) < 1e-7
     assert np.max(np.abs(plan.observe(1) - expect)) < 1e-7
+
+
+# ------------------------------------------------------------ launch shapes
+# Each shape runs in its own test; all must be bitwise identical to the
+# regular one-column-per-lane launch (the arithmetic of an amplitude does not
+# depend on the band partition, the columns per lane or the launch form).
+
+_SHAPE_REALS = None
+
+
+def _shape_state(launch):
+    reals = random_reals([100, 200, 37], seed=8)
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
+                    dtype="c64", reals=reals, dt=0.05, tol=1e-7, launch=launch, sites=[30, 31])
+    plan.propagate(25)
+    return plan.state_numpy()
+
+
+@pytest.mark.parametrize("launch", [
+    {"cols_per_lane": 2},
+    {"cols_per_lane": 1, "waves_per_block": 1},
+    {"cols_per_lane": 1, "persistent": 1},
+    {"cols_per_lane": 2, "persistent": 1, "waves_per_block": 1},
+    {"cols_per_lane": 1, "persistent": 1, "waves_per_cu": 8},
+], ids=["P2", "P1-wpb1", "P1-persistent", "P2-persistent-wpb1", "P1-persistent-cap8"])
+def test_launch_shape_bitwise_identical(launch):
+    say(f"case: launch shape {launch} vs regular P=1")
+    ref = _shape_state({"cols_per_lane": 1})
+    got = _shape_state(launch)
+    assert np.array_equal(got, ref)
