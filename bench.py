@@ -139,6 +139,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for scaling HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: realisations are independent, and a multi-GPU run would "
@@ -154,6 +156,23 @@ def main():
         log(f"cpu baseline: {cpu['value']:.3e} updates/s on {cpu['cores']} cores ({cpu['seconds']} s)")
 
     import torch
+    copy_probe = None
+    if a.copy_probe_mib > 0:
+        # A plain device-to-device copy of known size: its HBM counters per
+        # dispatch give the scale between counter units and bytes moved.
+        n = a.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt_copy = (time.perf_counter() - t0) / 5
+        copy_probe = {"bytes_read": n * 4, "bytes_written": n * 4,
+                      "gbs": round(2 * n * 4 / dt_copy / 1e9, 1)}
+        log(f"copy probe: {copy_probe}")
+        del src, dst
     sizes = w.lattice_sizes()
     amps = int(np.sum(sizes.astype(np.int64) ** 2))
     launch = {"cols_per_lane": a.cols_per_lane, "persistent": 1, "waves_per_block": 4}
@@ -212,6 +231,7 @@ def main():
         "speedup_fp32_batched_vs_fp64_plain": (round(updates / fp64["value"], 3) if fp64 else None),
         "norm_range": [st.min_norm, st.max_norm],
         "cpu_baseline": cpu,
+        "copy_probe": copy_probe,
     }
     print(json.dumps(line))
 

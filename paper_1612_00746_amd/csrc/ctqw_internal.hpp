@@ -63,6 +63,7 @@ struct StepArgs {
 struct StepConfig {
     int dtype;          // 0: complex64, 1: complex128
     int kahan;          // compensated accumulation (complex64 only)
+    int triangle;       // two bosons in the upper-triangle layout
     int cols_per_lane;  // 1 or 2
     int levels;         // compiled pipeline depth (>= max order in the batch)
     int waves_per_block;

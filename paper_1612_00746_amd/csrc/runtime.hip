@@ -61,7 +61,7 @@ struct ctqw_plan {
     std::vector<double> J, eps, U;   // user layout (packed, unpadded)
     std::vector<double> Jpad, Epad;  // padded [param_total]
     std::vector<int32_t> order;      // [R]
-    std::vector<double> tail_factor; // [R]
+    std::vector<double> xbound;      // [R] dt * Gershgorin bound of ||H_r||
     // groups (distinct N, ascending)
     std::vector<int32_t> group_N, group_first, group_members;
     std::vector<int64_t> group_out;
@@ -218,8 +218,8 @@ ctqw_status build_tables(ctqw_plan* p) {
     std::vector<int32_t> first(pr.R + 1, 0);
     for (int64_t r = 0; r < pr.R; ++r) {
         first[r] = (int32_t)items.size();
-        if (!make_bands(pr, (int)r, p->N[r], p->order[r], W, items))
-            return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", p->order[r], W);
+        if (!make_bands(pr, (int)r, p->N[r], levels, W, items))
+            return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", levels, W);
     }
     first[pr.R] = (int32_t)items.size();
     if (items.size() > (size_t)INT32_MAX) return fail(p, CTQW_ERR_OUT_OF_MEMORY, "too many work items");
@@ -227,7 +227,7 @@ ctqw_status build_tables(ctqw_plan* p) {
     std::vector<int64_t> cost(items.size());
     for (size_t k = 0; k < items.size(); ++k) {
         ord[k] = (int32_t)k;
-        cost[k] = (int64_t)(items[k].nrows + levels) * p->order[items[k].real];
+        cost[k] = (int64_t)(items[k].nrows + levels);
     }
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     p->items.swap(items);
@@ -281,16 +281,28 @@ ctqw_status upload_tables(ctqw_plan* p) {
         d.state_off = p->state_off[r];
         d.N = p->N[r];
         d.rows = pr.m == 1 ? 1 : p->N[r];
-        d.order = p->order[r];
+        // Every realisation of the batch takes the batch's order (at least its
+        // own a-priori order), so the pipeline has no per-realisation depth.
+        const int n = p->levels;
+        const double x = p->xbound[r];
+        d.order = n;
         d.param_off = p->param_off[r];
         d.row_param_off = pr.m == 1 ? p->zero_block : p->param_off[r];
         d.flags = (pr.boundary == CTQW_PERIODIC ? RF_PERIODIC : 0) |
                   (pr.m == 2 && pr.statistics == CTQW_BOSON ? RF_TRIANGLE : 0) |
                   (pr.interaction == CTQW_INT_NEAREST ? RF_NEAREST : 0);
         d.U = pr.m == 1 ? 0.0 : p->U[r];
-        d.tail_factor = p->tail_factor[r];
+        // remainder estimate: ||sum_{j>n} Phi^(j)|| <= ||Phi^(n)|| (x/(n+1)) / (1 - x/(n+2))
+        d.tail_factor = (x < n + 2) ? (x / (n + 1)) / (1.0 - x / (n + 2)) : INFINITY;
     }
-    std::vector<float> Jf(p->Jpad.begin(), p->Jpad.end()), Ef(p->Epad.begin(), p->Epad.end());
+    // Step kernels read J and eps pre-multiplied by dt.
+    const double dt = pr.dt;
+    std::vector<double> Jd(p->Jpad.size()), Ed(p->Epad.size());
+    for (size_t k = 0; k < Jd.size(); ++k) {
+        Jd[k] = dt * p->Jpad[k];
+        Ed[k] = dt * p->Epad[k];
+    }
+    std::vector<float> Jf(Jd.begin(), Jd.end()), Ef(Ed.begin(), Ed.end());
     std::vector<double> ones(R, 1.0);
     const hipMemcpyKind h2d = hipMemcpyHostToDevice;
     hipStream_t s = p->stream;
@@ -298,8 +310,8 @@ ctqw_status upload_tables(ctqw_plan* p) {
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.items.off, p->items.data(), L.items.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.order.off, p->item_order.data(), L.order.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.item_first.off, p->item_first.data(), L.item_first.bytes, h2d, s));
-    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Jd.off, p->Jpad.data(), L.Jd.bytes, h2d, s));
-    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Ed.off, p->Epad.data(), L.Ed.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Jd.off, Jd.data(), L.Jd.bytes, h2d, s));
+    HIP_TRY(p, hipMemcpyAsync(p->ws + L.Ed.off, Ed.data(), L.Ed.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.Jf.off, Jf.data(), L.Jf.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.Ef.off, Ef.data(), L.Ef.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.scale.off, ones.data(), L.scale.bytes, h2d, s));
@@ -327,6 +339,7 @@ StepConfig step_config(ctqw_plan* p) {
     StepConfig c{};
     c.dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
     c.kahan = (c.dtype == 0 && p->prob.accumulation == CTQW_ACC_KAHAN) ? 1 : 0;
+    c.triangle = (p->prob.m == 2 && p->prob.statistics == CTQW_BOSON) ? 1 : 0;
     c.cols_per_lane = p->launch.cols_per_lane;
     c.levels = p->levels;
     c.waves_per_block = p->launch.waves_per_block;
@@ -674,7 +687,7 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         p->launch.use_graph = 0;
         p->launch.waves_per_cu = 0;
         p->order.assign(R, 0);
-        p->tail_factor.assign(R, 0.0);
+        p->xbound.assign(R, 0.0);
     } catch (const std::bad_alloc&) {
         delete p;
         return fail(nullptr, CTQW_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -706,7 +719,7 @@ ctqw_status ctqw_set_params(ctqw_plan* p, const double* J, const double* eps, co
         if (!is_fin(U[r])) return fail(p, CTQW_ERR_INVALID_ARG, "U[%lld] is not finite", (long long)r);
 
     std::vector<int32_t> order(R);
-    std::vector<double> tf(R);
+    std::vector<double> xb(R);
     std::vector<double> Jpad(p->param_total, 0.0), Epad(p->param_total, 0.0);
     const int cap = max_order_cap(pr);
     int64_t jo = 0, eo = 0;
@@ -742,7 +755,7 @@ ctqw_status ctqw_set_params(ctqw_plan* p, const double* J, const double* eps, co
             }
         }
         order[r] = n;
-        tf[r] = (x < n + 2) ? (x / (n + 1)) / (1.0 - x / (n + 2)) : INFINITY;
+        xb[r] = x;
     }
     p->J.assign(J, J + nJ);
     p->eps.assign(eps, eps + nE);
@@ -750,7 +763,7 @@ ctqw_status ctqw_set_params(ctqw_plan* p, const double* J, const double* eps, co
     p->Jpad.swap(Jpad);
     p->Epad.swap(Epad);
     p->order.swap(order);
-    p->tail_factor.swap(tf);
+    p->xbound.swap(xb);
     p->params_set = true;
     return build_tables(p);
 }

@@ -3,47 +3,43 @@
 
 namespace ctqw {
 
-StepKernelFn step_table_f32k_p1(int levels);
-StepKernelFn step_table_f32k_p2(int levels);
-StepKernelFn step_table_f32p_p1(int levels);
-StepKernelFn step_table_f32p_p2(int levels);
-StepKernelFn step_table_f64_p1(int levels);
-StepKernelFn step_table_f64_p2(int levels);
+#define CTQW_DECLARE_TABLE(tag) StepKernelFn step_table_##tag(int levels);
+CTQW_DECLARE_TABLE(f32k_p1_full) CTQW_DECLARE_TABLE(f32k_p1_tri)
+CTQW_DECLARE_TABLE(f32k_p2_full) CTQW_DECLARE_TABLE(f32k_p2_tri)
+CTQW_DECLARE_TABLE(f32p_p1_full) CTQW_DECLARE_TABLE(f32p_p1_tri)
+CTQW_DECLARE_TABLE(f32p_p2_full) CTQW_DECLARE_TABLE(f32p_p2_tri)
+CTQW_DECLARE_TABLE(f64_p1_full) CTQW_DECLARE_TABLE(f64_p1_tri)
+CTQW_DECLARE_TABLE(f64_p2_full) CTQW_DECLARE_TABLE(f64_p2_tri)
+#undef CTQW_DECLARE_TABLE
 
 namespace {
 
-// Compiled depths, ascending; must match the step2d_*.hip tables.
-constexpr int kLevels32[] = {3, 4, 5, 6, 7, 8, 10, 12};
-constexpr int kLevels64p1[] = {3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 16};
-constexpr int kLevels64p2[] = {3, 4, 5, 6, 7, 8};
+// Deepest compiled pipeline per (dtype, columns per lane); every depth from
+// 1 up to it is compiled (see the step2d_*.hip tables).
+int max_levels(int dtype, int cols_per_lane) {
+    if (dtype == 1) return cols_per_lane == 1 ? 16 : 8;
+    return cols_per_lane == 1 ? 12 : 10;
+}
 
 StepKernelFn select_kernel(const StepConfig& c) {
-    if (c.dtype == 1) {
-        return c.cols_per_lane == 1 ? step_table_f64_p1(c.levels)
-                                    : (c.cols_per_lane == 2 ? step_table_f64_p2(c.levels) : nullptr);
-    }
-    if (c.kahan) {
-        return c.cols_per_lane == 1 ? step_table_f32k_p1(c.levels)
-                                    : (c.cols_per_lane == 2 ? step_table_f32k_p2(c.levels) : nullptr);
-    }
-    return c.cols_per_lane == 1 ? step_table_f32p_p1(c.levels)
-                                : (c.cols_per_lane == 2 ? step_table_f32p_p2(c.levels) : nullptr);
+    const bool t = c.triangle != 0;
+    if (c.cols_per_lane != 1 && c.cols_per_lane != 2) return nullptr;
+    const bool p1 = c.cols_per_lane == 1;
+    if (c.dtype == 1)
+        return p1 ? (t ? step_table_f64_p1_tri(c.levels) : step_table_f64_p1_full(c.levels))
+                  : (t ? step_table_f64_p2_tri(c.levels) : step_table_f64_p2_full(c.levels));
+    if (c.kahan)
+        return p1 ? (t ? step_table_f32k_p1_tri(c.levels) : step_table_f32k_p1_full(c.levels))
+                  : (t ? step_table_f32k_p2_tri(c.levels) : step_table_f32k_p2_full(c.levels));
+    return p1 ? (t ? step_table_f32p_p1_tri(c.levels) : step_table_f32p_p1_full(c.levels))
+              : (t ? step_table_f32p_p2_tri(c.levels) : step_table_f32p_p2_full(c.levels));
 }
 
 }  // namespace
 
 int step_levels_bucket(int dtype, int cols_per_lane, int order) {
-    if (order < 1) return -1;
-    if (dtype == 1) {
-        if (cols_per_lane == 2) {
-            for (int v : kLevels64p2) if (v >= order) return v;
-            return -1;
-        }
-        for (int v : kLevels64p1) if (v >= order) return v;
-        return -1;
-    }
-    for (int v : kLevels32) if (v >= order) return v;
-    return -1;
+    if (order < 1 || (cols_per_lane != 1 && cols_per_lane != 2)) return -1;
+    return order <= max_levels(dtype, cols_per_lane) ? order : -1;
 }
 
 hipError_t step_occupancy(const StepConfig& cfg, int* blocks_per_cu) {

@@ -14,10 +14,17 @@
 //  * a wave owns a band of 64*P consecutive columns (P per lane, so global
 //    loads and stores of a row are contiguous) and sweeps the rows;
 //  * a pipeline of n levels runs down the rows: at sweep iteration i, level 0
-//    loads row i, level j computes Phi^(j) on row i - j from level j-1 on
-//    rows i-j-1, i-j, i-j+1 (all already in registers), and row i - n is
-//    complete and stored.  Each level keeps a three-row window; the partial
-//    sums psi + Phi^(1) + ... of the rows in flight sit in an (n+1)-row window.
+//    loads row i, level j works on row i - j from level j-1 on rows i-j-1,
+//    i-j, i-j+1 (all already in registers), and row i - n is complete and
+//    stored.  Each level keeps a three-row window; the partial sums of the
+//    rows in flight (and their Kahan compensations) sit in an (n+1)-row
+//    window.  Windows start at zero and rows outside the sweep stay zero, so
+//    the pipeline fills and drains without per-level tests (the bond above
+//    the first row and below the last row of an open chain is 0).
+//  * the coefficients are pre-scaled by dt on the host and the recursion
+//    carries Psi_j = (-i dt H)^j psi = j! Phi^(j): the -i is a swap of the
+//    real and imaginary parts and the 1/j! multiplies the term as it is
+//    added, so a level costs the stencil plus the accumulation.
 //  * column neighbours come from the adjacent lanes through DPP row shifts
 //    (wave_shr / wave_shl); the band overlaps its neighbours by n columns
 //    (the halo), recomputed by both.
@@ -58,6 +65,23 @@ __device__ __forceinline__ double from_right(double x) {
 
 __host__ __device__ constexpr int window_rows(int nt) { return ((nt + 3) / 3) * 3; }
 __host__ __device__ constexpr int mod_pos(int x, int w) { return ((x % w) + w) % w; }
+__host__ __device__ constexpr double inv_factorial(int j) {
+    double f = 1.0;
+    for (int k = 2; k <= j; ++k) f *= k;
+    return 1.0 / f;
+}
+// (-i)^j = sign_re(j) on the real part / sign_im(j) on the imaginary part
+// after the swap of roles: re_j = s_{j-1}, im_j = -re_{j-1}, re_0 = im_0 = +1.
+__host__ __device__ constexpr double sign_re(int j) {
+    double re = 1.0, im = 1.0;
+    for (int k = 1; k <= j; ++k) { const double r = im, s = -re; re = r; im = s; }
+    return re;
+}
+__host__ __device__ constexpr double sign_im(int j) {
+    double re = 1.0, im = 1.0;
+    for (int k = 1; k <= j; ++k) { const double r = im, s = -re; re = r; im = s; }
+    return im;
+}
 __device__ __forceinline__ int wrap(int x, int n) { int r = x % n; return r < 0 ? r + n : r; }
 
 template <typename T> __device__ __forceinline__ const T* jpar(const StepArgs& a);
@@ -73,7 +97,7 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-template <typename T, int NT, int P, bool KAHAN>
+template <typename T, int NT, int P, bool KAHAN, bool TRI>
 __device__ __forceinline__ void process_item(const StepArgs& a, int home, int lane) {
     using C = typename CplxOf<T>::type;
     constexpr int WA = window_rows(NT);
@@ -82,11 +106,10 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     const RealDev rd = a.reals[it.real];
     const int N = rd.N;
     const int rows = rd.rows;
-    const int order = rd.order;
     const int nrows = it.nrows;
     const bool periodic = (rd.flags & RF_PERIODIC) != 0;
     const bool nearest = (rd.flags & RF_NEAREST) != 0;
-    const bool TRI = (rd.flags & RF_TRIANGLE) != 0;
+    // J and eps below are scaled by dt (host tables).
     const T* __restrict__ Jc = jpar<T>(a) + rd.param_off;
     const T* __restrict__ Ec = epar<T>(a) + rd.param_off;
     const T* __restrict__ Jr_ = jpar<T>(a) + rd.row_param_off;
@@ -94,11 +117,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     const C* __restrict__ in = reinterpret_cast<const C*>(a.psi_in) + rd.state_off;
     C* __restrict__ out = reinterpret_cast<C*>(a.psi_out) + rd.state_off;
     const T sc = static_cast<T>(a.scale[it.real]);
-    const T U = static_cast<T>(rd.U);
-
-    T dtj[NT + 1];
-#pragma unroll
-    for (int j = 1; j <= NT; ++j) dtj[j] = static_cast<T>(a.dt / j);
+    const T Udt = static_cast<T>(rd.U * a.dt);
 
     // Columns held by this lane.
     int col[P], colw[P];
@@ -118,9 +137,8 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         ec[p] = inb[p] ? Ec[cs] : T(0);
     }
 
-    auto load_row = [&](int q, C (&dst)[P]) {
-        const int qa = it.row0 + q;
-        const int qm = periodic ? wrap(qa, rows) : qa;
+    // Row of the grid (wrapped on a ring) -> its stored amplitudes.
+    auto load_row = [&](int qm, C (&dst)[P]) {
         const int base = TRI ? qm * N - (qm * (qm + 1)) / 2 : qm * N;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -133,11 +151,11 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         }
     };
 
-    T fr[NT][3][P], fi[NT][3][P];   // Phi^(j) rows, j < NT
+    T fr[NT][3][P], fi[NT][3][P];   // Psi_j rows, j < NT
     T ar[WA][P], ai[WA][P];         // partial sums of rows in flight
     T cr[WA][P], ci[WA][P];         // Kahan compensations
-    T dg[WA][P];                    // diagonal of H on rows in flight
-    T ju[WA];                       // bond above each row in flight
+    T dg[WA][P];                    // dt * diagonal of H on rows in flight
+    T ju[WA];                       // dt * bond above each row in flight
     C pre[3][P];                    // rows being fetched
 #pragma unroll
     for (int j = 0; j < NT; ++j)
@@ -153,9 +171,17 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
             ar[w][p] = ai[w][p] = cr[w][p] = ci[w][p] = dg[w][p] = T(0);
         }
     }
+    // Grid rows are tracked incrementally: qm_in is the row entering at the
+    // current iteration, qm_prev the one before it (its bond joins the two),
+    // qm_pf the row being prefetched three iterations ahead.
+    auto next_row = [&](int x) { return (x + 1 == rows) ? 0 : x + 1; };
+    int qm_in = periodic ? wrap(it.row0, rows) : it.row0;
+    int qm_prev = wrap(qm_in - 1, rows);
+    int qm_pf = qm_in;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        if (s < nrows) load_row(s, pre[s]);
+        if (s < nrows) load_row(qm_pf, pre[s]);
+        qm_pf = next_row(qm_pf);
     }
 
     double nrm = 0.0, tail = 0.0;
@@ -166,32 +192,34 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         for (int u = 0; u < WA; ++u) {
             const int i = i0 + u;
             if (i < total) {
-                // ---- level 0: row i enters.
+                // ---- level 0: row i enters (zero beyond the sweep).
                 {
                     const int s = u % 3;
                     if (i < nrows) {
                         C v[P];
 #pragma unroll
                         for (int p = 0; p < P; ++p) v[p] = pre[s][p];
-                        if (i + 3 < nrows) load_row(i + 3, pre[s]);
-                        const int qa = it.row0 + i;
-                        const int qm = periodic ? wrap(qa, rows) : qa;
-                        ju[u] = Jr_[wrap(qm - 1, rows)];
+                        if (i + 3 < nrows) load_row(qm_pf, pre[s]);
+                        const int qm = qm_in;
+                        ju[u] = Jr_[qm_prev];
                         const T er = Er_[qm];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const T re = v[p].x * sc, im = v[p].y * sc;
-                            if (NT > 0) { fr[0][s][p] = re; fi[0][s][p] = im; }
+                            fr[0][s][p] = re;
+                            fi[0][s][p] = im;
                             ar[u][p] = re;
                             ai[u][p] = im;
-                            cr[u][p] = T(0);
-                            ci[u][p] = T(0);
+                            if (KAHAN) {
+                                cr[u][p] = T(0);
+                                ci[u][p] = T(0);
+                            }
                             T vint = T(0);
                             if (rows > 1) {
                                 int d = qm - colw[p];
                                 d = d < 0 ? -d : d;
                                 if (periodic && N - d < d) d = N - d;
-                                vint = nearest ? (d == 1 ? U : T(0)) : (d == 0 ? U : T(0));
+                                vint = (d == (nearest ? 1 : 0)) ? Udt : T(0);
                             }
                             dg[u][p] = inb[p] ? er + ec[p] + vint : T(0);
                         }
@@ -200,103 +228,106 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 #pragma unroll
                         for (int p = 0; p < P; ++p) { fr[0][s][p] = T(0); fi[0][s][p] = T(0); }
                     }
+                    qm_prev = qm_in;
+                    qm_in = next_row(qm_in);
+                    qm_pf = next_row(qm_pf);
                 }
-                // ---- levels 1..NT: Phi^(j) on row i - j.
+                // ---- levels 1..NT: Psi_j on row i - j.
 #pragma unroll
                 for (int j = 1; j <= NT; ++j) {
-                    const int q = i - j;
                     const int su = mod_pos(u - j - 1, 3);
                     const int sm = mod_pos(u - j, 3);
                     const int sd = mod_pos(u - j + 1, 3);
                     const int w = mod_pos(u - j, WA);
                     const int w1 = mod_pos(u - j + 1, WA);
-                    if (q >= 0 && q < nrows) {
-                        if (j <= order) {
-                            const T Ju = ju[w];
-                            const T Jd = ju[w1];
-                            const int qa = it.row0 + q;
-                            const bool zone = TRI && (qa >= it.w0);
-                            T lr[P], li[P], rr[P], ri[P];
+                    const T Ju = ju[w];
+                    const T Jd = ju[w1];
+                    // Psi_j = sr_j A_j + i si_j B_j with A_j = H B_{j-1}, B_j = H A_{j-1}:
+                    // the factor -i only swaps the two parts and moves signs, which are
+                    // compile-time and folded into the accumulation coefficients.
+                    const T cr_j = static_cast<T>(sign_re(j) * inv_factorial(j));
+                    const T ci_j = static_cast<T>(sign_im(j) * inv_factorial(j));
+                    T lr[P], li[P], rr[P], ri[P];
 #pragma unroll
-                            for (int p = 0; p < P; ++p) {
-                                if (p > 0) { lr[p] = fr[j - 1][sm][p - 1]; li[p] = fi[j - 1][sm][p - 1]; }
-                                if (p < P - 1) { rr[p] = fr[j - 1][sm][p + 1]; ri[p] = fi[j - 1][sm][p + 1]; }
-                            }
-                            lr[0] = from_left(fr[j - 1][sm][P - 1]);
-                            li[0] = from_left(fi[j - 1][sm][P - 1]);
-                            rr[P - 1] = from_right(fr[j - 1][sm][0]);
-                            ri[P - 1] = from_right(fi[j - 1][sm][0]);
+                    for (int p = 0; p < P; ++p) {
+                        if (p > 0) { lr[p] = fr[j - 1][sm][p - 1]; li[p] = fi[j - 1][sm][p - 1]; }
+                        if (p < P - 1) { rr[p] = fr[j - 1][sm][p + 1]; ri[p] = fi[j - 1][sm][p + 1]; }
+                    }
+                    lr[0] = from_left(fr[j - 1][sm][P - 1]);
+                    li[0] = from_left(fi[j - 1][sm][P - 1]);
+                    rr[P - 1] = from_right(fr[j - 1][sm][0]);
+                    ri[P - 1] = from_right(fi[j - 1][sm][0]);
+                    // Triangle: the band's rows at and below its first column hold the
+                    // diagonal; there the couplings up and right double and the
+                    // lower triangle is held at zero.
+                    const int qa = it.row0 + (i - j);
+                    const bool zone = TRI && qa >= it.w0;
 #pragma unroll
-                            for (int p = 0; p < P; ++p) {
-                                T cu = Ju, crt = jr[p];
-                                bool low = false;
-                                if (zone) {
-                                    const bool isd = (col[p] == qa);
-                                    low = (col[p] < qa);
-                                    if (isd) { cu = Ju + Ju; crt = crt + crt; }
-                                }
-                                const T mr = fr[j - 1][sm][p], mi = fi[j - 1][sm][p];
-                                T hr = dg[w][p] * mr;
-                                T hi = dg[w][p] * mi;
-                                hr += cu * fr[j - 1][su][p];
-                                hi += cu * fi[j - 1][su][p];
-                                hr += Jd * fr[j - 1][sd][p];
-                                hi += Jd * fi[j - 1][sd][p];
-                                hr += jl[p] * lr[p];
-                                hi += jl[p] * li[p];
-                                hr += crt * rr[p];
-                                hi += crt * ri[p];
-                                T pr_ = dtj[j] * hi;
-                                T pi_ = -dtj[j] * hr;
-                                if (TRI && low) { pr_ = T(0); pi_ = T(0); }
-                                if (j < NT) { fr[j % NT][sm][p] = pr_; fi[j % NT][sm][p] = pi_; }
-                                if (KAHAN) {
-                                    const T yr = pr_ - cr[w][p];
-                                    const T tr = ar[w][p] + yr;
-                                    cr[w][p] = (tr - ar[w][p]) - yr;
-                                    ar[w][p] = tr;
-                                    const T yi = pi_ - ci[w][p];
-                                    const T ti = ai[w][p] + yi;
-                                    ci[w][p] = (ti - ai[w][p]) - yi;
-                                    ai[w][p] = ti;
-                                } else {
-                                    ar[w][p] += pr_;
-                                    ai[w][p] += pi_;
-                                }
-                                if (j == order) {
-                                    const bool rowok = qa >= it.out_lo && qa < it.out_hi;
-                                    if (rowok && outv[p] && (!TRI || col[p] >= qa)) {
-                                        const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
-                                        const double dr = pr_, di = pi_;
-                                        tail += wgt * (dr * dr + di * di);
-                                    }
-                                }
+                    for (int p = 0; p < P; ++p) {
+                        T cu = Ju, crt = jr[p];
+                        bool low = false;
+                        if (TRI && zone) {
+                            const bool isd = (col[p] == qa);
+                            low = (col[p] < qa);
+                            if (isd) { cu = Ju + Ju; crt = crt + crt; }
+                        }
+                        const T mr = fr[j - 1][sm][p], mi = fi[j - 1][sm][p];
+                        T hr = dg[w][p] * mr;
+                        T hi = dg[w][p] * mi;
+                        hr += cu * fr[j - 1][su][p];
+                        hi += cu * fi[j - 1][su][p];
+                        hr += Jd * fr[j - 1][sd][p];
+                        hi += Jd * fi[j - 1][sd][p];
+                        hr += jl[p] * lr[p];
+                        hi += jl[p] * li[p];
+                        hr += crt * rr[p];
+                        hi += crt * ri[p];
+                        // A_j = H B_{j-1} (from the imaginary-role array), B_j = H A_{j-1}
+                        T pr_ = hi;
+                        T pi_ = hr;
+                        if (TRI && low) { pr_ = T(0); pi_ = T(0); }
+                        if (j < NT) { fr[j % NT][sm][p] = pr_; fi[j % NT][sm][p] = pi_; }
+                        if (KAHAN) {
+                            const T yr = cr_j * pr_ - cr[w][p];
+                            const T tr = ar[w][p] + yr;
+                            cr[w][p] = (tr - ar[w][p]) - yr;
+                            ar[w][p] = tr;
+                            const T yi = ci_j * pi_ - ci[w][p];
+                            const T ti = ai[w][p] + yi;
+                            ci[w][p] = (ti - ai[w][p]) - yi;
+                            ai[w][p] = ti;
+                        } else {
+                            ar[w][p] += cr_j * pr_;
+                            ai[w][p] += ci_j * pi_;
+                        }
+                        if (j == NT) {
+                            const int q = i - NT;
+                            const bool rowok = q >= 0 && qa >= it.out_lo && qa < it.out_hi;
+                            if (rowok && outv[p] && (!TRI || col[p] >= qa)) {
+                                const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
+                                const double dr = pr_, di = pi_;
+                                tail += wgt * (dr * dr + di * di);
                             }
                         }
-                    } else if (q >= nrows && j < NT) {
-#pragma unroll
-                        for (int p = 0; p < P; ++p) { fr[j % NT][sm][p] = T(0); fi[j % NT][sm][p] = T(0); }
                     }
                 }
                 // ---- row i - NT is complete.
                 {
                     const int q = i - NT;
                     const int w = mod_pos(u - NT, WA);
-                    if (q >= 0 && q < nrows) {
-                        const int qa = it.row0 + q;
-                        if (qa >= it.out_lo && qa < it.out_hi) {
-                            const int base = TRI ? qa * N - (qa * (qa + 1)) / 2 : qa * N;
+                    const int qa = it.row0 + q;
+                    if (q >= 0 && qa >= it.out_lo && qa < it.out_hi) {
+                        const int base = TRI ? qa * N - (qa * (qa + 1)) / 2 : qa * N;
 #pragma unroll
-                            for (int p = 0; p < P; ++p) {
-                                if (outv[p] && (!TRI || col[p] >= qa)) {
-                                    C v;
-                                    v.x = ar[w][p];
-                                    v.y = ai[w][p];
-                                    out[base + colw[p]] = v;
-                                    const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
-                                    const double dr = v.x, di = v.y;
-                                    nrm += wgt * (dr * dr + di * di);
-                                }
+                        for (int p = 0; p < P; ++p) {
+                            if (outv[p] && (!TRI || col[p] >= qa)) {
+                                C v;
+                                v.x = ar[w][p];
+                                v.y = ai[w][p];
+                                out[base + colw[p]] = v;
+                                const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
+                                const double dr = v.x, di = v.y;
+                                nrm += wgt * (dr * dr + di * di);
                             }
                         }
                     }
@@ -307,8 +338,9 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     nrm = wave_sum(nrm);
     tail = wave_sum(tail);
     if (lane == 0) {
+        const double f = inv_factorial(NT);
         a.norm_part[home] = nrm;
-        a.tail_part[home] = tail;
+        a.tail_part[home] = tail * f * f;
     }
 }
 
@@ -319,14 +351,14 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 // large and small items.  The loop bound is wave-uniform and no counter
 // state is kept between launches, so the kernel can be launched again or
 // replayed in a graph as is.
-template <typename T, int NT, int P, bool KAHAN>
+template <typename T, int NT, int P, bool KAHAN, bool TRI>
 __global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k0 = blockIdx.x * (blockDim.x >> 6) + wv;
     const int stride = a.persistent ? a.n_waves : a.n_items;
     for (int k = k0; k < a.n_items; k += stride) {
-        process_item<T, NT, P, KAHAN>(a, a.item_order[k], lane);
+        process_item<T, NT, P, KAHAN, TRI>(a, a.item_order[k], lane);
     }
 }
 
@@ -337,6 +369,6 @@ using StepKernelFn = void (*)(StepArgs);
 }  // namespace ctqw
 
 // Table of compiled pipeline depths for one (type, columns per lane,
-// accumulation) combination; each translation unit instantiates one table.
-#define CTQW_STEP_CASE(T, NT, P, K) \
-    case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, P, K>;
+// accumulation, layout) combination; each translation unit instantiates one.
+#define CTQW_STEP_CASE(T, NT, P, K, TRI) \
+    case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, P, K, TRI>;
