@@ -211,6 +211,46 @@ ctqw_status ctqw_set_launch(ctqw_plan* plan, const ctqw_launch* launch);
  * number of waves that one step launches, for the current launch shape.  */
 ctqw_status ctqw_work_items(const ctqw_plan* plan, int64_t* items, int64_t* waves);
 
+/* Derivatives of an ensemble-averaged diagonal observable.  The paper does
+ * not differentiate; this extends its method.  With the state at the call
+ * as psi_0 and T = n_steps steps of Alg. 3 (the same map ctqw_propagate
+ * applies), the loss is
+ *     L = (1/R) sum_r <psi_r(T)| W |psi_r(T)>,  W diagonal in the occupation basis,
+ *   ONE_BODY: w(x) = sum_a g[x_a];   PRODUCT: w(x) = prod_a g[x_a]
+ * (g = site_weights[N]; PRODUCT with g the indicator of a block of nodes is
+ * the probability that all particles are in it).  The noise is additive
+ * (J^r = Jbar + dJ^r, eps^r = epsbar + deps^r), so dL/dJbar_i =
+ * sum_r dL/dJ^r_i; grad_J [n_bonds(N)] and grad_eps [N] return these, the
+ * exact derivatives of the discrete (truncated-Taylor) map, computed by a
+ * hand-written adjoint: the forward run keeps the state every ckpt_every
+ * steps, each segment is recomputed from its checkpoint, and the adjoint of
+ * every step applies p(A)^dagger with A = -i dt H by a Horner recursion
+ * (the same stencil with dt -> -dt) while FP64 kernels contract the bond
+ * and site operators.  All realisations must share one lattice size;
+ * renormalize must be 0.  grad_ws is caller-owned device memory of at
+ * least ctqw_gradient_workspace bytes (256-byte aligned).  On return the
+ * current state is psi(T).                                                */
+#define CTQW_LOSS_ONE_BODY 0
+#define CTQW_LOSS_PRODUCT 1
+ctqw_status ctqw_gradient_workspace(const ctqw_plan* plan, int64_t n_steps, int64_t ckpt_every, int64_t* bytes);
+/* The two halves of ctqw_gradient: ctqw_forward_ckpt advances n_steps and
+ * keeps the checkpoints in grad_ws; ctqw_backward evaluates the loss at the
+ * current state and runs the adjoint back to the state the forward started
+ * from.  Changing parameters, launch shape or state in between invalidates
+ * the checkpoints (CTQW_ERR_STATE); one backward per forward.            */
+ctqw_status ctqw_forward_ckpt(ctqw_plan* plan, int64_t n_steps, int64_t ckpt_every, void* grad_ws,
+                              int64_t grad_ws_bytes);
+ctqw_status ctqw_backward(ctqw_plan* plan, int32_t kind, const double* site_weights, void* grad_ws,
+                          int64_t grad_ws_bytes, double* loss, double* grad_J, double* grad_eps);
+/* The loss alone at the current state (FP64).  Uses scratch at the end of
+ * grad_ws (at least ctqw_gradient_workspace(plan, 0, 1) bytes) and leaves
+ * the checkpoints of a pending ctqw_forward_ckpt intact.                  */
+ctqw_status ctqw_loss(ctqw_plan* plan, int32_t kind, const double* site_weights, void* grad_ws,
+                      int64_t grad_ws_bytes, double* loss);
+ctqw_status ctqw_gradient(ctqw_plan* plan, int64_t n_steps, int64_t ckpt_every, int32_t kind,
+                          const double* site_weights, void* grad_ws, int64_t grad_ws_bytes, double* loss,
+                          double* grad_J, double* grad_eps);
+
 /* Autotuner.  Times `steps` propagation steps (after one warm-up step) for
  * every launch shape -- columns per lane {1, 2}, waves per block {1, 2, 4},
  * regular or persistent launch, and for the persistent form a cap of

@@ -202,6 +202,52 @@ class Plan:
         self._check(self.lib.ctqw_autotune(self.h, path, steps, C.byref(best), C.byref(ms)))
         return best, ms.value
 
+    # ------------------------------------------------------------ gradients
+    def _grad_workspace(self, n_steps: int, ckpt_every: int):
+        import torch
+        b = C.c_int64()
+        self._check(self.lib.ctqw_gradient_workspace(self.h, n_steps, ckpt_every, C.byref(b)))
+        ws = getattr(self, "_grad_ws", None)
+        if ws is None or ws.numel() < b.value:
+            self._grad_ws = None
+            ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=self._buffers[0].device)
+            self._grad_ws = ws
+        return ws, b.value
+
+    def forward_ckpt(self, n_steps: int, ckpt_every: int) -> None:
+        ws, nb = self._grad_workspace(n_steps, ckpt_every)
+        self._check(self.lib.ctqw_forward_ckpt(self.h, n_steps, ckpt_every, C.c_void_p(ws.data_ptr()), ws.numel()))
+
+    def backward(self, site_weights, kind: str = "product"):
+        """(loss, dL/dJbar [n_bonds], dL/depsbar [N]) after forward_ckpt."""
+        g = np.ascontiguousarray(site_weights, dtype=np.float64)
+        N = g.shape[0]
+        nb = N if self.problem.boundary == PERIODIC else N - 1
+        gJ = np.zeros(nb)
+        gE = np.zeros(N)
+        loss = C.c_double()
+        ws = self._grad_ws
+        k = L.LOSS_PRODUCT if kind == "product" else L.LOSS_ONE_BODY
+        self._check(self.lib.ctqw_backward(self.h, k, _ptr(g, C.c_double), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                           C.byref(loss), _ptr(gJ, C.c_double), _ptr(gE, C.c_double)))
+        return loss.value, gJ, gE
+
+    def loss(self, site_weights, kind: str = "product") -> float:
+        """The ensemble loss at the current state (needs forward_ckpt's workspace)."""
+        g = np.ascontiguousarray(site_weights, dtype=np.float64)
+        ws = getattr(self, "_grad_ws", None)
+        if ws is None:
+            ws, _ = self._grad_workspace(0, 1)
+        out = C.c_double()
+        k = L.LOSS_PRODUCT if kind == "product" else L.LOSS_ONE_BODY
+        self._check(self.lib.ctqw_loss(self.h, k, _ptr(g, C.c_double), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                       C.byref(out)))
+        return out.value
+
+    def gradient(self, n_steps: int, ckpt_every: int, site_weights, kind: str = "product"):
+        self.forward_ckpt(n_steps, ckpt_every)
+        return self.backward(site_weights, kind)
+
     def set_timing(self, enable: bool) -> None:
         self._check(self.lib.ctqw_set_timing(self.h, 1 if enable else 0))
 

@@ -23,6 +23,7 @@ INT_ONSITE, INT_NEAREST = 0, 1
 C64, C128 = 0, 1
 ACC_KAHAN, ACC_PLAIN = 0, 1
 OBS_OCCUPATION, OBS_PAIR = 1, 2
+LOSS_ONE_BODY, LOSS_PRODUCT = 0, 1
 
 
 class Problem(C.Structure):
@@ -96,6 +97,11 @@ SIGNATURES = {
     "ctqw_set_launch": (C.c_int, [PlanP, C.POINTER(Launch)]),
     "ctqw_work_items": (C.c_int, [PlanP, i64p, i64p]),
     "ctqw_autotune": (C.c_int, [PlanP, C.c_char_p, C.c_int32, C.POINTER(Launch), dp]),
+    "ctqw_gradient_workspace": (C.c_int, [PlanP, C.c_int64, C.c_int64, i64p]),
+    "ctqw_gradient": (C.c_int, [PlanP, C.c_int64, C.c_int64, C.c_int32, dp, C.c_void_p, C.c_int64, dp, dp, dp]),
+    "ctqw_forward_ckpt": (C.c_int, [PlanP, C.c_int64, C.c_int64, C.c_void_p, C.c_int64]),
+    "ctqw_backward": (C.c_int, [PlanP, C.c_int32, dp, C.c_void_p, C.c_int64, dp, dp, dp]),
+    "ctqw_loss": (C.c_int, [PlanP, C.c_int32, dp, C.c_void_p, C.c_int64, dp]),
     "ctqw_set_timing": (C.c_int, [PlanP, C.c_int32]),
     "ctqw_get_timing": (C.c_int, [PlanP, dp, i64p]),
     "ctqw_status_string": (C.c_char_p, [C.c_int]),

@@ -138,4 +138,69 @@ hipError_t launch_rescale(const RescaleArgs& a, hipStream_t stream);
 
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t stream);
 
+// ---------------------------------------------------------------- adjoint
+struct AdjApplyArgs {
+    const void* x;       // may be null
+    const void* z;       // may be null
+    void* y;
+    const RealDev* reals;
+    const void* Jt;      // dt-scaled tables of the step kernel (dtype of the state)
+    const void* Et;
+    double dt;
+    double cz;
+    int sign;            // +1: A = -i dt H; -1: A^dagger
+    int64_t R;
+    int max_N;
+    int max_rows;
+    int dtype;
+};
+hipError_t launch_adj_apply(const AdjApplyArgs& a, hipStream_t stream);
+
+struct AdjContractArgs {
+    const void* u;
+    const void* v;
+    const RealDev* reals;
+    const int64_t* site_off;
+    double* gJ;          // column parts (bond b / site b) per realisation
+    double* gE;
+    double* gJ2;         // row parts (distinguishable particles)
+    double* gE2;
+    int64_t R;
+    int max_N;
+    int max_rows;
+    int rows_part;
+    int dtype;
+};
+hipError_t launch_adj_contract(const AdjContractArgs& a, hipStream_t stream);
+
+struct AdjWeightArgs {
+    const void* psi;
+    void* lam;
+    const RealDev* reals;
+    const int64_t* site_off;
+    const double* site_w;
+    double* row_loss;
+    double inv_R;
+    int kind;            // 0: one-body sum, 1: product
+    int64_t R;
+    int max_rows;
+    int dtype;
+};
+hipError_t launch_adj_weights(const AdjWeightArgs& a, hipStream_t stream);
+
+struct AdjReduceArgs {
+    const double* gJ;
+    const double* gE;
+    const double* gJ2;
+    const double* gE2;
+    const double* row_loss;
+    const int64_t* site_off;
+    double* out;         // [2N + 1]: dL/dJ, dL/deps, loss
+    int64_t R;
+    int N;
+    int rows;
+    double dt;
+};
+hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t stream);
+
 }  // namespace ctqw

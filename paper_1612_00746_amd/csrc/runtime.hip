@@ -93,6 +93,10 @@ struct ctqw_plan {
     // captured step loops: (steps, starting buffer) -> executable graph
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;
+    // checkpointed forward run awaiting its backward pass
+    void* grad_ws = nullptr;
+    int64_t grad_steps = 0, grad_ckpt = 1, grad_tables = -1;
+    int64_t table_version = 0;       // bumped whenever the kernel tables change
     std::string err;
     void drop_graphs() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -268,6 +272,7 @@ ctqw_status build_tables(ctqw_plan* p) {
     p->lay = L;
     p->tables_dirty = true;
     p->drop_graphs();
+    ++p->table_version;
     return CTQW_OK;
 }
 
@@ -420,6 +425,34 @@ ctqw_status enqueue_step(ctqw_plan* p) {
     p->cur = 1 - p->cur;
     p->steps_done += 1;
     p->have_step_stats = true;
+    return CTQW_OK;
+}
+
+// One step kernel from `in` to `out` (no monitoring), for recomputation.
+ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
+    const Layout& L = p->lay;
+    StepConfig c = step_config(p);
+    int n_waves = 0;
+    ctqw_status st = grid_for(p, c, &n_waves);
+    if (st != CTQW_OK) return st;
+    StepArgs a{};
+    a.psi_in = in;
+    a.psi_out = out;
+    a.reals = at<RealDev>(p, L.reals);
+    a.items = at<ItemDev>(p, L.items);
+    a.item_order = at<int32_t>(p, L.order);
+    a.n_items = (int32_t)p->items.size();
+    a.n_waves = n_waves;
+    a.Jd = at<double>(p, L.Jd);
+    a.Ed = at<double>(p, L.Ed);
+    a.Jf = at<float>(p, L.Jf);
+    a.Ef = at<float>(p, L.Ef);
+    a.scale = at<double>(p, L.scale);
+    a.norm_part = at<double>(p, L.norm_part);
+    a.tail_part = at<double>(p, L.tail_part);
+    a.dt = p->prob.dt;
+    a.persistent = c.persistent;
+    HIP_TRY(p, launch_step(c, a, p->stream));
     return CTQW_OK;
 }
 
@@ -913,6 +946,7 @@ ctqw_status ctqw_init_product_state(ctqw_plan* p, const int32_t* sites, int32_t 
     p->cur = 0;
     p->steps_done = 0;
     p->have_step_stats = false;
+    p->grad_ws = nullptr;
     return CTQW_OK;
 }
 
@@ -931,6 +965,7 @@ ctqw_status ctqw_set_state(ctqw_plan* p, const void* psi, int32_t on_device) {
     p->cur = 0;
     p->steps_done = 0;
     p->have_step_stats = false;
+    p->grad_ws = nullptr;
     return CTQW_OK;
 }
 
@@ -1148,6 +1183,299 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
     if (best_out) *best_out = best;
     if (best_ms_out) *best_ms_out = best_ms;
     return CTQW_OK;
+}
+
+namespace {
+
+// Gradient workspace: checkpoints, recomputed segment states, the Taylor
+// vectors v_1..v_{n-1} of one step, two Horner vectors, two adjoint states,
+// then FP64 accumulators.
+struct GradLayout {
+    int64_t S = 0, n_ckpt = 0, n_seg = 0, n_v = 0;
+    int64_t ckpt = 0, seg = 0, v = 0, u = 0, lam = 0;
+    int64_t gJ = 0, gE = 0, gJ2 = 0, gE2 = 0, row_loss = 0, site_w = 0, out = 0;
+    int64_t total = 0;
+};
+
+GradLayout grad_layout(const ctqw_plan* p, int64_t n_steps, int64_t C) {
+    GradLayout g;
+    const int64_t esz = p->prob.dtype == CTQW_C128 ? 16 : 8;
+    g.S = (p->state_off.back() * esz + 255) & ~int64_t(255);
+    g.n_ckpt = n_steps > 0 ? (n_steps + C - 1) / C : 1;
+    g.n_seg = std::max<int64_t>(0, std::min(C, std::max<int64_t>(n_steps, 1)) - 1);
+    g.n_v = std::max(0, p->levels - 1);
+    int64_t o = 0;
+    g.ckpt = o; o += g.n_ckpt * g.S;
+    g.seg = o; o += g.n_seg * g.S;
+    g.v = o; o += g.n_v * g.S;
+    g.u = o; o += 2 * g.S;
+    g.lam = o; o += 2 * g.S;
+    auto dbl = [&](int64_t n) { const int64_t r = o; o += (n * 8 + 255) & ~int64_t(255); return r; };
+    g.gJ = dbl(p->site_total);
+    g.gE = dbl(p->site_total);
+    g.gJ2 = dbl(p->site_total);
+    g.gE2 = dbl(p->site_total);
+    g.row_loss = dbl(p->site_total);
+    g.site_w = dbl(p->max_N);
+    g.out = dbl(2 * (int64_t)p->max_N + 1);
+    g.total = o;
+    return g;
+}
+
+double inv_fact(int j) {
+    double f = 1.0;
+    for (int k = 2; k <= j; ++k) f *= k;
+    return 1.0 / f;
+}
+
+}  // namespace
+
+ctqw_status ctqw_gradient_workspace(const ctqw_plan* p, int64_t n_steps, int64_t ckpt_every, int64_t* bytes) {
+    if (!p || !bytes) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
+    if (n_steps < 0 || ckpt_every < 1)
+        return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "need n_steps >= 0 and ckpt_every >= 1");
+    *bytes = grad_layout(p, n_steps, ckpt_every).total;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_forward_ckpt(ctqw_plan* p, int64_t n_steps, int64_t ckpt_every, void* gws, int64_t gws_bytes) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!gws) return fail(p, CTQW_ERR_INVALID_ARG, "NULL gradient workspace");
+    if (n_steps < 0 || ckpt_every < 1) return fail(p, CTQW_ERR_INVALID_ARG, "need n_steps >= 0 and ckpt_every >= 1");
+    if (p->prob.renormalize) return fail(p, CTQW_ERR_UNSUPPORTED, "gradients need renormalize == 0 (a linear map)");
+    if (p->group_N.size() != 1)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "gradients with respect to shared baselines need one lattice size");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    const GradLayout g = grad_layout(p, n_steps, ckpt_every);
+    if (gws_bytes < g.total)
+        return fail(p, CTQW_ERR_INVALID_ARG, "gradient workspace too small (%lld < %lld bytes)", (long long)gws_bytes,
+                    (long long)g.total);
+    if (reinterpret_cast<uintptr_t>(gws) & 255) return fail(p, CTQW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    uint8_t* G = static_cast<uint8_t*>(gws);
+    hipStream_t s = p->stream;
+    const int64_t bytes = p->state_off.back() * (p->prob.dtype == CTQW_C128 ? 16 : 8);
+    const int64_t C = ckpt_every;
+    // forward, keeping the state at steps 0, C, 2C, ...
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (k % C == 0)
+            HIP_TRY(p, hipMemcpyAsync(G + g.ckpt + (k / C) * g.S, p->psi[p->cur], bytes, hipMemcpyDeviceToDevice, s));
+        if ((st = enqueue_step(p)) != CTQW_OK) return st;
+    }
+    if (n_steps == 0) HIP_TRY(p, hipMemcpyAsync(G + g.ckpt, p->psi[p->cur], bytes, hipMemcpyDeviceToDevice, s));
+    p->grad_ws = gws;
+    p->grad_steps = n_steps;
+    p->grad_ckpt = ckpt_every;
+    p->grad_tables = p->table_version;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_backward(ctqw_plan* p, int32_t kind, const double* site_w, void* gws, int64_t gws_bytes,
+                          double* loss, double* grad_J, double* grad_eps) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!site_w || !gws || !loss || !grad_J || !grad_eps) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (kind != CTQW_LOSS_ONE_BODY && kind != CTQW_LOSS_PRODUCT)
+        return fail(p, CTQW_ERR_INVALID_ARG, "unknown loss kind %d", kind);
+    if (gws != p->grad_ws || p->grad_tables != p->table_version)
+        return fail(p, CTQW_ERR_STATE, "no ctqw_forward_ckpt with this workspace since the last change");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    const int64_t n_steps = p->grad_steps;
+    const int64_t ckpt_every = p->grad_ckpt;
+    const GradLayout g = grad_layout(p, n_steps, ckpt_every);
+    if (gws_bytes < g.total)
+        return fail(p, CTQW_ERR_INVALID_ARG, "gradient workspace too small (%lld < %lld bytes)", (long long)gws_bytes,
+                    (long long)g.total);
+    for (int i = 0; i < p->N[0]; ++i)
+        if (!is_fin(site_w[i])) return fail(p, CTQW_ERR_INVALID_ARG, "site weight %d is not finite", i);
+    p->grad_ws = nullptr;   // one backward per forward
+
+    uint8_t* G = static_cast<uint8_t*>(gws);
+    hipStream_t s = p->stream;
+    const ctqw_problem& pr = p->prob;
+    const int n = p->levels;
+    const int N = p->N[0];
+    const int rows = pr.m == 1 ? 1 : N;
+    const int dtype = pr.dtype == CTQW_C128 ? 1 : 0;
+    const int64_t C = ckpt_every;
+    auto state = [&](int64_t off, int64_t k) { return static_cast<void*>(G + off + k * g.S); };
+
+    HIP_TRY(p, launch_fill_zero(G + g.gJ, g.site_w - g.gJ, s));
+    HIP_TRY(p, hipMemcpyAsync(G + g.site_w, site_w, N * 8, hipMemcpyHostToDevice, s));
+
+    const RealDev* reals = at<RealDev>(p, p->lay.reals);
+    const int64_t* site_off = at<int64_t>(p, p->lay.site_off);
+    AdjWeightArgs wa{};
+    wa.psi = p->psi[p->cur];
+    wa.lam = state(g.lam, 0);
+    wa.reals = reals;
+    wa.site_off = site_off;
+    wa.site_w = reinterpret_cast<const double*>(G + g.site_w);
+    wa.row_loss = reinterpret_cast<double*>(G + g.row_loss);
+    wa.inv_R = 1.0 / (double)pr.R;
+    wa.kind = kind;
+    wa.R = pr.R;
+    wa.max_rows = rows;
+    wa.dtype = dtype;
+    HIP_TRY(p, launch_adj_weights(wa, s));
+
+    AdjApplyArgs ap{};
+    ap.reals = reals;
+    ap.Jt = dtype ? static_cast<const void*>(at<double>(p, p->lay.Jd)) : static_cast<const void*>(at<float>(p, p->lay.Jf));
+    ap.Et = dtype ? static_cast<const void*>(at<double>(p, p->lay.Ed)) : static_cast<const void*>(at<float>(p, p->lay.Ef));
+    ap.dt = pr.dt;
+    ap.R = pr.R;
+    ap.max_N = N;
+    ap.max_rows = rows;
+    ap.dtype = dtype;
+    auto apply = [&](const void* x, const void* z, double cz, int sign, void* y) -> ctqw_status {
+        AdjApplyArgs a = ap;
+        a.x = x;
+        a.z = z;
+        a.cz = cz;
+        a.sign = sign;
+        a.y = y;
+        HIP_TRY(p, launch_adj_apply(a, s));
+        return CTQW_OK;
+    };
+    AdjContractArgs ca{};
+    ca.reals = reals;
+    ca.site_off = site_off;
+    ca.gJ = reinterpret_cast<double*>(G + g.gJ);
+    ca.gE = reinterpret_cast<double*>(G + g.gE);
+    ca.gJ2 = reinterpret_cast<double*>(G + g.gJ2);
+    ca.gE2 = reinterpret_cast<double*>(G + g.gE2);
+    ca.R = pr.R;
+    ca.max_N = N;
+    ca.max_rows = rows;
+    ca.rows_part = (pr.m == 2 && pr.statistics == CTQW_DISTINGUISHABLE) ? 1 : 0;
+    ca.dtype = dtype;
+    auto contract = [&](const void* u, const void* v) -> ctqw_status {
+        AdjContractArgs a = ca;
+        a.u = u;
+        a.v = v;
+        HIP_TRY(p, launch_adj_contract(a, s));
+        return CTQW_OK;
+    };
+
+    int lc = 0;   // state(g.lam, lc) holds lambda_{k+1}
+    std::vector<const void*> segp(C), vp(n);
+    for (int64_t sg = g.n_ckpt - 1; sg >= 0 && n_steps > 0; --sg) {
+        const int64_t k0 = sg * C;
+        const int64_t len = std::min(C, n_steps - k0);
+        segp[0] = state(g.ckpt, sg);
+        for (int64_t k = 1; k < len; ++k) {
+            segp[k] = state(g.seg, k - 1);
+            if ((st = enqueue_step_io(p, segp[k - 1], const_cast<void*>(segp[k]))) != CTQW_OK) return st;
+        }
+        for (int64_t k = len - 1; k >= 0; --k) {
+            const void* lam = state(g.lam, lc);
+            vp[0] = segp[k];
+            for (int i = 1; i < n; ++i) {
+                vp[i] = state(g.v, i - 1);
+                if ((st = apply(vp[i - 1], nullptr, 0.0, +1, const_cast<void*>(vp[i]))) != CTQW_OK) return st;
+            }
+            int uc = 0;
+            if ((st = apply(nullptr, lam, inv_fact(n), +1, state(g.u, uc))) != CTQW_OK) return st;
+            if ((st = contract(state(g.u, uc), vp[n - 1])) != CTQW_OK) return st;
+            for (int i = n - 2; i >= 0; --i) {
+                if ((st = apply(state(g.u, uc), lam, inv_fact(i + 1), -1, state(g.u, 1 - uc))) != CTQW_OK) return st;
+                uc ^= 1;
+                if ((st = contract(state(g.u, uc), vp[i])) != CTQW_OK) return st;
+            }
+            if ((st = apply(state(g.u, uc), lam, 1.0, -1, state(g.lam, 1 - lc))) != CTQW_OK) return st;
+            lc ^= 1;
+        }
+    }
+
+    AdjReduceArgs ra{};
+    ra.gJ = ca.gJ;
+    ra.gE = ca.gE;
+    ra.gJ2 = ca.gJ2;
+    ra.gE2 = ca.gE2;
+    ra.row_loss = wa.row_loss;
+    ra.site_off = site_off;
+    ra.out = reinterpret_cast<double*>(G + g.out);
+    ra.R = pr.R;
+    ra.N = N;
+    ra.rows = rows;
+    ra.dt = pr.dt;
+    HIP_TRY(p, launch_adj_reduce(ra, s));
+    std::vector<double> host(2 * (size_t)N + 1);
+    HIP_TRY(p, hipMemcpyAsync(host.data(), G + g.out, host.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    const int nb = n_bonds(pr, N);
+    std::memcpy(grad_J, host.data(), nb * 8);
+    std::memcpy(grad_eps, host.data() + N, N * 8);
+    *loss = host[2 * N];
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_loss(ctqw_plan* p, int32_t kind, const double* site_w, void* gws, int64_t gws_bytes, double* loss) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!site_w || !gws || !loss) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (kind != CTQW_LOSS_ONE_BODY && kind != CTQW_LOSS_PRODUCT)
+        return fail(p, CTQW_ERR_INVALID_ARG, "unknown loss kind %d", kind);
+    if (p->group_N.size() != 1) return fail(p, CTQW_ERR_UNSUPPORTED, "the loss needs one lattice size");
+    ctqw_status st = ensure_ready(p);
+    if (st != CTQW_OK) return st;
+    const GradLayout g = grad_layout(p, 0, 1);
+    if (gws_bytes < g.total)
+        return fail(p, CTQW_ERR_INVALID_ARG, "workspace too small (%lld < %lld bytes)", (long long)gws_bytes,
+                    (long long)g.total);
+    if (reinterpret_cast<uintptr_t>(gws) & 255) return fail(p, CTQW_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const int N = p->N[0];
+    for (int i = 0; i < N; ++i)
+        if (!is_fin(site_w[i])) return fail(p, CTQW_ERR_INVALID_ARG, "site weight %d is not finite", i);
+    // Scratch regions of a zero-step gradient layout at the end of the
+    // workspace, so that checkpoints of a pending forward run survive.
+    uint8_t* G = static_cast<uint8_t*>(gws) + (gws_bytes - g.total) / 256 * 256;
+    hipStream_t s = p->stream;
+    const ctqw_problem& pr = p->prob;
+    const int rows = pr.m == 1 ? 1 : N;
+    HIP_TRY(p, launch_fill_zero(G + g.gJ, g.site_w - g.gJ, s));
+    HIP_TRY(p, hipMemcpyAsync(G + g.site_w, site_w, N * 8, hipMemcpyHostToDevice, s));
+    AdjWeightArgs wa{};
+    wa.psi = p->psi[p->cur];
+    wa.lam = G + g.lam;
+    wa.reals = at<RealDev>(p, p->lay.reals);
+    wa.site_off = at<int64_t>(p, p->lay.site_off);
+    wa.site_w = reinterpret_cast<const double*>(G + g.site_w);
+    wa.row_loss = reinterpret_cast<double*>(G + g.row_loss);
+    wa.inv_R = 1.0 / (double)pr.R;
+    wa.kind = kind;
+    wa.R = pr.R;
+    wa.max_rows = rows;
+    wa.dtype = pr.dtype == CTQW_C128 ? 1 : 0;
+    HIP_TRY(p, launch_adj_weights(wa, s));
+    AdjReduceArgs ra{};
+    ra.gJ = reinterpret_cast<const double*>(G + g.gJ);
+    ra.gE = reinterpret_cast<const double*>(G + g.gE);
+    ra.gJ2 = reinterpret_cast<const double*>(G + g.gJ2);
+    ra.gE2 = reinterpret_cast<const double*>(G + g.gE2);
+    ra.row_loss = wa.row_loss;
+    ra.site_off = wa.site_off;
+    ra.out = reinterpret_cast<double*>(G + g.out);
+    ra.R = pr.R;
+    ra.N = N;
+    ra.rows = rows;
+    ra.dt = pr.dt;
+    HIP_TRY(p, launch_adj_reduce(ra, s));
+    HIP_TRY(p, hipMemcpyAsync(loss, G + g.out + 2 * (int64_t)N * 8, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(p, hipStreamSynchronize(s));
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_gradient(ctqw_plan* p, int64_t n_steps, int64_t ckpt_every, int32_t kind, const double* site_w,
+                          void* gws, int64_t gws_bytes, double* loss, double* grad_J, double* grad_eps) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!site_w || !loss || !grad_J || !grad_eps) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (kind != CTQW_LOSS_ONE_BODY && kind != CTQW_LOSS_PRODUCT)
+        return fail(p, CTQW_ERR_INVALID_ARG, "unknown loss kind %d", kind);
+    ctqw_status st = ctqw_forward_ckpt(p, n_steps, ckpt_every, gws, gws_bytes);
+    if (st != CTQW_OK) return st;
+    return ctqw_backward(p, kind, site_w, gws, gws_bytes, loss, grad_J, grad_eps);
 }
 
 ctqw_status ctqw_set_timing(ctqw_plan* p, int32_t enable) {
