@@ -194,3 +194,32 @@ def test_status_strings():
     for s in range(8):
         assert lib.ctqw_status_string(s)
     assert lib.ctqw_version().startswith(b"ctqw")
+
+
+def test_gradient_entry_points_validate_on_host():
+    from paper_1612_00746_amd import _lib as L
+    plan = make(R=2, n_sites=8, statistics="boson", taylor_order=6, taylor_tol=0.0)
+    J, eps, U = draw(8, 2, 7)
+    plan.set_params(J, eps, U)
+    lib = plan.lib
+    b = np.zeros(1, dtype=np.int64)
+    assert lib.ctqw_gradient_workspace(plan.h, 40, 8, b.ctypes.data_as(L.i64p)) == 0
+    esz = 16
+    S = ((8 * 9 // 2) * 2 * esz + 255) // 256 * 256
+    # 5 checkpoints + 7 segment states + 5 Taylor vectors + 2 Horner + 2 adjoint states
+    assert b[0] >= (5 + 7 + 5 + 4) * S
+    assert lib.ctqw_gradient_workspace(plan.h, 40, 0, b.ctypes.data_as(L.i64p)) == L.ERR_INVALID_ARG
+    w = np.ones(8)
+    out = np.zeros(16)
+    loss = np.zeros(1)
+    dp = L.dp
+    assert lib.ctqw_gradient(plan.h, 10, 2, 5, w.ctypes.data_as(dp), None, 0, loss.ctypes.data_as(dp),
+                             out.ctypes.data_as(dp), out.ctypes.data_as(dp)) == L.ERR_INVALID_ARG
+    assert lib.ctqw_backward(plan.h, 1, w.ctypes.data_as(dp), C.c_void_p(256), 1 << 30, loss.ctypes.data_as(dp),
+                             out.ctypes.data_as(dp), out.ctypes.data_as(dp)) == L.ERR_STATE
+    uneven = make(R=2, n_sites=[8, 10], taylor_order=6, taylor_tol=0.0)
+    uneven.set_params(np.ones(7 + 9), np.zeros(18), np.zeros(2))
+    assert lib.ctqw_forward_ckpt(uneven.h, 4, 2, C.c_void_p(256), 1 << 30) == L.ERR_UNSUPPORTED
+    renorm = make(R=2, n_sites=8, taylor_order=6, taylor_tol=0.0, renormalize=True)
+    renorm.set_params(J, eps, U)
+    assert lib.ctqw_forward_ckpt(renorm.h, 4, 2, C.c_void_p(256), 1 << 30) == L.ERR_UNSUPPORTED
