@@ -53,6 +53,10 @@ __global__ void init_sites_kernel(InitArgs a) {
         psi[s[0]] = one;
         return;
     }
+    if (a.m == 3) {
+        psi[((int64_t)s[0] * rd.N + s[1]) * rd.N + s[2]] = one;
+        return;
+    }
     int x1 = s[0], x2 = s[1];
     if (rd.flags & RF_TRIANGLE) {
         if (x1 > x2) { const int t = x1; x1 = x2; x2 = t; }

@@ -138,6 +138,46 @@ hipError_t launch_rescale(const RescaleArgs& a, hipStream_t stream);
 
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t stream);
 
+// ------------------------------------------------------- three particles
+struct Step3Args {
+    const void* phi_in;      // psi for the first pass, else Phi^(j-1)
+    void* phi_out;           // Phi^(j) (unused on the last pass)
+    void* acc;               // running sum = the new state
+    void* comp;              // Kahan compensation (complex64)
+    const RealDev* reals;
+    const void* Jt;          // dt-scaled tables (dtype of the state)
+    const void* Et;
+    const double* scale;
+    double* norm_part;
+    double* tail_part;
+    double dt;
+    double inv_j;            // 1 / j
+    int32_t first;
+    int32_t last;
+    int64_t R;
+    int64_t blocks_per_real;
+};
+hipError_t launch_term3d(const Step3Args& a, int kahan, int dtype, int N, hipStream_t stream);
+int64_t term3d_blocks_per_real(int N);
+
+struct Obs3Args {
+    const void* psi;
+    const RealDev* reals;
+    const double* scale;
+    double* M;               // [R][3][N][N] two-body marginals
+    double* occ_terms;       // [G][N][N]
+    const int32_t* group_members;
+    const int32_t* group_first;
+    const int32_t* group_N;
+    const int64_t* group_out;
+    double* out;
+    int64_t R;
+    int32_t G;
+    int32_t max_N;
+    int32_t want_pair;
+};
+hipError_t launch_obs3(const Obs3Args& a, int dtype, hipStream_t stream);
+
 // ---------------------------------------------------------------- adjoint
 struct AdjApplyArgs {
     const void* x;       // may be null

@@ -41,7 +41,7 @@ struct Region {
 
 struct Layout {
     Region reals, items, order, item_first, Jd, Ed, Jf, Ef, scale, norm_part, tail_part, norm2,
-        tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites;
+        tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites, s3, M3, occ3;
     int64_t total = 0;
 };
 
@@ -69,6 +69,7 @@ struct ctqw_plan {
     // work items
     std::vector<ItemDev> items;
     std::vector<int32_t> item_first, item_order;
+    int64_t n_parts = 0;             // per-step FP64 norm partials
     int levels = 0;
     ctqw_launch launch{};
     Layout lay;
@@ -135,12 +136,13 @@ int n_bonds(const ctqw_problem& pr, int N) { return pr.boundary == CTQW_PERIODIC
 
 int64_t amplitudes(const ctqw_problem& pr, int N) {
     if (pr.m == 1) return N;
+    if (pr.m == 3) return (int64_t)N * N * N;
     if (pr.statistics == CTQW_BOSON) return (int64_t)N * (N + 1) / 2;
     return (int64_t)N * N;
 }
 
 int max_order_cap(const ctqw_problem& pr) {
-    const int compiled = pr.dtype == CTQW_C128 ? 16 : 12;
+    const int compiled = pr.m == 3 ? 24 : (pr.dtype == CTQW_C128 ? 16 : 12);
     if (pr.taylor_max_order > 0) return std::min(pr.taylor_max_order, compiled);
     return compiled;
 }
@@ -214,18 +216,28 @@ ctqw_status build_tables(ctqw_plan* p) {
     const int W = 64 * P;
     int maxn = 0;
     for (int64_t r = 0; r < pr.R; ++r) maxn = std::max(maxn, p->order[r]);
-    const int levels = step_levels_bucket(pr.dtype == CTQW_C128 ? 1 : 0, P, maxn);
+    const int levels = pr.m == 3 ? maxn : step_levels_bucket(pr.dtype == CTQW_C128 ? 1 : 0, P, maxn);
     if (levels < 0)
         return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d has no compiled kernel for %d column(s) per lane",
                     maxn, P);
     std::vector<ItemDev> items;
     std::vector<int32_t> first(pr.R + 1, 0);
-    for (int64_t r = 0; r < pr.R; ++r) {
-        first[r] = (int32_t)items.size();
-        if (!make_bands(pr, (int)r, p->N[r], levels, W, items))
-            return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", levels, W);
+    int64_t n_parts = 0;
+    if (pr.m == 3) {
+        // one norm partial per block of the three-particle term kernel
+        const int64_t bpr = term3d_blocks_per_real(p->N[0]);
+        if (bpr * pr.R > INT32_MAX) return fail(p, CTQW_ERR_OUT_OF_MEMORY, "too many norm partials");
+        for (int64_t r = 0; r <= pr.R; ++r) first[r] = (int32_t)(r * bpr);
+        n_parts = bpr * pr.R;
+    } else {
+        for (int64_t r = 0; r < pr.R; ++r) {
+            first[r] = (int32_t)items.size();
+            if (!make_bands(pr, (int)r, p->N[r], levels, W, items))
+                return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", levels, W);
+        }
+        first[pr.R] = (int32_t)items.size();
+        n_parts = (int64_t)items.size();
     }
-    first[pr.R] = (int32_t)items.size();
     if (items.size() > (size_t)INT32_MAX) return fail(p, CTQW_ERR_OUT_OF_MEMORY, "too many work items");
     std::vector<int32_t> ord(items.size());
     std::vector<int64_t> cost(items.size());
@@ -253,8 +265,8 @@ ctqw_status build_tables(ctqw_plan* p) {
     align_region(L, L.Jf, p->param_total * 4);
     align_region(L, L.Ef, p->param_total * 4);
     align_region(L, L.scale, R * 8);
-    align_region(L, L.norm_part, nit * 8);
-    align_region(L, L.tail_part, nit * 8);
+    align_region(L, L.norm_part, n_parts * 8);
+    align_region(L, L.tail_part, n_parts * 8);
     align_region(L, L.norm2, R * 8);
     align_region(L, L.tail2, R * 8);
     align_region(L, L.status, 16);
@@ -268,7 +280,16 @@ ctqw_status build_tables(ctqw_plan* p) {
     align_region(L, L.gout, G * 8);
     align_region(L, L.obs, p->obs_per_snapshot * 8);
     align_region(L, L.sites, R * pr.m * 4);
+    if (pr.m == 3) {
+        // term buffers (two for Phi, one for the compensation) and marginals
+        const int64_t sb = p->state_off.back() * (pr.dtype == CTQW_C128 ? 16 : 8);
+        const int64_t NN = (int64_t)p->max_N * p->max_N;
+        align_region(L, L.s3, 3 * ((sb + 255) & ~int64_t(255)));
+        align_region(L, L.M3, R * 3 * NN * 8);
+        align_region(L, L.occ3, G * NN * 8);
+    }
     L.total = (L.total + 255) & ~int64_t(255);
+    p->n_parts = n_parts;
     p->lay = L;
     p->tables_dirty = true;
     p->drop_graphs();
@@ -285,7 +306,8 @@ ctqw_status upload_tables(ctqw_plan* p) {
         RealDev& d = reals[r];
         d.state_off = p->state_off[r];
         d.N = p->N[r];
-        d.rows = pr.m == 1 ? 1 : p->N[r];
+        // grid rows of N amplitudes: 1 (one particle), N (two), N^2 (three)
+        d.rows = pr.m == 1 ? 1 : (pr.m == 3 ? p->N[r] * p->N[r] : p->N[r]);
         // Every realisation of the batch takes the batch's order (at least its
         // own a-priori order), so the pipeline has no per-realisation depth.
         const int n = p->levels;
@@ -370,7 +392,81 @@ ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
     return CTQW_OK;
 }
 
+ctqw_status record_event(ctqw_plan* p, int which) {
+    if (which == 0 && p->ev_used + 2 > p->ev.size()) {
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t e;
+            HIP_TRY(p, hipEventCreate(&e));
+            p->ev.push_back(e);
+        }
+    }
+    HIP_TRY(p, hipEventRecord(p->ev[p->ev_used + which], p->stream));
+    if (which == 1) p->ev_used += 2;
+    return CTQW_OK;
+}
+
+ctqw_status enqueue_finalize(ctqw_plan* p) {
+    const Layout& L = p->lay;
+    FinalizeArgs f{};
+    f.item_first = at<int32_t>(p, L.item_first);
+    f.norm_part = at<double>(p, L.norm_part);
+    f.tail_part = at<double>(p, L.tail_part);
+    f.reals = at<RealDev>(p, L.reals);
+    f.norm2 = at<double>(p, L.norm2);
+    f.tail2 = at<double>(p, L.tail2);
+    f.scale = at<double>(p, L.scale);
+    f.status = at<int32_t>(p, L.status);
+    f.R = p->prob.R;
+    f.tol2 = p->prob.taylor_tol > 0 ? p->prob.taylor_tol * p->prob.taylor_tol : 0.0;
+    f.norm_alarm = p->prob.norm_alarm;
+    f.renormalize = p->prob.renormalize;
+    HIP_TRY(p, launch_finalize(f, p->stream));
+    return CTQW_OK;
+}
+
+// Three particles: n one-term passes from psi[cur] into psi[1-cur] (the sum),
+// Phi ping-ponging through two workspace buffers.
+ctqw_status enqueue_step3(ctqw_plan* p) {
+    const Layout& L = p->lay;
+    const ctqw_problem& pr = p->prob;
+    const int dtype = pr.dtype == CTQW_C128 ? 1 : 0;
+    const int64_t sb = (p->state_off.back() * (dtype ? 16 : 8) + 255) & ~int64_t(255);
+    uint8_t* s3 = p->ws + L.s3.off;
+    Step3Args a{};
+    a.acc = p->psi[1 - p->cur];
+    a.comp = s3 + 2 * sb;
+    a.reals = at<RealDev>(p, L.reals);
+    a.Jt = dtype ? static_cast<const void*>(at<double>(p, L.Jd)) : static_cast<const void*>(at<float>(p, L.Jf));
+    a.Et = dtype ? static_cast<const void*>(at<double>(p, L.Ed)) : static_cast<const void*>(at<float>(p, L.Ef));
+    a.scale = at<double>(p, L.scale);
+    a.norm_part = at<double>(p, L.norm_part);
+    a.tail_part = at<double>(p, L.tail_part);
+    a.dt = pr.dt;
+    a.R = pr.R;
+    a.blocks_per_real = term3d_blocks_per_real(p->N[0]);
+    const int kahan = (!dtype && pr.accumulation == CTQW_ACC_KAHAN) ? 1 : 0;
+    ctqw_status st;
+    if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
+    const void* in = p->psi[p->cur];
+    for (int j = 1; j <= p->levels; ++j) {
+        a.phi_in = in;
+        a.phi_out = s3 + (j & 1) * sb;
+        a.inv_j = 1.0 / j;
+        a.first = j == 1;
+        a.last = j == p->levels;
+        HIP_TRY(p, launch_term3d(a, kahan, dtype, p->N[0], p->stream));
+        in = a.phi_out;
+    }
+    if (p->timing && (st = record_event(p, 1)) != CTQW_OK) return st;
+    if ((st = enqueue_finalize(p)) != CTQW_OK) return st;
+    p->cur = 1 - p->cur;
+    p->steps_done += 1;
+    p->have_step_stats = true;
+    return CTQW_OK;
+}
+
 ctqw_status enqueue_step(ctqw_plan* p) {
+    if (p->prob.m == 3) return enqueue_step3(p);
     const Layout& L = p->lay;
     StepConfig c = step_config(p);
     int n_waves = 0;
@@ -393,35 +489,10 @@ ctqw_status enqueue_step(ctqw_plan* p) {
     a.tail_part = at<double>(p, L.tail_part);
     a.dt = p->prob.dt;
     a.persistent = c.persistent;
-    if (p->timing) {
-        if (p->ev_used + 2 > p->ev.size()) {
-            for (int k = 0; k < 2; ++k) {
-                hipEvent_t e;
-                HIP_TRY(p, hipEventCreate(&e));
-                p->ev.push_back(e);
-            }
-        }
-        HIP_TRY(p, hipEventRecord(p->ev[p->ev_used], p->stream));
-    }
+    if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
     HIP_TRY(p, launch_step(c, a, p->stream));
-    if (p->timing) {
-        HIP_TRY(p, hipEventRecord(p->ev[p->ev_used + 1], p->stream));
-        p->ev_used += 2;
-    }
-    FinalizeArgs f{};
-    f.item_first = at<int32_t>(p, L.item_first);
-    f.norm_part = a.norm_part;
-    f.tail_part = a.tail_part;
-    f.reals = a.reals;
-    f.norm2 = at<double>(p, L.norm2);
-    f.tail2 = at<double>(p, L.tail2);
-    f.scale = at<double>(p, L.scale);
-    f.status = at<int32_t>(p, L.status);
-    f.R = p->prob.R;
-    f.tol2 = p->prob.taylor_tol > 0 ? p->prob.taylor_tol * p->prob.taylor_tol : 0.0;
-    f.norm_alarm = p->prob.norm_alarm;
-    f.renormalize = p->prob.renormalize;
-    HIP_TRY(p, launch_finalize(f, p->stream));
+    if (p->timing && (st = record_event(p, 1)) != CTQW_OK) return st;
+    if ((st = enqueue_finalize(p)) != CTQW_OK) return st;
     p->cur = 1 - p->cur;
     p->steps_done += 1;
     p->have_step_stats = true;
@@ -430,6 +501,7 @@ ctqw_status enqueue_step(ctqw_plan* p) {
 
 // One step kernel from `in` to `out` (no monitoring), for recomputation.
 ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
+    if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "recomputation is built for one and two particles");
     const Layout& L = p->lay;
     StepConfig c = step_config(p);
     int n_waves = 0;
@@ -512,6 +584,25 @@ ctqw_status enqueue_steps(ctqw_plan* p, int64_t count) {
 
 ctqw_status enqueue_observe(ctqw_plan* p, int want_pair) {
     const Layout& L = p->lay;
+    if (p->prob.m == 3) {
+        Obs3Args o{};
+        o.psi = p->psi[p->cur];
+        o.reals = at<RealDev>(p, L.reals);
+        o.scale = at<double>(p, L.scale);
+        o.M = at<double>(p, L.M3);
+        o.occ_terms = at<double>(p, L.occ3);
+        o.group_members = at<int32_t>(p, L.gmembers);
+        o.group_first = at<int32_t>(p, L.gfirst);
+        o.group_N = at<int32_t>(p, L.gN);
+        o.group_out = at<int64_t>(p, L.gout);
+        o.out = at<double>(p, L.obs);
+        o.R = p->prob.R;
+        o.G = (int32_t)p->group_N.size();
+        o.max_N = p->max_N;
+        o.want_pair = want_pair;
+        HIP_TRY(p, launch_obs3(o, p->prob.dtype == CTQW_C128 ? 1 : 0, p->stream));
+        return CTQW_OK;
+    }
     ObsArgs o{};
     o.psi = p->psi[p->cur];
     o.reals = at<RealDev>(p, L.reals);
@@ -644,7 +735,10 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         return fail(nullptr, CTQW_ERR_INVALID_ARG, "set n_sites or n_sites_per_real");
     if (pr->n_sites < 0) return fail(nullptr, CTQW_ERR_INVALID_ARG, "n_sites must be >= 0");
     if (pr->R > 65535) return fail(nullptr, CTQW_ERR_UNSUPPORTED, "at most 65535 realisations per plan");
-    if (pr->m == 3) return fail(nullptr, CTQW_ERR_UNSUPPORTED, "three particles are not built yet");
+    if (pr->m == 3 && pr->statistics != CTQW_DISTINGUISHABLE)
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "three bosons are not built");
+    if (pr->m == 3 && (pr->n_sites <= 0 || pr->n_sites > 1024))
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "three particles need one lattice size N <= 1024");
     if (pr->statistics == CTQW_BOSON && pr->m != 2 && pr->m != 1)
         return fail(nullptr, CTQW_ERR_UNSUPPORTED, "bosons are built for m == 2");
     if (pr->statistics == CTQW_BOSON && pr->m == 2 && pr->boundary == CTQW_PERIODIC)
@@ -842,8 +936,9 @@ ctqw_status ctqw_sizes(const ctqw_plan* p, int64_t* state_bytes, int64_t* worksp
 ctqw_status ctqw_work_items(const ctqw_plan* p, int64_t* items, int64_t* waves) {
     if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
     if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
-    if (items) *items = (int64_t)p->items.size();
-    if (waves) *waves = (int64_t)p->items.size();
+    const int64_t n = p->prob.m == 3 ? p->n_parts : (int64_t)p->items.size();
+    if (items) *items = n;
+    if (waves) *waves = p->prob.m == 3 ? n * 4 : n;
     return CTQW_OK;
 }
 
@@ -1129,6 +1224,14 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
     if (steps < 1) return fail(p, CTQW_ERR_INVALID_ARG, "steps must be >= 1");
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
+    if (p->prob.m == 3) {
+        // one launch shape only: report its time
+        double ms = 0.0;
+        if ((st = time_steps(p, steps, &ms)) != CTQW_OK) return st;
+        if (best_out) *best_out = p->launch;
+        if (best_ms_out) *best_ms_out = ms;
+        return CTQW_OK;
+    }
     const char* path = cache_path ? cache_path : getenv("CTQW_TUNE_CACHE");
     const std::string key = tune_key(p);
     const ctqw_launch orig = p->launch;
@@ -1246,6 +1349,7 @@ ctqw_status ctqw_forward_ckpt(ctqw_plan* p, int64_t n_steps, int64_t ckpt_every,
     if (p->prob.renormalize) return fail(p, CTQW_ERR_UNSUPPORTED, "gradients need renormalize == 0 (a linear map)");
     if (p->group_N.size() != 1)
         return fail(p, CTQW_ERR_UNSUPPORTED, "gradients with respect to shared baselines need one lattice size");
+    if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "gradients are built for one and two particles");
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
     const GradLayout g = grad_layout(p, n_steps, ckpt_every);
@@ -1418,6 +1522,7 @@ ctqw_status ctqw_loss(ctqw_plan* p, int32_t kind, const double* site_w, void* gw
     if (kind != CTQW_LOSS_ONE_BODY && kind != CTQW_LOSS_PRODUCT)
         return fail(p, CTQW_ERR_INVALID_ARG, "unknown loss kind %d", kind);
     if (p->group_N.size() != 1) return fail(p, CTQW_ERR_UNSUPPORTED, "the loss needs one lattice size");
+    if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "the loss is built for one and two particles");
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
     const GradLayout g = grad_layout(p, 0, 1);

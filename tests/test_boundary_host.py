@@ -53,7 +53,8 @@ def status_of(fn):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(m=0), 1), (dict(m=4), 1), (dict(m=3), 2),
+    (dict(m=0), 1), (dict(m=4), 1), (dict(m=3, statistics="boson"), 2), (dict(m=3, n_sites=[8, 8, 9]), 2),
+    (dict(m=3, n_sites=2000), 2),
     (dict(n_sites=1), 1), (dict(R=0), 1),
     (dict(dt=0.0), 1), (dict(dt=float("nan")), 1), (dict(dt=-1.0), 1),
     (dict(taylor_tol=0.0), 1),
