@@ -59,8 +59,10 @@ typedef enum { CTQW_INT_ONSITE = 0, CTQW_INT_NEAREST = 1 } ctqw_interaction;
 /* State precision: interleaved complex FP32 or FP64 (torch.complex64/128). */
 typedef enum { CTQW_C64 = 0, CTQW_C128 = 1 } ctqw_dtype;
 /* Summation of the Taylor terms within one step.  KAHAN: compensated
- * (Kahan) accumulation of sum_j Phi^(j); PLAIN: ordinary accumulation.  The
- * FP64 state always uses PLAIN.                                           */
+ * accumulation of sum_j Phi^(j) in a word pair (a, c) worth a - c: Kahan's
+ * update adds the leading term Phi^(1) to psi exactly, the later (smaller)
+ * terms are collected in c, and a - c is rounded once on output.  PLAIN:
+ * ordinary accumulation.  The FP64 state always uses PLAIN.              */
 typedef enum { CTQW_ACC_KAHAN = 0, CTQW_ACC_PLAIN = 1 } ctqw_accumulation;
 
 /* Observables (bit mask).  OCCUPATION: <n_i> = sum_x p(x) #{a : x_a = i},
@@ -71,7 +73,8 @@ typedef enum { CTQW_ACC_KAHAN = 0, CTQW_ACC_PLAIN = 1 } ctqw_accumulation;
 #define CTQW_OBS_PAIR 2u
 
 typedef struct {
-    int32_t m;               /* particles: 1 or 2 (3: CTQW_ERR_UNSUPPORTED) */
+    int32_t m;               /* particles: 1, 2 or 3 (3: distinguishable, equal
+                                N_r <= 1024, no gradients)                 */
     int32_t statistics;      /* ctqw_statistics; BOSON needs m == 2 and OPEN */
     int32_t interaction;     /* ctqw_interaction */
     int32_t boundary;        /* ctqw_boundary; PERIODIC needs N >= 3 */
@@ -153,6 +156,7 @@ ctqw_status ctqw_orders(const ctqw_plan* plan, int32_t* orders);
  *                          N_r (N_r + 1) / 2 amplitudes.  In the normalised
  *                          symmetric basis the coefficient of |x1 x2> is
  *                          sqrt(2) phi for x1 < x2 and phi for x1 == x2.
+ *   m = 3 distinguishable: psi[x1][x2][x3], x3 fastest, N_r^3 amplitudes.
  * offsets: [R + 1], in amplitudes; offsets[R] is the total.                */
 ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
 

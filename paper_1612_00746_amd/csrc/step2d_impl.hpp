@@ -97,6 +97,10 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Wave-uniform tables (row couplings) are read through the constant address
+// space so that they land in scalar registers.
+template <typename T> using UniformPtr = const __attribute__((address_space(4))) T*;
+
 template <typename T, int NT, int P, bool KAHAN, bool TRI>
 __device__ __forceinline__ void process_item(const StepArgs& a, int home, int lane) {
     using C = typename CplxOf<T>::type;
@@ -112,14 +116,15 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     // J and eps below are scaled by dt (host tables).
     const T* __restrict__ Jc = jpar<T>(a) + rd.param_off;
     const T* __restrict__ Ec = epar<T>(a) + rd.param_off;
-    const T* __restrict__ Jr_ = jpar<T>(a) + rd.row_param_off;
-    const T* __restrict__ Er_ = epar<T>(a) + rd.row_param_off;
+    const UniformPtr<T> Jr = (UniformPtr<T>)(jpar<T>(a) + rd.row_param_off);
+    const UniformPtr<T> Er = (UniformPtr<T>)(epar<T>(a) + rd.row_param_off);
     const C* __restrict__ in = reinterpret_cast<const C*>(a.psi_in) + rd.state_off;
     C* __restrict__ out = reinterpret_cast<C*>(a.psi_out) + rd.state_off;
     const T sc = static_cast<T>(a.scale[it.real]);
     const T Udt = static_cast<T>(rd.U * a.dt);
 
-    // Columns held by this lane.
+    // Columns held by this lane.  Lanes outside [0, N) of an open chain hold
+    // zeros with zero couplings, so they stay zero at every level.
     int col[P], colw[P];
     bool inb[P], outv[P];
     T jl[P], jr[P], ec[P];
@@ -137,26 +142,27 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         ec[p] = inb[p] ? Ec[cs] : T(0);
     }
 
-    // Row of the grid (wrapped on a ring) -> its stored amplitudes.
+    // Row of the grid (wrapped on a ring) -> its stored amplitudes.  The
+    // loads are unconditional (lanes without a stored amplitude read the
+    // realisation's first one) so that the prefetch never waits; the mask is
+    // applied when the row is consumed.
     auto load_row = [&](int qm, C (&dst)[P]) {
         const int base = TRI ? qm * N - (qm * (qm + 1)) / 2 : qm * N;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const bool ok = inb[p] && (!TRI || col[p] >= qm);
-            C v;
-            v.x = T(0);
-            v.y = T(0);
-            if (ok) v = in[ok ? base + colw[p] : 0];
-            dst[p] = v;
+            dst[p] = in[ok ? base + colw[p] : 0];
         }
     };
+    auto row_mask = [&](int qm, int p) { return inb[p] && (!TRI || col[p] >= qm); };
 
     T fr[NT][3][P], fi[NT][3][P];   // Psi_j rows, j < NT
-    T ar[WA][P], ai[WA][P];         // partial sums of rows in flight
-    T cr[WA][P], ci[WA][P];         // Kahan compensations
-    T dg[WA][P];                    // dt * diagonal of H on rows in flight
-    T ju[WA];                       // dt * bond above each row in flight
+    T ar[WA][P], ai[WA][P];         // partial sums of the rows in flight
+    T cr[WA][P], ci[WA][P];         // compensation words (KAHAN)
+    T dg[WA][P];                    // dt * diagonal of H on the rows in flight
+    T ju[WA];                       // dt * bond above each row in flight (uniform)
     C pre[3][P];                    // rows being fetched
+    T pj[3], pe[3];                 // their bond above and row energy (uniform)
 #pragma unroll
     for (int j = 0; j < NT; ++j)
 #pragma unroll
@@ -172,63 +178,70 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         }
     }
     // Grid rows are tracked incrementally: qm_in is the row entering at the
-    // current iteration, qm_prev the one before it (its bond joins the two),
-    // qm_pf the row being prefetched three iterations ahead.
+    // current iteration, qm_pf the one being prefetched three iterations ahead.
     auto next_row = [&](int x) { return (x + 1 == rows) ? 0 : x + 1; };
+    auto fetch = [&](int qm, int s) {
+        load_row(qm, pre[s]);
+        pj[s] = Jr[qm == 0 ? rows - 1 : qm - 1];   // the padded last bond is 0 on an open chain
+        pe[s] = Er[qm];
+    };
     int qm_in = periodic ? wrap(it.row0, rows) : it.row0;
-    int qm_prev = wrap(qm_in - 1, rows);
     int qm_pf = qm_in;
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        if (s < nrows) load_row(qm_pf, pre[s]);
+    for (int s = 0; s < 3; ++s) {   // rows past the sweep are fetched and ignored
+        fetch(qm_pf, s);
         qm_pf = next_row(qm_pf);
     }
 
+    // Norm weights of this lane's outputs (full grid: 1 on the band's output
+    // columns; triangle: 2 off the diagonal, set per row).
+    double wcol[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) wcol[p] = outv[p] ? 1.0 : 0.0;
+
     double nrm = 0.0, tail = 0.0;
+    // The sweep runs nrows + NT iterations, rounded up to whole unrolled
+    // blocks: the extra iterations see zero rows and store nothing, and the
+    // block body has no early exit (which keeps the prefetch waits exact).
     const int total = nrows + NT;
 
     for (int i0 = 0; i0 < total; i0 += WA) {
 #pragma unroll
         for (int u = 0; u < WA; ++u) {
             const int i = i0 + u;
-            if (i < total) {
-                // ---- level 0: row i enters (zero beyond the sweep).
+            {
+                // ---- level 0: row i enters (zero beyond the sweep).  The
+                // bond above a row beyond the sweep is 0, so nothing flows
+                // back from there.
                 {
                     const int s = u % 3;
-                    if (i < nrows) {
-                        C v[P];
+                    const bool live = i < nrows;
+                    const int qm = qm_in;
+                    C v[P];
 #pragma unroll
-                        for (int p = 0; p < P; ++p) v[p] = pre[s][p];
-                        if (i + 3 < nrows) load_row(qm_pf, pre[s]);
-                        const int qm = qm_in;
-                        ju[u] = Jr_[qm_prev];
-                        const T er = Er_[qm];
-#pragma unroll
-                        for (int p = 0; p < P; ++p) {
-                            const T re = v[p].x * sc, im = v[p].y * sc;
-                            fr[0][s][p] = re;
-                            fi[0][s][p] = im;
-                            ar[u][p] = re;
-                            ai[u][p] = im;
-                            if (KAHAN) {
-                                cr[u][p] = T(0);
-                                ci[u][p] = T(0);
-                            }
-                            T vint = T(0);
-                            if (rows > 1) {
-                                int d = qm - colw[p];
-                                d = d < 0 ? -d : d;
-                                if (periodic && N - d < d) d = N - d;
-                                vint = (d == (nearest ? 1 : 0)) ? Udt : T(0);
-                            }
-                            dg[u][p] = inb[p] ? er + ec[p] + vint : T(0);
-                        }
-                    } else {
-                        ju[u] = T(0);
-#pragma unroll
-                        for (int p = 0; p < P; ++p) { fr[0][s][p] = T(0); fi[0][s][p] = T(0); }
+                    for (int p = 0; p < P; ++p) {
+                        v[p] = pre[s][p];
+                        if (!(live && row_mask(qm, p))) { v[p].x = T(0); v[p].y = T(0); }
                     }
-                    qm_prev = qm_in;
+                    const T er = pe[s];
+                    ju[u] = live ? pj[s] : T(0);
+                    fetch(qm_pf, s);
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const T re = v[p].x * sc, im = v[p].y * sc;
+                        fr[0][s][p] = re;
+                        fi[0][s][p] = im;
+                        ar[u][p] = re;
+                        ai[u][p] = im;
+                        T vint = T(0);
+                        if (rows > 1) {
+                            int d = qm - colw[p];
+                            d = d < 0 ? -d : d;
+                            if (periodic && N - d < d) d = N - d;
+                            vint = (d == (nearest ? 1 : 0)) ? Udt : T(0);
+                        }
+                        dg[u][p] = er + ec[p] + vint;
+                    }
                     qm_in = next_row(qm_in);
                     qm_pf = next_row(qm_pf);
                 }
@@ -287,26 +300,31 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         T pi_ = hr;
                         if (TRI && low) { pr_ = T(0); pi_ = T(0); }
                         if (j < NT) { fr[j % NT][sm][p] = pr_; fi[j % NT][sm][p] = pi_; }
-                        if (KAHAN) {
-                            const T yr = cr_j * pr_ - cr[w][p];
-                            const T tr = ar[w][p] + yr;
+                        if (KAHAN && j == 1) {
+                            // Kahan's update on the leading term: (a, c) with
+                            // a - c = psi + Phi^(1) exactly.
+                            const T yr = cr_j * pr_, yi = ci_j * pi_;   // cr_1, ci_1 = +-1
+                            const T tr = ar[w][p] + yr, ti = ai[w][p] + yi;
                             cr[w][p] = (tr - ar[w][p]) - yr;
-                            ar[w][p] = tr;
-                            const T yi = ci_j * pi_ - ci[w][p];
-                            const T ti = ai[w][p] + yi;
                             ci[w][p] = (ti - ai[w][p]) - yi;
+                            ar[w][p] = tr;
                             ai[w][p] = ti;
+                        } else if (KAHAN) {
+                            // Later terms are smaller than the leading one by
+                            // x/2 or more: they are collected in the low word.
+                            cr[w][p] -= cr_j * pr_;
+                            ci[w][p] -= ci_j * pi_;
                         } else {
                             ar[w][p] += cr_j * pr_;
                             ai[w][p] += ci_j * pi_;
                         }
                         if (j == NT) {
                             const int q = i - NT;
-                            const bool rowok = q >= 0 && qa >= it.out_lo && qa < it.out_hi;
-                            if (rowok && outv[p] && (!TRI || col[p] >= qa)) {
-                                const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
+                            if (q >= 0 && qa >= it.out_lo && qa < it.out_hi) {
+                                double wgt = wcol[p];
+                                if (TRI) wgt = (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
                                 const double dr = pr_, di = pi_;
-                                tail += wgt * (dr * dr + di * di);
+                                tail = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), tail);
                             }
                         }
                     }
@@ -320,15 +338,14 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         const int base = TRI ? qa * N - (qa * (qa + 1)) / 2 : qa * N;
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
-                            if (outv[p] && (!TRI || col[p] >= qa)) {
-                                C v;
-                                v.x = ar[w][p];
-                                v.y = ai[w][p];
-                                out[base + colw[p]] = v;
-                                const double wgt = (TRI && col[p] != qa) ? 2.0 : 1.0;
-                                const double dr = v.x, di = v.y;
-                                nrm += wgt * (dr * dr + di * di);
-                            }
+                            C v;
+                            v.x = KAHAN ? ar[w][p] - cr[w][p] : ar[w][p];
+                            v.y = KAHAN ? ai[w][p] - ci[w][p] : ai[w][p];
+                            if (outv[p] && (!TRI || col[p] >= qa)) out[base + colw[p]] = v;
+                            double wgt = wcol[p];
+                            if (TRI) wgt = (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
+                            const double dr = v.x, di = v.y;
+                            nrm = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), nrm);
                         }
                     }
                 }

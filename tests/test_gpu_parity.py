@@ -311,6 +311,37 @@ def test_c64_against_oracle(acc):
         assert np.max(np.abs(np.sqrt(n2) - 1)) < 1e-5
 
 
+def test_compensated_sum_against_plain():
+    """Rounding of the Taylor sum in complex64: 400 steps at a fixed order 7
+    against the oracle's FP64 map of the same order (so that truncation
+    cancels and only rounding is left).  The compensated sum keeps the norm
+    drift and the amplitude error below those of plain summation (an FP32
+    emulation of both sums predicts about 13x less norm drift and 2x less
+    amplitude error)."""
+    N, steps, dt = 48, 400, 0.05
+    g = np.random.default_rng(21)
+    reals = [(N, 1 + 0.1 * g.standard_normal(N - 1), np.zeros(N), 3.0) for _ in range(2)]
+    say(f"case: compensated vs plain sum, N={N}, {steps} steps, order 7")
+    res = {}
+    for acc in ("kahan", "plain"):
+        plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
+                        accumulation=acc, reals=reals, dt=dt, order=7, sites=[N // 2 - 1, N // 2])
+        plan.propagate(steps)
+        psi = plan.state_numpy()
+        err, drift = 0.0, 0.0
+        for r, (n, J, eps, U) in enumerate(reals):
+            H = oracle_H(N, 2, B.DISTINGUISHABLE, "open", "onsite", J, eps, U)
+            ref, _, _ = P.evolve_taylor(H, B.product_state(N, [N // 2 - 1, N // 2]), dt, steps, order=7)
+            got = gpu_to_oracle(psi[r * N * N:(r + 1) * N * N], N, 2, B.DISTINGUISHABLE)
+            err = max(err, float(np.max(np.abs(got - ref))))
+            drift = max(drift, abs(float(np.vdot(got, got).real) - float(np.vdot(ref, ref).real)))
+        res[acc] = (err, drift)
+        say(f"  {acc}: amplitude error {err:.2e}, norm drift {drift:.2e}")
+    assert res["kahan"][0] < 1e-6 and res["plain"][0] < 2e-6
+    assert res["kahan"][1] < 0.5 * res["plain"][1]
+    assert res["kahan"][0] < res["plain"][0]
+
+
 # ------------------------------------------------------ monitoring / errors
 
 def test_norm_alarm_raised_from_corrupted_state():
