@@ -19,11 +19,25 @@ is resident in HBM before the timed region.  The same JSON line carries
     per-step tolerance, one regular launch per step;
   * cpu_baseline: the FP64 oracle (CSR Taylor propagator) timed on a bounded
     sample of the same workload on the host cores.
+
+The timed region replays the captured step loop (one persistent launch of
+the step kernel per step, plus the FP64 finalize).  The step kernel's
+duration is taken from HIP events on the plan's stream around each replay,
+divided by its steps: it includes the ~7 us finalize kernel per step, so
+`roofline.achieved` is a slight underestimate (the rocprofv3 kernel average
+under profiles/ gives the kernel alone).
+
+`roofline.traffic` is the HBM traffic per launch from rocprofv3 counters,
+read from the summary under profiles/ that `--profile-summary` writes; it is
+reported only while the step kernel's sources hash to the value recorded
+there (null otherwise).
 """
 
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -93,6 +107,106 @@ def cpu_baseline(w, budget_s: float = 10.0):
             "seconds": round(wall, 2)}
 
 
+# ------------------------------------------------------ profile summaries
+
+KERNEL_SOURCES = ("paper_1612_00746_amd/csrc/step2d_impl.hpp", "paper_1612_00746_amd/csrc/ctqw_internal.hpp",
+                  "paper_1612_00746_amd/csrc/step2d_dispatch.hip")
+SUMMARY = os.path.join(ROOT, "profiles", "step2d_kernel_C3_c64_kahan.md")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per step-kernel launch from the committed counter summary,
+    if it was taken on the current kernel sources."""
+    try:
+        text = open(SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("kernel-source-sha256:", "traffic-bytes:")))
+    if fields.get("kernel-source-sha256", "").strip() != kernel_source_hash():
+        return None
+    try:
+        return int(fields["traffic-bytes"].strip())
+    except (KeyError, ValueError):
+        return None
+
+
+def _rows(path):
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY):
+    """Write the step kernel's rocprofv3 summary: duration statistics from
+    the kernel trace, FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the
+    same counters read for the 4 GiB device copy of the same run."""
+    def find(d, suffix):
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith(suffix):
+                    return os.path.join(root, f)
+        raise FileNotFoundError(f"{suffix} under {d}")
+    stats = [r for r in _rows(find(trace_dir, "kernel_stats.csv")) if "step2d_kernel<float" in r["Name"]]
+    if len(stats) != 1:
+        raise SystemExit("expected one complex64 step kernel in the trace")
+    st = stats[0]
+    probe_bytes = 4096 << 20
+
+    def counter(d, name):
+        rows = [r for r in _rows(find(d, "counter_collection.csv")) if r["Counter_Name"] == name]
+        k = [float(r["Counter_Value"]) for r in rows if "step2d_kernel<float" in r["Kernel_Name"]]
+        c = [float(r["Counter_Value"]) for r in rows
+             if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 100000]
+        if not k or not c:
+            raise SystemExit(f"{name}: no step kernel or copy probe dispatches in {d}")
+        return sum(k) / len(k), sum(c) / len(c)
+    fk, fc = counter(fetch_dir, "FETCH_SIZE")
+    wk, wc = counter(write_dir, "WRITE_SIZE")
+    f_scale = probe_bytes / (fc * 1024.0)
+    w_scale = probe_bytes / (wc * 1024.0)
+    fetch_b = fk * 1024.0 * f_scale
+    write_b = wk * 1024.0 * w_scale
+    lines = [
+        f"# {st['Name']}",
+        "",
+        "Workload: 4096 realisations of two distinguishable walkers on open chains,",
+        "N uniform in {64, 96, ..., 1024}, U ~ U[0, 4], J ~ N(1, 0.1^2), dt = 0.05,",
+        "Taylor tolerance 1e-7 (7 terms), complex64 with the compensated sum;",
+        "persistent launch, P = 1, 4 waves per block, captured step loop.",
+        "",
+        "Commands (from the repository root, TMPDIR=/tmp):",
+        "",
+        *[f"    {c}" for c in commands],
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        f"| dispatches traced | {st['Calls']} |",
+        f"| average duration | {float(st['AverageNs']) / 1e6:.4f} ms |",
+        f"| min / max duration | {float(st['MinNs']) / 1e6:.4f} / {float(st['MaxNs']) / 1e6:.4f} ms |",
+        f"| FETCH_SIZE per dispatch | {fk:.0f} KiB |",
+        f"| FETCH_SIZE of the 4 GiB copy probe | {fc:.0f} KiB (scale {f_scale:.4f}) |",
+        f"| WRITE_SIZE per dispatch | {wk:.0f} KiB |",
+        f"| WRITE_SIZE of the 4 GiB copy probe | {wc:.0f} KiB (scale {w_scale:.4f}) |",
+        f"| HBM bytes read per launch | {fetch_b / 1e9:.3f} GB |",
+        f"| HBM bytes written per launch | {write_b / 1e9:.3f} GB |",
+        "",
+        f"kernel-source-sha256: {kernel_source_hash()}",
+        f"traffic-bytes: {int(round(fetch_b + write_b))}",
+        "",
+    ]
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print(f"wrote {out}")
+
+
 # ---------------------------------------------------------------- GPU side
 
 def build_plan(w, dtype, accumulation, launch, tol):
@@ -115,18 +229,26 @@ def build_plan(w, dtype, accumulation, launch, tol):
 
 
 def time_plan(plan, steps, warmup):
+    """Wall time of `steps` steps and the step kernel's average duration from
+    HIP events on the plan's stream.  A captured step loop is captured (for
+    both starting buffers when `steps` is odd) before the timed region."""
     import torch
     plan.propagate(warmup)
-    torch.cuda.synchronize()
     plan.set_timing(True)
+    if plan.get_launch().use_graph:
+        for _ in range(1 if steps % 2 == 0 else 2):
+            plan.propagate(steps)
     torch.cuda.synchronize()
+    plan.set_timing(True)                      # reset the counters
     t0 = time.perf_counter()
     plan.propagate(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms, launches = plan.get_timing()
     plan.set_timing(False)
-    return wall, kern_ms / max(launches, 1)
+    if launches != steps:
+        raise RuntimeError(f"timed {launches} step kernels for {steps} steps")
+    return wall, kern_ms / launches
 
 
 def main():
@@ -141,7 +263,15 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM counters)")
+    ap.add_argument("--regular", action="store_true", help="one wave per work item instead of the persistent grid")
+    ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the step kernel's rocprofv3 summary under profiles/ and exit")
+    ap.add_argument("--profile-command", action="append", default=[],
+                    help="command line recorded in the profile summary (repeatable)")
     a = ap.parse_args()
+    if a.profile_summary:
+        profile_summary(*a.profile_summary, commands=a.profile_command)
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: realisations are independent, and a multi-GPU run would "
               "shard them with one all-reduce of the FP64 observables; only --gpus 1 is built.",
@@ -175,7 +305,8 @@ def main():
         del src, dst
     sizes = w.lattice_sizes()
     amps = int(np.sum(sizes.astype(np.int64) ** 2))
-    launch = {"cols_per_lane": a.cols_per_lane, "persistent": 1, "waves_per_block": 4}
+    launch = {"cols_per_lane": a.cols_per_lane, "persistent": 0 if a.regular else 1, "waves_per_block": 4,
+              "use_graph": 1}
     log("building the complex64 plan ...")
     plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
     log("timing complex64 ...")
@@ -188,6 +319,7 @@ def main():
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
     orders = plan.orders()
     items, _ = plan.work_items()
+    traffic = recorded_traffic()
     del plan
     torch.cuda.empty_cache()
 
@@ -225,7 +357,7 @@ def main():
                    "accumulation": a.accumulation, "launch": launch, "work_items": items},
         "hbm_gbs_algorithmic": round(updates * 16.0 / 1e9, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "step2d_kernel", "kernel_ms": round(kern_ms, 4)},
         "fp64_plain": fp64,
         "speedup_fp32_batched_vs_fp64_plain": (round(updates / fp64["value"], 3) if fp64 else None),

@@ -212,7 +212,8 @@ ctqw_status ctqw_get_launch(const ctqw_plan* plan, ctqw_launch* out);
 ctqw_status ctqw_set_launch(ctqw_plan* plan, const ctqw_launch* launch);
 
 /* Number of work items (realisation x column band) of one step and the
- * number of waves that one step launches, for the current launch shape.  */
+ * number of waves that one step launches, for the current launch shape
+ * (persistent: the device's resident waves, known once bound).           */
 ctqw_status ctqw_work_items(const ctqw_plan* plan, int64_t* items, int64_t* waves);
 
 /* Derivatives of an ensemble-averaged diagonal observable.  The paper does
@@ -272,8 +273,10 @@ ctqw_status ctqw_autotune(ctqw_plan* plan, const char* cache_path, int32_t steps
 
 /* Kernel timing: with enable != 0, every step-kernel launch is bracketed by
  * HIP events on the bound stream and ctqw_get_timing returns the summed
- * elapsed time (ms) and the number of timed launches since timing was
- * (re-)enabled.  For measurement only; adds two event records per step.    */
+ * elapsed time (ms) and the number of timed steps since timing was
+ * (re-)enabled.  With use_graph the events bracket each replay of a captured
+ * step loop, which counts for its steps: the time then also holds the FP64
+ * finalize kernel of each step.  For measurement only.                    */
 ctqw_status ctqw_set_timing(ctqw_plan* plan, int32_t enable);
 ctqw_status ctqw_get_timing(ctqw_plan* plan, double* step_kernel_ms, int64_t* launches);
 

@@ -47,6 +47,7 @@ struct StepArgs {
     const RealDev* reals;
     const ItemDev* items;
     const int32_t* item_order;   // processing order (largest first)
+    int32_t* claim;              // persistent launch: claim counter, zero at launch
     int32_t n_items;
     int32_t n_waves;             // persistent launch: waves in the grid
     const double* Jd;
@@ -57,7 +58,7 @@ struct StepArgs {
     double* norm_part;           // [n_items] sum of w |psi_out|^2 of each item
     double* tail_part;           // [n_items] sum of w |Phi^(n)|^2 of each item
     double dt;
-    int32_t persistent;          // 1: grid of n_waves waves, items round-robin
+    int32_t persistent;          // 1: grid of n_waves waves claiming items
 };
 
 struct StepConfig {

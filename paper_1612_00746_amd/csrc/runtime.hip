@@ -40,8 +40,9 @@ struct Region {
 };
 
 struct Layout {
-    Region reals, items, order, item_first, Jd, Ed, Jf, Ef, scale, norm_part, tail_part, norm2,
-        tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites, s3, M3, occ3;
+    Region reals, items, order, item_first, claim, Jd, Ed, Jf, Ef, scale, norm_part,
+        tail_part, norm2, tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites,
+        s3, M3, occ3;
     int64_t total = 0;
 };
 
@@ -89,6 +90,7 @@ struct ctqw_plan {
     bool timing = false;
     std::vector<hipEvent_t> ev;      // pairs (start, stop) per timed launch
     size_t ev_used = 0;              // events recorded and not yet read
+    std::vector<int64_t> ev_steps;   // steps covered by each recorded pair
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     // captured step loops: (steps, starting buffer) -> executable graph
@@ -260,6 +262,7 @@ ctqw_status build_tables(ctqw_plan* p) {
     align_region(L, L.items, nit * (int64_t)sizeof(ItemDev));
     align_region(L, L.order, nit * 4);
     align_region(L, L.item_first, (R + 1) * 4);
+    align_region(L, L.claim, 4);   // persistent launch: item claim counter
     align_region(L, L.Jd, p->param_total * 8);
     align_region(L, L.Ed, p->param_total * 8);
     align_region(L, L.Jf, p->param_total * 4);
@@ -380,6 +383,9 @@ ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
         *n_waves = (int)p->items.size();
         return CTQW_OK;
     }
+    // claims count in units of 64 (one per lane) in an int32 counter
+    if ((int64_t)p->items.size() >= (int64_t(1) << 25))
+        return fail(p, CTQW_ERR_UNSUPPORTED, "persistent launch takes at most 2^25 work items per step");
     int per_cu = 0;
     HIP_TRY(p, step_occupancy(c, &per_cu));
     if (p->launch.waves_per_cu > 0) per_cu = std::max(1, p->launch.waves_per_cu / c.waves_per_block);
@@ -392,7 +398,9 @@ ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
     return CTQW_OK;
 }
 
-ctqw_status record_event(ctqw_plan* p, int which) {
+// Timing: an event pair around each step kernel (eager) or around each
+// replay of a captured step loop, which then counts for its `steps` steps.
+ctqw_status record_event(ctqw_plan* p, int which, int64_t steps = 1) {
     if (which == 0 && p->ev_used + 2 > p->ev.size()) {
         for (int k = 0; k < 2; ++k) {
             hipEvent_t e;
@@ -401,7 +409,11 @@ ctqw_status record_event(ctqw_plan* p, int which) {
         }
     }
     HIP_TRY(p, hipEventRecord(p->ev[p->ev_used + which], p->stream));
-    if (which == 1) p->ev_used += 2;
+    if (which == 1) {
+        p->ev_steps.resize(p->ev_used / 2 + 1);
+        p->ev_steps[p->ev_used / 2] = steps;
+        p->ev_used += 2;
+    }
     return CTQW_OK;
 }
 
@@ -478,6 +490,7 @@ ctqw_status enqueue_step(ctqw_plan* p) {
     a.reals = at<RealDev>(p, L.reals);
     a.items = at<ItemDev>(p, L.items);
     a.item_order = at<int32_t>(p, L.order);
+    a.claim = at<int32_t>(p, L.claim);
     a.n_items = (int32_t)p->items.size();
     a.n_waves = n_waves;
     a.Jd = at<double>(p, L.Jd);
@@ -489,6 +502,7 @@ ctqw_status enqueue_step(ctqw_plan* p) {
     a.tail_part = at<double>(p, L.tail_part);
     a.dt = p->prob.dt;
     a.persistent = c.persistent;
+    if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
     if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
     HIP_TRY(p, launch_step(c, a, p->stream));
     if (p->timing && (st = record_event(p, 1)) != CTQW_OK) return st;
@@ -513,6 +527,7 @@ ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
     a.reals = at<RealDev>(p, L.reals);
     a.items = at<ItemDev>(p, L.items);
     a.item_order = at<int32_t>(p, L.order);
+    a.claim = at<int32_t>(p, L.claim);
     a.n_items = (int32_t)p->items.size();
     a.n_waves = n_waves;
     a.Jd = at<double>(p, L.Jd);
@@ -524,16 +539,19 @@ ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
     a.tail_part = at<double>(p, L.tail_part);
     a.dt = p->prob.dt;
     a.persistent = c.persistent;
+    if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
     HIP_TRY(p, launch_step(c, a, p->stream));
     return CTQW_OK;
 }
+
+ctqw_status collect_timing(ctqw_plan* p);
 
 // Advance `count` steps.  With use_graph the sequence of (step, finalize)
 // launches is captured once per (steps, starting buffer) on a private
 // capture stream and the executable graph is replayed on the bound stream.
 ctqw_status enqueue_steps(ctqw_plan* p, int64_t count) {
     if (count <= 0) return CTQW_OK;
-    if (!p->launch.use_graph || p->timing || count < 2) {
+    if (!p->launch.use_graph || count < 2) {
         for (int64_t s = 0; s < count; ++s) {
             ctqw_status st = enqueue_step(p);
             if (st != CTQW_OK) return st;
@@ -550,6 +568,8 @@ ctqw_status enqueue_steps(ctqw_plan* p, int64_t count) {
             const int cur0 = p->cur;
             const int64_t done0 = p->steps_done;
             hipStream_t user = p->stream;
+            const bool timing = p->timing;
+            p->timing = false;               // no events inside the graph
             p->stream = p->cap_stream;
             hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
             ctqw_status st = CTQW_OK;
@@ -558,6 +578,7 @@ ctqw_status enqueue_steps(ctqw_plan* p, int64_t count) {
             hipGraph_t g = nullptr;
             const hipError_t e2 = (e == hipSuccess) ? hipStreamEndCapture(p->stream, &g) : e;
             p->stream = user;
+            p->timing = timing;
             p->cur = cur0;
             p->steps_done = done0;
             if (st != CTQW_OK) {
@@ -573,7 +594,10 @@ ctqw_status enqueue_steps(ctqw_plan* p, int64_t count) {
                 return fail(p, CTQW_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e3));
             found = p->graphs.emplace(key, ex).first;
         }
+        ctqw_status st;
+        if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
         HIP_TRY(p, hipGraphLaunch(found->second, p->stream));
+        if (p->timing && (st = record_event(p, 1, n)) != CTQW_OK) return st;
         p->cur ^= (int)(n & 1);
         p->steps_done += n;
         p->have_step_stats = true;
@@ -666,7 +690,7 @@ ctqw_status collect_timing(ctqw_plan* p) {
         float ms = 0.f;
         HIP_TRY(p, hipEventElapsedTime(&ms, p->ev[k], p->ev[k + 1]));
         p->timed_ms += ms;
-        p->timed_launches += 1;
+        p->timed_launches += p->ev_steps[k / 2];
     }
     p->ev_used = 0;
     return CTQW_OK;
@@ -938,7 +962,18 @@ ctqw_status ctqw_work_items(const ctqw_plan* p, int64_t* items, int64_t* waves) 
     if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
     const int64_t n = p->prob.m == 3 ? p->n_parts : (int64_t)p->items.size();
     if (items) *items = n;
-    if (waves) *waves = p->prob.m == 3 ? n * 4 : n;
+    if (waves) {
+        *waves = p->prob.m == 3 ? n * 4 : n;
+        if (p->prob.m != 3 && p->launch.persistent && p->bound) {
+            // the persistent grid: resident waves of the device
+            ctqw_plan* q = const_cast<ctqw_plan*>(p);
+            StepConfig c = step_config(q);
+            int n_waves = 0;
+            ctqw_status st = grid_for(q, c, &n_waves);
+            if (st != CTQW_OK) return st;
+            *waves = n_waves;
+        }
+    }
     return CTQW_OK;
 }
 

@@ -105,6 +105,10 @@ template <typename T, int NT, int P, bool KAHAN, bool TRI>
 __device__ __forceinline__ void process_item(const StepArgs& a, int home, int lane) {
     using C = typename CplxOf<T>::type;
     constexpr int WA = window_rows(NT);
+    // Rows fetched ahead: a whole window for complex64 (512-byte rows need
+    // many loads in flight to cover the HBM latency), three for complex128
+    // (1 KB rows, and the registers are taken by the wider windows).
+    constexpr int PF = sizeof(T) == 4 ? WA : 3;
 
     const ItemDev it = a.items[home];
     const RealDev rd = a.reals[it.real];
@@ -161,8 +165,8 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     T cr[WA][P], ci[WA][P];         // compensation words (KAHAN)
     T dg[WA][P];                    // dt * diagonal of H on the rows in flight
     T ju[WA];                       // dt * bond above each row in flight (uniform)
-    C pre[3][P];                    // rows being fetched
-    T pj[3], pe[3];                 // their bond above and row energy (uniform)
+    C pre[PF][P];                   // rows being fetched
+    T pj[3], pe[3];                 // bond above and energy of the next rows (uniform)
 #pragma unroll
     for (int j = 0; j < NT; ++j)
 #pragma unroll
@@ -178,19 +182,27 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         }
     }
     // Grid rows are tracked incrementally: qm_in is the row entering at the
-    // current iteration, qm_pf the one being prefetched three iterations ahead.
+    // current iteration, qm_pf the one fetched PF iterations ahead and qm_pp
+    // the one whose couplings are read three iterations ahead.
     auto next_row = [&](int x) { return (x + 1 == rows) ? 0 : x + 1; };
-    auto fetch = [&](int qm, int s) {
-        load_row(qm, pre[s]);
+    auto fetch_params = [&](int qm, int s) {
         pj[s] = Jr[qm == 0 ? rows - 1 : qm - 1];   // the padded last bond is 0 on an open chain
         pe[s] = Er[qm];
     };
     int qm_in = periodic ? wrap(it.row0, rows) : it.row0;
-    int qm_pf = qm_in;
+    int qm_pf = qm_in, qm_pp = qm_in;
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {   // rows past the sweep are fetched and ignored
-        fetch(qm_pf, s);
+    for (int s = 0; s < PF; ++s) {   // rows past the sweep are fetched and ignored
+        load_row(qm_pf, pre[s]);
         qm_pf = next_row(qm_pf);
+        // Keep the prologue loads in slot order: the sweep consumes slot 0
+        // first, and the wait it needs is then for the oldest load only.
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        fetch_params(qm_pp, s);
+        qm_pp = next_row(qm_pp);
     }
 
     // Norm weights of this lane's outputs (full grid: 1 on the band's output
@@ -215,17 +227,19 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                 // back from there.
                 {
                     const int s = u % 3;
+                    const int sp = u % PF;
                     const bool live = i < nrows;
                     const int qm = qm_in;
                     C v[P];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        v[p] = pre[s][p];
+                        v[p] = pre[sp][p];
                         if (!(live && row_mask(qm, p))) { v[p].x = T(0); v[p].y = T(0); }
                     }
                     const T er = pe[s];
                     ju[u] = live ? pj[s] : T(0);
-                    fetch(qm_pf, s);
+                    load_row(qm_pf, pre[sp]);
+                    fetch_params(qm_pp, s);
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const T re = v[p].x * sc, im = v[p].y * sc;
@@ -244,6 +258,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     }
                     qm_in = next_row(qm_in);
                     qm_pf = next_row(qm_pf);
+                    qm_pp = next_row(qm_pp);
                 }
                 // ---- levels 1..NT: Psi_j on row i - j.
 #pragma unroll
@@ -361,21 +376,45 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     }
 }
 
-// One kernel serves both launch forms.  Regular: wave k of the grid takes
-// item k of the processing order.  Persistent (a grid sized to the device,
-// n_waves resident waves): wave w takes items w, w + n_waves, w + 2 n_waves,
-// ... of the processing order (largest first), so every wave gets a share of
-// large and small items.  The loop bound is wave-uniform and no counter
-// state is kept between launches, so the kernel can be launched again or
-// replayed in a graph as is.
+// One kernel serves both launch forms.  Items are taken in groups of one
+// item per wave of the block (consecutive in the processing order, so
+// mostly adjacent bands of one realisation, whose overlapping columns are
+// then read by one CU at about the same time).  Regular: block b takes
+// group b and the hardware hands out the blocks.  Persistent (a grid of
+// resident blocks): block b starts on group b and then claims the next
+// groups from a counter that the host zeroes before the launch.  Wave 0
+// makes the claim with all lanes adding 1 at the same address, which the
+// compiler folds into one atomic add of 64 from one lane (a claim is
+// counter / 64); lane 0 passes it to the block through LDS (two slots used
+// alternately, so a slot is rewritten only after every wave has passed the
+// next barrier) and every wave reads it back with readfirstlane, so the loop
+// bound is uniform over the block and every wave meets every barrier.
+// Claims grow monotonically and each block leaves after at most one claim
+// past the last group.  Static assignments of items to waves (round-robin,
+// longest-processing-time) ran 20 % slower: the resident waves do not all
+// advance at the same rate, and only claiming at run time follows that.
 template <typename T, int NT, int P, bool KAHAN, bool TRI>
 __global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int k0 = blockIdx.x * (blockDim.x >> 6) + wv;
-    const int stride = a.persistent ? a.n_waves : a.n_items;
-    for (int k = k0; k < a.n_items; k += stride) {
-        process_item<T, NT, P, KAHAN, TRI>(a, a.item_order[k], lane);
+    int g = blockIdx.x;
+    if (a.persistent) {
+        __shared__ int next_group[2];
+        const int n_blocks = a.n_waves / wpb;
+        for (int it = 0; g * wpb < a.n_items; ++it) {
+            const int k = g * wpb + wv;
+            if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI>(a, a.item_order[k], lane);
+            if (wv == 0) {
+                const int t = atomicAdd(a.claim, 1);
+                if (lane == 0) next_group[it & 1] = __builtin_amdgcn_readfirstlane(t) / 64;
+            }
+            __syncthreads();
+            g = n_blocks + __builtin_amdgcn_readfirstlane(next_group[it & 1]);
+        }
+    } else {
+        const int k = g * wpb + wv;
+        if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI>(a, a.item_order[k], lane);
     }
 }
 

@@ -222,7 +222,7 @@ def test_pair_correlation_c128():
 
 def test_graph_replays_match_eager_launches():
     """The step loop captured in a HIP graph (with the persistent kernel and
-    its self-resetting queue) and replayed several times, with eager work and
+    its per-wave item lists) and replayed several times, with eager work and
     synchronisation in between, gives the eager result after every replay."""
     say("case: hipGraph step loop vs eager, 4 replays of 6 steps")
     reals = random_reals([100, 33, 64], seed=14)
@@ -242,6 +242,26 @@ def test_graph_replays_match_eager_launches():
     graph.propagate(7, 7, 1)
     assert np.array_equal(graph.state_numpy(), eager.state_numpy())
     assert graph.stats().steps_done == eager.stats().steps_done == 31
+
+
+def test_timed_graph_replays_count_every_step_kernel():
+    """Timing of captured step loops: each replay is bracketed by an event
+    pair that counts for its steps, so the timed steps equal the steps taken,
+    and a timed loop gives the untimed loop's state bit for bit (300 steps =
+    graphs of 256 and 44 steps)."""
+    say("case: timed hipGraph step loops, 2 x 300 steps")
+    reals = random_reals([100, 33, 64], seed=16)
+    kw = dict(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
+              reals=reals, dt=0.05, tol=1e-7, launch={"persistent": 1, "use_graph": 1}, sites=[20, 21])
+    plain, timed = gpu_plan(**kw), gpu_plan(**kw)
+    timed.set_timing(True)
+    for rep in (1, 2):
+        plain.propagate(300)
+        timed.propagate(300)
+        ms, launches = timed.get_timing()
+        say(f"  after {300 * rep} steps: {launches} timed launches, {ms:.3f} ms")
+        assert launches == 300 * rep and ms > 0
+        assert np.array_equal(plain.state_numpy(), timed.state_numpy())
 
 
 def test_autotune_applies_and_caches_a_shape(tmp_path):
