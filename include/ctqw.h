@@ -140,6 +140,33 @@ ctqw_status ctqw_set_params(ctqw_plan* plan, const double* J, const double* eps,
                             const double* U);
 ctqw_status ctqw_get_params(const ctqw_plan* plan, double* J, double* eps, double* U);
 
+/* Noise model of Eq. 1 with static draws: parameter = baseline + draw,
+ * independent across realisations (the paper draws noise on the hoppings;
+ * on-site and interaction noise follow the same form).                   */
+typedef enum { CTQW_DIST_NONE = 0, CTQW_DIST_UNIFORM = 1 /* U[a, b] */,
+               CTQW_DIST_NORMAL = 2 /* N(a, b^2) */ } ctqw_dist;
+typedef struct {
+    int32_t dist;            /* ctqw_dist */
+    double a, b;
+} ctqw_noise;
+
+/* Draw every realisation's parameters on the host and apply them as
+ * ctqw_set_params does.  J_base: [n_bonds(max N_r)] baseline hoppings, or
+ * NULL for 1 on every bond; eps_base: [max N_r] baseline energies, or NULL
+ * for 0; realisation r uses the first n_bonds(N_r) / N_r entries.  A NULL
+ * noise pointer means no noise.  Generator: Philox4x32-10 (Salmon et al.,
+ * SC 2011), one block per parameter with counter (index, kind, r mod 2^32,
+ * r div 2^32) -- kind 0 bonds, 1 sites, 2 interaction -- and key (seed mod
+ * 2^32, seed div 2^32); from the block (w0..w3), u = (2^26 (w0 >> 5) +
+ * (w1 >> 6)) 2^-53 and v likewise from (w2, w3); uniform: a + (b - a) u;
+ * normal: a + b sqrt(-2 log(1 - u)) cos(2 pi v), in double without fused
+ * operations.  The drawn values are returned by ctqw_get_params.
+ * Errors: as ctqw_set_params; INVALID_ARG for an unknown dist or a
+ * non-finite a, b or baseline.                                            */
+ctqw_status ctqw_draw_params(ctqw_plan* plan, const double* J_base, const double* eps_base, double U_base,
+                             const ctqw_noise* J_noise, const ctqw_noise* eps_noise, const ctqw_noise* U_noise,
+                             uint64_t seed);
+
 /* Taylor terms per step of each realisation, [R].  With taylor_order > 0
  * every entry is taylor_order; otherwise n_r is the smallest n >= 1 with
  * x^(n+1)/(n+1)! / (1 - x/(n+2)) <= taylor_tol, x = dt * G_r, where G_r =

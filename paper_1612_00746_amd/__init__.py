@@ -77,6 +77,11 @@ class Plan:
         self.R = int(problem.R)
         self.m = int(problem.m)
         self.dtype = "c128" if problem.dtype == C128 else "c64"
+        if problem.n_sites > 0:
+            self.Ns = [int(problem.n_sites)] * self.R
+        else:
+            self.Ns = [int(problem.n_sites_per_real[r]) for r in range(self.R)]
+        self.periodic = problem.boundary == PERIODIC
         self._buffers = None
         self._keep = []
 
@@ -96,6 +101,40 @@ class Plan:
         U = np.ascontiguousarray(U, dtype=np.float64)
         self._check(self.lib.ctqw_set_params(self.h, _ptr(J, C.c_double), _ptr(eps, C.c_double),
                                              _ptr(U, C.c_double)))
+
+    def n_bonds(self, N: int) -> int:
+        return N if self.periodic else N - 1
+
+    def get_params(self) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """The packed J, eps, U in force (as set or drawn)."""
+        J = np.zeros(sum(self.n_bonds(N) for N in self.Ns))
+        eps = np.zeros(sum(self.Ns))
+        U = np.zeros(self.R)
+        self._check(self.lib.ctqw_get_params(self.h, _ptr(J, C.c_double), _ptr(eps, C.c_double),
+                                             _ptr(U, C.c_double)))
+        return J, eps, U
+
+    def draw_params(self, *, J_base=None, eps_base=None, U_base: float = 0.0, J_noise=None, eps_noise=None,
+                    U_noise=None, seed: int = 0) -> None:
+        """Draw every realisation's parameters in the library (baseline plus
+        a Philox4x32-10 draw per parameter).  Noises are (dist, a, b) with
+        dist in {"none", "uniform", "normal"}; None means no noise."""
+        dists = {"none": L.DIST_NONE, "uniform": L.DIST_UNIFORM, "normal": L.DIST_NORMAL}
+
+        def noise(n):
+            if n is None:
+                return None
+            d, a, b = n
+            return C.byref(L.Noise(dists[d], float(a), float(b)))
+        Jb = None if J_base is None else np.ascontiguousarray(J_base, dtype=np.float64)
+        Eb = None if eps_base is None else np.ascontiguousarray(eps_base, dtype=np.float64)
+        if Jb is not None and Jb.shape[0] < self.n_bonds(max(self.Ns)):
+            raise ValueError("J_base needs n_bonds(max N) entries")
+        if Eb is not None and Eb.shape[0] < max(self.Ns):
+            raise ValueError("eps_base needs max N entries")
+        self._check(self.lib.ctqw_draw_params(
+            self.h, None if Jb is None else _ptr(Jb, C.c_double), None if Eb is None else _ptr(Eb, C.c_double),
+            float(U_base), noise(J_noise), noise(eps_noise), noise(U_noise), int(seed)))
 
     def orders(self) -> np.ndarray:
         out = np.zeros(self.R, dtype=np.int32)

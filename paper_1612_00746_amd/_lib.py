@@ -24,6 +24,7 @@ C64, C128 = 0, 1
 ACC_KAHAN, ACC_PLAIN = 0, 1
 OBS_OCCUPATION, OBS_PAIR = 1, 2
 LOSS_ONE_BODY, LOSS_PRODUCT = 0, 1
+DIST_NONE, DIST_UNIFORM, DIST_NORMAL = 0, 1, 2
 
 
 class Problem(C.Structure):
@@ -45,6 +46,10 @@ class Problem(C.Structure):
         ("norm_alarm", C.c_double),
         ("observables", C.c_uint32),
     ]
+
+
+class Noise(C.Structure):
+    _fields_ = [("dist", C.c_int32), ("a", C.c_double), ("b", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -81,6 +86,8 @@ SIGNATURES = {
     "ctqw_plan_destroy": (C.c_int, [PlanP]),
     "ctqw_set_params": (C.c_int, [PlanP, dp, dp, dp]),
     "ctqw_get_params": (C.c_int, [PlanP, dp, dp, dp]),
+    "ctqw_draw_params": (C.c_int, [PlanP, dp, dp, C.c_double, C.POINTER(Noise), C.POINTER(Noise),
+                                   C.POINTER(Noise), C.c_uint64]),
     "ctqw_orders": (C.c_int, [PlanP, i32p]),
     "ctqw_layout": (C.c_int, [PlanP, i64p]),
     "ctqw_sizes": (C.c_int, [PlanP, i64p, i64p]),

@@ -26,6 +26,7 @@
 
 #include "../../include/ctqw.h"
 #include "ctqw_internal.hpp"
+#include "noise.hpp"
 
 using namespace ctqw;
 
@@ -917,6 +918,40 @@ ctqw_status ctqw_set_params(ctqw_plan* p, const double* J, const double* eps, co
     p->xbound.swap(xb);
     p->params_set = true;
     return build_tables(p);
+}
+
+ctqw_status ctqw_draw_params(ctqw_plan* p, const double* J_base, const double* eps_base, double U_base,
+                             const ctqw_noise* J_noise, const ctqw_noise* eps_noise, const ctqw_noise* U_noise,
+                             uint64_t seed) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    const ctqw_problem& pr = p->prob;
+    const ctqw_noise none{CTQW_DIST_NONE, 0.0, 0.0};
+    const ctqw_noise* noises[3] = {J_noise ? J_noise : &none, eps_noise ? eps_noise : &none,
+                                   U_noise ? U_noise : &none};
+    for (const ctqw_noise* n : noises) {
+        if (n->dist != CTQW_DIST_NONE && n->dist != CTQW_DIST_UNIFORM && n->dist != CTQW_DIST_NORMAL)
+            return fail(p, CTQW_ERR_INVALID_ARG, "unknown noise distribution %d", n->dist);
+        if (!is_fin(n->a) || !is_fin(n->b)) return fail(p, CTQW_ERR_INVALID_ARG, "non-finite noise parameter");
+    }
+    if (!is_fin(U_base)) return fail(p, CTQW_ERR_INVALID_ARG, "non-finite U_base");
+    const int nb_max = n_bonds(pr, p->max_N);
+    if (J_base)
+        for (int i = 0; i < nb_max; ++i)
+            if (!is_fin(J_base[i])) return fail(p, CTQW_ERR_INVALID_ARG, "J_base[%d] is not finite", i);
+    if (eps_base)
+        for (int i = 0; i < p->max_N; ++i)
+            if (!is_fin(eps_base[i])) return fail(p, CTQW_ERR_INVALID_ARG, "eps_base[%d] is not finite", i);
+    std::vector<double> J, eps, U(pr.R);
+    for (int64_t r = 0; r < pr.R; ++r) {
+        const int N = p->N[r];
+        const int nb = n_bonds(pr, N);
+        for (int i = 0; i < nb; ++i)
+            J.push_back((J_base ? J_base[i] : 1.0) + noise_draw(*noises[0], seed, r, NOISE_BOND, i));
+        for (int i = 0; i < N; ++i)
+            eps.push_back((eps_base ? eps_base[i] : 0.0) + noise_draw(*noises[1], seed, r, NOISE_SITE, i));
+        U[r] = U_base + noise_draw(*noises[2], seed, r, NOISE_INTERACTION, 0);
+    }
+    return ctqw_set_params(p, J.data(), eps.data(), U.data());
 }
 
 ctqw_status ctqw_get_params(const ctqw_plan* p, double* J, double* eps, double* U) {

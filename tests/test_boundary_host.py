@@ -224,3 +224,43 @@ def test_gradient_entry_points_validate_on_host():
     renorm = make(R=2, n_sites=8, taylor_order=6, taylor_tol=0.0, renormalize=True)
     renorm.set_params(J, eps, U)
     assert lib.ctqw_forward_ckpt(renorm.h, 4, 2, C.c_void_p(256), 1 << 30) == L.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("boundary", ["open", "periodic"])
+def test_draw_params_match_the_oracle_generator(boundary):
+    """Library draws (Philox4x32-10, host side) against the oracle's own
+    generator: uniform draws bit for bit, Box-Muller normals within 2 ulp
+    (libm's log/cos), for an uneven batch with baselines; the orders follow
+    from the drawn values."""
+    from oracle import noise
+    Ns = [8, 13, 8, 21]
+    plan = make(R=4, n_sites=Ns, boundary=boundary, dtype="c64", taylor_tol=1e-7)
+    nbmax = max(Ns) if boundary == "periodic" else max(Ns) - 1
+    g = np.random.default_rng(5)
+    Jb, Eb = 1 + 0.05 * g.standard_normal(nbmax), g.uniform(-0.2, 0.2, max(Ns))
+    kw = dict(J_base=Jb, eps_base=Eb, U_base=1.5, J_noise=("normal", 0.0, 0.1),
+              eps_noise=("uniform", -0.5, 0.5), U_noise=("uniform", 0.0, 4.0), seed=12345678901)
+    plan.draw_params(**kw)
+    J, eps, U = plan.get_params()
+    J0, eps0, U0 = noise.draw_params(Ns, boundary == "periodic", **kw)
+    assert np.array_equal(eps, eps0) and np.array_equal(U, U0)
+    np.testing.assert_array_max_ulp(J, np.array(J0), maxulp=2)
+    nb = [n if boundary == "periodic" else n - 1 for n in Ns]
+    jo = np.cumsum([0] + nb)
+    eo = np.cumsum([0] + Ns)
+    o = plan.orders()
+    for r in range(4):
+        assert o[r] == reference_order(J[jo[r]:jo[r + 1]], eps[eo[r]:eo[r + 1]], U[r], 2, 0.05, 1e-7)
+    # defaults: no noise -> J = 1, eps = 0, U = U_base
+    plan.draw_params(U_base=0.5)
+    J, eps, U = plan.get_params()
+    assert np.all(J == 1.0) and np.all(eps == 0.0) and np.all(U == 0.5)
+
+
+def test_draw_params_validation():
+    from paper_1612_00746_amd import _lib as L
+    plan = make(R=2, n_sites=8)
+    assert status_of(lambda: plan.draw_params(J_noise=("uniform", 0.0, float("nan")))) == 1
+    bad = L.Noise(7, 0.0, 1.0)
+    assert plan.lib.ctqw_draw_params(plan.h, None, None, 0.0, C.byref(bad), None, None, 0) == L.ERR_INVALID_ARG
+    assert status_of(lambda: plan.draw_params(U_base=float("inf"))) == 1

@@ -9,6 +9,7 @@ independent second-quantised construction of H, and symmetries.
 """
 
 import math
+import os
 
 import mpmath
 import numpy as np
@@ -381,3 +382,42 @@ def test_ensemble_mean_against_fsum():
     mean = O.ensemble_mean(vals)
     for c in range(3):
         assert abs(mean[c] - O.exact_mean(vals[:, c])) <= 1e-14 * np.max(np.abs(vals[:, c]))
+
+
+# ------------------------------------------------------------ noise draws
+
+def _kat_rows():
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            w = [int(x, 16) for x in line.split()]
+            yield w[:4], w[4:6], w[6:]
+
+
+def test_philox_known_answer_vectors():
+    """Philox4x32-10 against the generator's published known-answer vectors."""
+    from oracle import noise
+    rows = list(_kat_rows())
+    assert len(rows) == 3
+    for ctr, key, out in rows:
+        assert noise.philox4x32(ctr, key) == out
+
+
+def test_unit53_and_draw_mappings():
+    """The 53-bit fraction spans [0, 1 - 2^-53]; uniform draws land in
+    [a, b); Box-Muller normals have the stated mean and variance."""
+    from oracle import noise
+    assert noise.unit53(0, 0) == 0.0
+    assert noise.unit53(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0 ** -53
+    assert noise.unit53(1 << 31, 0) == 0.5
+    u = np.array([noise.draw("uniform", -0.5, 0.25, 7, r, noise.SITE, i) for r in range(40) for i in range(100)])
+    assert u.min() >= -0.5 and u.max() < 0.25
+    assert abs(u.mean() - (-0.125)) < 4 * 0.75 / math.sqrt(12 * u.size)
+    z = np.array([noise.draw("normal", 1.0, 0.2, 3, r, noise.BOND, i) for r in range(50) for i in range(100)])
+    n = z.size
+    assert abs(z.mean() - 1.0) < 4 * 0.2 / math.sqrt(n)
+    assert abs(z.var() / 0.04 - 1.0) < 4 * math.sqrt(2.0 / n)
+    assert noise.draw("none", 1.0, 2.0, 0, 0, 0, 0) == 0.0
+    # distinct counters and keys give distinct blocks
+    assert noise.philox4x32([0, 0, 0, 0], [0, 0]) != noise.philox4x32([1, 0, 0, 0], [0, 0])
+    assert noise.philox4x32([0, 0, 0, 0], [0, 0]) != noise.philox4x32([0, 0, 0, 0], [1, 0])
