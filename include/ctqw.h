@@ -114,10 +114,19 @@ typedef struct {
 typedef struct {
     int32_t cols_per_lane;   /* 1 or 2 lattice columns per SIMD lane */
     int32_t waves_per_block; /* 1, 2 or 4 */
-    int32_t persistent;      /* 0: one wave per work item; 1: a grid sized to
-                                the device pulls items from a queue */
+    int32_t persistent;      /* 0: one block per group of work items; 1: a grid
+                                sized to the device claims groups at run time */
     int32_t use_graph;       /* 1: capture the step loop into a HIP graph */
     int32_t waves_per_cu;    /* persistent grid: resident waves per CU (0: auto) */
+    int32_t chunked;         /* 0: all n Taylor terms of a step in one pass over
+                                the state when n fits the compiled pipeline
+                                (12 terms complex64 / 16 complex128 at one
+                                column per lane, 10 / 8 at two), else passes;
+                                1: always passes of K terms (K = 8 complex64,
+                                4 complex128, one column per lane), each
+                                reading and writing the partial sum and the
+                                last term (Alg. 3's term loop split over
+                                passes) */
 } ctqw_launch;
 
 /* Create a plan from a problem statement.  Host only: validates the

@@ -72,6 +72,7 @@ class Launch(C.Structure):
         ("persistent", C.c_int32),
         ("use_graph", C.c_int32),
         ("waves_per_cu", C.c_int32),
+        ("chunked", C.c_int32),
     ]
 
 

@@ -59,6 +59,17 @@ struct StepArgs {
     double* tail_part;           // [n_items] sum of w |Phi^(n)|^2 of each item
     double dt;
     int32_t persistent;          // 1: grid of n_waves waves claiming items
+    // Chunked step (orders above the fused depth): one pass of the kernel's
+    // depth NT continues the series from Psi_s (psi_in, true complex values)
+    // and the partial sum acc_in, writing the new partial sum to psi_out and
+    // Psi_{s+NT} to seed_out.  Unused by the fused kernel.
+    const void* acc_in;
+    void* seed_out;              // null on the last pass
+    double coef[16];             // 1/(s+j)! for j = 1..NT, 0 past the order
+    double tail_coef;            // 1/n! (last pass)
+    int32_t tail_level;          // level of the order's last term (last pass), else 0
+    int32_t first;               // first pass: loads carry the realisation's scale
+    int32_t last;                // last pass: norm and tail partials
 };
 
 struct StepConfig {
@@ -74,6 +85,12 @@ struct StepConfig {
 
 // Host entry points implemented in the .hip translation units.
 hipError_t launch_step(const StepConfig& cfg, const StepArgs& args, hipStream_t stream);
+// Chunked passes: terms per pass (8 for complex64, 4 for complex128, whose
+// pipeline at depth 8 needs more than 256 VGPRs), launched like the fused
+// kernel (cfg.levels is ignored, cols_per_lane must be 1).
+constexpr int chunk_depth(int dtype) { return dtype == 1 ? 4 : 8; }
+hipError_t launch_chunk_pass(const StepConfig& cfg, const StepArgs& args, hipStream_t stream);
+hipError_t chunk_occupancy(const StepConfig& cfg, int* blocks_per_cu);
 // Smallest compiled pipeline depth >= order (-1 if none).
 int step_levels_bucket(int dtype, int cols_per_lane, int order);
 hipError_t step_occupancy(const StepConfig& cfg, int* blocks_per_cu);

@@ -43,7 +43,7 @@ struct Region {
 struct Layout {
     Region reals, items, order, item_first, claim, Jd, Ed, Jf, Ef, scale, norm_part,
         tail_part, norm2, tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites,
-        s3, M3, occ3;
+        s3, M3, occ3, chunk;
     int64_t total = 0;
 };
 
@@ -72,7 +72,8 @@ struct ctqw_plan {
     std::vector<ItemDev> items;
     std::vector<int32_t> item_first, item_order;
     int64_t n_parts = 0;             // per-step FP64 norm partials
-    int levels = 0;
+    int levels = 0;                  // Taylor terms per step (the batch's order)
+    int chunk = 0;                   // terms per pass of a chunked step (0: fused)
     ctqw_launch launch{};
     Layout lay;
     bool tables_dirty = true;
@@ -144,10 +145,11 @@ int64_t amplitudes(const ctqw_problem& pr, int N) {
     return (int64_t)N * N;
 }
 
+// Orders above the fused pipeline's depth run as chunked passes (one and
+// two particles) or as one term per pass (three), so the cap is the user's.
+constexpr int kDefaultMaxOrder = 40;
 int max_order_cap(const ctqw_problem& pr) {
-    const int compiled = pr.m == 3 ? 24 : (pr.dtype == CTQW_C128 ? 16 : 12);
-    if (pr.taylor_max_order > 0) return std::min(pr.taylor_max_order, compiled);
-    return compiled;
+    return pr.taylor_max_order > 0 ? pr.taylor_max_order : kDefaultMaxOrder;
 }
 
 // a-priori remainder bound of the degree-n Taylor polynomial of exp(z),
@@ -219,10 +221,13 @@ ctqw_status build_tables(ctqw_plan* p) {
     const int W = 64 * P;
     int maxn = 0;
     for (int64_t r = 0; r < pr.R; ++r) maxn = std::max(maxn, p->order[r]);
-    const int levels = pr.m == 3 ? maxn : step_levels_bucket(pr.dtype == CTQW_C128 ? 1 : 0, P, maxn);
-    if (levels < 0)
-        return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d has no compiled kernel for %d column(s) per lane",
-                    maxn, P);
+    const int dtype = pr.dtype == CTQW_C128 ? 1 : 0;
+    const int fused = pr.m == 3 ? maxn : step_levels_bucket(dtype, P, maxn);
+    // chunked passes when the order has no fused pipeline, or on request
+    const int chunk = (pr.m != 3 && (fused < 0 || p->launch.chunked)) ? chunk_depth(dtype) : 0;
+    const int levels = maxn;
+    const int band_W = chunk ? 64 : W;          // chunked passes run one column per lane
+    const int halo = chunk ? chunk : levels;
     std::vector<ItemDev> items;
     std::vector<int32_t> first(pr.R + 1, 0);
     int64_t n_parts = 0;
@@ -235,8 +240,8 @@ ctqw_status build_tables(ctqw_plan* p) {
     } else {
         for (int64_t r = 0; r < pr.R; ++r) {
             first[r] = (int32_t)items.size();
-            if (!make_bands(pr, (int)r, p->N[r], levels, W, items))
-                return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", levels, W);
+            if (!make_bands(pr, (int)r, p->N[r], halo, band_W, items))
+                return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", halo, band_W);
         }
         first[pr.R] = (int32_t)items.size();
         n_parts = (int64_t)items.size();
@@ -246,13 +251,14 @@ ctqw_status build_tables(ctqw_plan* p) {
     std::vector<int64_t> cost(items.size());
     for (size_t k = 0; k < items.size(); ++k) {
         ord[k] = (int32_t)k;
-        cost[k] = (int64_t)(items[k].nrows + levels);
+        cost[k] = (int64_t)(items[k].nrows + halo);
     }
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     p->items.swap(items);
     p->item_first.swap(first);
     p->item_order.swap(ord);
     p->levels = levels;
+    p->chunk = chunk;
 
     // workspace layout
     Layout L;
@@ -291,6 +297,11 @@ ctqw_status build_tables(ctqw_plan* p) {
         align_region(L, L.s3, 3 * ((sb + 255) & ~int64_t(255)));
         align_region(L, L.M3, R * 3 * NN * 8);
         align_region(L, L.occ3, G * NN * 8);
+    }
+    if (chunk) {
+        // two buffers for the last term of a pass, one for the partial sum
+        const int64_t sb = p->state_off.back() * (pr.dtype == CTQW_C128 ? 16 : 8);
+        align_region(L, L.chunk, 3 * ((sb + 255) & ~int64_t(255)));
     }
     L.total = (L.total + 255) & ~int64_t(255);
     p->n_parts = n_parts;
@@ -371,8 +382,8 @@ StepConfig step_config(ctqw_plan* p) {
     c.dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
     c.kahan = (c.dtype == 0 && p->prob.accumulation == CTQW_ACC_KAHAN) ? 1 : 0;
     c.triangle = (p->prob.m == 2 && p->prob.statistics == CTQW_BOSON) ? 1 : 0;
-    c.cols_per_lane = p->launch.cols_per_lane;
-    c.levels = p->levels;
+    c.cols_per_lane = p->chunk ? 1 : p->launch.cols_per_lane;
+    c.levels = p->chunk ? p->chunk : p->levels;
     c.waves_per_block = p->launch.waves_per_block;
     c.persistent = p->launch.persistent;
     c.grid_blocks = 0;
@@ -388,7 +399,8 @@ ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
     if ((int64_t)p->items.size() >= (int64_t(1) << 25))
         return fail(p, CTQW_ERR_UNSUPPORTED, "persistent launch takes at most 2^25 work items per step");
     int per_cu = 0;
-    HIP_TRY(p, step_occupancy(c, &per_cu));
+    if (p->chunk) HIP_TRY(p, chunk_occupancy(c, &per_cu));
+    else HIP_TRY(p, step_occupancy(c, &per_cu));
     if (p->launch.waves_per_cu > 0) per_cu = std::max(1, p->launch.waves_per_cu / c.waves_per_block);
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)p->cu_count * per_cu;
@@ -478,45 +490,12 @@ ctqw_status enqueue_step3(ctqw_plan* p) {
     return CTQW_OK;
 }
 
-ctqw_status enqueue_step(ctqw_plan* p) {
-    if (p->prob.m == 3) return enqueue_step3(p);
-    const Layout& L = p->lay;
-    StepConfig c = step_config(p);
-    int n_waves = 0;
-    ctqw_status st = grid_for(p, c, &n_waves);
-    if (st != CTQW_OK) return st;
-    StepArgs a{};
-    a.psi_in = p->psi[p->cur];
-    a.psi_out = p->psi[1 - p->cur];
-    a.reals = at<RealDev>(p, L.reals);
-    a.items = at<ItemDev>(p, L.items);
-    a.item_order = at<int32_t>(p, L.order);
-    a.claim = at<int32_t>(p, L.claim);
-    a.n_items = (int32_t)p->items.size();
-    a.n_waves = n_waves;
-    a.Jd = at<double>(p, L.Jd);
-    a.Ed = at<double>(p, L.Ed);
-    a.Jf = at<float>(p, L.Jf);
-    a.Ef = at<float>(p, L.Ef);
-    a.scale = at<double>(p, L.scale);
-    a.norm_part = at<double>(p, L.norm_part);
-    a.tail_part = at<double>(p, L.tail_part);
-    a.dt = p->prob.dt;
-    a.persistent = c.persistent;
-    if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
-    if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
-    HIP_TRY(p, launch_step(c, a, p->stream));
-    if (p->timing && (st = record_event(p, 1)) != CTQW_OK) return st;
-    if ((st = enqueue_finalize(p)) != CTQW_OK) return st;
-    p->cur = 1 - p->cur;
-    p->steps_done += 1;
-    p->have_step_stats = true;
-    return CTQW_OK;
-}
-
-// One step kernel from `in` to `out` (no monitoring), for recomputation.
-ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
-    if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "recomputation is built for one and two particles");
+// The step kernel(s) from `in` to `out`: one fused launch, or the passes of
+// a chunked step.  Pass q of Q continues the series from the last term of
+// pass q-1 (two workspace buffers, alternately) and the partial sum, which
+// alternates between the workspace and `out` so that the last pass writes
+// `out` and no pass updates its own input.
+ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
     const Layout& L = p->lay;
     StepConfig c = step_config(p);
     int n_waves = 0;
@@ -540,9 +519,61 @@ ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
     a.tail_part = at<double>(p, L.tail_part);
     a.dt = p->prob.dt;
     a.persistent = c.persistent;
-    if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
-    HIP_TRY(p, launch_step(c, a, p->stream));
+    if (!p->chunk) {
+        if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
+        HIP_TRY(p, launch_step(c, a, p->stream));
+        return CTQW_OK;
+    }
+    const int n = p->levels, K = p->chunk;
+    const int passes = (n + K - 1) / K;
+    const int64_t sb = (p->state_off.back() * (c.dtype ? 16 : 8) + 255) & ~int64_t(255);
+    uint8_t* seed_buf[2] = {p->ws + L.chunk.off, p->ws + L.chunk.off + sb};
+    uint8_t* acc_tmp = p->ws + L.chunk.off + 2 * sb;
+    auto acc_buf = [&](int q) -> void* { return ((passes - 1 - q) & 1) == 0 ? out : acc_tmp; };
+    double inv_fact_n = 1.0;
+    for (int k = 2; k <= n; ++k) inv_fact_n /= k;
+    double f = 1.0;   // 1 / s!
+    for (int q = 0; q < passes; ++q) {
+        const int s0 = q * K;
+        a.psi_in = q == 0 ? in : seed_buf[(q - 1) & 1];
+        a.acc_in = q == 0 ? in : acc_buf(q - 1);
+        a.psi_out = acc_buf(q);
+        a.seed_out = q == passes - 1 ? nullptr : seed_buf[q & 1];
+        for (int j = 1; j <= 16; ++j) {
+            if (j <= K && s0 + j <= n) {
+                f /= (s0 + j);
+                a.coef[j - 1] = f;
+            } else {
+                a.coef[j - 1] = 0.0;
+            }
+        }
+        a.first = q == 0;
+        a.last = q == passes - 1;
+        a.tail_level = a.last ? n - s0 : 0;
+        a.tail_coef = inv_fact_n;
+        if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
+        HIP_TRY(p, launch_chunk_pass(c, a, p->stream));
+    }
     return CTQW_OK;
+}
+
+ctqw_status enqueue_step(ctqw_plan* p) {
+    if (p->prob.m == 3) return enqueue_step3(p);
+    ctqw_status st;
+    if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
+    if ((st = enqueue_step_kernels(p, p->psi[p->cur], p->psi[1 - p->cur])) != CTQW_OK) return st;
+    if (p->timing && (st = record_event(p, 1)) != CTQW_OK) return st;
+    if ((st = enqueue_finalize(p)) != CTQW_OK) return st;
+    p->cur = 1 - p->cur;
+    p->steps_done += 1;
+    p->have_step_stats = true;
+    return CTQW_OK;
+}
+
+// One step kernel from `in` to `out` (no monitoring), for recomputation.
+ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
+    if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "recomputation is built for one and two particles");
+    return enqueue_step_kernels(p, in, out);
 }
 
 ctqw_status collect_timing(ctqw_plan* p);
@@ -838,6 +869,7 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         p->launch.persistent = 0;
         p->launch.use_graph = 0;
         p->launch.waves_per_cu = 0;
+        p->launch.chunked = 0;
         p->order.assign(R, 0);
         p->xbound.assign(R, 0.0);
     } catch (const std::bad_alloc&) {
@@ -1025,8 +1057,8 @@ ctqw_status ctqw_set_launch(ctqw_plan* p, const ctqw_launch* l) {
     if (l->waves_per_block != 1 && l->waves_per_block != 2 && l->waves_per_block != 4)
         return fail(p, CTQW_ERR_INVALID_ARG, "waves_per_block must be 1, 2 or 4");
     if ((l->persistent != 0 && l->persistent != 1) || (l->use_graph != 0 && l->use_graph != 1) ||
-        l->waves_per_cu < 0)
-        return fail(p, CTQW_ERR_INVALID_ARG, "bad persistent / use_graph / waves_per_cu");
+        l->waves_per_cu < 0 || (l->chunked != 0 && l->chunked != 1))
+        return fail(p, CTQW_ERR_INVALID_ARG, "bad persistent / use_graph / waves_per_cu / chunked");
     const ctqw_launch old = p->launch;
     p->launch = *l;
     if (p->params_set) {

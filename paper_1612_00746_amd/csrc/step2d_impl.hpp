@@ -101,14 +101,18 @@ __device__ __forceinline__ double wave_sum(double v) {
 // space so that they land in scalar registers.
 template <typename T> using UniformPtr = const __attribute__((address_space(4))) T*;
 
-template <typename T, int NT, int P, bool KAHAN, bool TRI>
+// CHUNK: one pass of a chunked step (see StepArgs): the series continues
+// from Psi_s with run-time coefficients, the partial sum comes from acc_in,
+// and Psi_{s+NT} is stored for the next pass.
+template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false>
 __device__ __forceinline__ void process_item(const StepArgs& a, int home, int lane) {
     using C = typename CplxOf<T>::type;
     constexpr int WA = window_rows(NT);
     // Rows fetched ahead: a whole window for complex64 (512-byte rows need
     // many loads in flight to cover the HBM latency), three for complex128
-    // (1 KB rows, and the registers are taken by the wider windows).
-    constexpr int PF = sizeof(T) == 4 ? WA : 3;
+    // (1 KB rows, and the registers are taken by the wider windows) and for
+    // chunked passes (which fetch two rows per row).
+    constexpr int PF = (sizeof(T) == 4 && !CHUNK) ? WA : 3;
 
     const ItemDev it = a.items[home];
     const RealDev rd = a.reals[it.real];
@@ -124,8 +128,12 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     const UniformPtr<T> Er = (UniformPtr<T>)(epar<T>(a) + rd.row_param_off);
     const C* __restrict__ in = reinterpret_cast<const C*>(a.psi_in) + rd.state_off;
     C* __restrict__ out = reinterpret_cast<C*>(a.psi_out) + rd.state_off;
-    const T sc = static_cast<T>(a.scale[it.real]);
+    const T sc = (!CHUNK || a.first) ? static_cast<T>(a.scale[it.real]) : T(1);
     const T Udt = static_cast<T>(rd.U * a.dt);
+    const C* __restrict__ acc_in = reinterpret_cast<const C*>(CHUNK ? a.acc_in : a.psi_in) + rd.state_off;
+    C* __restrict__ seed_out = reinterpret_cast<C*>(CHUNK ? a.seed_out : a.psi_out) + rd.state_off;
+    const bool keep_seed = CHUNK && a.seed_out != nullptr;
+    const bool final_pass = !CHUNK || a.last;
 
     // Columns held by this lane.  Lanes outside [0, N) of an open chain hold
     // zeros with zero couplings, so they stay zero at every level.
@@ -150,14 +158,15 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     // loads are unconditional (lanes without a stored amplitude read the
     // realisation's first one) so that the prefetch never waits; the mask is
     // applied when the row is consumed.
-    auto load_row = [&](int qm, C (&dst)[P]) {
+    auto load_from = [&](const C* __restrict__ src, int qm, C (&dst)[P]) {
         const int base = TRI ? qm * N - (qm * (qm + 1)) / 2 : qm * N;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const bool ok = inb[p] && (!TRI || col[p] >= qm);
-            dst[p] = in[ok ? base + colw[p] : 0];
+            dst[p] = src[ok ? base + colw[p] : 0];
         }
     };
+    auto load_row = [&](int qm, C (&dst)[P]) { load_from(in, qm, dst); };
     auto row_mask = [&](int qm, int p) { return inb[p] && (!TRI || col[p] >= qm); };
 
     T fr[NT][3][P], fi[NT][3][P];   // Psi_j rows, j < NT
@@ -166,6 +175,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     T dg[WA][P];                    // dt * diagonal of H on the rows in flight
     T ju[WA];                       // dt * bond above each row in flight (uniform)
     C pre[PF][P];                   // rows being fetched
+    C prea[CHUNK ? PF : 1][P];      // chunked pass: their partial sums
     T pj[3], pe[3];                 // bond above and energy of the next rows (uniform)
 #pragma unroll
     for (int j = 0; j < NT; ++j)
@@ -194,6 +204,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 #pragma unroll
     for (int s = 0; s < PF; ++s) {   // rows past the sweep are fetched and ignored
         load_row(qm_pf, pre[s]);
+        if constexpr (CHUNK) load_from(acc_in, qm_pf, prea[s]);
         qm_pf = next_row(qm_pf);
         // Keep the prologue loads in slot order: the sweep consumes slot 0
         // first, and the wait it needs is then for the oldest load only.
@@ -230,23 +241,29 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     const int sp = u % PF;
                     const bool live = i < nrows;
                     const int qm = qm_in;
-                    C v[P];
+                    C v[P], va[P];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         v[p] = pre[sp][p];
-                        if (!(live && row_mask(qm, p))) { v[p].x = T(0); v[p].y = T(0); }
+                        va[p] = CHUNK ? prea[sp][p] : v[p];
+                        if (!(live && row_mask(qm, p))) {
+                            v[p].x = T(0);
+                            v[p].y = T(0);
+                            va[p] = v[p];
+                        }
                     }
                     const T er = pe[s];
                     ju[u] = live ? pj[s] : T(0);
                     load_row(qm_pf, pre[sp]);
+                    if constexpr (CHUNK) load_from(acc_in, qm_pf, prea[sp]);
                     fetch_params(qm_pp, s);
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const T re = v[p].x * sc, im = v[p].y * sc;
                         fr[0][s][p] = re;
                         fi[0][s][p] = im;
-                        ar[u][p] = re;
-                        ai[u][p] = im;
+                        ar[u][p] = CHUNK ? va[p].x * sc : re;
+                        ai[u][p] = CHUNK ? va[p].y * sc : im;
                         T vint = T(0);
                         if (rows > 1) {
                             int d = qm - colw[p];
@@ -273,8 +290,9 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     // Psi_j = sr_j A_j + i si_j B_j with A_j = H B_{j-1}, B_j = H A_{j-1}:
                     // the factor -i only swaps the two parts and moves signs, which are
                     // compile-time and folded into the accumulation coefficients.
-                    const T cr_j = static_cast<T>(sign_re(j) * inv_factorial(j));
-                    const T ci_j = static_cast<T>(sign_im(j) * inv_factorial(j));
+                    const T f_j = CHUNK ? static_cast<T>(a.coef[j - 1]) : static_cast<T>(inv_factorial(j));
+                    const T cr_j = static_cast<T>(sign_re(j)) * f_j;
+                    const T ci_j = static_cast<T>(sign_im(j)) * f_j;
                     T lr[P], li[P], rr[P], ri[P];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
@@ -318,7 +336,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         if (KAHAN && j == 1) {
                             // Kahan's update on the leading term: (a, c) with
                             // a - c = psi + Phi^(1) exactly.
-                            const T yr = cr_j * pr_, yi = ci_j * pi_;   // cr_1, ci_1 = +-1
+                            const T yr = cr_j * pr_, yi = ci_j * pi_;   // fused step: cr_1, ci_1 = +-1
                             const T tr = ar[w][p] + yr, ti = ai[w][p] + yi;
                             cr[w][p] = (tr - ar[w][p]) - yr;
                             ci[w][p] = (ti - ai[w][p]) - yi;
@@ -333,13 +351,25 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                             ar[w][p] += cr_j * pr_;
                             ai[w][p] += ci_j * pi_;
                         }
-                        if (j == NT) {
-                            const int q = i - NT;
+                        const bool tail_here = CHUNK ? (final_pass && j == a.tail_level) : (j == NT);
+                        if (tail_here) {
+                            const int q = i - j;
                             if (q >= 0 && qa >= it.out_lo && qa < it.out_hi) {
                                 double wgt = wcol[p];
                                 if (TRI) wgt = (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
                                 const double dr = pr_, di = pi_;
                                 tail = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), tail);
+                            }
+                        }
+                        if (CHUNK && j == NT && keep_seed) {
+                            // Psi_{s+NT} of row i - NT, with its true signs, for the next pass
+                            const int q = i - NT;
+                            if (q >= 0 && qa >= it.out_lo && qa < it.out_hi && outv[p] && (!TRI || col[p] >= qa)) {
+                                const int base = TRI ? qa * N - (qa * (qa + 1)) / 2 : qa * N;
+                                C sv;
+                                sv.x = static_cast<T>(sign_re(NT)) * pr_;
+                                sv.y = static_cast<T>(sign_im(NT)) * pi_;
+                                seed_out[base + colw[p]] = sv;
                             }
                         }
                     }
@@ -357,10 +387,12 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                             v.x = KAHAN ? ar[w][p] - cr[w][p] : ar[w][p];
                             v.y = KAHAN ? ai[w][p] - ci[w][p] : ai[w][p];
                             if (outv[p] && (!TRI || col[p] >= qa)) out[base + colw[p]] = v;
-                            double wgt = wcol[p];
-                            if (TRI) wgt = (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
-                            const double dr = v.x, di = v.y;
-                            nrm = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), nrm);
+                            if (final_pass) {
+                                double wgt = wcol[p];
+                                if (TRI) wgt = (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
+                                const double dr = v.x, di = v.y;
+                                nrm = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), nrm);
+                            }
                         }
                     }
                 }
@@ -369,8 +401,8 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     }
     nrm = wave_sum(nrm);
     tail = wave_sum(tail);
-    if (lane == 0) {
-        const double f = inv_factorial(NT);
+    if (lane == 0 && final_pass) {
+        const double f = CHUNK ? a.tail_coef : inv_factorial(NT);
         a.norm_part[home] = nrm;
         a.tail_part[home] = tail * f * f;
     }
@@ -393,7 +425,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 // past the last group.  Static assignments of items to waves (round-robin,
 // longest-processing-time) ran 20 % slower: the resident waves do not all
 // advance at the same rate, and only claiming at run time follows that.
-template <typename T, int NT, int P, bool KAHAN, bool TRI>
+template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false>
 __global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -404,7 +436,7 @@ __global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
         const int n_blocks = a.n_waves / wpb;
         for (int it = 0; g * wpb < a.n_items; ++it) {
             const int k = g * wpb + wv;
-            if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI>(a, a.item_order[k], lane);
+            if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI, CHUNK>(a, a.item_order[k], lane);
             if (wv == 0) {
                 const int t = atomicAdd(a.claim, 1);
                 if (lane == 0) next_group[it & 1] = __builtin_amdgcn_readfirstlane(t) / 64;
@@ -414,7 +446,7 @@ __global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
         }
     } else {
         const int k = g * wpb + wv;
-        if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI>(a, a.item_order[k], lane);
+        if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI, CHUNK>(a, a.item_order[k], lane);
     }
 }
 

@@ -135,8 +135,29 @@ def test_fixed_order_and_cap():
     assert list(plan.orders()) == [5, 5, 5]
     plan2 = make(dt=2.0, taylor_tol=1e-14)
     assert status_of(lambda: plan2.set_params(J, eps, U)) == 5   # NOT_CONVERGED
-    plan3 = make(taylor_order=30, taylor_tol=0.0)
+    plan3 = make(taylor_order=45, taylor_tol=0.0)      # above the default cap of 40
     assert status_of(lambda: plan3.set_params(J, eps, U)) == 5
+    plan4 = make(taylor_order=30, taylor_tol=0.0, taylor_max_order=25)
+    assert status_of(lambda: plan4.set_params(J, eps, U)) == 5
+
+
+def test_orders_above_the_fused_depth_run_in_passes():
+    """Order 20 (above the fused pipeline's 12 / 16 terms) is accepted and
+    laid out for chunked passes: 64-column bands with a halo of the pass
+    depth (8 terms complex64, 4 complex128) and three extra state buffers;
+    the chunked launch flag forces the same layout for low orders."""
+    for dtype, K, esz in (("c64", 8, 8), ("c128", 4, 16)):
+        N = 200
+        plan = make(R=1, n_sites=N, taylor_order=20, taylor_tol=0.0, dtype=dtype)
+        plan.set_params(np.ones(N - 1), np.zeros(N), np.zeros(1))
+        bands = -(-(N - (64 - K)) // (64 - 2 * K)) + 1
+        assert plan.work_items()[0] == bands, dtype
+        fused = make(R=1, n_sites=N, taylor_order=6, taylor_tol=0.0, dtype=dtype)
+        fused.set_params(np.ones(N - 1), np.zeros(N), np.zeros(1))
+        sb_f, ws_f = fused.sizes()
+        fused.set_launch(chunked=1)
+        sb_c, ws_c = fused.sizes()
+        assert ws_c - ws_f >= 3 * N * N * esz
 
 
 def test_layout_sizes_groups_uneven():
