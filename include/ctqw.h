@@ -294,8 +294,9 @@ ctqw_status ctqw_gradient(ctqw_plan* plan, int64_t n_steps, int64_t ckpt_every, 
 
 /* Autotuner.  Times `steps` propagation steps (after one warm-up step) for
  * every launch shape -- columns per lane {1, 2}, waves per block {1, 2, 4},
- * regular or persistent launch, and for the persistent form a cap of
- * {auto, 8, 16} resident waves per CU -- that fits the bound workspace,
+ * regular or persistent launch, for the persistent form a cap of
+ * {auto, 8, 16} resident waves per CU, and all terms in one pass or passes
+ * of K terms (one column per lane) -- that fits the bound workspace,
  * keeps the fastest (average step-kernel time from HIP events) and applies
  * it with ctqw_set_launch (use_graph is left as set).  With a cache path
  * (or the CTQW_TUNE_CACHE environment variable when cache_path is NULL),

@@ -530,23 +530,20 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
     uint8_t* seed_buf[2] = {p->ws + L.chunk.off, p->ws + L.chunk.off + sb};
     uint8_t* acc_tmp = p->ws + L.chunk.off + 2 * sb;
     auto acc_buf = [&](int q) -> void* { return ((passes - 1 - q) & 1) == 0 ? out : acc_tmp; };
-    double inv_fact_n = 1.0;
-    for (int k = 2; k <= n; ++k) inv_fact_n /= k;
-    double f = 1.0;   // 1 / s!
+    // 1/k! as one division of the product, as the fused kernel's constants
+    auto inv_fact = [](int k) {
+        double prod = 1.0;
+        for (int i = 2; i <= k; ++i) prod *= i;
+        return 1.0 / prod;
+    };
+    const double inv_fact_n = inv_fact(n);
     for (int q = 0; q < passes; ++q) {
         const int s0 = q * K;
         a.psi_in = q == 0 ? in : seed_buf[(q - 1) & 1];
         a.acc_in = q == 0 ? in : acc_buf(q - 1);
         a.psi_out = acc_buf(q);
         a.seed_out = q == passes - 1 ? nullptr : seed_buf[q & 1];
-        for (int j = 1; j <= 16; ++j) {
-            if (j <= K && s0 + j <= n) {
-                f /= (s0 + j);
-                a.coef[j - 1] = f;
-            } else {
-                a.coef[j - 1] = 0.0;
-            }
-        }
+        for (int j = 1; j <= 16; ++j) a.coef[j - 1] = (j <= K && s0 + j <= n) ? inv_fact(s0 + j) : 0.0;
         a.first = q == 0;
         a.last = q == passes - 1;
         a.tail_level = a.last ? n - s0 : 0;
@@ -738,7 +735,7 @@ ctqw_status read_status(ctqw_plan* p, int32_t* st) {
 
 extern "C" {
 
-const char* ctqw_version(void) { return "ctqw-mi355x 0.1 (gfx950)"; }
+const char* ctqw_version(void) { return "ctqw-mi355x 0.2 (gfx950)"; }
 
 const char* ctqw_status_string(ctqw_status s) {
     switch (s) {
@@ -1277,6 +1274,7 @@ bool cache_lookup(const char* path, const std::string& key, ctqw_launch* out, do
         if (parse_int_field(s, "cols_per_lane", &l.cols_per_lane) &&
             parse_int_field(s, "waves_per_block", &l.waves_per_block) &&
             parse_int_field(s, "persistent", &l.persistent) && parse_int_field(s, "waves_per_cu", &l.waves_per_cu)) {
+            if (!parse_int_field(s, "chunked", &l.chunked)) l.chunked = 0;
             *out = l;
             const size_t at = s.find("\"ms\": ");
             *ms = at == std::string::npos ? NAN : atof(s.c_str() + at + 6);
@@ -1292,8 +1290,8 @@ void cache_append(const char* path, const std::string& key, const ctqw_launch& l
     if (!f) return;
     fprintf(f,
             "{\"key\": \"%s\", \"cols_per_lane\": %d, \"waves_per_block\": %d, \"persistent\": %d, "
-            "\"waves_per_cu\": %d, \"ms\": %.6f}\n",
-            key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, ms);
+            "\"waves_per_cu\": %d, \"chunked\": %d, \"ms\": %.6f}\n",
+            key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, l.chunked, ms);
     fclose(f);
 }
 
@@ -1354,16 +1352,19 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
         }
     }
     if (!cached) {
+        for (int chunked : {0, 1})
         for (int P : {1, 2})
             for (int wpb : {1, 2, 4})
                 for (int pers : {0, 1})
                     for (int cap : {0, 8, 16}) {
                         if (!pers && cap) continue;
+                        if (chunked && (P != 1 || p->prob.m == 3)) continue;   // passes run one column per lane
                         ctqw_launch c = orig;
                         c.cols_per_lane = P;
                         c.waves_per_block = wpb;
                         c.persistent = pers;
                         c.waves_per_cu = cap;
+                        c.chunked = chunked;
                         p->launch = c;
                         if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
                         if ((st = upload_tables(p)) != CTQW_OK) return st;

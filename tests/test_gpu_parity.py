@@ -274,20 +274,23 @@ def test_autotune_applies_and_caches_a_shape(tmp_path):
                   reals=reals, dt=0.05, tol=1e-7)
     best, ms = p1.autotune(cache, steps=2)
     say(f"  best: P={best.cols_per_lane} wpb={best.waves_per_block} persistent={best.persistent} "
-        f"cap={best.waves_per_cu} {ms:.4f} ms")
+        f"cap={best.waves_per_cu} chunked={best.chunked} {ms:.4f} ms")
     assert ms > 0 and open(cache).read().count("\n") == 1
     p2 = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
                   reals=reals, dt=0.05, tol=1e-7)
     best2, ms2 = p2.autotune(cache, steps=2)
-    assert (best2.cols_per_lane, best2.waves_per_block, best2.persistent) == \
-        (best.cols_per_lane, best.waves_per_block, best.persistent)
+    assert (best2.cols_per_lane, best2.waves_per_block, best2.persistent, best2.chunked) == \
+        (best.cols_per_lane, best.waves_per_block, best.persistent, best.chunked)
     assert open(cache).read().count("\n") == 1
     ref = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
                    reals=reals, dt=0.05, tol=1e-7)
     for p in (p1, ref):
         p.init_product_state([30, 31])
         p.propagate(10)
-    assert np.array_equal(p1.state_numpy(), ref.state_numpy())
+    if best.cols_per_lane == 1:
+        assert np.array_equal(p1.state_numpy(), ref.state_numpy())
+    else:   # two columns per lane round differently (see the launch-shape tests)
+        assert np.max(np.abs(p1.state_numpy() - ref.state_numpy())) < 2e-6
 
 
 def test_boson_kernel_matches_distinguishable_symmetrised():
