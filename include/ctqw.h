@@ -120,8 +120,8 @@ typedef struct {
     int32_t waves_per_cu;    /* persistent grid: resident waves per CU (0: auto) */
     int32_t chunked;         /* 0: all n Taylor terms of a step in one pass over
                                 the state when n fits the compiled pipeline
-                                (12 terms complex64 / 16 complex128 at one
-                                column per lane, 10 / 8 at two), else passes;
+                                (12 terms at one column per lane, 9 complex64
+                                / 7 complex128 at two), else passes;
                                 1: always passes of K terms (K = 8 complex64,
                                 4 complex128, one column per lane), each
                                 reading and writing the partial sum and the

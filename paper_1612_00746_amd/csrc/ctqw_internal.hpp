@@ -91,9 +91,12 @@ hipError_t launch_step(const StepConfig& cfg, const StepArgs& args, hipStream_t 
 constexpr int chunk_depth(int dtype) { return dtype == 1 ? 4 : 8; }
 hipError_t launch_chunk_pass(const StepConfig& cfg, const StepArgs& args, hipStream_t stream);
 hipError_t chunk_occupancy(const StepConfig& cfg, int* blocks_per_cu);
+hipError_t chunk_max_block(const StepConfig& cfg, int* threads);
 // Smallest compiled pipeline depth >= order (-1 if none).
 int step_levels_bucket(int dtype, int cols_per_lane, int order);
 hipError_t step_occupancy(const StepConfig& cfg, int* blocks_per_cu);
+// Largest block the selected kernel was compiled for (its launch bound).
+hipError_t step_max_block(const StepConfig& cfg, int* threads);
 
 struct FinalizeArgs {
     const int32_t* item_first;   // [R + 1] home items of each realisation

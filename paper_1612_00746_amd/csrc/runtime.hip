@@ -391,6 +391,12 @@ StepConfig step_config(ctqw_plan* p) {
 }
 
 ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
+    int max_threads = 0;
+    if (p->chunk) HIP_TRY(p, chunk_max_block(c, &max_threads));
+    else HIP_TRY(p, step_max_block(c, &max_threads));
+    if (64 * c.waves_per_block > max_threads)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "%d waves per block exceed this kernel's %d threads", c.waves_per_block,
+                    max_threads);
     if (!c.persistent) {
         *n_waves = (int)p->items.size();
         return CTQW_OK;
@@ -1369,7 +1375,9 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
                         if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
                         if ((st = upload_tables(p)) != CTQW_OK) return st;
                         double ms = INFINITY;
-                        if ((st = time_steps(p, steps, &ms)) != CTQW_OK) return st;
+                        st = time_steps(p, steps, &ms);
+                        if (st == CTQW_ERR_UNSUPPORTED) continue;   // block larger than the kernel's bound
+                        if (st != CTQW_OK) return st;
                         if (ms < best_ms) {
                             best_ms = ms;
                             best = c;

@@ -29,6 +29,15 @@ hipError_t launch_chunk_pass(const StepConfig& cfg, const StepArgs& args, hipStr
     return hipGetLastError();
 }
 
+hipError_t chunk_max_block(const StepConfig& cfg, int* threads) {
+    StepKernelFn fn = select_chunk(cfg);
+    if (!fn) return hipErrorInvalidValue;
+    hipFuncAttributes attr{};
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(fn));
+    if (e == hipSuccess) *threads = attr.maxThreadsPerBlock;
+    return e;
+}
+
 hipError_t chunk_occupancy(const StepConfig& cfg, int* blocks_per_cu) {
     StepKernelFn fn = select_chunk(cfg);
     if (!fn) return hipErrorInvalidValue;

@@ -15,10 +15,11 @@ CTQW_DECLARE_TABLE(f64_p2_full) CTQW_DECLARE_TABLE(f64_p2_tri)
 namespace {
 
 // Deepest compiled pipeline per (dtype, columns per lane); every depth from
-// 1 up to it is compiled (see the step2d_*.hip tables).
+// 1 up to it is compiled (see the step2d_*.hip tables).  Deeper pipelines
+// spill to scratch memory; their orders run as chunked passes.
 int max_levels(int dtype, int cols_per_lane) {
-    if (dtype == 1) return cols_per_lane == 1 ? 16 : 8;
-    return cols_per_lane == 1 ? 12 : 10;
+    if (dtype == 1) return cols_per_lane == 1 ? 12 : 7;
+    return cols_per_lane == 1 ? 12 : 9;
 }
 
 StepKernelFn select_kernel(const StepConfig& c) {
@@ -47,6 +48,15 @@ hipError_t step_occupancy(const StepConfig& cfg, int* blocks_per_cu) {
     if (!fn) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, reinterpret_cast<const void*>(fn),
                                                         cfg.waves_per_block * 64, 0);
+}
+
+hipError_t step_max_block(const StepConfig& cfg, int* threads) {
+    StepKernelFn fn = select_kernel(cfg);
+    if (!fn) return hipErrorInvalidValue;
+    hipFuncAttributes attr{};
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(fn));
+    if (e == hipSuccess) *threads = attr.maxThreadsPerBlock;
+    return e;
 }
 
 hipError_t launch_step(const StepConfig& cfg, const StepArgs& args, hipStream_t stream) {

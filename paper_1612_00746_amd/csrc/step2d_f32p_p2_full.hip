@@ -13,7 +13,6 @@ StepKernelFn step_table_f32p_p2_full(int levels) {
         CTQW_STEP_CASE(float, 7, 2, false, false)
         CTQW_STEP_CASE(float, 8, 2, false, false)
         CTQW_STEP_CASE(float, 9, 2, false, false)
-        CTQW_STEP_CASE(float, 10, 2, false, false)
         default: return nullptr;
     }
 }

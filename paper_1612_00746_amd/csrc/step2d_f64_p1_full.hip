@@ -16,10 +16,6 @@ StepKernelFn step_table_f64_p1_full(int levels) {
         CTQW_STEP_CASE(double, 10, 1, false, false)
         CTQW_STEP_CASE(double, 11, 1, false, false)
         CTQW_STEP_CASE(double, 12, 1, false, false)
-        CTQW_STEP_CASE(double, 13, 1, false, false)
-        CTQW_STEP_CASE(double, 14, 1, false, false)
-        CTQW_STEP_CASE(double, 15, 1, false, false)
-        CTQW_STEP_CASE(double, 16, 1, false, false)
         default: return nullptr;
     }
 }

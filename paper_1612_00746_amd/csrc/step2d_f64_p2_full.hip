@@ -11,7 +11,6 @@ StepKernelFn step_table_f64_p2_full(int levels) {
         CTQW_STEP_CASE(double, 5, 2, false, false)
         CTQW_STEP_CASE(double, 6, 2, false, false)
         CTQW_STEP_CASE(double, 7, 2, false, false)
-        CTQW_STEP_CASE(double, 8, 2, false, false)
         default: return nullptr;
     }
 }

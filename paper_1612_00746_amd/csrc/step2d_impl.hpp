@@ -193,7 +193,9 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     }
     // Grid rows are tracked incrementally: qm_in is the row entering at the
     // current iteration, qm_pf the one fetched PF iterations ahead and qm_pp
-    // the one whose couplings are read three iterations ahead.
+    // the one whose couplings are read three iterations ahead.  (Holding the
+    // fetch on the sweep's last row instead of running past it measured the
+    // same.)
     auto next_row = [&](int x) { return (x + 1 == rows) ? 0 : x + 1; };
     auto fetch_params = [&](int qm, int s) {
         pj[s] = Jr[qm == 0 ? rows - 1 : qm - 1];   // the padded last bond is 0 on an open chain
@@ -201,11 +203,12 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     };
     int qm_in = periodic ? wrap(it.row0, rows) : it.row0;
     int qm_pf = qm_in, qm_pp = qm_in;
+    auto advance_pf = [&]() { qm_pf = next_row(qm_pf); };
 #pragma unroll
     for (int s = 0; s < PF; ++s) {   // rows past the sweep are fetched and ignored
         load_row(qm_pf, pre[s]);
         if constexpr (CHUNK) load_from(acc_in, qm_pf, prea[s]);
-        qm_pf = next_row(qm_pf);
+        advance_pf();
         // Keep the prologue loads in slot order: the sweep consumes slot 0
         // first, and the wait it needs is then for the oldest load only.
         __builtin_amdgcn_sched_barrier(0);
@@ -274,7 +277,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         dg[u][p] = er + ec[p] + vint;
                     }
                     qm_in = next_row(qm_in);
-                    qm_pf = next_row(qm_pf);
+                    advance_pf();
                     qm_pp = next_row(qm_pp);
                 }
                 // ---- levels 1..NT: Psi_j on row i - j.
