@@ -143,7 +143,7 @@ def _rows(path):
         return list(csv.DictReader(fh))
 
 
-def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY):
+def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols_per_lane=1):
     """Write the step kernel's rocprofv3 summary: duration statistics from
     the kernel trace, FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the
     same counters read for the 4 GiB device copy of the same run."""
@@ -179,7 +179,7 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY):
         "Workload: 4096 realisations of two distinguishable walkers on open chains,",
         "N uniform in {64, 96, ..., 1024}, U ~ U[0, 4], J ~ N(1, 0.1^2), dt = 0.05,",
         "Taylor tolerance 1e-7 (7 terms), complex64 with the compensated sum;",
-        "persistent launch, P = 1, 4 waves per block, captured step loop.",
+        f"persistent launch, {cols_per_lane} column(s) per lane, 4 waves per block, captured step loop.",
         "",
         "Commands (from the repository root, TMPDIR=/tmp):",
         "",
@@ -263,14 +263,15 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM counters)")
-    ap.add_argument("--regular", action="store_true", help="one wave per work item instead of the persistent grid")
+    ap.add_argument("--regular", action="store_true", help="one block per item group instead of the persistent grid")
+    ap.add_argument("--no-autotune", action="store_true", help="keep --cols-per-lane and 4 waves per block")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the step kernel's rocprofv3 summary under profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the profile summary (repeatable)")
     a = ap.parse_args()
     if a.profile_summary:
-        profile_summary(*a.profile_summary, commands=a.profile_command)
+        profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: realisations are independent, and a multi-GPU run would "
@@ -309,6 +310,26 @@ def main():
               "use_graph": 1}
     log("building the complex64 plan ...")
     plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
+    tuned = None
+    if not a.no_autotune:
+        # The autotuner times every launch shape on this batch; the batch's
+        # launch form stays persistent with the captured step loop, and the
+        # tuned columns per lane, waves per block, wave cap and chunking are
+        # kept.  The state is overwritten by tuning: start again after it.
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            best, best_ms = plan.autotune(os.path.join(td, "tune.jsonl"), steps=3)
+        tuned = {"cols_per_lane": best.cols_per_lane, "waves_per_block": best.waves_per_block,
+                 "persistent": best.persistent, "waves_per_cu": best.waves_per_cu, "chunked": best.chunked,
+                 "ms": round(best_ms, 4)}
+        log(f"autotune: {tuned}")
+        launch = {"cols_per_lane": best.cols_per_lane, "persistent": 0 if a.regular else 1,
+                  "waves_per_block": best.waves_per_block, "waves_per_cu": best.waves_per_cu,
+                  "chunked": best.chunked, "use_graph": 1}
+        plan.set_launch(**launch)
+        plan.bind()
+        sizes0 = w.lattice_sizes()
+        plan.init_product_state(np.array([[n // 2 - 1, n // 2] for n in sizes0], dtype=np.int32))
     log("timing complex64 ...")
     wall, kern_ms = time_plan(plan, a.steps, a.warmup)
     log(f"complex64: {1e3 * wall / a.steps:.3f} ms/step, kernel {kern_ms:.3f} ms")
@@ -364,6 +385,7 @@ def main():
         "norm_range": [st.min_norm, st.max_norm],
         "cpu_baseline": cpu,
         "copy_probe": copy_probe,
+        "autotune": tuned,
     }
     print(json.dumps(line))
 

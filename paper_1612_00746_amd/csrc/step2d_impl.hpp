@@ -101,6 +101,19 @@ __device__ __forceinline__ double wave_sum(double v) {
 // space so that they land in scalar registers.
 template <typename T> using UniformPtr = const __attribute__((address_space(4))) T*;
 
+// A table entry read word by word through the constant address space (a
+// struct copy cannot bind to that address space).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const S* table, int index) {
+    static_assert(sizeof(S) % 4 == 0, "word-sized entries");
+    S v;
+    const UniformPtr<int32_t> src = (UniformPtr<int32_t>)(table + index);
+    int32_t* dst = reinterpret_cast<int32_t*>(&v);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(S) / 4); ++k) dst[k] = src[k];
+    return v;
+}
+
 // CHUNK: one pass of a chunked step (see StepArgs): the series continues
 // from Psi_s with run-time coefficients, the partial sum comes from acc_in,
 // and Psi_{s+NT} is stored for the next pass.
@@ -112,10 +125,12 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     // many loads in flight to cover the HBM latency), three for complex128
     // (1 KB rows, and the registers are taken by the wider windows) and for
     // chunked passes (which fetch two rows per row).
-    constexpr int PF = (sizeof(T) == 4 && !CHUNK) ? WA : 3;
+    constexpr int PF = (sizeof(T) == 4 && !CHUNK && P == 1) ? WA : 3;
 
-    const ItemDev it = a.items[home];
-    const RealDev rd = a.reals[it.real];
+    // The item and its realisation are wave-uniform: scalar loads, so every
+    // pointer and row base derived from them stays in scalar registers.
+    const ItemDev it = load_uniform(a.items, home);
+    const RealDev rd = load_uniform(a.reals, it.real);
     const int N = rd.N;
     const int rows = rd.rows;
     const int nrows = it.nrows;
@@ -128,7 +143,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     const UniformPtr<T> Er = (UniformPtr<T>)(epar<T>(a) + rd.row_param_off);
     const C* __restrict__ in = reinterpret_cast<const C*>(a.psi_in) + rd.state_off;
     C* __restrict__ out = reinterpret_cast<C*>(a.psi_out) + rd.state_off;
-    const T sc = (!CHUNK || a.first) ? static_cast<T>(a.scale[it.real]) : T(1);
+    const T sc = (!CHUNK || a.first) ? static_cast<T>(((UniformPtr<double>)a.scale)[it.real]) : T(1);
     const T Udt = static_cast<T>(rd.U * a.dt);
     const C* __restrict__ acc_in = reinterpret_cast<const C*>(CHUNK ? a.acc_in : a.psi_in) + rd.state_off;
     C* __restrict__ seed_out = reinterpret_cast<C*>(CHUNK ? a.seed_out : a.psi_out) + rd.state_off;
@@ -156,18 +171,28 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 
     // Row of the grid (wrapped on a ring) -> its stored amplitudes.  The
     // loads are unconditional (lanes without a stored amplitude read the
-    // realisation's first one) so that the prefetch never waits; the mask is
-    // applied when the row is consumed.
+    // row's first one) so that the prefetch never waits; the mask is applied
+    // when the row is consumed.  The row base is wave-uniform and each lane
+    // adds a fixed byte offset, so a load needs no per-row vector arithmetic
+    // (full grid; the triangle's mask moves with the row).
+    uint32_t loff[P];
+    T lmul[P];                      // load scale, 0 on lanes without an amplitude
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        loff[p] = inb[p] ? (uint32_t)colw[p] * (uint32_t)sizeof(C) : 0u;
+        lmul[p] = inb[p] ? sc : T(0);
+    }
     auto load_from = [&](const C* __restrict__ src, int qm, C (&dst)[P]) {
         const int base = TRI ? qm * N - (qm * (qm + 1)) / 2 : qm * N;
+        const char* row = reinterpret_cast<const char*>(src + base);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const bool ok = inb[p] && (!TRI || col[p] >= qm);
-            dst[p] = src[ok ? base + colw[p] : 0];
+            uint32_t off = loff[p];
+            if (TRI && col[p] < qm) off = 0u;
+            dst[p] = *reinterpret_cast<const C*>(row + off);
         }
     };
     auto load_row = [&](int qm, C (&dst)[P]) { load_from(in, qm, dst); };
-    auto row_mask = [&](int qm, int p) { return inb[p] && (!TRI || col[p] >= qm); };
 
     T fr[NT][3][P], fi[NT][3][P];   // Psi_j rows, j < NT
     T ar[WA][P], ai[WA][P];         // partial sums of the rows in flight
@@ -225,7 +250,10 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 #pragma unroll
     for (int p = 0; p < P; ++p) wcol[p] = outv[p] ? 1.0 : 0.0;
 
-    double nrm = 0.0, tail = 0.0;
+    double nrm = 0.0, tail = 0.0;   // triangle: weighted per row
+    double nrmp[P], tailp[P];       // full grid: per column, weighted at the end
+#pragma unroll
+    for (int p = 0; p < P; ++p) nrmp[p] = tailp[p] = 0.0;
     // The sweep runs nrows + NT iterations, rounded up to whole unrolled
     // blocks: the extra iterations see zero rows and store nothing, and the
     // block body has no early exit (which keeps the prefetch waits exact).
@@ -245,36 +273,49 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     const bool live = i < nrows;
                     const int qm = qm_in;
                     C v[P], va[P];
+                    T mul[P];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         v[p] = pre[sp][p];
                         va[p] = CHUNK ? prea[sp][p] : v[p];
-                        if (!(live && row_mask(qm, p))) {
-                            v[p].x = T(0);
-                            v[p].y = T(0);
-                            va[p] = v[p];
-                        }
+                        // zero past the sweep and off the stored lanes (incl. the triangle's lower part)
+                        mul[p] = (live && (!TRI || col[p] >= qm)) ? lmul[p] : T(0);
                     }
                     const T er = pe[s];
                     ju[u] = live ? pj[s] : T(0);
+                    // consume the slot before it is refilled (no copy of the old row)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const T re = v[p].x * mul[p], im = v[p].y * mul[p];
+                        fr[0][s][p] = re;
+                        fi[0][s][p] = im;
+                        ar[u][p] = CHUNK ? va[p].x * mul[p] : re;
+                        ai[u][p] = CHUNK ? va[p].y * mul[p] : im;
+                    }
                     load_row(qm_pf, pre[sp]);
                     if constexpr (CHUNK) load_from(acc_in, qm_pf, prea[sp]);
                     fetch_params(qm_pp, s);
+                    // The columns that interact with row qm (wave-uniform): qm itself
+                    // (on site), or qm - 1 and qm + 1 (nearest, wrapped on a ring;
+                    // off the chain they match no stored column).  -2^30: none.
+                    int t1 = -(1 << 30), t2 = -(1 << 30);
+                    if (rows > 1) {
+                        if (nearest) {
+                            t1 = qm - 1;
+                            t2 = qm + 1;
+                            if (periodic) {
+                                t1 = t1 < 0 ? t1 + N : t1;
+                                t2 = t2 >= N ? t2 - N : t2;
+                            }
+                        } else {
+                            t1 = qm;
+                        }
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const T re = v[p].x * sc, im = v[p].y * sc;
-                        fr[0][s][p] = re;
-                        fi[0][s][p] = im;
-                        ar[u][p] = CHUNK ? va[p].x * sc : re;
-                        ai[u][p] = CHUNK ? va[p].y * sc : im;
-                        T vint = T(0);
-                        if (rows > 1) {
-                            int d = qm - colw[p];
-                            d = d < 0 ? -d : d;
-                            if (periodic && N - d < d) d = N - d;
-                            vint = (d == (nearest ? 1 : 0)) ? Udt : T(0);
-                        }
-                        dg[u][p] = er + ec[p] + vint;
+                        T d0 = er + ec[p];
+                        if (colw[p] == t1 || colw[p] == t2) d0 += Udt;
+                        dg[u][p] = d0;
                     }
                     qm_in = next_row(qm_in);
                     advance_pf();
@@ -358,10 +399,15 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         if (tail_here) {
                             const int q = i - j;
                             if (q >= 0 && qa >= it.out_lo && qa < it.out_hi) {
-                                double wgt = wcol[p];
-                                if (TRI) wgt = (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
                                 const double dr = pr_, di = pi_;
-                                tail = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), tail);
+                                if (TRI) {
+                                    const double wgt =
+                                        (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
+                                    tail = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), tail);
+                                } else {   // column weight applied once at the end
+                                    tailp[p] = __builtin_fma(dr, dr, tailp[p]);
+                                    tailp[p] = __builtin_fma(di, di, tailp[p]);
+                                }
                             }
                         }
                         if (CHUNK && j == NT && keep_seed) {
@@ -372,7 +418,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                                 C sv;
                                 sv.x = static_cast<T>(sign_re(NT)) * pr_;
                                 sv.y = static_cast<T>(sign_im(NT)) * pi_;
-                                seed_out[base + colw[p]] = sv;
+                                *reinterpret_cast<C*>(reinterpret_cast<char*>(seed_out + base) + loff[p]) = sv;
                             }
                         }
                     }
@@ -389,17 +435,30 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                             C v;
                             v.x = KAHAN ? ar[w][p] - cr[w][p] : ar[w][p];
                             v.y = KAHAN ? ai[w][p] - ci[w][p] : ai[w][p];
-                            if (outv[p] && (!TRI || col[p] >= qa)) out[base + colw[p]] = v;
+                            if (outv[p] && (!TRI || col[p] >= qa))
+                                *reinterpret_cast<C*>(reinterpret_cast<char*>(out + base) + loff[p]) = v;
                             if (final_pass) {
-                                double wgt = wcol[p];
-                                if (TRI) wgt = (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
                                 const double dr = v.x, di = v.y;
-                                nrm = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), nrm);
+                                if (TRI) {
+                                    const double wgt =
+                                        (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
+                                    nrm = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), nrm);
+                                } else {
+                                    nrmp[p] = __builtin_fma(dr, dr, nrmp[p]);
+                                    nrmp[p] = __builtin_fma(di, di, nrmp[p]);
+                                }
                             }
                         }
                     }
                 }
             }
+        }
+    }
+    if (!TRI) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            nrm = __builtin_fma(wcol[p], nrmp[p], nrm);
+            tail = __builtin_fma(wcol[p], tailp[p], tail);
         }
     }
     nrm = wave_sum(nrm);
@@ -428,28 +487,35 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 // past the last group.  Static assignments of items to waves (round-robin,
 // longest-processing-time) ran 20 % slower: the resident waves do not all
 // advance at the same rate, and only claiming at run time follows that.
+// Two columns per lane in complex64 up to 7 terms sit at the 256-VGPR line
+// (two waves per SIMD); ask the compiler to stay under it.
+template <typename T, int NT, int P, bool CHUNK>
+constexpr int min_blocks_per_cu() {
+    return (P == 2 && sizeof(T) == 4 && NT <= 7 && !CHUNK) ? 2 : 1;
+}
+
 template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false>
-__global__ void __launch_bounds__(256) step2d_kernel(StepArgs a) {
+__global__ void __launch_bounds__(256, (min_blocks_per_cu<T, NT, P, CHUNK>())) step2d_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __shared__ int next_group[2];
+    const int n_blocks = a.persistent ? a.n_waves / wpb : 0;
+    // One loop for both forms, so the item code is inlined once and both
+    // forms run the same instructions: a regular launch leaves after its
+    // first group.
     int g = blockIdx.x;
-    if (a.persistent) {
-        __shared__ int next_group[2];
-        const int n_blocks = a.n_waves / wpb;
-        for (int it = 0; g * wpb < a.n_items; ++it) {
-            const int k = g * wpb + wv;
-            if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI, CHUNK>(a, a.item_order[k], lane);
-            if (wv == 0) {
-                const int t = atomicAdd(a.claim, 1);
-                if (lane == 0) next_group[it & 1] = __builtin_amdgcn_readfirstlane(t) / 64;
-            }
-            __syncthreads();
-            g = n_blocks + __builtin_amdgcn_readfirstlane(next_group[it & 1]);
-        }
-    } else {
+    for (int it = 0; g * wpb < a.n_items; ++it) {
         const int k = g * wpb + wv;
-        if (k < a.n_items) process_item<T, NT, P, KAHAN, TRI, CHUNK>(a, a.item_order[k], lane);
+        if (k < a.n_items)
+            process_item<T, NT, P, KAHAN, TRI, CHUNK>(a, ((UniformPtr<int32_t>)a.item_order)[k], lane);
+        if (!a.persistent) break;
+        if (wv == 0) {
+            const int t = atomicAdd(a.claim, 1);
+            if (lane == 0) next_group[it & 1] = __builtin_amdgcn_readfirstlane(t) / 64;
+        }
+        __syncthreads();
+        g = n_blocks + __builtin_amdgcn_readfirstlane(next_group[it & 1]);
     }
 }
 
