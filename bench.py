@@ -12,22 +12,23 @@ realisation (all Taylor terms, the FP64 norm / truncation check).
 Metric: amplitude-updates/s = (stored amplitudes of all realisations) x
 (steps) / (time); one update advances one amplitude by one dt.  The state
 is resident in HBM before the timed region.  The same JSON line carries
-  * roofline: algorithmic HBM bytes of the dominant (step) kernel per launch
-    (read psi + write psi once) over its average duration, timed with HIP
+  * roofline: algorithmic HBM bytes of the dominant (step) kernel per step
+    (read psi + write psi once) over its duration per step, timed with HIP
     events on the kernel's stream, against the 8 TB/s HBM3E peak;
   * fp64_plain: the same workload with complex128 state at the same
-    per-step tolerance, one regular launch per step;
+    per-step tolerance, regular launches;
   * cpu_baseline: the FP64 oracle (CSR Taylor propagator) timed on a bounded
     sample of the same workload on the host cores.
 
-The timed region replays the captured step loop (one persistent launch of
-the step kernel per step, plus the FP64 finalize).  The step kernel's
-duration is taken from HIP events on the plan's stream around each replay,
-divided by its steps: it includes the ~7 us finalize kernel per step, so
-`roofline.achieved` is a slight underestimate (the rocprofv3 kernel average
-under profiles/ gives the kernel alone).
+The timed region replays the captured step loop (per step: one persistent
+launch of the step kernel per Taylor order present in the batch, each at
+its own depth, plus the FP64 finalize).  The step kernels' duration is
+taken from HIP events on the plan's stream around each replay, divided by
+its steps: it includes the ~7 us finalize kernel and the claim-counter
+fills, so `roofline.achieved` is a slight underestimate (the rocprofv3
+kernel averages under profiles/ give the kernels alone).
 
-`roofline.traffic` is the HBM traffic per launch from rocprofv3 counters,
+`roofline.traffic` is the HBM traffic per step from rocprofv3 counters,
 read from the summary under profiles/ that `--profile-summary` writes; it is
 reported only while the step kernel's sources hash to the value recorded
 there (null otherwise).
@@ -144,9 +145,11 @@ def _rows(path):
 
 
 def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols_per_lane=1):
-    """Write the step kernel's rocprofv3 summary: duration statistics from
+    """Write the step kernels' rocprofv3 summary: duration statistics from
     the kernel trace, FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the
-    same counters read for the 4 GiB device copy of the same run."""
+    same counters read for the 4 GiB device copy of the same run.  A step
+    launches one complex64 step kernel per Taylor order present in the
+    batch; per-step figures are sums over those kernels."""
     def find(d, suffix):
         for root, _, files in os.walk(d):
             for f in files:
@@ -154,48 +157,58 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
                     return os.path.join(root, f)
         raise FileNotFoundError(f"{suffix} under {d}")
     stats = [r for r in _rows(find(trace_dir, "kernel_stats.csv")) if "step2d_kernel<float" in r["Name"]]
-    if len(stats) != 1:
-        raise SystemExit("expected one complex64 step kernel in the trace")
-    st = stats[0]
+    if not stats:
+        raise SystemExit("no complex64 step kernel in the trace")
+    calls = {int(r["Calls"]) for r in stats}
+    if len(calls) != 1:
+        raise SystemExit(f"step kernels dispatched unequal times: {sorted(calls)}")
     probe_bytes = 4096 << 20
 
     def counter(d, name):
         rows = [r for r in _rows(find(d, "counter_collection.csv")) if r["Counter_Name"] == name]
-        k = [float(r["Counter_Value"]) for r in rows if "step2d_kernel<float" in r["Kernel_Name"]]
+        per = {}
+        for r in rows:
+            if "step2d_kernel<float" in r["Kernel_Name"]:
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
         c = [float(r["Counter_Value"]) for r in rows
              if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 100000]
-        if not k or not c:
-            raise SystemExit(f"{name}: no step kernel or copy probe dispatches in {d}")
-        return sum(k) / len(k), sum(c) / len(c)
+        if len(per) != len(stats) or not c:
+            raise SystemExit(f"{name}: step kernels or copy probe dispatches missing in {d}")
+        return {k: sum(v) / len(v) for k, v in per.items()}, sum(c) / len(c)
     fk, fc = counter(fetch_dir, "FETCH_SIZE")
     wk, wc = counter(write_dir, "WRITE_SIZE")
     f_scale = probe_bytes / (fc * 1024.0)
     w_scale = probe_bytes / (wc * 1024.0)
-    fetch_b = fk * 1024.0 * f_scale
-    write_b = wk * 1024.0 * w_scale
+    fetch_b = sum(fk.values()) * 1024.0 * f_scale
+    write_b = sum(wk.values()) * 1024.0 * w_scale
+    step_ns = sum(float(r["AverageNs"]) for r in stats)
     lines = [
-        f"# {st['Name']}",
+        "# complex64 step kernels (step2d_kernel<float, ...>)",
         "",
         "Workload: 4096 realisations of two distinguishable walkers on open chains,",
         "N uniform in {64, 96, ..., 1024}, U ~ U[0, 4], J ~ N(1, 0.1^2), dt = 0.05,",
-        "Taylor tolerance 1e-7 (7 terms), complex64 with the compensated sum;",
-        f"persistent launch, {cols_per_lane} column(s) per lane, 4 waves per block, captured step loop.",
+        "Taylor tolerance 1e-7 (6 or 7 terms per realisation), complex64 with the",
+        f"compensated sum; persistent launches, {cols_per_lane} column(s) per lane, 4 waves per block,",
+        "captured step loop; one launch per Taylor order and step.",
         "",
         "Commands (from the repository root, TMPDIR=/tmp):",
         "",
         *[f"    {c}" for c in commands],
         "",
-        "| quantity | value |",
+        "| kernel | dispatches | average | min / max | FETCH_SIZE | WRITE_SIZE |",
+        "|---|---|---|---|---|---|",
+        *[f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} ms | "
+          f"{float(r['MinNs']) / 1e6:.4f} / {float(r['MaxNs']) / 1e6:.4f} ms | "
+          f"{fk.get(r['Name'], float('nan')):.0f} KiB | {wk.get(r['Name'], float('nan')):.0f} KiB |"
+          for r in stats],
+        "",
+        "| per step (sum over the step kernels) | value |",
         "|---|---|",
-        f"| dispatches traced | {st['Calls']} |",
-        f"| average duration | {float(st['AverageNs']) / 1e6:.4f} ms |",
-        f"| min / max duration | {float(st['MinNs']) / 1e6:.4f} / {float(st['MaxNs']) / 1e6:.4f} ms |",
-        f"| FETCH_SIZE per dispatch | {fk:.0f} KiB |",
+        f"| step kernels' duration | {step_ns / 1e6:.4f} ms |",
         f"| FETCH_SIZE of the 4 GiB copy probe | {fc:.0f} KiB (scale {f_scale:.4f}) |",
-        f"| WRITE_SIZE per dispatch | {wk:.0f} KiB |",
         f"| WRITE_SIZE of the 4 GiB copy probe | {wc:.0f} KiB (scale {w_scale:.4f}) |",
-        f"| HBM bytes read per launch | {fetch_b / 1e9:.3f} GB |",
-        f"| HBM bytes written per launch | {write_b / 1e9:.3f} GB |",
+        f"| HBM bytes read per step | {fetch_b / 1e9:.3f} GB |",
+        f"| HBM bytes written per step | {write_b / 1e9:.3f} GB |",
         "",
         f"kernel-source-sha256: {kernel_source_hash()}",
         f"traffic-bytes: {int(round(fetch_b + write_b))}",
@@ -321,11 +334,12 @@ def main():
             best, best_ms = plan.autotune(os.path.join(td, "tune.jsonl"), steps=3)
         tuned = {"cols_per_lane": best.cols_per_lane, "waves_per_block": best.waves_per_block,
                  "persistent": best.persistent, "waves_per_cu": best.waves_per_cu, "chunked": best.chunked,
+                 "band_align": best.band_align,
                  "ms": round(best_ms, 4)}
         log(f"autotune: {tuned}")
         launch = {"cols_per_lane": best.cols_per_lane, "persistent": 0 if a.regular else 1,
                   "waves_per_block": best.waves_per_block, "waves_per_cu": best.waves_per_cu,
-                  "chunked": best.chunked, "use_graph": 1}
+                  "chunked": best.chunked, "band_align": best.band_align, "use_graph": 1}
         plan.set_launch(**launch)
         plan.bind()
         sizes0 = w.lattice_sizes()
@@ -355,7 +369,7 @@ def main():
                 "ms_per_step": round(1e3 * wall64 / s64, 4),
                 "kernel_ms": round(kern64, 4),
                 "hbm_gbs_algorithmic": round(amps * 32.0 / (kern64 * 1e-3) / 1e9, 1),
-                "taylor_order": int(p64.orders().max()), "launch": "regular, one per step"}
+                "taylor_order": int(p64.orders().max()), "launch": "regular, one per Taylor order and step"}
         del p64
         torch.cuda.empty_cache()
 

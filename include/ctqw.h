@@ -127,6 +127,12 @@ typedef struct {
                                 reading and writing the partial sum and the
                                 last term (Alg. 3's term loop split over
                                 passes) */
+    int32_t band_align;      /* bytes (0, 64, 128 or 256; default 128): the
+                                boundaries between the column bands of a
+                                realisation are moved down to multiples of
+                                this many bytes of a row, so that no cache
+                                line of the new state is stored by two waves
+                                (0: bands as wide as the halo allows) */
 } ctqw_launch;
 
 /* Create a plan from a problem statement.  Host only: validates the
@@ -180,7 +186,12 @@ ctqw_status ctqw_draw_params(ctqw_plan* plan, const double* J_base, const double
  * every entry is taylor_order; otherwise n_r is the smallest n >= 1 with
  * x^(n+1)/(n+1)! / (1 - x/(n+2)) <= taylor_tol, x = dt * G_r, where G_r =
  * m * max_i(|eps_i| + |J_(i-1)| + |J_i|) + |U_r| m(m-1)/2 bounds ||H_r||_2
- * (Gershgorin).  Valid after ctqw_set_params.                            */
+ * (Gershgorin).  Valid after ctqw_set_params.
+ * Steps of one and two particles apply each realisation's own n_r: items
+ * are grouped by order and each group is one launch at that depth.  The
+ * batch's largest order is applied to every realisation by chunked passes,
+ * by three-particle steps, and in ctqw_gradient (one polynomial for the
+ * adjoint); the truncation estimate follows the order applied.           */
 ctqw_status ctqw_orders(const ctqw_plan* plan, int32_t* orders);
 
 /* Amplitudes stored per realisation and their offsets in a state buffer.
@@ -249,7 +260,8 @@ ctqw_status ctqw_set_launch(ctqw_plan* plan, const ctqw_launch* launch);
 
 /* Number of work items (realisation x column band) of one step and the
  * number of waves that one step launches, for the current launch shape
- * (persistent: the device's resident waves, known once bound).           */
+ * (persistent: the device's resident waves, known once bound; with
+ * several orders, the largest of the per-order launches).                */
 ctqw_status ctqw_work_items(const ctqw_plan* plan, int64_t* items, int64_t* waves);
 
 /* Derivatives of an ensemble-averaged diagonal observable.  The paper does

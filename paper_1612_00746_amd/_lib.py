@@ -73,6 +73,7 @@ class Launch(C.Structure):
         ("use_graph", C.c_int32),
         ("waves_per_cu", C.c_int32),
         ("chunked", C.c_int32),
+        ("band_align", C.c_int32),
     ]
 
 

@@ -79,7 +79,7 @@ __global__ void finalize_kernel(FinalizeArgs a) {
         s += a.norm_part[k];
         t += a.tail_part[k];
     }
-    const double tf = a.reals[r].tail_factor;
+    const double tf = a.use_max ? a.reals[r].tail_factor_max : a.reals[r].tail_factor;
     const double err2 = t * tf * tf;
     a.norm2[r] = s;
     a.tail2[r] = err2;

@@ -26,7 +26,8 @@ struct RealDev {
     int32_t row_param_off;  // J / eps for the row axis (a zero block if rows == 1)
     int32_t flags;       // RF_*
     double U;            // interaction strength (0 for one particle)
-    double tail_factor;  // remainder estimate / ||Phi^(n)|| (see runtime)
+    double tail_factor;  // remainder estimate / ||Phi^(n)||, n = the realisation's order
+    double tail_factor_max;  // the same for the batch's largest order (one-depth launches)
 };
 
 // One work item: a band of columns of one realisation, swept over all rows.
@@ -81,6 +82,7 @@ struct StepConfig {
     int waves_per_block;
     int persistent;
     int grid_blocks;    // persistent: blocks to launch
+    int vec;            // complex64, two columns per lane: paired 16-byte accesses
 };
 
 // Host entry points implemented in the .hip translation units.
@@ -111,6 +113,7 @@ struct FinalizeArgs {
     double tol2;
     double norm_alarm;
     int renormalize;
+    int use_max;                 // the step ran every realisation at the batch's largest order
 };
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t stream);
 

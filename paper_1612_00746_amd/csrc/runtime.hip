@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -71,6 +72,11 @@ struct ctqw_plan {
     // work items
     std::vector<ItemDev> items;
     std::vector<int32_t> item_first, item_order;
+    // fused steps: runs of item_order with one Taylor order each, largest
+    // order first: {order, first, end}
+    std::vector<std::array<int32_t, 4>> order_runs;   // {order, first, end, paired access}
+    bool all_vec = false;            // every item takes the paired-access kernel
+    bool one_depth = false;          // set while a gradient run needs one polynomial for all
     int64_t n_parts = 0;             // per-step FP64 norm partials
     int levels = 0;                  // Taylor terms per step (the batch's order)
     int chunk = 0;                   // terms per pass of a chunked step (0: fused)
@@ -174,8 +180,15 @@ T* at(ctqw_plan* p, const Region& r) {
 }
 
 // Column bands of one realisation for halo h (= its Taylor order) and a
-// window of W columns.  Returns false if the halo leaves no output column.
-bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, std::vector<ItemDev>& out) {
+// window of W columns.  Band boundaries inside the chain are moved down to
+// multiples of `align` columns where that leaves the band an output column,
+// so that the stores of neighbouring bands do not share cache lines.
+// Returns false if the halo leaves no output column.
+// With `pairs` (lanes holding two adjacent columns) the window starts on an
+// even column where the chain allows, so that the lanes' column pairs are
+// read and written as one 16-byte access.
+bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, int align, bool pairs,
+                std::vector<ItemDev>& out) {
     const int rows = pr.m == 1 ? 1 : N;
     const bool periodic = pr.boundary == CTQW_PERIODIC;
     const bool tri = pr.m == 2 && pr.statistics == CTQW_BOSON;
@@ -184,17 +197,25 @@ bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, std::vector<
     while (lo < N) {
         ItemDev it{};
         it.real = r;
+        auto aligned = [&](int c) {
+            const int a = (c / align) * align;
+            return a > lo ? a : c;
+        };
         if (periodic) {
-            it.w0 = lo - h;
+            int w0 = lo - h;
+            if (pairs && (w0 & 1)) --w0;
+            it.w0 = w0;
             it.lo = lo;
-            it.hi = std::min(N, lo + W - 2 * h);
+            const int end = w0 + W - h;
+            it.hi = end >= N ? N : aligned(end);
         } else {
             int w0 = std::max(0, lo - h);
+            if (pairs && (w0 & 1)) --w0;
             if (w0 + W > N) w0 = std::max(0, N - W);
             const int w1 = std::min(N, w0 + W);
             it.w0 = w0;
             it.lo = lo;
-            it.hi = (w1 == N) ? N : w1 - h;
+            it.hi = (w1 == N) ? N : aligned(w1 - h);
         }
         if (it.hi <= it.lo) return false;
         if (periodic && rows > 1) {
@@ -228,6 +249,8 @@ ctqw_status build_tables(ctqw_plan* p) {
     const int levels = maxn;
     const int band_W = chunk ? 64 : W;          // chunked passes run one column per lane
     const int halo = chunk ? chunk : levels;
+    const int amp_bytes = dtype ? 16 : 8;
+    const int align = std::max(1, p->launch.band_align / amp_bytes);
     std::vector<ItemDev> items;
     std::vector<int32_t> first(pr.R + 1, 0);
     int64_t n_parts = 0;
@@ -240,20 +263,45 @@ ctqw_status build_tables(ctqw_plan* p) {
     } else {
         for (int64_t r = 0; r < pr.R; ++r) {
             first[r] = (int32_t)items.size();
-            if (!make_bands(pr, (int)r, p->N[r], halo, band_W, items))
+            if (!make_bands(pr, (int)r, p->N[r], halo, band_W, align, band_W == 128 && dtype == 0, items))
                 return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", halo, band_W);
         }
         first[pr.R] = (int32_t)items.size();
         n_parts = (int64_t)items.size();
     }
     if (items.size() > (size_t)INT32_MAX) return fail(p, CTQW_ERR_OUT_OF_MEMORY, "too many work items");
+    // Fused steps run each realisation at its own a-priori order: the items
+    // are ordered by order (largest first), then by kernel variant, then by
+    // cost, and each run of one (order, variant) is a launch of that depth.
+    // Paired 16-byte access (complex64, two columns per lane, full grid)
+    // needs an even chain length and an even window start and output range.
+    const bool pairs = !chunk && P == 2 && dtype == 0 && !(pr.m == 2 && pr.statistics == CTQW_BOSON);
     std::vector<int32_t> ord(items.size());
     std::vector<int64_t> cost(items.size());
+    std::vector<int32_t> iord(items.size()), ivec(items.size());
+    bool all_vec = !items.empty();
     for (size_t k = 0; k < items.size(); ++k) {
+        const ItemDev& it = items[k];
         ord[k] = (int32_t)k;
-        cost[k] = (int64_t)(items[k].nrows + halo);
+        cost[k] = (int64_t)(it.nrows + halo);
+        iord[k] = chunk ? levels : p->order[it.real];
+        ivec[k] = (pairs && (p->N[it.real] & 1) == 0 && (it.w0 & 1) == 0 && (it.lo & 1) == 0 && (it.hi & 1) == 0)
+                      ? 1 : 0;
+        all_vec = all_vec && ivec[k];
     }
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        if (iord[a] != iord[b]) return iord[a] > iord[b];
+        if (ivec[a] != ivec[b]) return ivec[a] > ivec[b];
+        return cost[a] > cost[b];
+    });
+    p->order_runs.clear();
+    for (size_t k = 0; k < ord.size(); ++k) {
+        const int32_t o = iord[ord[k]], v = ivec[ord[k]];
+        if (p->order_runs.empty() || p->order_runs.back()[0] != o || p->order_runs.back()[3] != v)
+            p->order_runs.push_back({o, (int32_t)k, (int32_t)k, v});
+        p->order_runs.back()[2] = (int32_t)k + 1;
+    }
+    p->all_vec = all_vec;
     p->items.swap(items);
     p->item_first.swap(first);
     p->item_order.swap(ord);
@@ -323,9 +371,11 @@ ctqw_status upload_tables(ctqw_plan* p) {
         d.N = p->N[r];
         // grid rows of N amplitudes: 1 (one particle), N (two), N^2 (three)
         d.rows = pr.m == 1 ? 1 : (pr.m == 3 ? p->N[r] * p->N[r] : p->N[r]);
-        // Every realisation of the batch takes the batch's order (at least its
-        // own a-priori order), so the pipeline has no per-realisation depth.
-        const int n = p->levels;
+        // Fused two-dimensional steps run the realisation's own order;
+        // one-depth launches (chunked passes, gradients, three particles)
+        // run the batch's largest.
+        const int n = (p->chunk || pr.m == 3) ? p->levels : p->order[r];
+        const int nmax = p->levels;
         const double x = p->xbound[r];
         d.order = n;
         d.param_off = p->param_off[r];
@@ -336,6 +386,7 @@ ctqw_status upload_tables(ctqw_plan* p) {
         d.U = pr.m == 1 ? 0.0 : p->U[r];
         // remainder estimate: ||sum_{j>n} Phi^(j)|| <= ||Phi^(n)|| (x/(n+1)) / (1 - x/(n+2))
         d.tail_factor = (x < n + 2) ? (x / (n + 1)) / (1.0 - x / (n + 2)) : INFINITY;
+        d.tail_factor_max = (x < nmax + 2) ? (x / (nmax + 1)) / (1.0 - x / (nmax + 2)) : INFINITY;
     }
     // Step kernels read J and eps pre-multiplied by dt.
     const double dt = pr.dt;
@@ -390,7 +441,10 @@ StepConfig step_config(ctqw_plan* p) {
     return c;
 }
 
-ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
+// Grid of one step launch over `n_items` items (regular: one wave per item;
+// persistent: the device's resident waves, at most the items' blocks).
+ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves, int64_t n_items = -1) {
+    if (n_items < 0) n_items = (int64_t)p->items.size();
     int max_threads = 0;
     if (p->chunk) HIP_TRY(p, chunk_max_block(c, &max_threads));
     else HIP_TRY(p, step_max_block(c, &max_threads));
@@ -398,11 +452,11 @@ ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
         return fail(p, CTQW_ERR_UNSUPPORTED, "%d waves per block exceed this kernel's %d threads", c.waves_per_block,
                     max_threads);
     if (!c.persistent) {
-        *n_waves = (int)p->items.size();
+        *n_waves = (int)n_items;
         return CTQW_OK;
     }
     // claims count in units of 64 (one per lane) in an int32 counter
-    if ((int64_t)p->items.size() >= (int64_t(1) << 25))
+    if (n_items >= (int64_t(1) << 25))
         return fail(p, CTQW_ERR_UNSUPPORTED, "persistent launch takes at most 2^25 work items per step");
     int per_cu = 0;
     if (p->chunk) HIP_TRY(p, chunk_occupancy(c, &per_cu));
@@ -410,7 +464,7 @@ ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves) {
     if (p->launch.waves_per_cu > 0) per_cu = std::max(1, p->launch.waves_per_cu / c.waves_per_block);
     if (per_cu < 1) per_cu = 1;
     int64_t blocks = (int64_t)p->cu_count * per_cu;
-    const int64_t need = ((int64_t)p->items.size() + c.waves_per_block - 1) / c.waves_per_block;
+    const int64_t need = (n_items + c.waves_per_block - 1) / c.waves_per_block;
     blocks = std::max<int64_t>(1, std::min(blocks, need));
     c.grid_blocks = (int)blocks;
     *n_waves = (int)(blocks * c.waves_per_block);
@@ -451,6 +505,7 @@ ctqw_status enqueue_finalize(ctqw_plan* p) {
     f.tol2 = p->prob.taylor_tol > 0 ? p->prob.taylor_tol * p->prob.taylor_tol : 0.0;
     f.norm_alarm = p->prob.norm_alarm;
     f.renormalize = p->prob.renormalize;
+    f.use_max = (p->chunk || p->one_depth) ? 1 : 0;
     HIP_TRY(p, launch_finalize(f, p->stream));
     return CTQW_OK;
 }
@@ -504,6 +559,7 @@ ctqw_status enqueue_step3(ctqw_plan* p) {
 ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
     const Layout& L = p->lay;
     StepConfig c = step_config(p);
+    c.vec = (!p->chunk && p->all_vec) ? 1 : 0;
     int n_waves = 0;
     ctqw_status st = grid_for(p, c, &n_waves);
     if (st != CTQW_OK) return st;
@@ -526,8 +582,27 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
     a.dt = p->prob.dt;
     a.persistent = c.persistent;
     if (!p->chunk) {
-        if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
-        HIP_TRY(p, launch_step(c, a, p->stream));
+        if (p->one_depth || p->order_runs.size() <= 1) {
+            // one launch at the batch's largest order (paired access only
+            // when every item allows it)
+            if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
+            HIP_TRY(p, launch_step(c, a, p->stream));
+            return CTQW_OK;
+        }
+        // one launch per run of equal orders, each at its own depth
+        const int32_t* order_base = at<int32_t>(p, L.order);
+        for (const auto& run : p->order_runs) {
+            StepConfig cr = step_config(p);
+            cr.levels = run[0];
+            cr.vec = run[3];
+            const int64_t n = run[2] - run[1];
+            if ((st = grid_for(p, cr, &n_waves, n)) != CTQW_OK) return st;
+            a.item_order = order_base + run[1];
+            a.n_items = (int32_t)n;
+            a.n_waves = n_waves;
+            if (cr.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
+            HIP_TRY(p, launch_step(cr, a, p->stream));
+        }
         return CTQW_OK;
     }
     const int n = p->levels, K = p->chunk;
@@ -573,10 +648,15 @@ ctqw_status enqueue_step(ctqw_plan* p) {
     return CTQW_OK;
 }
 
-// One step kernel from `in` to `out` (no monitoring), for recomputation.
+// One step kernel from `in` to `out` (no monitoring), for the adjoint's
+// recomputation: every realisation at the batch's largest order.
 ctqw_status enqueue_step_io(ctqw_plan* p, const void* in, void* out) {
     if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "recomputation is built for one and two particles");
-    return enqueue_step_kernels(p, in, out);
+    const bool was = p->one_depth;
+    p->one_depth = true;
+    const ctqw_status st = enqueue_step_kernels(p, in, out);
+    p->one_depth = was;
+    return st;
 }
 
 ctqw_status collect_timing(ctqw_plan* p);
@@ -741,7 +821,7 @@ ctqw_status read_status(ctqw_plan* p, int32_t* st) {
 
 extern "C" {
 
-const char* ctqw_version(void) { return "ctqw-mi355x 0.2 (gfx950)"; }
+const char* ctqw_version(void) { return "ctqw-mi355x 0.3 (gfx950)"; }
 
 const char* ctqw_status_string(ctqw_status s) {
     switch (s) {
@@ -873,6 +953,7 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         p->launch.use_graph = 0;
         p->launch.waves_per_cu = 0;
         p->launch.chunked = 0;
+        p->launch.band_align = 128;
         p->order.assign(R, 0);
         p->xbound.assign(R, 0.0);
     } catch (const std::bad_alloc&) {
@@ -1035,12 +1116,25 @@ ctqw_status ctqw_work_items(const ctqw_plan* p, int64_t* items, int64_t* waves) 
     if (waves) {
         *waves = p->prob.m == 3 ? n * 4 : n;
         if (p->prob.m != 3 && p->launch.persistent && p->bound) {
-            // the persistent grid: resident waves of the device
+            // the persistent grid: resident waves of the device (the
+            // largest of the per-order launches)
             ctqw_plan* q = const_cast<ctqw_plan*>(p);
             StepConfig c = step_config(q);
+            c.vec = (!p->chunk && p->all_vec) ? 1 : 0;
             int n_waves = 0;
             ctqw_status st = grid_for(q, c, &n_waves);
             if (st != CTQW_OK) return st;
+            if (!p->chunk && p->order_runs.size() > 1) {
+                n_waves = 0;
+                for (const auto& run : p->order_runs) {
+                    StepConfig cr = step_config(q);
+                    cr.levels = run[0];
+                    cr.vec = run[3];
+                    int w = 0;
+                    if ((st = grid_for(q, cr, &w, run[2] - run[1])) != CTQW_OK) return st;
+                    n_waves = std::max(n_waves, w);
+                }
+            }
             *waves = n_waves;
         }
     }
@@ -1062,6 +1156,8 @@ ctqw_status ctqw_set_launch(ctqw_plan* p, const ctqw_launch* l) {
     if ((l->persistent != 0 && l->persistent != 1) || (l->use_graph != 0 && l->use_graph != 1) ||
         l->waves_per_cu < 0 || (l->chunked != 0 && l->chunked != 1))
         return fail(p, CTQW_ERR_INVALID_ARG, "bad persistent / use_graph / waves_per_cu / chunked");
+    if (l->band_align != 0 && l->band_align != 64 && l->band_align != 128 && l->band_align != 256)
+        return fail(p, CTQW_ERR_INVALID_ARG, "band_align must be 0, 64, 128 or 256 bytes");
     const ctqw_launch old = p->launch;
     p->launch = *l;
     if (p->params_set) {
@@ -1281,6 +1377,7 @@ bool cache_lookup(const char* path, const std::string& key, ctqw_launch* out, do
             parse_int_field(s, "waves_per_block", &l.waves_per_block) &&
             parse_int_field(s, "persistent", &l.persistent) && parse_int_field(s, "waves_per_cu", &l.waves_per_cu)) {
             if (!parse_int_field(s, "chunked", &l.chunked)) l.chunked = 0;
+            if (!parse_int_field(s, "band_align", &l.band_align)) l.band_align = 0;
             *out = l;
             const size_t at = s.find("\"ms\": ");
             *ms = at == std::string::npos ? NAN : atof(s.c_str() + at + 6);
@@ -1296,8 +1393,9 @@ void cache_append(const char* path, const std::string& key, const ctqw_launch& l
     if (!f) return;
     fprintf(f,
             "{\"key\": \"%s\", \"cols_per_lane\": %d, \"waves_per_block\": %d, \"persistent\": %d, "
-            "\"waves_per_cu\": %d, \"chunked\": %d, \"ms\": %.6f}\n",
-            key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, l.chunked, ms);
+            "\"waves_per_cu\": %d, \"chunked\": %d, \"band_align\": %d, \"ms\": %.6f}\n",
+            key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, l.chunked, l.band_align,
+            ms);
     fclose(f);
 }
 
@@ -1358,6 +1456,7 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
         }
     }
     if (!cached) {
+        for (int align : {128, 64, 0})
         for (int chunked : {0, 1})
         for (int P : {1, 2})
             for (int wpb : {1, 2, 4})
@@ -1371,6 +1470,7 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
                         c.persistent = pers;
                         c.waves_per_cu = cap;
                         c.chunked = chunked;
+                        c.band_align = align;
                         p->launch = c;
                         if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
                         if ((st = upload_tables(p)) != CTQW_OK) return st;
@@ -1472,12 +1572,18 @@ ctqw_status ctqw_forward_ckpt(ctqw_plan* p, int64_t n_steps, int64_t ckpt_every,
     hipStream_t s = p->stream;
     const int64_t bytes = p->state_off.back() * (p->prob.dtype == CTQW_C128 ? 16 : 8);
     const int64_t C = ckpt_every;
-    // forward, keeping the state at steps 0, C, 2C, ...
+    // forward, keeping the state at steps 0, C, 2C, ...; every realisation
+    // runs the batch's largest order, the polynomial the adjoint inverts
+    p->one_depth = true;
     for (int64_t k = 0; k < n_steps; ++k) {
         if (k % C == 0)
             HIP_TRY(p, hipMemcpyAsync(G + g.ckpt + (k / C) * g.S, p->psi[p->cur], bytes, hipMemcpyDeviceToDevice, s));
-        if ((st = enqueue_step(p)) != CTQW_OK) return st;
+        if ((st = enqueue_step(p)) != CTQW_OK) {
+            p->one_depth = false;
+            return st;
+        }
     }
+    p->one_depth = false;
     if (n_steps == 0) HIP_TRY(p, hipMemcpyAsync(G + g.ckpt, p->psi[p->cur], bytes, hipMemcpyDeviceToDevice, s));
     p->grad_ws = gws;
     p->grad_steps = n_steps;

@@ -10,6 +10,7 @@ CTQW_DECLARE_TABLE(f32p_p1_full) CTQW_DECLARE_TABLE(f32p_p1_tri)
 CTQW_DECLARE_TABLE(f32p_p2_full) CTQW_DECLARE_TABLE(f32p_p2_tri)
 CTQW_DECLARE_TABLE(f64_p1_full) CTQW_DECLARE_TABLE(f64_p1_tri)
 CTQW_DECLARE_TABLE(f64_p2_full) CTQW_DECLARE_TABLE(f64_p2_tri)
+CTQW_DECLARE_TABLE(f32k_p2_vec) CTQW_DECLARE_TABLE(f32p_p2_vec)
 #undef CTQW_DECLARE_TABLE
 
 namespace {
@@ -29,6 +30,10 @@ StepKernelFn select_kernel(const StepConfig& c) {
     if (c.dtype == 1)
         return p1 ? (t ? step_table_f64_p1_tri(c.levels) : step_table_f64_p1_full(c.levels))
                   : (t ? step_table_f64_p2_tri(c.levels) : step_table_f64_p2_full(c.levels));
+    if (c.vec) {
+        if (t || p1) return nullptr;
+        return c.kahan ? step_table_f32k_p2_vec(c.levels) : step_table_f32p_p2_vec(c.levels);
+    }
     if (c.kahan)
         return p1 ? (t ? step_table_f32k_p1_tri(c.levels) : step_table_f32k_p1_full(c.levels))
                   : (t ? step_table_f32k_p2_tri(c.levels) : step_table_f32k_p2_full(c.levels));

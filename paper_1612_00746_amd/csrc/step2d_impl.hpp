@@ -63,6 +63,68 @@ __device__ __forceinline__ double from_right(double x) {
     return __builtin_amdgcn_update_dpp(0.0, x, 0x130, 0xF, 0xF, true);
 }
 
+// The complex64 full-grid stencil of one level, h = (H Psi) scaled by dt:
+//   h(c) = d(c) m(c) + Ju u(c) + Jd v(c) + jl(c) m(c-1) + jr(c) m(c+1)
+// (m, u, v: the level below on this row and the rows above and below; Ju,
+// Jd: the wave-uniform row bonds), accumulated in this order, real and
+// imaginary parts alike.  Written out so that the neighbour columns held
+// by the adjacent lanes enter through DPP-routed FMAs (no separate moves)
+// and the independent chains are interleaved.  A DPP read of a VGPR must
+// follow the VALU write of that register by two wait states; every DPP
+// instruction here comes after at least six VALU instructions of the same
+// block, and its source is an input of the block.
+__device__ __forceinline__ void stencil_c64_p1(float& hr, float& hi, float d, float mr, float mi, float ur, float ui,
+                                               float vr, float vi, float Ju, float Jd, float jl, float jr) {
+    asm("v_mul_f32 %0, %2, %3\n\t"
+        "v_mul_f32 %1, %2, %4\n\t"
+        "v_fmac_f32 %0, %9, %5\n\t"
+        "v_fmac_f32 %1, %9, %6\n\t"
+        "v_fmac_f32 %0, %10, %7\n\t"
+        "v_fmac_f32 %1, %10, %8\n\t"
+        "v_fmac_f32_dpp %0, %3, %11 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %4, %11 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %0, %3, %12 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %4, %12 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(hr), "=&v"(hi)
+        : "v"(d), "v"(mr), "v"(mi), "v"(ur), "v"(ui), "v"(vr), "v"(vi), "s"(Ju), "s"(Jd), "v"(jl), "v"(jr));
+}
+// Two columns per lane: column 0's left neighbour and column 1's right
+// neighbour come from the adjacent lanes, the others from this lane.
+__device__ __forceinline__ void stencil_c64_p2(float (&hr)[2], float (&hi)[2], const float (&d)[2], const float (&mr)[2],
+                                               const float (&mi)[2], const float (&ur)[2], const float (&ui)[2],
+                                               const float (&vr)[2], const float (&vi)[2], float Ju, float Jd,
+                                               const float (&jl)[2], const float (&jr)[2]) {
+    asm("v_mul_f32 %0, %4, %6\n\t"
+        "v_mul_f32 %1, %4, %7\n\t"
+        "v_mul_f32 %2, %5, %8\n\t"
+        "v_mul_f32 %3, %5, %9\n\t"
+        "v_fmac_f32 %0, %18, %10\n\t"
+        "v_fmac_f32 %1, %18, %11\n\t"
+        "v_fmac_f32 %2, %18, %12\n\t"
+        "v_fmac_f32 %3, %18, %13\n\t"
+        "v_fmac_f32 %0, %19, %14\n\t"
+        "v_fmac_f32 %1, %19, %15\n\t"
+        "v_fmac_f32 %2, %19, %16\n\t"
+        "v_fmac_f32 %3, %19, %17\n\t"
+        "v_fmac_f32_dpp %0, %8, %20 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %9, %20 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32 %2, %21, %6\n\t"
+        "v_fmac_f32 %3, %21, %7\n\t"
+        "v_fmac_f32 %0, %22, %8\n\t"
+        "v_fmac_f32 %1, %22, %9\n\t"
+        "v_fmac_f32_dpp %2, %6, %23 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %3, %7, %23 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(hr[0]), "=&v"(hi[0]), "=&v"(hr[1]), "=&v"(hi[1])
+        : "v"(d[0]), "v"(d[1]), "v"(mr[0]), "v"(mi[0]), "v"(mr[1]), "v"(mi[1]), "v"(ur[0]), "v"(ui[0]), "v"(ur[1]),
+          "v"(ui[1]), "v"(vr[0]), "v"(vi[0]), "v"(vr[1]), "v"(vi[1]), "s"(Ju), "s"(Jd), "v"(jl[0]), "v"(jl[1]),
+          "v"(jr[0]), "v"(jr[1]));
+}
+
+// Raw buffer resources: the last descriptor word for gfx9-family buffers
+// without format conversion.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufferWord3 = 0x00020000;
+
 __host__ __device__ constexpr int window_rows(int nt) { return ((nt + 3) / 3) * 3; }
 __host__ __device__ constexpr int mod_pos(int x, int w) { return ((x % w) + w) % w; }
 __host__ __device__ constexpr double inv_factorial(int j) {
@@ -117,7 +179,7 @@ __device__ __forceinline__ S load_uniform(const S* table, int index) {
 // CHUNK: one pass of a chunked step (see StepArgs): the series continues
 // from Psi_s with run-time coefficients, the partial sum comes from acc_in,
 // and Psi_{s+NT} is stored for the next pass.
-template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false>
+template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false, bool VEC = false>
 __device__ __forceinline__ void process_item(const StepArgs& a, int home, int lane) {
     using C = typename CplxOf<T>::type;
     constexpr int WA = window_rows(NT);
@@ -182,9 +244,34 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         loff[p] = inb[p] ? (uint32_t)colw[p] * (uint32_t)sizeof(C) : 0u;
         lmul[p] = inb[p] ? sc : T(0);
     }
+    // VEC (complex64, two columns per lane): every lane's two columns are
+    // either both on the chain and adjacent in memory or both off it, and
+    // the band's output columns start and end on even columns (the host
+    // groups such items: even chain length, even window start and bounds).
+    // A row is then read and written with one 16-byte access per lane, so
+    // that every access instruction covers whole cache lines.
+    // The accesses are buffer instructions on a per-row resource (base and
+    // length of the row in scalar registers) with a fixed per-lane offset:
+    // lanes off the chain, or without an output column, use an offset past
+    // the row, which reads zero and drops the store.
+    static_assert(!VEC || (P == 2 && sizeof(T) == 4 && !TRI && !CHUNK), "paired access: complex64, P = 2");
+    constexpr uint32_t kPastRow = 0x80000000u;
+    const uint32_t voff_in = (inb[0] && inb[P - 1]) ? loff[0] : kPastRow;
+    const uint32_t voff_out = outv[0] ? loff[0] : kPastRow;
+    const uint32_t row_bytes = (uint32_t)N * (uint32_t)sizeof(C);
     auto load_from = [&](const C* __restrict__ src, int qm, C (&dst)[P]) {
         const int base = TRI ? qm * N - (qm * (qm + 1)) / 2 : qm * N;
         const char* row = reinterpret_cast<const char*>(src + base);
+        if constexpr (VEC) {
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(row), 0, (int)row_bytes, kBufferWord3);
+            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff_in, 0, 0);
+            dst[0].x = __uint_as_float(v.x);
+            dst[0].y = __uint_as_float(v.y);
+            dst[P - 1].x = __uint_as_float(v.z);
+            dst[P - 1].y = __uint_as_float(v.w);
+            return;
+        }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             uint32_t off = loff[p];
@@ -337,41 +424,54 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     const T f_j = CHUNK ? static_cast<T>(a.coef[j - 1]) : static_cast<T>(inv_factorial(j));
                     const T cr_j = static_cast<T>(sign_re(j)) * f_j;
                     const T ci_j = static_cast<T>(sign_im(j)) * f_j;
-                    T lr[P], li[P], rr[P], ri[P];
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        if (p > 0) { lr[p] = fr[j - 1][sm][p - 1]; li[p] = fi[j - 1][sm][p - 1]; }
-                        if (p < P - 1) { rr[p] = fr[j - 1][sm][p + 1]; ri[p] = fi[j - 1][sm][p + 1]; }
-                    }
-                    lr[0] = from_left(fr[j - 1][sm][P - 1]);
-                    li[0] = from_left(fi[j - 1][sm][P - 1]);
-                    rr[P - 1] = from_right(fr[j - 1][sm][0]);
-                    ri[P - 1] = from_right(fi[j - 1][sm][0]);
                     // Triangle: the band's rows at and below its first column hold the
                     // diagonal; there the couplings up and right double and the
                     // lower triangle is held at zero.
                     const int qa = it.row0 + (i - j);
                     const bool zone = TRI && qa >= it.w0;
+                    T hrv[P], hiv[P];
+                    if constexpr (sizeof(T) == 4 && !TRI) {
+                        if constexpr (P == 1)
+                            stencil_c64_p1(hrv[0], hiv[0], dg[w][0], fr[j - 1][sm][0], fi[j - 1][sm][0],
+                                           fr[j - 1][su][0], fi[j - 1][su][0], fr[j - 1][sd][0], fi[j - 1][sd][0], Ju,
+                                           Jd, jl[0], jr[0]);
+                        else
+                            stencil_c64_p2(hrv, hiv, dg[w], fr[j - 1][sm], fi[j - 1][sm], fr[j - 1][su], fi[j - 1][su],
+                                           fr[j - 1][sd], fi[j - 1][sd], Ju, Jd, jl, jr);
+                    } else {
+                        T lr[P], li[P], rr[P], ri[P];
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            if (p > 0) { lr[p] = fr[j - 1][sm][p - 1]; li[p] = fi[j - 1][sm][p - 1]; }
+                            if (p < P - 1) { rr[p] = fr[j - 1][sm][p + 1]; ri[p] = fi[j - 1][sm][p + 1]; }
+                        }
+                        lr[0] = from_left(fr[j - 1][sm][P - 1]);
+                        li[0] = from_left(fi[j - 1][sm][P - 1]);
+                        rr[P - 1] = from_right(fr[j - 1][sm][0]);
+                        ri[P - 1] = from_right(fi[j - 1][sm][0]);
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            T cu = Ju, crt = jr[p];
+                            if (TRI && zone && col[p] == qa) { cu = Ju + Ju; crt = crt + crt; }
+                            const T mr = fr[j - 1][sm][p], mi = fi[j - 1][sm][p];
+                            T hr = dg[w][p] * mr;
+                            T hi = dg[w][p] * mi;
+                            hr += cu * fr[j - 1][su][p];
+                            hi += cu * fi[j - 1][su][p];
+                            hr += Jd * fr[j - 1][sd][p];
+                            hi += Jd * fi[j - 1][sd][p];
+                            hr += jl[p] * lr[p];
+                            hi += jl[p] * li[p];
+                            hr += crt * rr[p];
+                            hi += crt * ri[p];
+                            hrv[p] = hr;
+                            hiv[p] = hi;
+                        }
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        T cu = Ju, crt = jr[p];
-                        bool low = false;
-                        if (TRI && zone) {
-                            const bool isd = (col[p] == qa);
-                            low = (col[p] < qa);
-                            if (isd) { cu = Ju + Ju; crt = crt + crt; }
-                        }
-                        const T mr = fr[j - 1][sm][p], mi = fi[j - 1][sm][p];
-                        T hr = dg[w][p] * mr;
-                        T hi = dg[w][p] * mi;
-                        hr += cu * fr[j - 1][su][p];
-                        hi += cu * fi[j - 1][su][p];
-                        hr += Jd * fr[j - 1][sd][p];
-                        hi += Jd * fi[j - 1][sd][p];
-                        hr += jl[p] * lr[p];
-                        hi += jl[p] * li[p];
-                        hr += crt * rr[p];
-                        hi += crt * ri[p];
+                        const bool low = TRI && zone && col[p] < qa;
+                        const T hr = hrv[p], hi = hiv[p];
                         // A_j = H B_{j-1} (from the imaginary-role array), B_j = H A_{j-1}
                         T pr_ = hi;
                         T pi_ = hr;
@@ -430,12 +530,26 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     const int qa = it.row0 + q;
                     if (q >= 0 && qa >= it.out_lo && qa < it.out_hi) {
                         const int base = TRI ? qa * N - (qa * (qa + 1)) / 2 : qa * N;
+                        C vo[P];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
-                            C v;
-                            v.x = KAHAN ? ar[w][p] - cr[w][p] : ar[w][p];
-                            v.y = KAHAN ? ai[w][p] - ci[w][p] : ai[w][p];
-                            if (outv[p] && (!TRI || col[p] >= qa))
+                            vo[p].x = KAHAN ? ar[w][p] - cr[w][p] : ar[w][p];
+                            vo[p].y = KAHAN ? ai[w][p] - ci[w][p] : ai[w][p];
+                        }
+                        if constexpr (VEC) {
+                            u32x4 v4;
+                            v4.x = __float_as_uint(vo[0].x);
+                            v4.y = __float_as_uint(vo[0].y);
+                            v4.z = __float_as_uint(vo[P - 1].x);
+                            v4.w = __float_as_uint(vo[P - 1].y);
+                            const __amdgpu_buffer_rsrc_t rs =
+                                __builtin_amdgcn_make_buffer_rsrc(out + base, 0, (int)row_bytes, kBufferWord3);
+                            __builtin_amdgcn_raw_buffer_store_b128(v4, rs, (int)voff_out, 0, 0);
+                        }
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const C v = vo[p];
+                            if (!VEC && outv[p] && (!TRI || col[p] >= qa))
                                 *reinterpret_cast<C*>(reinterpret_cast<char*>(out + base) + loff[p]) = v;
                             if (final_pass) {
                                 const double dr = v.x, di = v.y;
@@ -494,7 +608,7 @@ constexpr int min_blocks_per_cu() {
     return (P == 2 && sizeof(T) == 4 && NT <= 7 && !CHUNK) ? 2 : 1;
 }
 
-template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false>
+template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false, bool VEC = false>
 __global__ void __launch_bounds__(256, (min_blocks_per_cu<T, NT, P, CHUNK>())) step2d_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -508,7 +622,7 @@ __global__ void __launch_bounds__(256, (min_blocks_per_cu<T, NT, P, CHUNK>())) s
     for (int it = 0; g * wpb < a.n_items; ++it) {
         const int k = g * wpb + wv;
         if (k < a.n_items)
-            process_item<T, NT, P, KAHAN, TRI, CHUNK>(a, ((UniformPtr<int32_t>)a.item_order)[k], lane);
+            process_item<T, NT, P, KAHAN, TRI, CHUNK, VEC>(a, ((UniformPtr<int32_t>)a.item_order)[k], lane);
         if (!a.persistent) break;
         if (wv == 0) {
             const int t = atomicAdd(a.claim, 1);
@@ -529,3 +643,5 @@ using StepKernelFn = void (*)(StepArgs);
 // accumulation, layout) combination; each translation unit instantiates one.
 #define CTQW_STEP_CASE(T, NT, P, K, TRI) \
     case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, P, K, TRI>;
+#define CTQW_STEP_CASE_VEC(T, NT, K) \
+    case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, 2, K, false, false, true>;

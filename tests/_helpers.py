@@ -18,6 +18,35 @@ def say(msg: str) -> None:
     sys.stdout.flush()
 
 
+def gershgorin_x(J, eps, U, m, dt):
+    """x = dt * G with G = m*max_i(|eps_i| + |J_{i-1}| + |J_i|) + |U| m(m-1)/2,
+    the documented bound on ||H||_2 (Gershgorin; J padded with a zero bond
+    for open chains)."""
+    N = len(eps)
+    Jp = np.zeros(N)
+    Jp[:len(J)] = J
+    G = m * max(abs(eps[i]) + abs(Jp[(i - 1) % N]) + abs(Jp[i]) for i in range(N))
+    G += abs(U) * m * (m - 1) / 2
+    return G * dt
+
+
+def tail_bound(x, n):
+    """Remainder factor of the truncated series: sum_{j>n} x^j/j! is at most
+    x^n/n! * (x/(n+1)) / (1 - x/(n+2)) (geometric bound of the ratios)."""
+    return (x / (n + 1)) / (1 - x / (n + 2)) if x < n + 2 else math.inf
+
+
+def reference_order(J, eps, U, m, dt, tol, periodic=False):
+    """Smallest n with x^(n+1)/(n+1)!/(1 - x/(n+2)) <= tol (documented rule)."""
+    x = gershgorin_x(J, eps, U, m, dt)
+    n = 1
+    while True:
+        b = x ** (n + 1) / math.factorial(n + 1) / (1 - x / (n + 2)) if x < n + 2 else math.inf
+        if b <= tol:
+            return n
+        n += 1
+
+
 def params_for(w, subset=None):
     """[(N, J, eps, U)] for realisations of a workload."""
     return w.all_realizations(subset)

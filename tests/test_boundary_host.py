@@ -10,6 +10,8 @@ import re
 import numpy as np
 import pytest
 
+from _helpers import reference_order
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ctqw.h")
 
@@ -95,23 +97,6 @@ def test_set_params_rejects_nonfinite_and_keeps_state():
     o = plan.orders()
     assert status_of(lambda: plan.set_params(J, eps, np.array([0, np.nan, 0.0]))) == 1
     assert np.array_equal(plan.orders(), o)
-
-
-def reference_order(J, eps, U, m, dt, tol, periodic=False):
-    """Smallest n with x^(n+1)/(n+1)!/(1 - x/(n+2)) <= tol, x = dt*G, with
-    G = m*max_i(|eps_i| + |J_{i-1}| + |J_i|) + |U| m(m-1)/2 (documented rule)."""
-    N = len(eps)
-    Jp = np.zeros(N)
-    Jp[:len(J)] = J
-    G = m * max(abs(eps[i]) + abs(Jp[(i - 1) % N]) + abs(Jp[i]) for i in range(N))
-    G += abs(U) * m * (m - 1) / 2
-    x = G * dt
-    n = 1
-    while True:
-        b = x ** (n + 1) / math.factorial(n + 1) / (1 - x / (n + 2)) if x < n + 2 else math.inf
-        if b <= tol:
-            return n
-        n += 1
 
 
 @pytest.mark.parametrize("m,periodic,tol,dt", [(2, False, 1e-14, 0.05), (2, True, 1e-7, 0.05),
