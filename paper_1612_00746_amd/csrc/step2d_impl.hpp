@@ -124,6 +124,33 @@ __device__ __forceinline__ void stencil_c64_p2(float (&hr)[2], float (&hi)[2], c
 // without format conversion.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufferWord3 = 0x00020000;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <typename C>
+__device__ __forceinline__ C buffer_load_cplx(__amdgpu_buffer_rsrc_t rs, uint32_t off);
+template <>
+__device__ __forceinline__ float2 buffer_load_cplx<float2>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+template <>
+__device__ __forceinline__ double2 buffer_load_cplx<double2>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+}
+__device__ __forceinline__ void buffer_store_cplx(float2 c, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    u32x2 v;
+    v.x = __float_as_uint(c.x);
+    v.y = __float_as_uint(c.y);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buffer_store_cplx(double2 c, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    u32x4 v;
+    v.x = (unsigned)__double2loint(c.x);
+    v.y = (unsigned)__double2hiint(c.x);
+    v.z = (unsigned)__double2loint(c.y);
+    v.w = (unsigned)__double2hiint(c.y);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, 0);
+}
 
 __host__ __device__ constexpr int window_rows(int nt) { return ((nt + 3) / 3) * 3; }
 __host__ __device__ constexpr int mod_pos(int x, int w) { return ((x % w) + w) % w; }
@@ -244,32 +271,47 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
         loff[p] = inb[p] ? (uint32_t)colw[p] * (uint32_t)sizeof(C) : 0u;
         lmul[p] = inb[p] ? sc : T(0);
     }
+    // Full grid, one pass per step (BUF): rows are read and written with
+    // buffer instructions on a per-row resource (base and length of the row
+    // in scalar registers) and a fixed per-lane offset.  Lanes off the
+    // chain, or without an output column, use an offset past the row, which
+    // reads zero and drops the store; a row past the sweep is fetched with
+    // length 0 and reads zero.  So a row needs no per-lane address
+    // arithmetic and no masking when it enters.
     // VEC (complex64, two columns per lane): every lane's two columns are
     // either both on the chain and adjacent in memory or both off it, and
     // the band's output columns start and end on even columns (the host
     // groups such items: even chain length, even window start and bounds).
-    // A row is then read and written with one 16-byte access per lane, so
-    // that every access instruction covers whole cache lines.
-    // The accesses are buffer instructions on a per-row resource (base and
-    // length of the row in scalar registers) with a fixed per-lane offset:
-    // lanes off the chain, or without an output column, use an offset past
-    // the row, which reads zero and drops the store.
-    static_assert(!VEC || (P == 2 && sizeof(T) == 4 && !TRI && !CHUNK), "paired access: complex64, P = 2");
+    // A row is then one 16-byte access per lane, so that every access
+    // instruction covers whole cache lines.
+    constexpr bool BUF = !TRI && !CHUNK;
+    static_assert(!VEC || (P == 2 && sizeof(T) == 4 && BUF), "paired access: complex64, P = 2");
     constexpr uint32_t kPastRow = 0x80000000u;
-    const uint32_t voff_in = (inb[0] && inb[P - 1]) ? loff[0] : kPastRow;
-    const uint32_t voff_out = outv[0] ? loff[0] : kPastRow;
+    uint32_t voff_in[P], voff_out[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        voff_in[p] = inb[p] ? loff[p] : kPastRow;
+        voff_out[p] = outv[p] ? loff[p] : kPastRow;
+    }
     const uint32_t row_bytes = (uint32_t)N * (uint32_t)sizeof(C);
-    auto load_from = [&](const C* __restrict__ src, int qm, C (&dst)[P]) {
+    // the renormalisation scale of the input (1 unless renormalising)
+    const bool scaled = sc != T(1);
+    auto load_from = [&](const C* __restrict__ src, int qm, bool live_row, C (&dst)[P]) {
         const int base = TRI ? qm * N - (qm * (qm + 1)) / 2 : qm * N;
         const char* row = reinterpret_cast<const char*>(src + base);
-        if constexpr (VEC) {
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(row), 0, (int)row_bytes, kBufferWord3);
-            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff_in, 0, 0);
-            dst[0].x = __uint_as_float(v.x);
-            dst[0].y = __uint_as_float(v.y);
-            dst[P - 1].x = __uint_as_float(v.z);
-            dst[P - 1].y = __uint_as_float(v.w);
+        if constexpr (BUF) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char*>(row), 0, live_row ? (int)row_bytes : 0, kBufferWord3);
+            if constexpr (VEC) {
+                const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff_in[0], 0, 0);
+                dst[0].x = __uint_as_float(v.x);
+                dst[0].y = __uint_as_float(v.y);
+                dst[P - 1].x = __uint_as_float(v.z);
+                dst[P - 1].y = __uint_as_float(v.w);
+            } else {
+#pragma unroll
+                for (int p = 0; p < P; ++p) dst[p] = buffer_load_cplx<C>(rs, voff_in[p]);
+            }
             return;
         }
 #pragma unroll
@@ -279,7 +321,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
             dst[p] = *reinterpret_cast<const C*>(row + off);
         }
     };
-    auto load_row = [&](int qm, C (&dst)[P]) { load_from(in, qm, dst); };
+    auto load_row = [&](int qm, bool live_row, C (&dst)[P]) { load_from(in, qm, live_row, dst); };
 
     T fr[NT][3][P], fi[NT][3][P];   // Psi_j rows, j < NT
     T ar[WA][P], ai[WA][P];         // partial sums of the rows in flight
@@ -318,8 +360,8 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     auto advance_pf = [&]() { qm_pf = next_row(qm_pf); };
 #pragma unroll
     for (int s = 0; s < PF; ++s) {   // rows past the sweep are fetched and ignored
-        load_row(qm_pf, pre[s]);
-        if constexpr (CHUNK) load_from(acc_in, qm_pf, prea[s]);
+        load_row(qm_pf, s < nrows, pre[s]);
+        if constexpr (CHUNK) load_from(acc_in, qm_pf, true, prea[s]);
         advance_pf();
         // Keep the prologue loads in slot order: the sweep consumes slot 0
         // first, and the wait it needs is then for the oldest load only.
@@ -366,21 +408,33 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         v[p] = pre[sp][p];
                         va[p] = CHUNK ? prea[sp][p] : v[p];
                         // zero past the sweep and off the stored lanes (incl. the triangle's lower part)
-                        mul[p] = (live && (!TRI || col[p] >= qm)) ? lmul[p] : T(0);
+                        mul[p] = BUF ? T(1) : ((live && (!TRI || col[p] >= qm)) ? lmul[p] : T(0));
                     }
                     const T er = pe[s];
                     ju[u] = live ? pj[s] : T(0);
                     // consume the slot before it is refilled (no copy of the old row)
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const T re = v[p].x * mul[p], im = v[p].y * mul[p];
+                        T re, im;
+                        if constexpr (BUF) {
+                            // zero off the chain and past the sweep already
+                            re = v[p].x;
+                            im = v[p].y;
+                            if (scaled) {
+                                re *= sc;
+                                im *= sc;
+                            }
+                        } else {
+                            re = v[p].x * mul[p];
+                            im = v[p].y * mul[p];
+                        }
                         fr[0][s][p] = re;
                         fi[0][s][p] = im;
                         ar[u][p] = CHUNK ? va[p].x * mul[p] : re;
                         ai[u][p] = CHUNK ? va[p].y * mul[p] : im;
                     }
-                    load_row(qm_pf, pre[sp]);
-                    if constexpr (CHUNK) load_from(acc_in, qm_pf, prea[sp]);
+                    load_row(qm_pf, i + PF < nrows, pre[sp]);
+                    if constexpr (CHUNK) load_from(acc_in, qm_pf, true, prea[sp]);
                     fetch_params(qm_pp, s);
                     // The columns that interact with row qm (wave-uniform): qm itself
                     // (on site), or qm - 1 and qm + 1 (nearest, wrapped on a ring;
@@ -536,20 +590,25 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                             vo[p].x = KAHAN ? ar[w][p] - cr[w][p] : ar[w][p];
                             vo[p].y = KAHAN ? ai[w][p] - ci[w][p] : ai[w][p];
                         }
-                        if constexpr (VEC) {
-                            u32x4 v4;
-                            v4.x = __float_as_uint(vo[0].x);
-                            v4.y = __float_as_uint(vo[0].y);
-                            v4.z = __float_as_uint(vo[P - 1].x);
-                            v4.w = __float_as_uint(vo[P - 1].y);
+                        if constexpr (BUF) {
                             const __amdgpu_buffer_rsrc_t rs =
                                 __builtin_amdgcn_make_buffer_rsrc(out + base, 0, (int)row_bytes, kBufferWord3);
-                            __builtin_amdgcn_raw_buffer_store_b128(v4, rs, (int)voff_out, 0, 0);
+                            if constexpr (VEC) {
+                                u32x4 v4;
+                                v4.x = __float_as_uint(vo[0].x);
+                                v4.y = __float_as_uint(vo[0].y);
+                                v4.z = __float_as_uint(vo[P - 1].x);
+                                v4.w = __float_as_uint(vo[P - 1].y);
+                                __builtin_amdgcn_raw_buffer_store_b128(v4, rs, (int)voff_out[0], 0, 0);
+                            } else {
+#pragma unroll
+                                for (int p = 0; p < P; ++p) buffer_store_cplx(vo[p], rs, voff_out[p]);
+                            }
                         }
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             const C v = vo[p];
-                            if (!VEC && outv[p] && (!TRI || col[p] >= qa))
+                            if (!BUF && outv[p] && (!TRI || col[p] >= qa))
                                 *reinterpret_cast<C*>(reinterpret_cast<char*>(out + base) + loff[p]) = v;
                             if (final_pass) {
                                 const double dr = v.x, di = v.y;
