@@ -56,6 +56,8 @@ __device__ __forceinline__ double from_left(double x) {
     return __builtin_amdgcn_update_dpp(0.0, x, 0x138, 0xF, 0xF, true);
 }
 // Lane i receives lane i+1 (lane 63 receives 0).
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float from_right(float x) {
     return __builtin_amdgcn_update_dpp(0.0f, x, 0x130, 0xF, 0xF, true);
 }
@@ -380,9 +382,17 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     for (int p = 0; p < P; ++p) wcol[p] = outv[p] ? 1.0 : 0.0;
 
     double nrm = 0.0, tail = 0.0;   // triangle: weighted per row
-    double nrmp[P], tailp[P];       // full grid: per column, weighted at the end
+    // Full grid: per column, weighted at the end.  The squared norm sums
+    // exact FP64 squares; the last term's squared norm only scales the
+    // remainder bound, so it is summed in the state's precision (relative
+    // error below 1e-4 for complex64 over any sweep) and widened at the end.
+    double nrmp[P];
+    T tailp[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) nrmp[p] = tailp[p] = 0.0;
+    for (int p = 0; p < P; ++p) {
+        nrmp[p] = 0.0;
+        tailp[p] = T(0);
+    }
     // The sweep runs nrows + NT iterations, rounded up to whole unrolled
     // blocks: the extra iterations see zero rows and store nothing, and the
     // block body has no early exit (which keeps the prefetch waits exact).
@@ -559,8 +569,8 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                                         (col[p] > qa) ? 2.0 * wcol[p] : (col[p] == qa ? wcol[p] : 0.0);
                                     tail = __builtin_fma(wgt, __builtin_fma(di, di, dr * dr), tail);
                                 } else {   // column weight applied once at the end
-                                    tailp[p] = __builtin_fma(dr, dr, tailp[p]);
-                                    tailp[p] = __builtin_fma(di, di, tailp[p]);
+                                    tailp[p] = fma_t(pr_, pr_, tailp[p]);
+                                    tailp[p] = fma_t(pi_, pi_, tailp[p]);
                                 }
                             }
                         }
@@ -631,7 +641,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             nrm = __builtin_fma(wcol[p], nrmp[p], nrm);
-            tail = __builtin_fma(wcol[p], tailp[p], tail);
+            tail = __builtin_fma(wcol[p], (double)tailp[p], tail);
         }
     }
     nrm = wave_sum(nrm);
