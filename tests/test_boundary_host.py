@@ -270,3 +270,57 @@ def test_draw_params_validation():
     bad = L.Noise(7, 0.0, 1.0)
     assert plan.lib.ctqw_draw_params(plan.h, None, None, 0.0, C.byref(bad), None, None, 0) == L.ERR_INVALID_ARG
     assert status_of(lambda: plan.draw_params(U_base=float("inf"))) == 1
+
+
+def reference_band_count(N, h, W, align_cols, pairs):
+    """Bands of one open chain by the documented rule: windows of W columns
+    with a halo of h, boundaries moved down to multiples of align_cols
+    columns where a band keeps an output column, window starts made even
+    for paired (two-column) lanes."""
+    lo, n = 0, 0
+    while lo < N:
+        w0 = max(0, lo - h)
+        if pairs and w0 % 2:
+            w0 -= 1
+        if w0 + W > N:
+            w0 = max(0, N - W)
+        w1 = min(N, w0 + W)
+        if w1 == N:
+            hi = N
+        else:
+            hi = w1 - h
+            a = (hi // align_cols) * align_cols
+            hi = a if a > lo else hi
+        assert hi > lo
+        n += 1
+        lo = hi
+    return n
+
+
+@pytest.mark.parametrize("P", [1, 2])
+@pytest.mark.parametrize("align", [0, 64, 128])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_band_boundaries_follow_the_alignment(P, align, dtype):
+    """Work items per step for open chains of several lengths at order 7
+    match the band rule; 128-byte boundaries never give fewer items than
+    unaligned ones."""
+    Ns = [64, 96, 300, 999, 1024]
+    plan = make(R=len(Ns), n_sites=Ns, taylor_order=7, taylor_tol=0.0, dtype=dtype)
+    plan.set_launch(cols_per_lane=P, band_align=align)
+    nb = sum(N - 1 for N in Ns)
+    J, _, U = draw(1, len(Ns), nb)
+    eps = np.zeros(sum(Ns))
+    plan.set_params(J, eps, U)
+    amp = 8 if dtype == "c64" else 16
+    cols = max(1, align // amp)
+    want = sum(reference_band_count(N, 7, 64 * P, cols, P == 2 and dtype == "c64") for N in Ns)
+    items, _ = plan.work_items()
+    assert items == want
+    plan.set_launch(cols_per_lane=P, band_align=0)
+    assert plan.work_items()[0] <= items
+
+
+def test_band_align_values_are_checked():
+    plan = make()
+    assert status_of(lambda: plan.set_launch(band_align=96)) == 1
+    assert status_of(lambda: plan.set_launch(band_align=-1)) == 1
