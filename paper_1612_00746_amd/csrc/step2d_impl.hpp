@@ -126,6 +126,11 @@ __device__ __forceinline__ void stencil_c64_p2(float (&hr)[2], float (&hi)[2], c
 // without format conversion.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufferWord3 = 0x00020000;
+// Cache policy of the state's stores: non-temporal (the new state is read
+// again only at the next step, after the whole state has streamed through
+// the caches).  Loads keep the default policy: the halo columns of adjacent
+// bands are read twice.
+constexpr int kStorePolicy = 2;   // nt
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 template <typename C>
 __device__ __forceinline__ C buffer_load_cplx(__amdgpu_buffer_rsrc_t rs, uint32_t off);
@@ -143,7 +148,7 @@ __device__ __forceinline__ void buffer_store_cplx(float2 c, __amdgpu_buffer_rsrc
     u32x2 v;
     v.x = __float_as_uint(c.x);
     v.y = __float_as_uint(c.y);
-    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)off, 0, kStorePolicy);
 }
 __device__ __forceinline__ void buffer_store_cplx(double2 c, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
     u32x4 v;
@@ -151,7 +156,7 @@ __device__ __forceinline__ void buffer_store_cplx(double2 c, __amdgpu_buffer_rsr
     v.y = (unsigned)__double2hiint(c.x);
     v.z = (unsigned)__double2loint(c.y);
     v.w = (unsigned)__double2hiint(c.y);
-    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kStorePolicy);
 }
 
 __host__ __device__ constexpr int window_rows(int nt) { return ((nt + 3) / 3) * 3; }
@@ -609,7 +614,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                                 v4.y = __float_as_uint(vo[0].y);
                                 v4.z = __float_as_uint(vo[P - 1].x);
                                 v4.w = __float_as_uint(vo[P - 1].y);
-                                __builtin_amdgcn_raw_buffer_store_b128(v4, rs, (int)voff_out[0], 0, 0);
+                                __builtin_amdgcn_raw_buffer_store_b128(v4, rs, (int)voff_out[0], 0, kStorePolicy);
                             } else {
 #pragma unroll
                                 for (int p = 0; p < P; ++p) buffer_store_cplx(vo[p], rs, voff_out[p]);
