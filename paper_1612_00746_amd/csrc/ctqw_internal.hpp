@@ -83,6 +83,7 @@ struct StepConfig {
     int persistent;
     int grid_blocks;    // persistent: blocks to launch
     int vec;            // complex64, two columns per lane: paired 16-byte accesses
+    int two;            // complex64 full grid: items of orders levels and levels - 1
 };
 
 // Host entry points implemented in the .hip translation units.

@@ -74,7 +74,7 @@ struct ctqw_plan {
     std::vector<int32_t> item_first, item_order;
     // fused steps: runs of item_order with one Taylor order each, largest
     // order first: {order, first, end}
-    std::vector<std::array<int32_t, 4>> order_runs;   // {order, first, end, paired access}
+    std::vector<std::array<int32_t, 5>> order_runs;   // {order, first, end, paired access, two orders}
     bool all_vec = false;            // every item takes the paired-access kernel
     bool one_depth = false;          // set while a gradient run needs one polynomial for all
     int64_t n_parts = 0;             // per-step FP64 norm partials
@@ -289,17 +289,39 @@ ctqw_status build_tables(ctqw_plan* p) {
                       ? 1 : 0;
         all_vec = all_vec && ivec[k];
     }
+    // Complex64 full-grid launches take two adjacent orders n, n - 1 together
+    // (kernel variant TWO): their items are mixed largest first, so the
+    // instruction-heavier and the lighter items share the device.
+    std::vector<int32_t> igrp(items.size());
+    {
+        // (measured: a gain at two columns per lane, a loss at one)
+        const bool two_ok = !chunk && dtype == 0 && P == 2 && !(pr.m == 2 && pr.statistics == CTQW_BOSON) && pr.m != 3;
+        std::vector<int32_t> present;
+        for (size_t k = 0; k < items.size(); ++k) present.push_back(iord[k]);
+        std::sort(present.begin(), present.end(), std::greater<int32_t>());
+        present.erase(std::unique(present.begin(), present.end()), present.end());
+        std::map<int32_t, int32_t> group_of;
+        for (size_t q = 0; q < present.size(); ++q) {
+            group_of[present[q]] = present[q];
+            if (two_ok && q + 1 < present.size() && present[q + 1] == present[q] - 1) {
+                group_of[present[q + 1]] = present[q];
+                ++q;
+            }
+        }
+        for (size_t k = 0; k < items.size(); ++k) igrp[k] = group_of[iord[k]];
+    }
     std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
-        if (iord[a] != iord[b]) return iord[a] > iord[b];
+        if (igrp[a] != igrp[b]) return igrp[a] > igrp[b];
         if (ivec[a] != ivec[b]) return ivec[a] > ivec[b];
         return cost[a] > cost[b];
     });
     p->order_runs.clear();
     for (size_t k = 0; k < ord.size(); ++k) {
-        const int32_t o = iord[ord[k]], v = ivec[ord[k]];
-        if (p->order_runs.empty() || p->order_runs.back()[0] != o || p->order_runs.back()[3] != v)
-            p->order_runs.push_back({o, (int32_t)k, (int32_t)k, v});
+        const int32_t g = igrp[ord[k]], v = ivec[ord[k]], two = iord[ord[k]] != g;
+        if (p->order_runs.empty() || p->order_runs.back()[0] != g || p->order_runs.back()[3] != v)
+            p->order_runs.push_back({g, (int32_t)k, (int32_t)k, v, 0});
         p->order_runs.back()[2] = (int32_t)k + 1;
+        if (two) p->order_runs.back()[4] = 1;
     }
     p->all_vec = all_vec;
     p->items.swap(items);
@@ -582,19 +604,21 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
     a.dt = p->prob.dt;
     a.persistent = c.persistent;
     if (!p->chunk) {
-        if (p->one_depth || p->order_runs.size() <= 1) {
-            // one launch at the batch's largest order (paired access only
-            // when every item allows it)
+        if (p->one_depth || p->order_runs.empty()) {
+            // one launch at the batch's largest order for every item
+            // (paired access only when every item allows it)
             if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
             HIP_TRY(p, launch_step(c, a, p->stream));
             return CTQW_OK;
         }
-        // one launch per run of equal orders, each at its own depth
+        // one launch per run of items (one order, or two adjacent orders),
+        // each item at its own depth
         const int32_t* order_base = at<int32_t>(p, L.order);
         for (const auto& run : p->order_runs) {
             StepConfig cr = step_config(p);
             cr.levels = run[0];
             cr.vec = run[3];
+            cr.two = run[4];
             const int64_t n = run[2] - run[1];
             if ((st = grid_for(p, cr, &n_waves, n)) != CTQW_OK) return st;
             a.item_order = order_base + run[1];
@@ -1124,12 +1148,13 @@ ctqw_status ctqw_work_items(const ctqw_plan* p, int64_t* items, int64_t* waves) 
             int n_waves = 0;
             ctqw_status st = grid_for(q, c, &n_waves);
             if (st != CTQW_OK) return st;
-            if (!p->chunk && p->order_runs.size() > 1) {
+            if (!p->chunk && !p->order_runs.empty()) {
                 n_waves = 0;
                 for (const auto& run : p->order_runs) {
                     StepConfig cr = step_config(q);
                     cr.levels = run[0];
                     cr.vec = run[3];
+                    cr.two = run[4];
                     int w = 0;
                     if ((st = grid_for(q, cr, &w, run[2] - run[1])) != CTQW_OK) return st;
                     n_waves = std::max(n_waves, w);

@@ -11,6 +11,8 @@ CTQW_DECLARE_TABLE(f32p_p2_full) CTQW_DECLARE_TABLE(f32p_p2_tri)
 CTQW_DECLARE_TABLE(f64_p1_full) CTQW_DECLARE_TABLE(f64_p1_tri)
 CTQW_DECLARE_TABLE(f64_p2_full) CTQW_DECLARE_TABLE(f64_p2_tri)
 CTQW_DECLARE_TABLE(f32k_p2_vec) CTQW_DECLARE_TABLE(f32p_p2_vec)
+CTQW_DECLARE_TABLE(f32k_p2_full_two) CTQW_DECLARE_TABLE(f32k_p2_vec_two)
+CTQW_DECLARE_TABLE(f32p_p2_full_two) CTQW_DECLARE_TABLE(f32p_p2_vec_two)
 #undef CTQW_DECLARE_TABLE
 
 namespace {
@@ -30,6 +32,12 @@ StepKernelFn select_kernel(const StepConfig& c) {
     if (c.dtype == 1)
         return p1 ? (t ? step_table_f64_p1_tri(c.levels) : step_table_f64_p1_full(c.levels))
                   : (t ? step_table_f64_p2_tri(c.levels) : step_table_f64_p2_full(c.levels));
+    if (c.two) {
+        // two orders per launch: complex64 full grid, two columns per lane
+        if (t || p1) return nullptr;
+        if (c.kahan) return c.vec ? step_table_f32k_p2_vec_two(c.levels) : step_table_f32k_p2_full_two(c.levels);
+        return c.vec ? step_table_f32p_p2_vec_two(c.levels) : step_table_f32p_p2_full_two(c.levels);
+    }
     if (c.vec) {
         if (t || p1) return nullptr;
         return c.kahan ? step_table_f32k_p2_vec(c.levels) : step_table_f32p_p2_vec(c.levels);

@@ -1,0 +1,19 @@
+// Compiled pipeline depths for launches holding two orders (n and n - 1): float state,
+// 2 columns per lane, full grid, Kahan accumulation.
+#include "step2d_impl.hpp"
+
+namespace ctqw {
+StepKernelFn step_table_f32k_p2_full_two(int levels) {
+    switch (levels) {
+        CTQW_STEP_CASE_TWO(float, 2, 2, true, false)
+        CTQW_STEP_CASE_TWO(float, 3, 2, true, false)
+        CTQW_STEP_CASE_TWO(float, 4, 2, true, false)
+        CTQW_STEP_CASE_TWO(float, 5, 2, true, false)
+        CTQW_STEP_CASE_TWO(float, 6, 2, true, false)
+        CTQW_STEP_CASE_TWO(float, 7, 2, true, false)
+        CTQW_STEP_CASE_TWO(float, 8, 2, true, false)
+        CTQW_STEP_CASE_TWO(float, 9, 2, true, false)
+        default: return nullptr;
+    }
+}
+}  // namespace ctqw

@@ -682,7 +682,11 @@ constexpr int min_blocks_per_cu() {
     return (P == 2 && sizeof(T) == 4 && NT <= 7 && !CHUNK) ? 2 : 1;
 }
 
-template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false, bool VEC = false>
+// TWO: the launch holds items of two orders, NT and NT - 1 (mixed in one
+// largest-first list, so that the instruction-heavier and the lighter items
+// share the device instead of running as two phases); each item runs at
+// its realisation's order.
+template <typename T, int NT, int P, bool KAHAN, bool TRI, bool CHUNK = false, bool VEC = false, bool TWO = false>
 __global__ void __launch_bounds__(256, (min_blocks_per_cu<T, NT, P, CHUNK>())) step2d_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -695,8 +699,19 @@ __global__ void __launch_bounds__(256, (min_blocks_per_cu<T, NT, P, CHUNK>())) s
     int g = blockIdx.x;
     for (int it = 0; g * wpb < a.n_items; ++it) {
         const int k = g * wpb + wv;
-        if (k < a.n_items)
-            process_item<T, NT, P, KAHAN, TRI, CHUNK, VEC>(a, ((UniformPtr<int32_t>)a.item_order)[k], lane);
+        if (k < a.n_items) {
+            const int home = ((UniformPtr<int32_t>)a.item_order)[k];
+            if constexpr (TWO) {
+                static_assert(NT >= 2 && !CHUNK, "two orders: NT and NT - 1");
+                const int real = ((UniformPtr<int32_t>)(a.items + home))[0];
+                if (load_uniform(a.reals, real).order == NT)
+                    process_item<T, NT, P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
+                else
+                    process_item<T, (TWO ? NT - 1 : NT), P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
+            } else {
+                process_item<T, NT, P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
+            }
+        }
         if (!a.persistent) break;
         if (wv == 0) {
             const int t = atomicAdd(a.claim, 1);
@@ -719,3 +734,5 @@ using StepKernelFn = void (*)(StepArgs);
     case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, P, K, TRI>;
 #define CTQW_STEP_CASE_VEC(T, NT, K) \
     case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, 2, K, false, false, true>;
+#define CTQW_STEP_CASE_TWO(T, NT, P, K, VEC) \
+    case NT: return &::ctqw::step2d_detail::step2d_kernel<T, NT, P, K, false, false, VEC, true>;
