@@ -144,7 +144,8 @@ def _rows(path):
         return list(csv.DictReader(fh))
 
 
-def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols_per_lane=1):
+def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols_per_lane=1, waves_per_block=4,
+                    waves_per_cu=0):
     """Write the step kernels' rocprofv3 summary: duration statistics from
     the kernel trace, FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the
     same counters read for the 4 GiB device copy of the same run.  A step
@@ -188,14 +189,15 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         "Workload: 4096 realisations of two distinguishable walkers on open chains,",
         "N uniform in {64, 96, ..., 1024}, U ~ U[0, 4], J ~ N(1, 0.1^2), dt = 0.05,",
         "Taylor tolerance 1e-7 (6 or 7 terms per realisation), complex64 with the",
-        f"compensated sum; persistent launches, {cols_per_lane} column(s) per lane, 4 waves per block,",
-        "captured step loop; one launch per Taylor order and step.",
+        f"compensated sum; persistent launches, {cols_per_lane} column(s) per lane, {waves_per_block} wave(s) per block,",
+        f"{waves_per_cu or 'all'} resident waves per CU, 128-byte band boundaries, captured step loop;",
+        "adjacent Taylor orders share one launch (each item at its own order).",
         "",
         "Commands (from the repository root, TMPDIR=/tmp):",
         "",
         *[f"    {c}" for c in commands],
         "",
-        "| kernel | dispatches | average | min / max | FETCH_SIZE | WRITE_SIZE |",
+        "| kernel | dispatches | average | min / max | FETCH_SIZE per dispatch | WRITE_SIZE per dispatch |",
         "|---|---|---|---|---|---|",
         *[f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} ms | "
           f"{float(r['MinNs']) / 1e6:.4f} / {float(r['MaxNs']) / 1e6:.4f} ms | "
@@ -277,14 +279,18 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for scaling HBM counters)")
     ap.add_argument("--regular", action="store_true", help="one block per item group instead of the persistent grid")
-    ap.add_argument("--no-autotune", action="store_true", help="keep --cols-per-lane and 4 waves per block")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep --cols-per-lane, --waves-per-block and --waves-per-cu")
+    ap.add_argument("--waves-per-block", type=int, default=4)
+    ap.add_argument("--waves-per-cu", type=int, default=0, help="persistent grid: resident waves per CU (0: all)")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the step kernel's rocprofv3 summary under profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the profile summary (repeatable)")
     a = ap.parse_args()
     if a.profile_summary:
-        profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane)
+        profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane,
+                        waves_per_block=a.waves_per_block, waves_per_cu=a.waves_per_cu)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: realisations are independent, and a multi-GPU run would "
@@ -319,8 +325,8 @@ def main():
         del src, dst
     sizes = w.lattice_sizes()
     amps = int(np.sum(sizes.astype(np.int64) ** 2))
-    launch = {"cols_per_lane": a.cols_per_lane, "persistent": 0 if a.regular else 1, "waves_per_block": 4,
-              "use_graph": 1}
+    launch = {"cols_per_lane": a.cols_per_lane, "persistent": 0 if a.regular else 1,
+              "waves_per_block": a.waves_per_block, "waves_per_cu": a.waves_per_cu, "use_graph": 1}
     log("building the complex64 plan ...")
     plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
     tuned = None
