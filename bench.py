@@ -123,15 +123,23 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per step-kernel launch from the committed counter summary,
-    if it was taken on the current kernel sources."""
+def shape_tag(launch) -> str:
+    return (f"cols_per_lane={launch.get('cols_per_lane', 1)} waves_per_block={launch.get('waves_per_block', 4)} "
+            f"waves_per_cu={launch.get('waves_per_cu', 0)}")
+
+
+def recorded_traffic(launch):
+    """HBM bytes per step from the committed counter summary, if it was taken
+    on the current kernel sources and at this launch shape."""
     try:
         text = open(SUMMARY).read()
     except OSError:
         return None
-    fields = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("kernel-source-sha256:", "traffic-bytes:")))
+    keys = ("kernel-source-sha256:", "traffic-bytes:", "launch-shape:")
+    fields = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(keys))
     if fields.get("kernel-source-sha256", "").strip() != kernel_source_hash():
+        return None
+    if fields.get("launch-shape", "").strip() != shape_tag(launch):
         return None
     try:
         return int(fields["traffic-bytes"].strip())
@@ -213,6 +221,8 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         f"| HBM bytes written per step | {write_b / 1e9:.3f} GB |",
         "",
         f"kernel-source-sha256: {kernel_source_hash()}",
+        "launch-shape: " + shape_tag({"cols_per_lane": cols_per_lane, "waves_per_block": waves_per_block,
+                                      "waves_per_cu": waves_per_cu}),
         f"traffic-bytes: {int(round(fetch_b + write_b))}",
         "",
     ]
@@ -360,7 +370,7 @@ def main():
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
     orders = plan.orders()
     items, _ = plan.work_items()
-    traffic = recorded_traffic()
+    traffic = recorded_traffic(launch)
     del plan
     torch.cuda.empty_cache()
 
