@@ -81,6 +81,30 @@ def test_per_order_launch_forms_are_bitwise_identical(dtype, acc):
             assert np.array_equal(p.state_numpy(), ref), (P_, launch)
 
 
+@pytest.mark.parametrize("acc", ["kahan", "plain"])
+def test_two_order_launches_match_separate_launches(acc):
+    """Complex64 at two columns per lane launches orders n and n - 1
+    together (each item branching to its own pipeline); one column per lane
+    launches each order alone.  The full-grid arithmetic is the same at one
+    and two columns per lane, so the states agree bit for bit, and they
+    differ from a run with every realisation at the largest order."""
+    reals = mixed_reals(15)
+    want = expected_orders(reals)
+    say(f"case: two-order launch vs separate launches, c64 {acc}, orders {want}")
+    assert len(set(want)) >= 2
+    kw = dict(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
+              accumulation=acc, reals=reals, dt=DT, sites=[14, 15])
+    out = {}
+    for P_ in (1, 2):
+        plan = gpu_plan(**kw, tol=TOL, launch={"cols_per_lane": P_, "persistent": 1})
+        plan.propagate(11)
+        out[P_] = plan.state_numpy()
+    assert np.array_equal(out[1], out[2])
+    fixed = gpu_plan(**kw, tol=0.0, order=max(want), launch={"cols_per_lane": 2})
+    fixed.propagate(11)
+    assert not np.array_equal(fixed.state_numpy(), out[2])
+
+
 def test_truncation_estimate_follows_the_applied_order():
     """After four steps the squared truncation estimate of realisation r is
     ||Phi^(n_r)||^2 f(x_r, n_r)^2, with Phi^(n) = (-i dt H)^n psi / n! of the
