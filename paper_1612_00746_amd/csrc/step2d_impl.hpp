@@ -222,6 +222,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     // (1 KB rows, and the registers are taken by the wider windows) and for
     // chunked passes (which fetch two rows per row).
     constexpr int PF = (sizeof(T) == 4 && !CHUNK && P == 1) ? WA : 3;
+    static_assert(WA % PF == 0, "the prefetch ring must tile the unrolled block");
 
     // The item and its realisation are wave-uniform: scalar loads, so every
     // pointer and row base derived from them stays in scalar registers.
