@@ -276,6 +276,52 @@ def time_plan(plan, steps, warmup):
     return wall, kern_ms / launches
 
 
+def three_walkers(a):
+    """Three distinguishable walkers on N = 256 (64 realisations, 1.07e9
+    amplitudes, nearest-neighbour U, complex64 with the compensated sum):
+    each Taylor term is one pass over the state.  The first pass reads psi
+    and writes the first term, the sum and its compensation (32 B per
+    amplitude), middle passes read and write all three (48 B), the last
+    reads three and writes the new state (32 B): 48 n - 32 B per amplitude
+    and step for n >= 2 terms."""
+    import torch
+    from paper_1612_00746_amd import Plan, make_problem
+    from workloads import C5
+    w = C5()
+    sizes = w.lattice_sizes()
+    reals = w.all_realizations()
+    J = np.concatenate([r[1] for r in reals])
+    eps = np.concatenate([r[2] for r in reals])
+    U = np.array([r[3] for r in reals])
+    pr, keep = make_problem(3, w.R, int(sizes[0]), w.dt, statistics=w.statistics, interaction=w.interaction,
+                            dtype="c64", accumulation="kahan", taylor_tol=w.tol, observables=1)
+    plan = Plan(pr)
+    plan._keep.append(keep)
+    plan.set_launch(use_graph=1)
+    plan.set_params(J, eps, U)
+    plan.bind()
+    plan.init_product_state(np.array([w.start_sites(int(n)) for n in sizes], dtype=np.int32))
+    wall, kern_ms = time_plan(plan, a.steps, a.warmup)
+    amps = int(np.sum(sizes.astype(np.int64) ** 3))
+    n = int(plan.orders().max())
+    achieved = amps * (48.0 * n - 32.0 if n >= 2 else 16.0) / (kern_ms * 1e-3) / 1e9
+    st = plan.stats()
+    print(json.dumps({
+        "metric": "amplitude-updates/s per Taylor step", "value": amps * a.steps / wall,
+        "unit": "amplitude-updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(1e3 * wall / a.steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic (seeded noise draws, no dataset)",
+        "config": {"workload": w.name, "realisations": w.R, "sites": int(sizes[0]), "particles": 3,
+                   "amplitudes": amps, "dt": w.dt, "taylor_tol": w.tol, "taylor_order": n},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "term3d_kernel",
+                     "kernel_ms": round(kern_ms, 4)},
+        "norm_range": [st.min_norm, st.max_norm],
+    }))
+    del plan
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +343,8 @@ def main():
                     help="write the step kernel's rocprofv3 summary under profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the profile summary (repeatable)")
+    ap.add_argument("--three-walkers", action="store_true",
+                    help="time the three-walker path instead (64 x 256^3 amplitudes, complex64, one term per pass)")
     a = ap.parse_args()
     if a.profile_summary:
         profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane,
@@ -307,6 +355,10 @@ def main():
               "shard them with one all-reduce of the FP64 observables; only --gpus 1 is built.",
               file=sys.stderr)
         sys.exit(2)
+
+    if a.three_walkers:
+        three_walkers(a)
+        return
 
     from workloads import C3
     w = C3("c64")

@@ -71,14 +71,24 @@ __global__ void init_sites_kernel(InitArgs a) {
 
 // ------------------------------------------------------------ step finalize
 
+// One wave per realisation: lane l sums the partials l, l + 64, ... of its
+// realisation, then a fixed butterfly combines the lanes (deterministic;
+// three walkers have 65536 partials per realisation at N = 256).
 __global__ void finalize_kernel(FinalizeArgs a) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.R) return;
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= a.R) return;   // wave-uniform
     double s = 0.0, t = 0.0;
-    for (int32_t k = a.item_first[r]; k < a.item_first[r + 1]; ++k) {
+    for (int32_t k = a.item_first[r] + lane; k < a.item_first[r + 1]; k += 64) {
         s += a.norm_part[k];
         t += a.tail_part[k];
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        t += __shfl_xor(t, off, 64);
+    }
+    if (lane != 0) return;
     const double tf = a.use_max ? a.reals[r].tail_factor_max : a.reals[r].tail_factor;
     const double err2 = t * tf * tf;
     a.norm2[r] = s;
@@ -234,7 +244,7 @@ hipError_t launch_init(const InitArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t stream) {
-    const unsigned blocks = (unsigned)((a.R + 255) / 256);
+    const unsigned blocks = (unsigned)((a.R + 3) / 4);   // four waves (realisations) per block
     hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(256), 0, stream, a);
     return hipGetLastError();
 }
