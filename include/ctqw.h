@@ -131,8 +131,11 @@ typedef struct {
                                 boundaries between the column bands of a
                                 realisation are moved down to multiples of
                                 this many bytes of a row, so that no cache
-                                line of the new state is stored by two waves
-                                (0: bands as wide as the halo allows) */
+                                line of the new state is stored by two waves;
+                                per realisation the largest power-of-two
+                                fraction of it that needs no more bands than
+                                unaligned boundaries is taken (0: bands as
+                                wide as the halo allows) */
 } ctqw_launch;
 
 /* Create a plan from a problem statement.  Host only: validates the

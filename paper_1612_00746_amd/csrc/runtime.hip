@@ -182,7 +182,8 @@ T* at(ctqw_plan* p, const Region& r) {
 // Column bands of one realisation for halo h (= its Taylor order) and a
 // window of W columns.  Band boundaries inside the chain are moved down to
 // multiples of `align` columns where that leaves the band an output column,
-// so that the stores of neighbouring bands do not share cache lines.
+// so that the stores of neighbouring bands do not share cache lines (the
+// caller halves the alignment while it would add a band).
 // Returns false if the halo leaves no output column.
 // With `pairs` (lanes holding two adjacent columns) the window starts on an
 // even column where the chain allows, so that the lanes' column pairs are
@@ -263,8 +264,21 @@ ctqw_status build_tables(ctqw_plan* p) {
     } else {
         for (int64_t r = 0; r < pr.R; ++r) {
             first[r] = (int32_t)items.size();
-            if (!make_bands(pr, (int)r, p->N[r], halo, band_W, align, band_W == 128 && dtype == 0, items))
+            // the largest alignment (at most the requested one) that needs no
+            // more bands than unaligned boundaries
+            const bool pairs_r = band_W == 128 && dtype == 0;
+            std::vector<ItemDev> plain, trial;
+            if (!make_bands(pr, (int)r, p->N[r], halo, band_W, 1, pairs_r, plain))
                 return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", halo, band_W);
+            const std::vector<ItemDev>* use = &plain;
+            for (int a = align; a > 1; a /= 2) {
+                trial.clear();
+                if (make_bands(pr, (int)r, p->N[r], halo, band_W, a, pairs_r, trial) && trial.size() <= plain.size()) {
+                    use = &trial;
+                    break;
+                }
+            }
+            items.insert(items.end(), use->begin(), use->end());
         }
         first[pr.R] = (int32_t)items.size();
         n_parts = (int64_t)items.size();

@@ -302,8 +302,7 @@ def reference_band_count(N, h, W, align_cols, pairs):
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 def test_band_boundaries_follow_the_alignment(P, align, dtype):
     """Work items per step for open chains of several lengths at order 7
-    match the band rule; 128-byte boundaries never give fewer items than
-    unaligned ones."""
+    match the band rule; alignment never changes the number of items."""
     Ns = [64, 96, 300, 999, 1024]
     plan = make(R=len(Ns), n_sites=Ns, taylor_order=7, taylor_tol=0.0, dtype=dtype)
     plan.set_launch(cols_per_lane=P, band_align=align)
@@ -313,11 +312,19 @@ def test_band_boundaries_follow_the_alignment(P, align, dtype):
     plan.set_params(J, eps, U)
     amp = 8 if dtype == "c64" else 16
     cols = max(1, align // amp)
-    want = sum(reference_band_count(N, 7, 64 * P, cols, P == 2 and dtype == "c64") for N in Ns)
+    pairs = P == 2 and dtype == "c64"
+    want = 0
+    for N in Ns:
+        # the largest power-of-two fraction of the alignment adding no band
+        base = reference_band_count(N, 7, 64 * P, 1, pairs)
+        a = cols
+        while a > 1 and reference_band_count(N, 7, 64 * P, a, pairs) > base:
+            a //= 2
+        want += reference_band_count(N, 7, 64 * P, a, pairs)
     items, _ = plan.work_items()
     assert items == want
     plan.set_launch(cols_per_lane=P, band_align=0)
-    assert plan.work_items()[0] <= items
+    assert plan.work_items()[0] == items
 
 
 def test_band_align_values_are_checked():
