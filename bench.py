@@ -276,6 +276,56 @@ def time_plan(plan, steps, warmup):
     return wall, kern_ms / launches
 
 
+def rk4_compare(a):
+    """Runtime of the two propagators at equal per-step accuracy (the
+    analogue of the paper's RK4 / Taylor comparison, Fig. 2): the batch's
+    Taylor steps at dt = 0.05 with the a-priori order for tolerance 1e-7
+    against RK4 (the degree-4 step) at the largest dt for which the same
+    a-priori bound allows 4 terms for every realisation; both reported as
+    milliseconds per unit of simulated time."""
+    import torch
+    from paper_1612_00746_amd import Plan, make_problem
+    from workloads import C3
+    w = C3("c64")
+    sizes = w.lattice_sizes()
+    reals = w.all_realizations()
+    J = np.concatenate([r[1] for r in reals])
+    eps = np.concatenate([r[2] for r in reals])
+    U = np.array([r[3] for r in reals])
+    launch = dict(cols_per_lane=2, persistent=1, waves_per_block=1, waves_per_cu=8, use_graph=1)
+
+    def max_order(dt):
+        pr, keep = make_problem(2, w.R, sizes.tolist(), dt, dtype="c64", taylor_tol=w.tol)
+        p = Plan(pr)
+        p._keep.append(keep)
+        p.set_params(J, eps, U)
+        return int(p.orders().max())
+    lo, hi = 1e-4, w.dt
+    for _ in range(40):   # largest dt with every a-priori order <= 4
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if max_order(mid) <= 4 else (lo, mid)
+    dt_rk4 = lo
+    out = {}
+    for name, dt, kw in (("taylor", w.dt, dict(taylor_tol=w.tol)), ("rk4", dt_rk4, dict(method="rk4"))):
+        pr, keep = make_problem(2, w.R, sizes.tolist(), dt, statistics=w.statistics, dtype="c64",
+                                accumulation="kahan", observables=1, **kw)
+        plan = Plan(pr)
+        plan._keep.append(keep)
+        plan.set_launch(**launch)
+        plan.set_params(J, eps, U)
+        plan.bind()
+        plan.init_product_state(np.array([[n // 2 - 1, n // 2] for n in sizes], dtype=np.int32))
+        wall, kern_ms = time_plan(plan, a.steps, a.warmup)
+        ms = 1e3 * wall / a.steps
+        out[name] = {"dt": dt, "terms": [int(plan.orders().min()), int(plan.orders().max())],
+                     "ms_per_step": round(ms, 4), "ms_per_unit_time": round(ms / dt, 2)}
+        del plan
+        torch.cuda.empty_cache()
+    out["rk4_over_taylor_time"] = round(out["rk4"]["ms_per_unit_time"] / out["taylor"]["ms_per_unit_time"], 3)
+    print(json.dumps({"comparison": "RK4 (Alg. 2) vs adaptive Taylor (Alg. 3) at per-step tolerance 1e-7",
+                      "workload": w.name, **out}))
+
+
 def three_walkers(a):
     """Three distinguishable walkers on N = 256 (64 realisations, 1.07e9
     amplitudes, nearest-neighbour U, complex64 with the compensated sum):
@@ -343,6 +393,8 @@ def main():
                     help="write the step kernel's rocprofv3 summary under profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the profile summary (repeatable)")
+    ap.add_argument("--rk4-compare", action="store_true",
+                    help="time Alg. 2 (RK4) against the adaptive Taylor step at equal per-step accuracy on the batch")
     ap.add_argument("--three-walkers", action="store_true",
                     help="time the three-walker path instead (64 x 256^3 amplitudes, complex64, one term per pass)")
     a = ap.parse_args()
@@ -358,6 +410,9 @@ def main():
 
     if a.three_walkers:
         three_walkers(a)
+        return
+    if a.rk4_compare:
+        rk4_compare(a)
         return
 
     from workloads import C3

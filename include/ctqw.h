@@ -85,7 +85,9 @@ typedef struct {
     const int32_t* n_sites_per_real; /* ... [R] sizes (uneven batch), copied */
     double dt;               /* time step, finite and > 0 */
     int32_t taylor_order;    /* > 0: fixed n terms per step (Alg. 3);
-                                0: n_r chosen per realisation from taylor_tol */
+                                0: n_r chosen per realisation from taylor_tol;
+                                CTQW_RK4_ORDER: the classical Runge-Kutta
+                                step of Alg. 2 (see below) */
     double taylor_tol;       /* per-step relative 2-norm truncation tolerance */
     int32_t taylor_max_order;/* cap on n_r; 0 or above the compiled maximum
                                 (12 for complex64, 16 for complex128) means
@@ -184,6 +186,15 @@ typedef struct {
 ctqw_status ctqw_draw_params(ctqw_plan* plan, const double* J_base, const double* eps_base, double U_base,
                              const ctqw_noise* J_noise, const ctqw_noise* eps_noise, const ctqw_noise* U_noise,
                              uint64_t seed);
+
+/* Alg. 2 (classical fourth-order Runge-Kutta).  For dpsi/dt = -i H psi
+ * with H constant over the step, the stages K1 = A psi, K2 = A (psi +
+ * K1/2), K3 = A (psi + K2/2), K4 = A (psi + K3) with A = -i dt H combine
+ * to psi + (K1 + 2 K2 + 2 K3 + K4)/6 = sum_{k<=4} A^k psi / k!, the
+ * degree-4 Taylor step; taylor_order = CTQW_RK4_ORDER (with taylor_tol
+ * unused) therefore runs Alg. 2, as one fused pass per step.  Like any
+ * truncated series it does not conserve the norm exactly.                 */
+#define CTQW_RK4_ORDER 4
 
 /* Taylor terms per step of each realisation, [R].  With taylor_order > 0
  * every entry is taylor_order; otherwise n_r is the smallest n >= 1 with

@@ -16,7 +16,7 @@ import numpy as np
 
 from . import _lib as L
 from ._lib import (ACC_KAHAN, ACC_PLAIN, BOSON, C64, C128, DISTINGUISHABLE, INT_NEAREST,  # noqa: F401
-                   INT_ONSITE, OBS_OCCUPATION, OBS_PAIR, OPEN, PERIODIC, CtqwError)
+                   INT_ONSITE, OBS_OCCUPATION, OBS_PAIR, OPEN, PERIODIC, RK4_ORDER, CtqwError)
 
 __all__ = ["Plan", "CtqwError", "make_problem"]
 
@@ -36,8 +36,17 @@ def make_problem(m: int, R: int, n_sites: int | Sequence[int], dt: float, *,
                  interaction: str = "onsite", dtype: str = "c128", accumulation: str = "kahan",
                  taylor_order: int = 0, taylor_tol: float = 0.0, taylor_max_order: int = 0,
                  renormalize: bool = False, norm_alarm: float = 0.0,
-                 observables: int = OBS_OCCUPATION):
-    """Build a ``ctqw_problem``; returns (struct, keep-alive array or None)."""
+                 observables: int = OBS_OCCUPATION, method: str = "taylor"):
+    """Build a ``ctqw_problem``; returns (struct, keep-alive array or None).
+    method="rk4": the classical Runge-Kutta step (Alg. 2), which for this
+    linear system is the degree-4 Taylor step (include/ctqw.h,
+    CTQW_RK4_ORDER); taylor_order and taylor_tol must then be left unset."""
+    if method == "rk4":
+        if taylor_order or taylor_tol:
+            raise ValueError("method='rk4' fixes the step; leave taylor_order and taylor_tol unset")
+        taylor_order = RK4_ORDER
+    elif method != "taylor":
+        raise ValueError(f"unknown method {method!r}")
     pr = L.Problem()
     pr.m = m
     pr.statistics = _STAT[statistics]

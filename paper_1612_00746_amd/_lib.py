@@ -25,6 +25,7 @@ ACC_KAHAN, ACC_PLAIN = 0, 1
 OBS_OCCUPATION, OBS_PAIR = 1, 2
 LOSS_ONE_BODY, LOSS_PRODUCT = 0, 1
 DIST_NONE, DIST_UNIFORM, DIST_NORMAL = 0, 1, 2
+RK4_ORDER = 4
 
 
 class Problem(C.Structure):

@@ -331,3 +331,21 @@ def test_band_align_values_are_checked():
     plan = make()
     assert status_of(lambda: plan.set_launch(band_align=96)) == 1
     assert status_of(lambda: plan.set_launch(band_align=-1)) == 1
+
+
+def test_rk4_method_is_the_degree_four_step():
+    """method="rk4" runs Alg. 2 as the degree-4 Taylor step: every
+    realisation takes CTQW_RK4_ORDER terms, and the constant matches the
+    header."""
+    from paper_1612_00746_amd import _lib as L, make_problem
+    text = open(HEADER).read()
+    m = re.search(r"#define CTQW_RK4_ORDER (\d+)", text)
+    assert m and int(m.group(1)) == L.RK4_ORDER == 4
+    plan = make(method="rk4", taylor_tol=0.0)
+    J, eps, U = draw(8, 3, 7)
+    plan.set_params(J, eps, U)
+    assert list(plan.orders()) == [4, 4, 4]
+    with pytest.raises(ValueError):
+        make_problem(2, 3, 8, 0.05, method="rk4", taylor_tol=1e-7)
+    with pytest.raises(ValueError):
+        make_problem(2, 3, 8, 0.05, method="euler")
