@@ -326,6 +326,46 @@ def rk4_compare(a):
                       "workload": w.name, **out}))
 
 
+def density(a):
+    """Ensemble-averaged density matrix (Eq. 2) of 1000 realisations of two
+    bosons on N = 128 (D = 8256, complex64): the gather of the states and
+    one Hermitian rank-1000 update.  FLOPs counted for the lower triangle:
+    4 D (D + 1) R real operations (one complex multiply-add is 8); the
+    matrix cores' dense FP32 peak is 157.3 TFLOP/s."""
+    import torch
+    from workloads import C2
+    w = C2("c64")
+    reals = w.all_realizations()
+    J = np.concatenate([r[1] for r in reals])
+    eps = np.concatenate([r[2] for r in reals])
+    U = np.array([r[3] for r in reals])
+    from paper_1612_00746_amd import Plan, make_problem
+    pr, keep = make_problem(2, w.R, w.N, w.dt, statistics="boson", dtype="c64", accumulation="kahan",
+                            taylor_tol=w.tol, observables=1)
+    plan = Plan(pr)
+    plan.set_params(J, eps, U)
+    plan.bind()
+    plan.init_product_state(np.array(w.start_sites(w.N), dtype=np.int32))
+    plan.propagate(20)
+    rho = plan.density_matrix(0)          # warm-up (rocBLAS initialisation)
+    D = rho.shape[0]
+    times = []
+    for _ in range(max(3, a.steps // 4)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rho = plan.density_matrix(0)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    flops = 4.0 * D * (D + 1) * w.R
+    tr = float(torch.trace(rho).real)
+    print(json.dumps({"metric": "ensemble density matrix, TFLOP/s", "workload": "C2 shape: 1000 x two bosons, N = 128",
+                      "D": D, "realisations": w.R, "ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+                      "peak_fp32_mfma_tflops": 157.3, "frac": round(flops / (ms * 1e-3) / 157.3e12, 4),
+                      "trace": tr}))
+
+
 def three_walkers(a):
     """Three distinguishable walkers on N = 256 (64 realisations, 1.07e9
     amplitudes, nearest-neighbour U, complex64 with the compensated sum):
@@ -395,6 +435,8 @@ def main():
                     help="command line recorded in the profile summary (repeatable)")
     ap.add_argument("--rk4-compare", action="store_true",
                     help="time Alg. 2 (RK4) against the adaptive Taylor step at equal per-step accuracy on the batch")
+    ap.add_argument("--density", action="store_true",
+                    help="time the ensemble density matrix of 1000 two-boson states on N = 128 (complex64)")
     ap.add_argument("--three-walkers", action="store_true",
                     help="time the three-walker path instead (64 x 256^3 amplitudes, complex64, one term per pass)")
     a = ap.parse_args()
@@ -413,6 +455,9 @@ def main():
         return
     if a.rk4_compare:
         rk4_compare(a)
+        return
+    if a.density:
+        density(a)
         return
 
     from workloads import C3

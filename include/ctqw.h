@@ -262,6 +262,24 @@ ctqw_status ctqw_observe(ctqw_plan* plan, uint32_t obs, double* out);
 /* Number of groups (distinct lattice sizes) and their sizes, ascending.   */
 ctqw_status ctqw_groups(const ctqw_plan* plan, int32_t* n_groups, int32_t* sizes);
 
+/* Ensemble-averaged density matrix of one group (Eq. 2; the paper updates
+ * it with one Hermitian rank-1 update per realisation):
+ *     rho_g = (1/R_g) sum_{r in g} |psi_r><psi_r|,
+ * D_g x D_g complex of the plan's dtype in the basis of ctqw_layout (bosons:
+ * the normalised symmetric basis, coefficient sqrt(2) phi off the
+ * diagonal), column-major with leading dimension ld >= D_g, written to the
+ * caller's device memory rho.  lower_only != 0: only the lower triangle is
+ * written; else the full Hermitian matrix.  workspace: device memory of at
+ * least ctqw_density_workspace(group) bytes (the group's states gathered
+ * with the load scale into a D_g x R_g matrix); rho = A A^H / R_g is one
+ * rocBLAS cherk / zherk on the matrix cores.  Enqueued on the plan's
+ * stream.  Errors: INVALID_ARG (NULL, group out of range, ld or workspace
+ * too small), UNSUPPORTED (D_g or ld >= 2^31, R_g > 65535, full matrix
+ * with D_g > 16776960), STATE (not bound), DEVICE.                        */
+ctqw_status ctqw_density_workspace(const ctqw_plan* plan, int32_t group, int64_t* bytes);
+ctqw_status ctqw_density_matrix(ctqw_plan* plan, int32_t group, void* rho, int64_t ld, int32_t lower_only,
+                                void* workspace, int64_t workspace_bytes);
+
 /* Monitoring after the last step (see ctqw_step_stats).                   */
 ctqw_status ctqw_stats(ctqw_plan* plan, ctqw_step_stats* out);
 /* FP64 squared norms and estimated squared truncation errors of every

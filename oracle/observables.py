@@ -72,3 +72,13 @@ def exact_mean(values) -> float:
     """Correctly rounded mean of a 1-D list (math.fsum), for checks."""
     values = [float(v) for v in values]
     return math.fsum(values) / len(values)
+
+
+def density_matrix(states) -> np.ndarray:
+    """<rho> = (1/R) sum_r |psi_r><psi_r| (Eq. 2), the full matrix, from the
+    realisations' coefficient vectors in one basis (rows of `states`)."""
+    states = [np.asarray(s, dtype=np.complex128) for s in states]
+    rho = np.zeros((states[0].size, states[0].size), dtype=np.complex128)
+    for psi in states:
+        rho += np.outer(psi, psi.conj())
+    return rho / len(states)

@@ -238,6 +238,30 @@ class Plan:
         self._check(self.lib.ctqw_observe(self.h, obs, _ptr(out, C.c_double)))
         return out
 
+    def density_matrix(self, group: int = 0, lower_only: bool = False):
+        """Ensemble-averaged density matrix of lattice-size group `group`
+        (ctqw_density_matrix) as a device tensor, row-major rho[i, j]."""
+        import torch
+        ws_bytes = C.c_int64()
+        self._check(self.lib.ctqw_density_workspace(self.h, group, C.byref(ws_bytes)))
+        psi_a = self._buffers[0]
+        ctype = torch.complex128 if self.dtype == "c128" else torch.complex64
+        esz = 16 if self.dtype == "c128" else 8
+        D = int(round((ws_bytes.value // esz) / self.group_sizes(group)))
+        rho = torch.zeros((D, D), dtype=ctype, device=psi_a.device)
+        ws = torch.empty(max(ws_bytes.value, 256), dtype=torch.uint8, device=psi_a.device)
+        self._check(self.lib.ctqw_density_matrix(self.h, group, C.c_void_p(rho.data_ptr()), D,
+                                                 1 if lower_only else 0, C.c_void_p(ws.data_ptr()),
+                                                 ws_bytes.value))
+        self._stream.synchronize()
+        # the buffer is column-major: its row-major view is rho transposed
+        return rho.transpose(0, 1)
+
+    def group_sizes(self, group: int) -> int:
+        """Realisations in lattice-size group `group`."""
+        N = int(self.groups()[group])
+        return sum(1 for n in self.Ns if n == N)
+
     def stats(self) -> "L.StepStats":
         s = L.StepStats()
         self._check(self.lib.ctqw_stats(self.h, C.byref(s)))

@@ -28,6 +28,7 @@
 #include "../../include/ctqw.h"
 #include "ctqw_internal.hpp"
 #include "noise.hpp"
+#include "density.hpp"
 
 using namespace ctqw;
 
@@ -113,8 +114,10 @@ struct ctqw_plan {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
     }
+    void* blas = nullptr;            // rocBLAS handle of the density-matrix update (lazy)
     ~ctqw_plan() {
         drop_graphs();
+        density_release(blas);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
@@ -1134,6 +1137,59 @@ ctqw_status ctqw_groups(const ctqw_plan* p, int32_t* n_groups, int32_t* sizes) {
     if (!p || !n_groups) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
     *n_groups = (int32_t)p->group_N.size();
     if (sizes) std::memcpy(sizes, p->group_N.data(), p->group_N.size() * 4);
+    return CTQW_OK;
+}
+
+namespace {
+// Stored amplitudes of the realisations of group g (all equal).
+int64_t group_dim(const ctqw_plan* p, int32_t g) {
+    const int32_t r = p->group_members[p->group_first[g]];
+    return p->state_off[r + 1] - p->state_off[r];
+}
+}  // namespace
+
+ctqw_status ctqw_density_workspace(const ctqw_plan* p, int32_t group, int64_t* bytes) {
+    if (!p || !bytes) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (!p->params_set) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_STATE, "parameters not set");
+    if (group < 0 || group >= (int32_t)p->group_N.size())
+        return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "group %d out of range", group);
+    const int64_t Rg = p->group_first[group + 1] - p->group_first[group];
+    *bytes = group_dim(p, group) * Rg * (p->prob.dtype == CTQW_C128 ? 16 : 8);
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_density_matrix(ctqw_plan* p, int32_t group, void* rho, int64_t ld, int32_t lower_only,
+                                void* workspace, int64_t workspace_bytes) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!rho || !workspace) return fail(p, CTQW_ERR_INVALID_ARG, "NULL argument");
+    int64_t need = 0;
+    ctqw_status st = ctqw_density_workspace(p, group, &need);
+    if (st != CTQW_OK) return st;
+    const int64_t D = group_dim(p, group);
+    const int64_t Rg = p->group_first[group + 1] - p->group_first[group];
+    if (ld < D) return fail(p, CTQW_ERR_INVALID_ARG, "ld %lld below the dimension %lld", (long long)ld, (long long)D);
+    if (workspace_bytes < need)
+        return fail(p, CTQW_ERR_INVALID_ARG, "workspace too small (%lld < %lld bytes)", (long long)workspace_bytes,
+                    (long long)need);
+    if (D > INT32_MAX || ld > INT32_MAX || Rg > 65535)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "density matrix limited to D, ld < 2^31 and 65535 realisations");
+    if (!lower_only && D > 65535 * 256)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "full density matrix limited to D <= 16776960");
+    if ((st = ensure_ready(p)) != CTQW_OK) return st;
+    const int dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
+    DensityArgs a{};
+    a.psi = p->psi[p->cur];
+    a.reals = at<RealDev>(p, p->lay.reals);
+    a.scale = at<double>(p, p->lay.scale);
+    a.members = at<int32_t>(p, p->lay.gmembers) + p->group_first[group];
+    a.A = workspace;
+    a.D = D;
+    a.R_g = Rg;
+    a.triangle = (p->prob.m == 2 && p->prob.statistics == CTQW_BOSON) ? 1 : 0;
+    HIP_TRY(p, launch_density_gather(a, dtype, p->stream));
+    const int e = density_herk(&p->blas, p->stream, dtype, D, Rg, workspace, rho, ld);
+    if (e != 0) return fail(p, CTQW_ERR_DEVICE, "Hermitian rank-k update failed (rocBLAS status %d)", e);
+    if (!lower_only) HIP_TRY(p, launch_density_mirror(rho, D, ld, dtype, p->stream));
     return CTQW_OK;
 }
 

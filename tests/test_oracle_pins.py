@@ -421,3 +421,25 @@ def test_unit53_and_draw_mappings():
     # distinct counters and keys give distinct blocks
     assert noise.philox4x32([0, 0, 0, 0], [0, 0]) != noise.philox4x32([1, 0, 0, 0], [0, 0])
     assert noise.philox4x32([0, 0, 0, 0], [0, 0]) != noise.philox4x32([0, 0, 0, 0], [1, 0])
+
+
+def test_density_matrix_properties():
+    """<rho> from the oracle: Hermitian, unit trace, positive semidefinite,
+    its diagonal the mean probabilities; a single pure state is a
+    projector (rho^2 = rho) and a mixture of orthogonal states is not."""
+    from oracle import observables as O
+    g = np.random.default_rng(5)
+    states = []
+    for _ in range(4):
+        v = g.standard_normal(12) + 1j * g.standard_normal(12)
+        states.append(v / np.linalg.norm(v))
+    rho = O.density_matrix(states)
+    assert np.allclose(rho, rho.conj().T, atol=1e-15)
+    assert abs(np.trace(rho) - 1) < 1e-14
+    assert np.min(np.linalg.eigvalsh(rho)) > -1e-14
+    assert np.allclose(np.diag(rho).real, np.mean([np.abs(s) ** 2 for s in states], axis=0), atol=1e-15)
+    pure = O.density_matrix(states[:1])
+    assert np.allclose(pure @ pure, pure, atol=1e-14)
+    e = np.eye(12)
+    mixed = O.density_matrix([e[0], e[1]])
+    assert np.allclose(mixed @ mixed, mixed / 2, atol=1e-15) and not np.allclose(mixed @ mixed, mixed)
