@@ -326,6 +326,31 @@ def rk4_compare(a):
                       "workload": w.name, **out}))
 
 
+def telegraph(a):
+    """The batch's step with switching hopping noise (amplitude 0.1, rate 1
+    per unit time: the device flips the bonds' signs and rewrites the
+    hopping tables before every step) against the same batch with static
+    noise, at the tuned launch shape."""
+    import torch
+    from workloads import C3
+    w = C3("c64")
+    launch = dict(cols_per_lane=2, persistent=1, waves_per_block=1, waves_per_cu=8, use_graph=1)
+    out = {}
+    for name, amp in (("static", 0.0), ("switching", 0.1)):
+        plan = build_plan(w, "c64", "kahan", launch, w.tol)
+        if amp:
+            plan.set_telegraph(amp, 1.0, 7)
+            plan.bind()
+            sizes = w.lattice_sizes()
+            plan.init_product_state(np.array([[n // 2 - 1, n // 2] for n in sizes], dtype=np.int32))
+        wall, kern_ms = time_plan(plan, a.steps, a.warmup)
+        out[name] = {"ms_per_step": round(1e3 * wall / a.steps, 4),
+                     "terms": [int(plan.orders().min()), int(plan.orders().max())]}
+        del plan
+        torch.cuda.empty_cache()
+    print(json.dumps({"comparison": "switching hopping noise vs static noise", "workload": w.name, **out}))
+
+
 def density(a):
     """Ensemble-averaged density matrix (Eq. 2) of 1000 realisations of two
     bosons on N = 128 (D = 8256, complex64): the gather of the states and
@@ -435,6 +460,8 @@ def main():
                     help="command line recorded in the profile summary (repeatable)")
     ap.add_argument("--rk4-compare", action="store_true",
                     help="time Alg. 2 (RK4) against the adaptive Taylor step at equal per-step accuracy on the batch")
+    ap.add_argument("--telegraph", action="store_true",
+                    help="time the batch with switching hopping noise (a = 0.1, rate 1) against static noise")
     ap.add_argument("--density", action="store_true",
                     help="time the ensemble density matrix of 1000 two-boson states on N = 128 (complex64)")
     ap.add_argument("--three-walkers", action="store_true",
@@ -458,6 +485,9 @@ def main():
         return
     if a.density:
         density(a)
+        return
+    if a.telegraph:
+        telegraph(a)
         return
 
     from workloads import C3

@@ -196,6 +196,22 @@ ctqw_status ctqw_draw_params(ctqw_plan* plan, const double* J_base, const double
  * truncated series it does not conserve the norm exactly.                 */
 #define CTQW_RK4_ORDER 4
 
+/* Time-dependent hopping noise (Eq. 1 with switching stochastic terms):
+ * every bond i of every realisation r carries J_i(t) = Jbar_i + xi_i(t)
+ * with Jbar the J of ctqw_set_params and xi = +-amplitude, flipping sign at
+ * the events of a Poisson process of the given rate (per unit time).  At
+ * the start of step s each bond flips with probability 1 - exp(-rate dt)
+ * and the new J holds during the step.  Draws: Philox4x32-10, counter
+ * (i, 4 (s + 1), r mod 2^32, r div 2^32), key (seed mod 2^32 XOR
+ * 0x54454C45, seed div 2^32), u = 53-bit fraction of (w0, w1): flip if
+ * u < p; s = -1 gives the initial sign, + if u < 1/2.  The a-priori
+ * orders take |Jbar_i| + amplitude.  The process starts (s = 0) when the
+ * tables are next uploaded (ctqw_bind, the first call after this one) and
+ * advances one draw per step, also inside captured step loops.
+ * amplitude = 0 returns to static noise.  Not combined with gradients.
+ * Errors: INVALID_ARG (negative or non-finite), NOT_CONVERGED (orders). */
+ctqw_status ctqw_set_telegraph(ctqw_plan* plan, double amplitude, double rate, uint64_t seed);
+
 /* Taylor terms per step of each realisation, [R].  With taylor_order > 0
  * every entry is taylor_order; otherwise n_r is the smallest n >= 1 with
  * x^(n+1)/(n+1)! / (1 - x/(n+2)) <= taylor_tol, x = dt * G_r, where G_r =

@@ -145,6 +145,10 @@ class Plan:
             self.h, None if Jb is None else _ptr(Jb, C.c_double), None if Eb is None else _ptr(Eb, C.c_double),
             float(U_base), noise(J_noise), noise(eps_noise), noise(U_noise), int(seed)))
 
+    def set_telegraph(self, amplitude: float, rate: float, seed: int = 0) -> None:
+        """Switching hopping noise +-amplitude at the given rate (ctqw_set_telegraph)."""
+        self._check(self.lib.ctqw_set_telegraph(self.h, float(amplitude), float(rate), int(seed)))
+
     def orders(self) -> np.ndarray:
         out = np.zeros(self.R, dtype=np.int32)
         self._check(self.lib.ctqw_orders(self.h, _ptr(out, C.c_int32)))

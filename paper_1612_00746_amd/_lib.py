@@ -102,6 +102,7 @@ SIGNATURES = {
     "ctqw_observe": (C.c_int, [PlanP, C.c_uint32, dp]),
     "ctqw_groups": (C.c_int, [PlanP, i32p, i32p]),
     "ctqw_density_workspace": (C.c_int, [PlanP, C.c_int32, i64p]),
+    "ctqw_set_telegraph": (C.c_int, [PlanP, C.c_double, C.c_double, C.c_uint64]),
     "ctqw_density_matrix": (C.c_int, [PlanP, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64]),
     "ctqw_stats": (C.c_int, [PlanP, C.POINTER(StepStats)]),
     "ctqw_realization_norms": (C.c_int, [PlanP, dp, dp]),

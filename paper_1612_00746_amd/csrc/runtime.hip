@@ -29,6 +29,7 @@
 #include "ctqw_internal.hpp"
 #include "noise.hpp"
 #include "density.hpp"
+#include "telegraph.hpp"
 
 using namespace ctqw;
 
@@ -45,7 +46,7 @@ struct Region {
 struct Layout {
     Region reals, items, order, item_first, claim, Jd, Ed, Jf, Ef, scale, norm_part,
         tail_part, norm2, tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites,
-        s3, M3, occ3, chunk;
+        s3, M3, occ3, chunk, tbase, tsign, tstep;
     int64_t total = 0;
 };
 
@@ -115,6 +116,8 @@ struct ctqw_plan {
         graphs.clear();
     }
     void* blas = nullptr;            // rocBLAS handle of the density-matrix update (lazy)
+    double tele_amp = 0.0, tele_rate = 0.0;   // switching hopping noise (0: static)
+    uint64_t tele_seed = 0;
     ~ctqw_plan() {
         drop_graphs();
         density_release(blas);
@@ -385,6 +388,12 @@ ctqw_status build_tables(ctqw_plan* p) {
         align_region(L, L.M3, R * 3 * NN * 8);
         align_region(L, L.occ3, G * NN * 8);
     }
+    if (p->tele_amp > 0.0) {
+        // switching noise: baseline hoppings, current signs, step counter
+        align_region(L, L.tbase, p->param_total * 8);
+        align_region(L, L.tsign, p->param_total * 4);
+        align_region(L, L.tstep, 16);
+    }
     if (chunk) {
         // two buffers for the last term of a pass, one for the partial sum
         const int64_t sb = p->state_off.back() * (pr.dtype == CTQW_C128 ? 16 : 8);
@@ -434,6 +443,23 @@ ctqw_status upload_tables(ctqw_plan* p) {
         Jd[k] = dt * p->Jpad[k];
         Ed[k] = dt * p->Epad[k];
     }
+    std::vector<float> tsign;
+    if (p->tele_amp > 0.0) {
+        // switching noise: initial signs (draw s = -1), J = Jbar + a * sign
+        tsign.assign(p->Jpad.size(), 0.0f);
+        const uint32_t key[2] = {(uint32_t)(p->tele_seed & 0xffffffffu) ^ 0x54454C45u, (uint32_t)(p->tele_seed >> 32)};
+        for (int64_t r = 0; r < R; ++r) {
+            const int nb = n_bonds(pr, p->N[r]);
+            for (int i = 0; i < nb; ++i) {
+                const uint32_t ctr[4] = {(uint32_t)i, 0u, (uint32_t)((uint64_t)r & 0xffffffffu), (uint32_t)((uint64_t)r >> 32)};
+                uint32_t w[4];
+                philox4x32_10(ctr, key, w);
+                const int64_t k = p->param_off[r] + i;
+                tsign[k] = unit_double(w[0], w[1]) < 0.5 ? 1.0f : -1.0f;
+                Jd[k] = dt * (p->Jpad[k] + p->tele_amp * (double)tsign[k]);
+            }
+        }
+    }
     std::vector<float> Jf(Jd.begin(), Jd.end()), Ef(Ed.begin(), Ed.end());
     std::vector<double> ones(R, 1.0);
     const hipMemcpyKind h2d = hipMemcpyHostToDevice;
@@ -453,6 +479,11 @@ ctqw_status upload_tables(ctqw_plan* p) {
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.gN.off, p->group_N.data(), L.gN.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.gout.off, p->group_out.data(), L.gout.bytes, h2d, s));
     HIP_TRY(p, launch_fill_zero(p->ws + L.status.off, 32, s));
+    if (p->tele_amp > 0.0) {
+        HIP_TRY(p, hipMemcpyAsync(p->ws + L.tbase.off, p->Jpad.data(), L.tbase.bytes, h2d, s));
+        HIP_TRY(p, hipMemcpyAsync(p->ws + L.tsign.off, tsign.data(), L.tsign.bytes, h2d, s));
+        HIP_TRY(p, launch_fill_zero(p->ws + L.tstep.off, 16, s));
+    }
     HIP_TRY(p, hipStreamSynchronize(s));
     p->tables_dirty = false;
     return CTQW_OK;
@@ -551,7 +582,13 @@ ctqw_status enqueue_finalize(ctqw_plan* p) {
 
 // Three particles: n one-term passes from psi[cur] into psi[1-cur] (the sum),
 // Phi ping-ponging through two workspace buffers.
+ctqw_status enqueue_telegraph(ctqw_plan* p);
+
 ctqw_status enqueue_step3(ctqw_plan* p) {
+    {
+        const ctqw_status st = enqueue_telegraph(p);
+        if (st != CTQW_OK) return st;
+    }
     const Layout& L = p->lay;
     const ctqw_problem& pr = p->prob;
     const int dtype = pr.dtype == CTQW_C128 ? 1 : 0;
@@ -676,9 +713,32 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
     return CTQW_OK;
 }
 
+// Switching noise: flip the bonds' signs for this step and rewrite the
+// dt-scaled hopping tables (before the step's kernels).
+ctqw_status enqueue_telegraph(ctqw_plan* p) {
+    if (p->tele_amp <= 0.0) return CTQW_OK;
+    const Layout& L = p->lay;
+    TeleArgs t{};
+    t.reals = at<RealDev>(p, L.reals);
+    t.Jbase = at<double>(p, L.tbase);
+    t.sign = at<float>(p, L.tsign);
+    t.step = at<int32_t>(p, L.tstep);
+    t.Jd = at<double>(p, L.Jd);
+    t.Jf = at<float>(p, L.Jf);
+    t.dt = p->prob.dt;
+    t.amp = p->tele_amp;
+    t.p_flip = -std::expm1(-p->tele_rate * p->prob.dt);
+    t.key0 = (uint32_t)(p->tele_seed & 0xffffffffu) ^ 0x54454C45u;
+    t.key1 = (uint32_t)(p->tele_seed >> 32);
+    t.R = p->prob.R;
+    HIP_TRY(p, launch_telegraph(t, p->max_N, p->stream));
+    return CTQW_OK;
+}
+
 ctqw_status enqueue_step(ctqw_plan* p) {
     if (p->prob.m == 3) return enqueue_step3(p);
     ctqw_status st;
+    if ((st = enqueue_telegraph(p)) != CTQW_OK) return st;
     if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
     if ((st = enqueue_step_kernels(p, p->psi[p->cur], p->psi[1 - p->cur])) != CTQW_OK) return st;
     if (p->timing && (st = record_event(p, 1)) != CTQW_OK) return st;
@@ -1040,10 +1100,12 @@ ctqw_status ctqw_set_params(ctqw_plan* p, const double* J, const double* eps, co
         for (int i = 0; i < N; ++i) Epad[po + i] = eps[eo + i];
         jo += nb;
         eo += N;
+        // switching noise: every bond's |J| may reach |Jbar| + a
         double gmax = 0.0;
+        auto absJ = [&](int b) { return b < nb ? std::fabs(Jpad[po + b]) + p->tele_amp : 0.0; };
         for (int i = 0; i < N; ++i) {
-            const double jl = std::fabs(Jpad[po + (i + N - 1) % N]);
-            const double jr = std::fabs(Jpad[po + i]);
+            const double jl = absJ((i + N - 1) % N);
+            const double jr = absJ(i);
             gmax = std::max(gmax, std::fabs(Epad[po + i]) + jl + jr);
         }
         const double G = pr.m * gmax + (pr.m > 1 ? std::fabs(U[r]) * pr.m * (pr.m - 1) / 2.0 : 0.0);
@@ -1147,6 +1209,31 @@ int64_t group_dim(const ctqw_plan* p, int32_t g) {
     return p->state_off[r + 1] - p->state_off[r];
 }
 }  // namespace
+
+ctqw_status ctqw_set_telegraph(ctqw_plan* p, double amplitude, double rate, uint64_t seed) {
+    if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
+    if (!is_fin(amplitude) || amplitude < 0.0 || !is_fin(rate) || rate < 0.0)
+        return fail(p, CTQW_ERR_INVALID_ARG, "amplitude and rate must be finite and >= 0");
+    const double a0 = p->tele_amp, r0 = p->tele_rate;
+    const uint64_t s0 = p->tele_seed;
+    p->tele_amp = amplitude;
+    p->tele_rate = rate;
+    p->tele_seed = seed;
+    if (p->params_set) {
+        // orders follow the largest |J|; the tables (and the signs) are
+        // uploaded again, so the switching process starts anew
+        const std::vector<double> J = p->J, eps = p->eps, U = p->U;
+        const ctqw_status st = ctqw_set_params(p, J.data(), eps.data(), U.data());
+        if (st != CTQW_OK) {
+            p->tele_amp = a0;
+            p->tele_rate = r0;
+            p->tele_seed = s0;
+            (void)ctqw_set_params(p, J.data(), eps.data(), U.data());
+            return st;
+        }
+    }
+    return CTQW_OK;
+}
 
 ctqw_status ctqw_density_workspace(const ctqw_plan* p, int32_t group, int64_t* bytes) {
     if (!p || !bytes) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");
@@ -1649,6 +1736,8 @@ ctqw_status ctqw_gradient_workspace(const ctqw_plan* p, int64_t n_steps, int64_t
 }
 
 ctqw_status ctqw_forward_ckpt(ctqw_plan* p, int64_t n_steps, int64_t ckpt_every, void* gws, int64_t gws_bytes) {
+    if (p && p->tele_amp > 0.0)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "gradients are built for static noise (switching noise is on)");
     if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
     if (!gws) return fail(p, CTQW_ERR_INVALID_ARG, "NULL gradient workspace");
     if (n_steps < 0 || ckpt_every < 1) return fail(p, CTQW_ERR_INVALID_ARG, "need n_steps >= 0 and ckpt_every >= 1");

@@ -349,3 +349,23 @@ def test_rk4_method_is_the_degree_four_step():
         make_problem(2, 3, 8, 0.05, method="rk4", taylor_tol=1e-7)
     with pytest.raises(ValueError):
         make_problem(2, 3, 8, 0.05, method="euler")
+
+
+def test_switching_noise_orders_and_validation():
+    """With switching noise of amplitude a the a-priori orders take
+    |Jbar| + a on every bond; bad amplitudes and rates are rejected."""
+    N, R = 12, 4
+    plan = make(R=R, n_sites=N, dt=0.05, taylor_tol=1e-10, dtype="c128")
+    J, eps, U = draw(N, R, N - 1, seed=8)
+    plan.set_params(J, eps, U)
+    static = plan.orders().copy()
+    plan.set_telegraph(0.8, 3.0, 5)
+    got = plan.orders()
+    for r in range(R):
+        Jr = np.abs(J[r * (N - 1):(r + 1) * (N - 1)]) + 0.8
+        assert got[r] == reference_order(Jr, eps[r * N:(r + 1) * N], U[r], 2, 0.05, 1e-10)
+    assert np.all(got >= static) and np.any(got > static)
+    assert status_of(lambda: plan.set_telegraph(-0.1, 1.0, 0)) == 1
+    assert status_of(lambda: plan.set_telegraph(0.1, float("nan"), 0)) == 1
+    plan.set_telegraph(0.0, 0.0, 0)
+    assert np.array_equal(plan.orders(), static)

@@ -443,3 +443,22 @@ def test_density_matrix_properties():
     e = np.eye(12)
     mixed = O.density_matrix([e[0], e[1]])
     assert np.allclose(mixed @ mixed, mixed / 2, atol=1e-15) and not np.allclose(mixed @ mixed, mixed)
+
+
+def test_telegraph_sign_process():
+    """The switching signs: rate 0 keeps the initial signs, flip
+    probability 1 alternates them every step, the initial signs are about
+    half positive, and the flip frequency over many steps is within five
+    standard deviations of p."""
+    from oracle import telegraph as T
+    s0 = T.sign_history(7, 3, 64, 5, 0.0)
+    assert np.all(s0 == s0[0]) and set(np.unique(s0)) <= {-1.0, 1.0}
+    s1 = T.sign_history(7, 3, 64, 4, 1.0)
+    assert np.all(s1[1] == -s1[0]) and np.all(s1[2] == s1[0])
+    init = T.sign_history(11, 0, 2000, 1, 0.0)[0]
+    assert abs(np.mean(init > 0) - 0.5) < 5 * 0.5 / np.sqrt(2000)
+    p = T.flip_probability(4.0, 0.05)
+    h = T.sign_history(5, 1, 200, 50, p)
+    flips = np.sum(h[1:] != h[:-1])
+    n = 200 * 49
+    assert abs(flips / n - p) < 5 * np.sqrt(p * (1 - p) / n)
