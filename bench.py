@@ -123,12 +123,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def shape_tag(launch) -> str:
-    return (f"cols_per_lane={launch.get('cols_per_lane', 1)} waves_per_block={launch.get('waves_per_block', 4)} "
-            f"waves_per_cu={launch.get('waves_per_cu', 0)}")
+def shape_tag(cols_per_lane, waves_per_block, grid_waves) -> str:
+    """Launch shape of the step kernel: columns per lane, waves per block and
+    the waves of the (persistent) grid."""
+    return f"cols_per_lane={cols_per_lane} waves_per_block={waves_per_block} grid_waves={grid_waves}"
 
 
-def recorded_traffic(launch):
+def recorded_traffic(launch, grid_waves):
     """HBM bytes per step from the committed counter summary, if it was taken
     on the current kernel sources and at this launch shape."""
     try:
@@ -139,7 +140,8 @@ def recorded_traffic(launch):
     fields = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(keys))
     if fields.get("kernel-source-sha256", "").strip() != kernel_source_hash():
         return None
-    if fields.get("launch-shape", "").strip() != shape_tag(launch):
+    tag = shape_tag(launch.get("cols_per_lane", 1), launch.get("waves_per_block", 4), grid_waves)
+    if fields.get("launch-shape", "").strip() != tag:
         return None
     try:
         return int(fields["traffic-bytes"].strip())
@@ -168,6 +170,11 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
     stats = [r for r in _rows(find(trace_dir, "kernel_stats.csv")) if "step2d_kernel<float" in r["Name"]]
     if not stats:
         raise SystemExit("no complex64 step kernel in the trace")
+    grids = {int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) // 64
+             for r in _rows(find(trace_dir, "kernel_trace.csv")) if "step2d_kernel<float" in r["Kernel_Name"]}
+    if len(grids) != 1:
+        raise SystemExit(f"step kernels launched with different grids: {sorted(grids)}")
+    grid_waves = grids.pop()
     calls = {int(r["Calls"]) for r in stats}
     if len(calls) != 1:
         raise SystemExit(f"step kernels dispatched unequal times: {sorted(calls)}")
@@ -221,8 +228,7 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         f"| HBM bytes written per step | {write_b / 1e9:.3f} GB |",
         "",
         f"kernel-source-sha256: {kernel_source_hash()}",
-        "launch-shape: " + shape_tag({"cols_per_lane": cols_per_lane, "waves_per_block": waves_per_block,
-                                      "waves_per_cu": waves_per_cu}),
+        "launch-shape: " + shape_tag(cols_per_lane, waves_per_block, grid_waves),
         f"traffic-bytes: {int(round(fetch_b + write_b))}",
         "",
     ]
@@ -551,8 +557,8 @@ def main():
     bytes_per_launch = amps * 16.0
     achieved = bytes_per_launch / (kern_ms * 1e-3) / 1e9
     orders = plan.orders()
-    items, _ = plan.work_items()
-    traffic = recorded_traffic(launch)
+    items, grid_waves = plan.work_items()
+    traffic = recorded_traffic(launch, grid_waves)
     del plan
     torch.cuda.empty_cache()
 
