@@ -290,8 +290,8 @@ ctqw_status ctqw_groups(const ctqw_plan* plan, int32_t* n_groups, int32_t* sizes
  * with the load scale into a D_g x R_g matrix); rho = A A^H / R_g is one
  * rocBLAS cherk / zherk on the matrix cores.  Enqueued on the plan's
  * stream.  Errors: INVALID_ARG (NULL, group out of range, ld or workspace
- * too small), UNSUPPORTED (D_g or ld >= 2^31, R_g > 65535, full matrix
- * with D_g > 16776960), STATE (not bound), DEVICE.                        */
+ * too small), UNSUPPORTED (D_g or ld >= 2^31, R_g > 65535), STATE (not
+ * bound), DEVICE.                                                         */
 ctqw_status ctqw_density_workspace(const ctqw_plan* plan, int32_t group, int64_t* bytes);
 ctqw_status ctqw_density_matrix(ctqw_plan* plan, int32_t group, void* rho, int64_t ld, int32_t lower_only,
                                 void* workspace, int64_t workspace_bytes);

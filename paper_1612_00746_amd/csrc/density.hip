@@ -10,6 +10,8 @@
 
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
+
 namespace ctqw {
 namespace {
 
@@ -38,16 +40,18 @@ __global__ void gather_group_kernel(DensityArgs a) {
     reinterpret_cast<C*>(a.A)[i + a.D * k] = v;
 }
 
-// rho[j][i] = conj(rho[i][j]) for i > j (column-major, ld): upper from lower
+// rho[j][i] = conj(rho[i][j]) for i > j (column-major, ld): upper from lower;
+// block rows of 256, columns strided over the grid's second dimension
 template <typename C>
 __global__ void mirror_kernel(void* rho, int64_t D, int64_t ld) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // row
-    const int64_t j = blockIdx.y;                                       // column
-    if (i >= D || i <= j) return;
+    if (i >= D) return;
     C* m = reinterpret_cast<C*>(rho);
-    C v = m[i + ld * j];
-    v.y = -v.y;
-    m[j + ld * i] = v;
+    for (int64_t j = blockIdx.y; j < i; j += gridDim.y) {
+        C v = m[i + ld * j];
+        v.y = -v.y;
+        m[j + ld * i] = v;
+    }
 }
 
 }  // namespace
@@ -63,8 +67,8 @@ hipError_t launch_density_gather(const DensityArgs& a, int dtype, hipStream_t s)
 }
 
 hipError_t launch_density_mirror(void* rho, int64_t D, int64_t ld, int dtype, hipStream_t s) {
-    if (D > 65535 * 256 || D > 2147483647) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((D + 255) / 256), (unsigned)D);
+    if (D > 2147483647) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((D + 255) / 256), (unsigned)std::min<int64_t>(D, 65535));
     if (dtype == 1)
         hipLaunchKernelGGL(mirror_kernel<double2>, grid, dim3(256), 0, s, rho, D, ld);
     else

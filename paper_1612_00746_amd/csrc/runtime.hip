@@ -1260,8 +1260,6 @@ ctqw_status ctqw_density_matrix(ctqw_plan* p, int32_t group, void* rho, int64_t 
                     (long long)need);
     if (D > INT32_MAX || ld > INT32_MAX || Rg > 65535)
         return fail(p, CTQW_ERR_UNSUPPORTED, "density matrix limited to D, ld < 2^31 and 65535 realisations");
-    if (!lower_only && D > 65535 * 256)
-        return fail(p, CTQW_ERR_UNSUPPORTED, "full density matrix limited to D <= 16776960");
     if ((st = ensure_ready(p)) != CTQW_OK) return st;
     const int dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
     DensityArgs a{};

@@ -32,12 +32,9 @@ __device__ __forceinline__ void philox_device(uint32_t c0, uint32_t c1, uint32_t
     w1 = c1;
 }
 
-__global__ void telegraph_kernel(TeleArgs a) {
-    const int64_t r = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const RealDev rd = a.reals[r];
-    const int nb = (rd.flags & RF_PERIODIC) ? rd.N : rd.N - 1;
-    if (i >= nb) return;
+// One bond of realisation r: the flip test of the current step, the new sign
+// and the bond's dt-scaled table entries.
+__device__ void flip_bond(const TeleArgs& a, const RealDev& rd, int64_t r, int i) {
     const int64_t k = rd.param_off + i;
     const int32_t s = *a.step;
     uint32_t w0, w1;
@@ -52,6 +49,16 @@ __global__ void telegraph_kernel(TeleArgs a) {
     a.Jf[k] = (float)Jdt;
 }
 
+// thread per bond; realisations strided over the grid's second dimension
+__global__ void telegraph_kernel(TeleArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t r = blockIdx.y; r < a.R; r += gridDim.y) {
+        const RealDev rd = a.reals[r];
+        const int nb = (rd.flags & RF_PERIODIC) ? rd.N : rd.N - 1;
+        if (i < nb) flip_bond(a, rd, r, i);
+    }
+}
+
 __global__ void step_count_kernel(int32_t* step) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
 }
@@ -59,8 +66,8 @@ __global__ void step_count_kernel(int32_t* step) {
 }  // namespace
 
 hipError_t launch_telegraph(const TeleArgs& a, int max_bonds, hipStream_t s) {
-    if (a.R <= 0 || a.R > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((max_bonds + 255) / 256), (unsigned)a.R);
+    if (a.R <= 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((max_bonds + 255) / 256), (unsigned)(a.R < 65535 ? a.R : 65535));
     hipLaunchKernelGGL(telegraph_kernel, grid, dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
