@@ -25,6 +25,18 @@ template <typename T> struct Cplx3;
 template <> struct Cplx3<float> { using type = float2; };
 template <> struct Cplx3<double> { using type = double2; };
 
+// Non-temporal store of one amplitude: every array a pass writes is read
+// again only in the next pass, after the whole state has streamed by.
+template <typename C>
+__device__ __forceinline__ void store_nt(C* p, C v) {
+    using T = decltype(v.x);
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 x;
+    x.x = v.x;
+    x.y = v.y;
+    __builtin_nontemporal_store(x, reinterpret_cast<v2*>(p));
+}
+
 __device__ __forceinline__ int dist(int a, int b, int N, bool periodic) {
     int d = a - b;
     d = d < 0 ? -d : d;
@@ -107,13 +119,13 @@ __global__ void __launch_bounds__(256) term3d_kernel(Step3Args a) {
             sum.x += pr;
             sum.y += pi;
         }
-        acc[o] = sum;
+        store_nt(acc + o, sum);
         if (!a.last) {
-            if (KAHAN) cmp[o] = cp;
+            if (KAHAN) store_nt(cmp + o, cp);
             C f;
             f.x = pr;
             f.y = pi;
-            reinterpret_cast<C*>(a.phi_out)[rd.state_off + o] = f;
+            store_nt(reinterpret_cast<C*>(a.phi_out) + rd.state_off + o, f);
         } else {
             nrm = (double)sum.x * sum.x + (double)sum.y * sum.y;
             tail = (double)pr * pr + (double)pi * pi;
