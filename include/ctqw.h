@@ -80,7 +80,7 @@ typedef struct {
     int32_t boundary;        /* ctqw_boundary; PERIODIC needs N >= 3 */
     int32_t dtype;           /* ctqw_dtype */
     int32_t accumulation;    /* ctqw_accumulation (ignored for CTQW_C128) */
-    int64_t R;               /* realisations, >= 1 */
+    int64_t R;               /* realisations, 1 .. 65535 (UNSUPPORTED above) */
     int32_t n_sites;         /* N for every realisation, or 0 to use ... */
     const int32_t* n_sites_per_real; /* ... [R] sizes (uneven batch), copied */
     double dt;               /* time step, finite and > 0 */
