@@ -205,9 +205,10 @@ ctqw_status ctqw_draw_params(ctqw_plan* plan, const double* J_base, const double
  * (i, 4 (s + 1), r mod 2^32, r div 2^32), key (seed mod 2^32 XOR
  * 0x54454C45, seed div 2^32), u = 53-bit fraction of (w0, w1): flip if
  * u < p; s = -1 gives the initial sign, + if u < 1/2.  The a-priori
- * orders take |Jbar_i| + amplitude.  The process starts (s = 0) when the
- * tables are next uploaded (ctqw_bind, the first call after this one) and
- * advances one draw per step, also inside captured step loops.
+ * orders take |Jbar_i| + amplitude.  The process starts (s = 0) whenever
+ * the tables are uploaded — the first device call after this one,
+ * ctqw_set_params, ctqw_set_launch or a re-bind — and advances one draw
+ * per step, also inside captured step loops.
  * amplitude = 0 returns to static noise.  Not combined with gradients.
  * Errors: INVALID_ARG (negative or non-finite), NOT_CONVERGED (orders). */
 ctqw_status ctqw_set_telegraph(ctqw_plan* plan, double amplitude, double rate, uint64_t seed);
