@@ -252,7 +252,9 @@ class Plan:
         ctype = torch.complex128 if self.dtype == "c128" else torch.complex64
         esz = 16 if self.dtype == "c128" else 8
         D = int(round((ws_bytes.value // esz) / self.group_sizes(group)))
-        rho = torch.zeros((D, D), dtype=ctype, device=psi_a.device)
+        # the full matrix is written element by element; lower_only leaves the upper at zero
+        alloc = torch.zeros if lower_only else torch.empty
+        rho = alloc((D, D), dtype=ctype, device=psi_a.device)
         ws = torch.empty(max(ws_bytes.value, 256), dtype=torch.uint8, device=psi_a.device)
         self._check(self.lib.ctqw_density_matrix(self.h, group, C.c_void_p(rho.data_ptr()), D,
                                                  1 if lower_only else 0, C.c_void_p(ws.data_ptr()),

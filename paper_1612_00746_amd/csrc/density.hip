@@ -40,17 +40,37 @@ __global__ void gather_group_kernel(DensityArgs a) {
     reinterpret_cast<C*>(a.A)[i + a.D * k] = v;
 }
 
-// rho[j][i] = conj(rho[i][j]) for i > j (column-major, ld): upper from lower;
-// block rows of 256, columns strided over the grid's second dimension
+// rho[j][i] = conj(rho[i][j]) for i > j (column-major, ld): the upper
+// triangle from the lower, one 32 x 32 tile pair per block iteration.  The
+// block reads lower tile (bi, bj), bi >= bj, down its columns (coalesced),
+// and writes its conjugate transpose into upper tile (bj, bi), again down
+// the columns, through a padded LDS tile.  Only strictly lower elements are
+// copied, so on a diagonal tile the elements read and the elements written
+// are disjoint.  Block rows of tiles bi = blockIdx.x; tile columns strided
+// over the grid's second dimension; blocks with bj > bi have nothing to do.
 template <typename C>
-__global__ void mirror_kernel(void* rho, int64_t D, int64_t ld) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // row
-    if (i >= D) return;
+__global__ __launch_bounds__(256) void mirror_kernel(void* rho, int64_t D, int64_t ld) {
+    __shared__ C tile[32][33];
     C* m = reinterpret_cast<C*>(rho);
-    for (int64_t j = blockIdx.y; j < i; j += gridDim.y) {
-        C v = m[i + ld * j];
-        v.y = -v.y;
-        m[j + ld * i] = v;
+    const int tx = (int)(threadIdx.x & 31), ty = (int)(threadIdx.x >> 5);
+    const int64_t bi = blockIdx.x;
+    for (int64_t bj = blockIdx.y; bj <= bi; bj += gridDim.y) {
+        const int64_t i = bi * 32 + tx;            // source row
+        for (int k = 0; k < 32; k += 8) {
+            const int64_t j = bj * 32 + ty + k;    // source column
+            if (i < D && j < i) tile[ty + k][tx] = m[i + ld * j];
+        }
+        __syncthreads();
+        const int64_t jj = bj * 32 + tx;           // destination row (source column)
+        for (int k = 0; k < 32; k += 8) {
+            const int64_t ii = bi * 32 + ty + k;   // destination column (source row)
+            if (ii < D && jj < ii) {
+                C v = tile[tx][ty + k];
+                v.y = -v.y;
+                m[jj + ld * ii] = v;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -68,7 +88,8 @@ hipError_t launch_density_gather(const DensityArgs& a, int dtype, hipStream_t s)
 
 hipError_t launch_density_mirror(void* rho, int64_t D, int64_t ld, int dtype, hipStream_t s) {
     if (D > 2147483647) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((D + 255) / 256), (unsigned)std::min<int64_t>(D, 65535));
+    const int64_t tiles = (D + 31) / 32;
+    const dim3 grid((unsigned)tiles, (unsigned)std::min<int64_t>(tiles, 65535));
     if (dtype == 1)
         hipLaunchKernelGGL(mirror_kernel<double2>, grid, dim3(256), 0, s, rho, D, ld);
     else
