@@ -397,6 +397,48 @@ def density(a):
                       "trace": tr}))
 
 
+def graph(a):
+    """One particle on a 128 x 128 open square lattice (q = 2, 16384
+    nodes), 4096 noisy realisations (J = 1 + 0.1 N(0, 1) per bond,
+    eps ~ U[-0.5, 0.5]), complex128, dt = 0.05, 10 Taylor terms per step,
+    one pass per term.  Algorithmic bytes per node, realisation and term:
+    the previous term (16; neighbours counted as cache hits), the on-site
+    energy (8), width couplings (8 each), the partial sum in and out (32)
+    and the term out (16, not on the last term)."""
+    import torch
+    from paper_1612_00746_amd import ell_tables, graph_evolve, lattice_edges
+    side, R, order, dt = 128, 4096, 10, 0.05
+    n = side * side
+    g = np.random.default_rng(71)
+    edges = lattice_edges((side, side))
+    nbr, hop = ell_tables(n, edges, 1.0 + 0.1 * g.standard_normal((R, len(edges))))
+    width = nbr.shape[0]
+    dev = "cuda"
+    nbr_d, hop_d = torch.from_numpy(nbr).to(dev), torch.from_numpy(hop).to(dev)
+    del hop
+    eps_d = torch.from_numpy(g.uniform(-0.5, 0.5, (R, n))).to(dev)
+    psi = torch.zeros((R, n), dtype=torch.complex128, device=dev)
+    psi[:, n // 2 + side // 2] = 1.0
+    ws = torch.empty(3 * R * n * 16, dtype=torch.uint8, device=dev)
+    graph_evolve(nbr_d, hop_d, eps_d, psi, dt, order, max(1, a.warmup), ws)
+    torch.cuda.synchronize()
+    steps = max(1, a.steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    graph_evolve(nbr_d, hop_d, eps_d, psi, dt, order, steps, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    per_term = 16 + 8 + 8 * width + 32 + 16
+    bytes_step = (order * per_term - 16) * R * n
+    norm = float(torch.linalg.vector_norm(psi[0]).item())
+    print(json.dumps({"metric": "graph walk node-updates/s", "workload": "128 x 128 lattice, 4096 realisations, c128",
+                      "order": order, "width": width, "ms_per_step": round(ms, 4),
+                      "value": R * n / (ms * 1e-3), "unit": "node-updates/s",
+                      "achieved_GBps": round(bytes_step / (ms * 1e-3) / 1e9, 1),
+                      "frac_hbm": round(bytes_step / (ms * 1e-3) / 8e12, 4), "norm_r0": norm}))
+
+
 def three_walkers(a):
     """Three distinguishable walkers on N = 256 (64 realisations, 1.07e9
     amplitudes, nearest-neighbour U, complex64 with the compensated sum):
@@ -466,6 +508,8 @@ def main():
                     help="command line recorded in the profile summary (repeatable)")
     ap.add_argument("--rk4-compare", action="store_true",
                     help="time Alg. 2 (RK4) against the adaptive Taylor step at equal per-step accuracy on the batch")
+    ap.add_argument("--graph", action="store_true",
+                    help="time one particle on a 128 x 128 lattice, 4096 realisations (complex128)")
     ap.add_argument("--telegraph", action="store_true",
                     help="time the batch with switching hopping noise (a = 0.1, rate 1) against static noise")
     ap.add_argument("--density", action="store_true",
@@ -491,6 +535,9 @@ def main():
         return
     if a.density:
         density(a)
+        return
+    if a.graph:
+        graph(a)
         return
     if a.telegraph:
         telegraph(a)

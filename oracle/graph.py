@@ -1,0 +1,54 @@
+"""One particle on a general graph (Sec. 2) for checking the library.  Test
+infrastructure only: nothing in the product path imports this module.
+
+Sec. 2 lets each node couple to its own set of neighbours; a q-dimensional
+regular lattice with nearest-neighbour coupling along each axis is one such
+graph.  For one particle H is then the n x n matrix of Eq. (1) with
+H[a, a] = eps_a on the diagonal and H[a, b] = H[b, a] = J_e for each bond
+e = (a, b) (equal rates both ways, Sec. 2.2), zero elsewhere.  The
+evolution itself is ``propagate.evolve_taylor`` on this H.
+
+Pins in tests/test_oracle_pins.py: the clean lattice spectra against the
+closed forms (sums of 2 cos(pi k / (N + 1)) over the axes, open; sums of
+2 cos(2 pi k / N), periodic), node degrees, symmetry.
+"""
+
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def lattice_bonds(shape, periodic=False):
+    """Bonds of the lattice with sides ``shape``: node (c_1, ..., c_q) is
+    numbered row-major; each node is joined to the next node along every
+    axis (and, on a periodic axis longer than 2, the last to the first).
+    Returned as a sorted list of (a, b) with a < b."""
+    shape = tuple(int(s) for s in shape)
+    strides = [int(np.prod(shape[i + 1:])) for i in range(len(shape))]
+    bonds = set()
+    for c in itertools.product(*[range(s) for s in shape]):
+        a = sum(ci * st for ci, st in zip(c, strides))
+        for ax, s in enumerate(shape):
+            nxt = c[ax] + 1
+            if nxt == s:
+                if not (periodic and s > 2):
+                    continue
+                nxt = 0
+            b = a + (nxt - c[ax]) * strides[ax]
+            bonds.add((min(a, b), max(a, b)))
+    return sorted(bonds)
+
+
+def hamiltonian(n, bonds, J, eps):
+    """H of one realisation: eps on the diagonal, J[e] on both entries of
+    bond e."""
+    H = sp.lil_matrix((n, n), dtype=np.float64)
+    for a in range(n):
+        H[a, a] = eps[a]
+    for (a, b), j in zip(bonds, J):
+        H[a, b] += j
+        H[b, a] += j
+    return H.tocsr()

@@ -339,3 +339,90 @@ class Plan:
         t2 = np.zeros(self.R)
         self._check(self.lib.ctqw_realization_norms(self.h, _ptr(n2, C.c_double), _ptr(t2, C.c_double)))
         return n2, t2
+
+
+# ------------------------------------------------------------------ graphs
+def lattice_edges(shape: Sequence[int], periodic: bool = False) -> np.ndarray:
+    """Bonds of a q-dimensional regular lattice with nearest-neighbour
+    coupling along each axis (Sec. 2, k_i = 1), nodes numbered row-major
+    (last axis fastest).  Returns int32 [E, 2] with a < b in each pair; a
+    periodic axis of length > 2 adds the wrap-around bond."""
+    shape = [int(s) for s in shape]
+    if not shape or min(shape) < 1:
+        raise ValueError("lattice sides must be positive")
+    idx = np.arange(int(np.prod(shape))).reshape(shape)
+    out = []
+    for ax, s in enumerate(shape):
+        if s < 2:
+            continue
+        a = np.take(idx, np.arange(s - 1), axis=ax).ravel()
+        b = np.take(idx, np.arange(1, s), axis=ax).ravel()
+        out.append(np.stack([a, b], 1))
+        if periodic and s > 2:
+            a = np.take(idx, [s - 1], axis=ax).ravel()
+            b = np.take(idx, [0], axis=ax).ravel()
+            out.append(np.stack([np.minimum(a, b), np.maximum(a, b)], 1))
+    if not out:
+        return np.zeros((0, 2), dtype=np.int32)
+    return np.concatenate(out).astype(np.int32)
+
+
+def ell_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Neighbour and coupling tables of ctqw_graph_evolve from an undirected
+    bond list: edges int [E, 2] (no self-loops, no repeated bonds), J [R, E]
+    the bond couplings of each realisation.  Each bond fills one slot of
+    both of its nodes, slots in bond order; width = the largest degree.
+    Returns nbr int32 [width, n] (-1 in empty slots) and hop float64
+    [R, width, n]."""
+    edges = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    J = np.atleast_2d(np.asarray(J, dtype=np.float64))
+    if J.shape[1] != len(edges):
+        raise ValueError("J must be [R, E]")
+    if len(edges) and (edges.min() < 0 or edges.max() >= n_nodes):
+        raise ValueError("bond endpoint out of range")
+    if np.any(edges[:, 0] == edges[:, 1]):
+        raise ValueError("self-loops belong to the on-site energies")
+    key = np.minimum(edges[:, 0], edges[:, 1]) * n_nodes + np.maximum(edges[:, 0], edges[:, 1])
+    if len(np.unique(key)) != len(key):
+        raise ValueError("repeated bond")
+    ends = np.concatenate([edges[:, 0], edges[:, 1]])       # node that owns the slot
+    other = np.concatenate([edges[:, 1], edges[:, 0]])
+    bond = np.concatenate([np.arange(len(edges))] * 2)
+    order = np.argsort(bond * 2 + np.repeat([0, 1], len(edges)), kind="stable")   # bond order, a-end first
+    ends, other, bond = ends[order], other[order], bond[order]
+    deg = np.bincount(ends, minlength=n_nodes)
+    width = int(deg.max()) if len(edges) else 0
+    slot = np.zeros(len(ends), dtype=np.int64)
+    fill = np.zeros(n_nodes, dtype=np.int64)
+    for t, a in enumerate(ends):
+        slot[t] = fill[a]
+        fill[a] += 1
+    nbr = np.full((width, n_nodes), -1, dtype=np.int32)
+    nbr[slot, ends] = other
+    hop = np.zeros((J.shape[0], width, n_nodes))
+    hop[:, slot, ends] = J[:, bond]
+    return nbr, hop
+
+
+def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, workspace=None) -> None:
+    """ctqw_graph_evolve on device tensors: one particle on a general graph,
+    R realisations advanced in place.  nbr int32 [width, n], hop float64
+    [R, width, n], onsite float64 [R, n], psi complex128 [R, n], all
+    contiguous on one device; enqueued on that device's current stream."""
+    import torch
+    lib = L.load()
+    R, n = psi.shape
+    width = nbr.shape[0]
+    for t, dt_, shp in ((nbr, torch.int32, (width, n)), (hop, torch.float64, (R, width, n)),
+                        (onsite, torch.float64, (R, n)), (psi, torch.complex128, (R, n))):
+        if t.dtype != dt_ or tuple(t.shape) != shp or not t.is_contiguous() or t.device != psi.device:
+            raise ValueError(f"expected a contiguous {dt_} tensor of shape {shp} on {psi.device}")
+    b = C.c_int64()
+    L.check(lib.ctqw_graph_workspace(n, R, C.byref(b)))
+    if workspace is None:
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=psi.device)
+    stream = torch.cuda.current_stream(psi.device).cuda_stream
+    p = lambda t: C.c_void_p(t.data_ptr()) if t.numel() else None  # noqa: E731
+    L.check(lib.ctqw_graph_evolve(n, width, p(nbr), p(hop), p(onsite), R, float(dt), int(order), int(n_steps),
+                                  p(psi), p(workspace), workspace.numel() * workspace.element_size(),
+                                  C.c_void_p(stream)))

@@ -1,0 +1,23 @@
+// One particle on a general graph (see graph.hip).
+#pragma once
+#include "ctqw_internal.hpp"
+
+namespace ctqw {
+
+// One Taylor term of every realisation: t = (-i c) H src, acc_out = acc_in + t.
+struct GraphTermArgs {
+    const int32_t* nbr;      // [width][n] neighbour of node i in slot k; outside [0, n): empty slot
+    const double* hop;       // [R][width][n] coupling of that slot
+    const double* onsite;    // [R][n] diagonal
+    const double2* src;      // [R][n] the previous term (or the state)
+    double2* t_out;          // [R][n] this term, or NULL when no later term needs it
+    const double2* acc_in;   // [R][n] partial sum before this term
+    double2* acc_out;        // [R][n] partial sum after it
+    double c;                // dt / j for term j
+    int32_t n;
+    int32_t width;
+    int32_t R;
+};
+hipError_t launch_graph_term(const GraphTermArgs& a, hipStream_t s);
+
+}  // namespace ctqw

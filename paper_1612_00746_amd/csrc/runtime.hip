@@ -29,6 +29,7 @@
 #include "ctqw_internal.hpp"
 #include "noise.hpp"
 #include "density.hpp"
+#include "graph.hpp"
 #include "telegraph.hpp"
 
 using namespace ctqw;
@@ -1275,6 +1276,62 @@ ctqw_status ctqw_density_matrix(ctqw_plan* p, int32_t group, void* rho, int64_t 
     const int e = density_herk(&p->blas, p->stream, dtype, D, Rg, workspace, rho, ld);
     if (e != 0) return fail(p, CTQW_ERR_DEVICE, "Hermitian rank-k update failed (rocBLAS status %d)", e);
     if (!lower_only) HIP_TRY(p, launch_density_mirror(rho, D, ld, dtype, p->stream));
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int64_t* bytes) {
+    if (!bytes) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (n_nodes < 1 || R < 1)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "n_nodes and R must be positive (got %d, %d)", n_nodes, R);
+    // two term buffers and the partial sum, complex128
+    *bytes = 3 * (int64_t)n_nodes * (int64_t)R * 16;
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const double* hop,
+                              const double* onsite, int32_t R, double dt, int32_t order, int64_t n_steps, void* psi,
+                              void* workspace, int64_t workspace_bytes, void* hip_stream) {
+    int64_t need = 0;
+    ctqw_status st = ctqw_graph_workspace(n_nodes, R, &need);
+    if (st != CTQW_OK) return st;
+    if (width < 0) return fail(nullptr, CTQW_ERR_INVALID_ARG, "width must be >= 0 (got %d)", width);
+    if (!onsite || !psi || !workspace || (width > 0 && (!nbr || !hop)))
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (!std::isfinite(dt)) return fail(nullptr, CTQW_ERR_INVALID_ARG, "dt must be finite");
+    constexpr int32_t kGraphMaxOrder = 64;   // one pass per term, no pipeline depth limit
+    if (order < 1 || order > kGraphMaxOrder)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "order must be in 1..%d (got %d)", kGraphMaxOrder, order);
+    if (n_steps < 0) return fail(nullptr, CTQW_ERR_INVALID_ARG, "n_steps must be >= 0");
+    if (workspace_bytes < need)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "workspace too small (%lld < %lld bytes)",
+                    (long long)workspace_bytes, (long long)need);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t cnt = (int64_t)n_nodes * R;
+    double2* T[2] = {static_cast<double2*>(workspace), static_cast<double2*>(workspace) + cnt};
+    double2* acc = static_cast<double2*>(workspace) + 2 * cnt;
+    double2* x = static_cast<double2*>(psi);
+    for (int64_t step = 0; step < n_steps; ++step) {
+        GraphTermArgs a{};
+        a.nbr = nbr;
+        a.hop = hop;
+        a.onsite = onsite;
+        a.n = n_nodes;
+        a.width = width;
+        a.R = R;
+        a.src = x;
+        a.acc_in = x;
+        for (int32_t j = 1; j <= order; ++j) {
+            const bool last = j == order;
+            a.t_out = last ? nullptr : T[(j - 1) & 1];
+            // the last term may write the state: it reads only the previous term and the sum
+            a.acc_out = (last && order > 1) ? x : acc;
+            a.c = dt / (double)j;
+            HIP_TRY(nullptr, launch_graph_term(a, s));
+            a.src = a.t_out;
+            a.acc_in = acc;
+        }
+        if (order == 1) HIP_TRY(nullptr, hipMemcpyAsync(x, acc, cnt * 16, hipMemcpyDeviceToDevice, s));
+    }
     return CTQW_OK;
 }
 

@@ -388,3 +388,64 @@ def test_density_matrix_arguments_are_checked():
     buf = C2.create_string_buffer(4096)
     assert plan.lib.ctqw_density_matrix(plan.h, 0, buf, 36, 0, buf, 4096) == 7   # STATE: not bound
     assert plan.lib.ctqw_density_matrix(plan.h, 0, buf, 20, 0, buf, 4096) == 1   # ld below D
+
+
+# ---------------------------------------------------------------- general graphs
+@pytest.mark.parametrize("shape,periodic", [((5, 7), False), ((3, 4, 5), True), ((2, 6), True), ((1, 4), False)])
+def test_lattice_edges_match_the_oracle_bonds(shape, periodic):
+    from paper_1612_00746_amd import lattice_edges
+    from oracle import graph as G
+    got = sorted(map(tuple, lattice_edges(shape, periodic).tolist()))
+    assert got == G.lattice_bonds(shape, periodic)
+
+
+def test_ell_tables_rebuild_the_oracle_hamiltonian():
+    """A random graph with degrees 0 to several (an isolated node
+    included): the ELL tables, read back as a matrix, equal the oracle's
+    off-diagonal H for every realisation."""
+    from paper_1612_00746_amd import ell_tables
+    from oracle import graph as G
+    g = np.random.default_rng(7)
+    n = 30
+    pairs = {(int(a), int(b)) for a, b in g.integers(0, n - 1, (80, 2)) if a != b}
+    edges = sorted((min(a, b), max(a, b)) for a, b in pairs)
+    edges = sorted(set(edges))
+    J = g.standard_normal((3, len(edges)))
+    nbr, hop = ell_tables(n, np.array(edges), J)
+    assert nbr.shape[0] == max(np.bincount(np.array(edges).ravel(), minlength=n))
+    assert np.all(nbr[:, n - 1] == -1)
+    for r in range(3):
+        M = np.zeros((n, n))
+        for k in range(nbr.shape[0]):
+            for i in range(n):
+                if nbr[k, i] >= 0:
+                    M[i, nbr[k, i]] += hop[r, k, i]
+        ref = G.hamiltonian(n, edges, J[r], np.zeros(n)).toarray()
+        assert np.array_equal(M, ref)
+
+
+def test_ell_tables_reject_bad_bonds():
+    from paper_1612_00746_amd import ell_tables
+    for edges in ([(0, 0)], [(0, 1), (1, 0)], [(0, 5)]):
+        with pytest.raises(ValueError):
+            ell_tables(4, np.array(edges), np.ones((1, len(edges))))
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_nodes=0), 1), (dict(R=0), 1), (dict(width=-1), 1), (dict(order=0), 1), (dict(order=65), 1),
+    (dict(n_steps=-1), 1), (dict(dt=float("nan")), 1), (dict(ws=10), 1), (dict(psi=None), 1),
+])
+def test_graph_evolve_validation(kw, status):
+    """Invalid requests are refused on the host, before any device work."""
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    a = dict(n_nodes=8, width=2, nbr=C.c_void_p(16), hop=C.c_void_p(16), onsite=C.c_void_p(16), R=2, dt=0.1,
+             order=4, n_steps=1, psi=C.c_void_p(16), ws=C.c_void_p(16), ws_bytes=3 * 8 * 2 * 16)
+    if "ws" in kw:
+        a["ws_bytes"] = kw.pop("ws")
+    a.update(kw)
+    st = lib.ctqw_graph_evolve(a["n_nodes"], a["width"], a["nbr"], a["hop"], a["onsite"], a["R"], a["dt"],
+                               a["order"], a["n_steps"], a["psi"], a["ws"], a["ws_bytes"], None)
+    assert st == status
+    b = C.c_int64()
+    assert lib.ctqw_graph_workspace(8, 2, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 16

@@ -1,0 +1,97 @@
+"""GPU parity of one particle on a general graph (Sec. 2; q-dimensional
+lattices and irregular graphs): R noisy realisations sharing one topology,
+each advanced by the order-n Taylor polynomial (Eqs. 5-7) through
+ctqw_graph_evolve, against the oracle's FP64 Taylor map of each
+realisation's own H built from the same bond list."""
+
+import numpy as np
+import pytest
+
+from oracle import graph as G
+from oracle import propagate as P
+
+from _helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def random_states(R, n, seed):
+    g = np.random.default_rng(seed)
+    psi = g.standard_normal((R, n)) + 1j * g.standard_normal((R, n))
+    return psi / np.linalg.norm(psi, axis=1, keepdims=True)
+
+
+def run_case(n, edges, R, dt, order, steps, seed):
+    import torch
+    from paper_1612_00746_amd import ell_tables, graph_evolve
+    g = np.random.default_rng(seed)
+    J = 1.0 + 0.1 * g.standard_normal((R, len(edges)))
+    eps = g.uniform(-0.5, 0.5, (R, n))
+    psi0 = random_states(R, n, seed + 1)
+    nbr, hop = ell_tables(n, np.array(edges, dtype=np.int64).reshape(-1, 2), J)
+    dev = "cuda"
+    psi = torch.from_numpy(psi0.copy()).to(dev)
+    graph_evolve(torch.from_numpy(nbr).to(dev), torch.from_numpy(np.ascontiguousarray(hop)).to(dev),
+                 torch.from_numpy(eps).to(dev), psi, dt, order, steps)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy()
+    worst = 0.0
+    for r in range(R):
+        H = G.hamiltonian(n, edges, J[r], eps[r])
+        ref, _, _ = P.evolve_taylor(H, psi0[r], dt, steps, order=order)
+        worst = max(worst, float(np.max(np.abs(got[r] - ref))))
+    return worst, got, psi0
+
+
+@pytest.mark.parametrize("shape,periodic,order", [((9, 7), False, 8), ((6, 5, 4), True, 6), ((17, 16), False, 12)])
+def test_lattice_against_the_oracle(shape, periodic, order):
+    """q = 2 and q = 3 lattices (open and periodic), c128: within 1e-12 of
+    the oracle's Taylor map of the same order, norms within the truncation
+    error of 1."""
+    n = int(np.prod(shape))
+    edges = G.lattice_bonds(shape, periodic)
+    say(f"case: graph lattice {shape} periodic={periodic}, n={n}, order {order}")
+    worst, got, _ = run_case(n, edges, 4, 0.05, order, 40, 61)
+    say(f"  max |psi - oracle| = {worst:.2e}")
+    assert worst <= 1e-12
+    assert np.allclose(np.linalg.norm(got, axis=1), 1.0, atol=1e-8)
+
+
+def test_irregular_graph_against_the_oracle():
+    """A random graph of 300 nodes (two blocks of nodes, a ragged tail),
+    degrees 0 to the maximum (an isolated node included), 5 realisations."""
+    g = np.random.default_rng(62)
+    n = 300
+    pairs = {(int(min(a, b)), int(max(a, b))) for a, b in g.integers(0, n - 1, (900, 2)) if a != b}
+    edges = sorted(pairs)
+    say(f"case: irregular graph n={n}, {len(edges)} bonds")
+    worst, _, _ = run_case(n, edges, 5, 0.04, 7, 30, 63)
+    say(f"  max |psi - oracle| = {worst:.2e}")
+    assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_shallowest_orders_and_no_bonds(order):
+    """Order 1 (the sum copied back) and 2 on a 5 x 5 lattice, and a graph
+    without bonds (width 0: pure on-site phases)."""
+    edges = G.lattice_bonds((5, 5))
+    say(f"case: graph order {order}, 5 x 5 lattice and no bonds")
+    worst, _, _ = run_case(25, edges, 3, 0.01, order, 6, 64)
+    say(f"  lattice: max |psi - oracle| = {worst:.2e}")
+    assert worst <= 1e-13
+    worst, _, _ = run_case(10, [], 2, 0.01, order, 6, 65)
+    say(f"  no bonds: max |psi - oracle| = {worst:.2e}")
+    assert worst <= 1e-13
+
+
+def test_zero_steps_leave_the_state():
+    import torch
+    from paper_1612_00746_amd import ell_tables, graph_evolve
+    edges = np.array(G.lattice_bonds((4, 4)))
+    nbr, hop = ell_tables(16, edges, np.ones((2, len(edges))))
+    psi0 = random_states(2, 16, 66)
+    psi = torch.from_numpy(psi0.copy()).cuda()
+    graph_evolve(torch.from_numpy(nbr).cuda(), torch.from_numpy(hop).cuda(), torch.zeros((2, 16), dtype=torch.float64).cuda(),
+                 psi, 0.1, 5, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(psi.cpu().numpy(), psi0)

@@ -462,3 +462,56 @@ def test_telegraph_sign_process():
     flips = np.sum(h[1:] != h[:-1])
     n = 200 * 49
     assert abs(flips / n - p) < 5 * np.sqrt(p * (1 - p) / n)
+
+
+# ---------------------------------------------------------------- graphs (Sec. 2)
+from oracle import graph as G  # noqa: E402
+
+
+@pytest.mark.parametrize("shape,periodic", [((5, 7), False), ((3, 4, 5), True), ((6,), False), ((4, 1, 3), False)])
+def test_graph_lattice_spectrum_closed_form(shape, periodic):
+    """Clean q-dimensional lattice (J = 1, eps = 0): the eigenvalues are the
+    sums over the axes of the chain's 2 cos(pi k / (N + 1)), k = 1..N (open)
+    or the ring's 2 cos(2 pi k / N) (periodic)."""
+    n = int(np.prod(shape))
+    bonds = G.lattice_bonds(shape, periodic)
+    H = G.hamiltonian(n, bonds, np.ones(len(bonds)), np.zeros(n)).toarray()
+    axes = []
+    for s in shape:
+        if periodic and s > 2:
+            axes.append(2 * np.cos(2 * np.pi * np.arange(s) / s))
+        elif s == 1:
+            axes.append(np.zeros(1))
+        else:
+            axes.append(2 * np.cos(np.pi * np.arange(1, s + 1) / (s + 1)))
+    want = np.zeros(1)
+    for ev in axes:
+        want = (want[:, None] + ev[None, :]).ravel()
+    assert np.allclose(np.linalg.eigvalsh(H), np.sort(want), atol=1e-12)
+
+
+def test_graph_lattice_degrees_and_bond_count():
+    """Open 4 x 6 lattice: (N1 - 1) N2 + N1 (N2 - 1) bonds; interior nodes
+    have 4 neighbours, side nodes 3, corners 2; H is symmetric."""
+    bonds = G.lattice_bonds((4, 6))
+    assert len(bonds) == 3 * 6 + 4 * 5
+    deg = np.zeros(24, int)
+    for a, b in bonds:
+        deg[a] += 1
+        deg[b] += 1
+    grid = deg.reshape(4, 6)
+    assert np.all(grid[1:-1, 1:-1] == 4)
+    assert grid[0, 0] == grid[0, -1] == grid[-1, 0] == grid[-1, -1] == 2
+    assert np.all(grid[0, 1:-1] == 3) and np.all(grid[1:-1, 0] == 3)
+    g = np.random.default_rng(3)
+    H = G.hamiltonian(24, bonds, g.standard_normal(len(bonds)), g.standard_normal(24)).toarray()
+    assert np.array_equal(H, H.T)
+
+
+def test_graph_two_node_evolution_closed_form():
+    """One bond of coupling J between two nodes, eps = 0: a walker started on
+    node 0 has amplitudes (cos Jt, -i sin Jt)."""
+    J, t = 0.7, 2.3
+    H = G.hamiltonian(2, [(0, 1)], [J], [0.0, 0.0])
+    psi, _, _ = P.evolve_taylor(H, np.array([1.0, 0.0]), t / 50, 50, tol=1e-16)
+    assert np.allclose(psi, [np.cos(J * t), -1j * np.sin(J * t)], atol=1e-14)
