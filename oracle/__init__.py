@@ -24,6 +24,13 @@ What it computes (Piccinini et al., arXiv:1612.00746):
                       Daleckii-Krein formula on the eigen-decomposition.  The
                       paper does not differentiate; this is a reference for
                       an extension of the method.
+* ``telegraph``    -- switching (telegraph) hopping noise: the documented
+                      counter-based sign process and the step-by-step
+                      evolution with H rebuilt every step (Eq. 1, time
+                      dependent).
+* ``graph``        -- one particle on a general graph or q-dimensional
+                      lattice (Sec. 2): bonds of the lattice and H from a
+                      bond list.
 
 Every function is FP64 and written for clarity, not speed.  Pins that tie the
 oracle to closed forms, textbook routines and invariants live in
