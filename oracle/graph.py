@@ -10,7 +10,9 @@ evolution itself is ``propagate.evolve_taylor`` on this H.
 
 Pins in tests/test_oracle_pins.py: the clean lattice spectra against the
 closed forms (sums of 2 cos(pi k / (N + 1)) over the axes, open; sums of
-2 cos(2 pi k / N), periodic), node degrees, symmetry.
+2 cos(2 pi k / N), periodic), node degrees, symmetry, the two-node closed
+form; for two particles, the non-interacting spectra (sums of one-particle
+eigenvalues) and, on a chain, the pinned many-particle chain Hamiltonian.
 """
 
 from __future__ import annotations
@@ -52,3 +54,21 @@ def hamiltonian(n, bonds, J, eps):
         H[a, b] += j
         H[b, a] += j
     return H.tocsr()
+
+
+def pair_hamiltonian(n, bonds, J, eps, U, statistics):
+    """Two particles on the graph (Eq. 1 with m = 2): the one-particle H
+    acting on either particle, H1 x 1 + 1 x H1, plus U on the states with
+    both particles on one node (on-site interaction).  Distinguishable:
+    the n^2 grid in row-major order; bosons: S^T H S with the symmetrising
+    isometry of ``basis.symmetrizer`` (sorted pairs, lexicographic)."""
+    from .basis import BOSON, symmetrizer
+    H1 = hamiltonian(n, bonds, J, eps)
+    one = sp.identity(n, format="csr")
+    H = sp.kron(H1, one) + sp.kron(one, H1)
+    double = np.array([float(a == b) for a in range(n) for b in range(n)])
+    H = (H + sp.diags(U * double)).tocsr()
+    if statistics == BOSON:
+        S = symmetrizer(n, 2)
+        H = (S.T @ H @ S).tocsr()
+    return H

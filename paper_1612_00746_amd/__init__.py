@@ -367,17 +367,10 @@ def lattice_edges(shape: Sequence[int], periodic: bool = False) -> np.ndarray:
     return np.concatenate(out).astype(np.int32)
 
 
-def ell_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
-    """Neighbour and coupling tables of ctqw_graph_evolve from an undirected
-    bond list: edges int [E, 2] (no self-loops, no repeated bonds), J [R, E]
-    the bond couplings of each realisation.  Each bond fills one slot of
-    both of its nodes, slots in bond order; width = the largest degree.
-    Returns nbr int32 [width, n] (-1 in empty slots) and hop float64
-    [R, width, n]."""
+def _ell_topology(n_nodes: int, edges: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Slots of an undirected bond list: nbr int32 [width, n] (-1 empty) and
+    the bond that fills each slot, int64 [width, n] (-1 empty)."""
     edges = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
-    J = np.atleast_2d(np.asarray(J, dtype=np.float64))
-    if J.shape[1] != len(edges):
-        raise ValueError("J must be [R, E]")
     if len(edges) and (edges.min() < 0 or edges.max() >= n_nodes):
         raise ValueError("bond endpoint out of range")
     if np.any(edges[:, 0] == edges[:, 1]):
@@ -399,9 +392,73 @@ def ell_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray) -> tuple[np.ndarr
         fill[a] += 1
     nbr = np.full((width, n_nodes), -1, dtype=np.int32)
     nbr[slot, ends] = other
-    hop = np.zeros((J.shape[0], width, n_nodes))
-    hop[:, slot, ends] = J[:, bond]
-    return nbr, hop
+    bond_of = np.full((width, n_nodes), -1, dtype=np.int64)
+    bond_of[slot, ends] = bond
+    return nbr, bond_of
+
+
+def ell_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Neighbour and coupling tables of ctqw_graph_evolve from an undirected
+    bond list: edges int [E, 2] (no self-loops, no repeated bonds), J [R, E]
+    the bond couplings of each realisation.  Each bond fills one slot of
+    both of its nodes, slots in bond order; width = the largest degree.
+    Returns nbr int32 [width, n] (-1 in empty slots) and hop float64
+    [R, width, n]."""
+    J = np.atleast_2d(np.asarray(J, dtype=np.float64))
+    if J.shape[1] != len(np.asarray(edges).reshape(-1, 2)):
+        raise ValueError("J must be [R, E]")
+    nbr, bond_of = _ell_topology(n_nodes, edges)
+    hop = np.where(bond_of >= 0, J[:, np.maximum(bond_of, 0)], 0.0)
+    return nbr, np.ascontiguousarray(hop)
+
+
+def pair_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: np.ndarray, U: np.ndarray,
+                statistics: str = "distinguishable") -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Two particles on a graph (Sec. 2 with m = 2) as one particle on the
+    pair graph, for ctqw_graph_evolve.  States: (a, b) at a * n + b
+    (distinguishable) or the pairs a <= b in lexicographic order, each the
+    normalised symmetric state (bosons).  Either particle moves along a
+    bond; in the boson sector a move between a doubly occupied node pair
+    (a, a) and a pair (a, c) carries sqrt(2) J, split over the two slots of
+    the diagonal state.  On-site energies add, and U acts on double
+    occupation.  J [R, E], eps [R, n], U [R].  Returns nbr int32 [2 width,
+    D], hop float64 [R, 2 width, D] and onsite float64 [R, D]."""
+    J = np.atleast_2d(np.asarray(J, dtype=np.float64))
+    eps = np.atleast_2d(np.asarray(eps, dtype=np.float64))
+    U = np.atleast_1d(np.asarray(U, dtype=np.float64))
+    n = int(n_nodes)
+    if J.shape[1] != len(np.asarray(edges).reshape(-1, 2)) or eps.shape != (J.shape[0], n) or U.shape != (J.shape[0],):
+        raise ValueError("J must be [R, E], eps [R, n] and U [R]")
+    nbr1, bond1 = _ell_topology(n, edges)
+    w = nbr1.shape[0]
+    if statistics == "distinguishable":
+        A, B = np.divmod(np.arange(n * n), n)
+        index = lambda a, b: a * n + b  # noqa: E731
+    elif statistics == "boson":
+        A, B = np.triu_indices(n)
+        # position of the sorted pair (a, b), a <= b, in lexicographic order
+        index = lambda a, b: (lambda lo, hi: lo * n - lo * (lo - 1) // 2 + (hi - lo))(np.minimum(a, b), np.maximum(a, b))  # noqa: E731
+    else:
+        raise ValueError(f"unknown statistics {statistics!r}")
+    D = len(A)
+    nbr = np.full((2 * w, D), -1, dtype=np.int32)
+    bond = np.full((2 * w, D), -1, dtype=np.int64)
+    fac = np.zeros((2 * w, D))
+    for k in range(w):
+        for half, (mover, still) in enumerate(((A, B), (B, A))):
+            c = nbr1[k, mover]
+            ok = c >= 0
+            cc = np.where(ok, c, 0)
+            tgt = np.where(ok, index(cc, still) if half == 0 else index(still, cc), -1)
+            f = np.ones(D)
+            if statistics == "boson":
+                f = np.where(A == B, 1 / np.sqrt(2), np.where(c == still, np.sqrt(2), 1.0))
+            nbr[half * w + k] = tgt
+            bond[half * w + k] = np.where(ok, bond1[k, mover], -1)
+            fac[half * w + k] = np.where(ok, f, 0.0)
+    hop = np.where(bond >= 0, J[:, np.maximum(bond, 0)], 0.0) * fac
+    onsite = eps[:, A] + eps[:, B] + U[:, None] * (A == B)
+    return nbr, np.ascontiguousarray(hop), np.ascontiguousarray(onsite)
 
 
 def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, workspace=None) -> None:

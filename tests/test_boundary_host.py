@@ -412,6 +412,7 @@ def test_ell_tables_rebuild_the_oracle_hamiltonian():
     edges = sorted(set(edges))
     J = g.standard_normal((3, len(edges)))
     nbr, hop = ell_tables(n, np.array(edges), J)
+    assert nbr.flags.c_contiguous and hop.flags.c_contiguous
     assert nbr.shape[0] == max(np.bincount(np.array(edges).ravel(), minlength=n))
     assert np.all(nbr[:, n - 1] == -1)
     for r in range(3):
@@ -449,3 +450,28 @@ def test_graph_evolve_validation(kw, status):
     assert st == status
     b = C.c_int64()
     assert lib.ctqw_graph_workspace(8, 2, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 16
+
+
+@pytest.mark.parametrize("statistics", ["distinguishable", "boson"])
+def test_pair_tables_rebuild_the_oracle_pair_hamiltonian(statistics):
+    """Two particles on a 3 x 4 lattice with noise and U: the pair-graph
+    tables, read back as a matrix (ELL slots summed, on-site on the
+    diagonal), equal the oracle's two-particle H for every realisation."""
+    from paper_1612_00746_amd import lattice_edges, pair_tables
+    from oracle import graph as G
+    g = np.random.default_rng(10)
+    edges = lattice_edges((3, 4))
+    R = 2
+    J, eps, U = 1 + 0.2 * g.standard_normal((R, len(edges))), g.uniform(-0.5, 0.5, (R, 12)), g.uniform(0.5, 2, R)
+    nbr, hop, onsite = pair_tables(12, edges, J, eps, U, statistics)
+    assert nbr.flags.c_contiguous and hop.flags.c_contiguous and onsite.flags.c_contiguous
+    D = nbr.shape[1]
+    bonds = [tuple(e) for e in edges.tolist()]
+    for r in range(R):
+        M = np.diag(onsite[r])
+        for k in range(nbr.shape[0]):
+            for i in range(D):
+                if nbr[k, i] >= 0:
+                    M[i, nbr[k, i]] += hop[r, k, i]
+        ref = G.pair_hamiltonian(12, bonds, J[r], eps[r], U[r], statistics).toarray()
+        assert np.allclose(M, ref, atol=1e-15)

@@ -515,3 +515,39 @@ def test_graph_two_node_evolution_closed_form():
     H = G.hamiltonian(2, [(0, 1)], [J], [0.0, 0.0])
     psi, _, _ = P.evolve_taylor(H, np.array([1.0, 0.0]), t / 50, 50, tol=1e-16)
     assert np.allclose(psi, [np.cos(J * t), -1j * np.sin(J * t)], atol=1e-14)
+
+
+@pytest.mark.parametrize("statistics", [B.DISTINGUISHABLE, B.BOSON])
+def test_graph_pair_non_interacting_spectrum(statistics):
+    """Two particles, U = 0, on a noisy 3 x 4 lattice: the eigenvalues are
+    the sums e_i + e_j of one-particle eigenvalues (all ordered pairs for
+    distinguishable particles, i <= j for bosons)."""
+    g = np.random.default_rng(8)
+    bonds = G.lattice_bonds((3, 4))
+    J, eps = 1 + 0.2 * g.standard_normal(len(bonds)), g.uniform(-0.5, 0.5, 12)
+    e = np.linalg.eigvalsh(G.hamiltonian(12, bonds, J, eps).toarray())
+    if statistics == B.DISTINGUISHABLE:
+        want = (e[:, None] + e[None, :]).ravel()
+    else:
+        i, j = np.triu_indices(12)
+        want = e[i] + e[j]
+    H = G.pair_hamiltonian(12, bonds, J, eps, 0.0, statistics).toarray()
+    assert np.allclose(np.linalg.eigvalsh(H), np.sort(want), atol=1e-12)
+
+
+@pytest.mark.parametrize("statistics", [B.DISTINGUISHABLE, B.BOSON])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_graph_pair_on_a_chain_is_the_chain_hamiltonian(statistics, periodic):
+    """On the chain graph the two-particle graph H equals the (pinned)
+    many-particle chain Hamiltonian with on-site U, open and ring."""
+    g = np.random.default_rng(9)
+    N = 7
+    bonds = G.lattice_bonds((N,), periodic)
+    nb = N if periodic else N - 1
+    J, eps, U = 1 + 0.2 * g.standard_normal(nb), g.uniform(-0.5, 0.5, N), 1.3
+    # the chain module orders bonds i = (i, i + 1), the wrap bond (N - 1, 0) last
+    Jb = np.array([J[[k for k, bd in enumerate(bonds) if bd == (min(i, (i + 1) % N), max(i, (i + 1) % N))][0]]
+                   for i in range(nb)])
+    ref = Hm.hamiltonian(N, 2, Jb, eps, U, statistics, Hm.PERIODIC if periodic else Hm.OPEN, Hm.ONSITE).toarray()
+    got = G.pair_hamiltonian(N, bonds, J, eps, U, statistics).toarray()
+    assert np.allclose(got, ref, atol=1e-15)
