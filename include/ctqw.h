@@ -254,14 +254,20 @@ ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
  *   psi     device complex128 [R][n_nodes] (interleaved re, im), advanced
  *           in place.
  *   workspace  device memory of ctqw_graph_workspace(n_nodes, R) bytes.
- * order: 1..64 terms (fixed; no norm check).  Enqueued on hip_stream
+ *   norms   device double [n_steps][R] or NULL: the squared FP64 2-norm
+ *           of each realisation after each step (the per-step norm check
+ *           of Alg. 3; a fixed summation order, so reruns give the same
+ *           bits).  The library raises no alarm on this path: the caller
+ *           reads the norms.
+ * order: 1..64 terms (fixed).  Enqueued on hip_stream
  * (hipStream_t, NULL = default); psi, the tables and the workspace must stay
  * valid until the work has run.  Errors: INVALID_ARG (non-positive sizes,
  * NULL, non-finite dt, order out of range, workspace too small), DEVICE.   */
 ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int64_t* bytes);
 ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const double* hop,
                               const double* onsite, int32_t R, double dt, int32_t order, int64_t n_steps,
-                              void* psi, void* workspace, int64_t workspace_bytes, void* hip_stream);
+                              void* psi, void* workspace, int64_t workspace_bytes, double* norms,
+                              void* hip_stream);
 
 /* Device bytes the caller must provide: each of the two state buffers and
  * the workspace, for the current parameters and launch shape.             */

@@ -461,11 +461,13 @@ def pair_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: np.ndarray,
     return nbr, np.ascontiguousarray(hop), np.ascontiguousarray(onsite)
 
 
-def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, workspace=None) -> None:
+def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, workspace=None, norms=None) -> None:
     """ctqw_graph_evolve on device tensors: one particle on a general graph,
     R realisations advanced in place.  nbr int32 [width, n], hop float64
     [R, width, n], onsite float64 [R, n], psi complex128 [R, n], all
-    contiguous on one device; enqueued on that device's current stream."""
+    contiguous on one device; norms (optional) float64 [n_steps, R]
+    receives each step's squared norms.  Enqueued on that device's current
+    stream."""
     import torch
     lib = L.load()
     R, n = psi.shape
@@ -474,6 +476,9 @@ def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, wor
                         (onsite, torch.float64, (R, n)), (psi, torch.complex128, (R, n))):
         if t.dtype != dt_ or tuple(t.shape) != shp or not t.is_contiguous() or t.device != psi.device:
             raise ValueError(f"expected a contiguous {dt_} tensor of shape {shp} on {psi.device}")
+    if norms is not None and (norms.dtype != torch.float64 or tuple(norms.shape) != (int(n_steps), R)
+                              or not norms.is_contiguous() or norms.device != psi.device):
+        raise ValueError(f"norms must be a contiguous float64 tensor of shape ({n_steps}, {R}) on {psi.device}")
     b = C.c_int64()
     L.check(lib.ctqw_graph_workspace(n, R, C.byref(b)))
     if workspace is None:
@@ -482,4 +487,4 @@ def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, wor
     p = lambda t: C.c_void_p(t.data_ptr()) if t.numel() else None  # noqa: E731
     L.check(lib.ctqw_graph_evolve(n, width, p(nbr), p(hop), p(onsite), R, float(dt), int(order), int(n_steps),
                                   p(psi), p(workspace), workspace.numel() * workspace.element_size(),
-                                  C.c_void_p(stream)))
+                                  p(norms) if norms is not None else None, C.c_void_p(stream)))

@@ -47,7 +47,32 @@ __global__ __launch_bounds__(256) void graph_term_kernel(GraphTermArgs a) {
     }
 }
 
+// Squared FP64 norm of each realisation: block r strides over its nodes,
+// then a fixed shared-memory tree, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void graph_norm_kernel(const double2* psi, int32_t n, double* out) {
+    __shared__ double part[256];
+    const int64_t r = blockIdx.x;
+    const double2* x = psi + r * (int64_t)n;
+    double acc = 0.0;
+    for (int32_t i = (int32_t)threadIdx.x; i < n; i += 256) {
+        const double2 v = x[i];
+        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[r] = part[0];
+}
+
 }  // namespace
+
+hipError_t launch_graph_norms(const double2* psi, int32_t n, int32_t R, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(graph_norm_kernel, dim3((unsigned)R), dim3(256), 0, s, psi, n, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_graph_term(const GraphTermArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)std::min<int32_t>(a.R, 65535));

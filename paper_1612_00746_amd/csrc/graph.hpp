@@ -19,5 +19,7 @@ struct GraphTermArgs {
     int32_t R;
 };
 hipError_t launch_graph_term(const GraphTermArgs& a, hipStream_t s);
+// out[r] = sum_i |psi[r][i]|^2 in FP64, one block per realisation, fixed summation order.
+hipError_t launch_graph_norms(const double2* psi, int32_t n, int32_t R, double* out, hipStream_t s);
 
 }  // namespace ctqw

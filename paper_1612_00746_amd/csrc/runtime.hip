@@ -1290,7 +1290,7 @@ ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int64_t* bytes) {
 
 ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const double* hop,
                               const double* onsite, int32_t R, double dt, int32_t order, int64_t n_steps, void* psi,
-                              void* workspace, int64_t workspace_bytes, void* hip_stream) {
+                              void* workspace, int64_t workspace_bytes, double* norms, void* hip_stream) {
     int64_t need = 0;
     ctqw_status st = ctqw_graph_workspace(n_nodes, R, &need);
     if (st != CTQW_OK) return st;
@@ -1331,6 +1331,7 @@ ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr
             a.acc_in = acc;
         }
         if (order == 1) HIP_TRY(nullptr, hipMemcpyAsync(x, acc, cnt * 16, hipMemcpyDeviceToDevice, s));
+        if (norms) HIP_TRY(nullptr, launch_graph_norms(x, n_nodes, R, norms + step * (int64_t)R, s));
     }
     return CTQW_OK;
 }

@@ -446,7 +446,7 @@ def test_graph_evolve_validation(kw, status):
         a["ws_bytes"] = kw.pop("ws")
     a.update(kw)
     st = lib.ctqw_graph_evolve(a["n_nodes"], a["width"], a["nbr"], a["hop"], a["onsite"], a["R"], a["dt"],
-                               a["order"], a["n_steps"], a["psi"], a["ws"], a["ws_bytes"], None)
+                               a["order"], a["n_steps"], a["psi"], a["ws"], a["ws_bytes"], None, None)
     assert st == status
     b = C.c_int64()
     assert lib.ctqw_graph_workspace(8, 2, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 16

@@ -31,15 +31,20 @@ def run_case(n, edges, R, dt, order, steps, seed):
     nbr, hop = ell_tables(n, np.array(edges, dtype=np.int64).reshape(-1, 2), J)
     dev = "cuda"
     psi = torch.from_numpy(psi0.copy()).to(dev)
+    norms = torch.full((steps, R), -1.0, dtype=torch.float64, device=dev)
     graph_evolve(torch.from_numpy(nbr).to(dev), torch.from_numpy(np.ascontiguousarray(hop)).to(dev),
-                 torch.from_numpy(eps).to(dev), psi, dt, order, steps)
+                 torch.from_numpy(eps).to(dev), psi, dt, order, steps, norms=norms)
     torch.cuda.synchronize()
     got = psi.cpu().numpy()
+    n2 = norms.cpu().numpy()
     worst = 0.0
     for r in range(R):
         H = G.hamiltonian(n, edges, J[r], eps[r])
-        ref, _, _ = P.evolve_taylor(H, psi0[r], dt, steps, order=order)
+        ref, snaps, _ = P.evolve_taylor(H, psi0[r], dt, steps, order=order, output_every=1)
         worst = max(worst, float(np.max(np.abs(got[r] - ref))))
+        # the per-step squared norms follow the oracle's states step by step
+        want = np.array([np.vdot(v, v).real for v in snaps[1:]])
+        assert np.max(np.abs(n2[:, r] - want)) <= 1e-13, (r, n2[:, r], want)
     return worst, got, psi0
 
 
@@ -55,6 +60,29 @@ def test_lattice_against_the_oracle(shape, periodic, order):
     say(f"  max |psi - oracle| = {worst:.2e}")
     assert worst <= 1e-12
     assert np.allclose(np.linalg.norm(got, axis=1), 1.0, atol=1e-8)
+
+
+def test_norms_are_reproducible():
+    """The per-step norms of two identical runs agree bit for bit, and the
+    last row equals the squared norms of the final state to rounding."""
+    import torch
+    from paper_1612_00746_amd import ell_tables, graph_evolve
+    edges = np.array(G.lattice_bonds((40, 30)))
+    n, R, steps = 1200, 3, 5
+    g = np.random.default_rng(69)
+    nbr, hop = ell_tables(n, edges, 1 + 0.1 * g.standard_normal((R, len(edges))))
+    args = [torch.from_numpy(nbr).cuda(), torch.from_numpy(hop).cuda(), torch.from_numpy(g.uniform(-1, 1, (R, n))).cuda()]
+    psi0 = random_states(R, n, 70)
+    out = []
+    for _ in range(2):
+        psi = torch.from_numpy(psi0.copy()).cuda()
+        norms = torch.zeros((steps, R), dtype=torch.float64, device="cuda")
+        graph_evolve(*args, psi, 0.05, 9, steps, norms=norms)
+        torch.cuda.synchronize()
+        out.append((psi.cpu().numpy(), norms.cpu().numpy()))
+    say(f"case: graph norms reproducible, 40 x 30 lattice, last norms {out[0][1][-1]}")
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][0], out[1][0])
+    assert np.allclose(out[0][1][-1], np.sum(np.abs(out[0][0]) ** 2, axis=1), rtol=1e-14, atol=0)
 
 
 def test_irregular_graph_against_the_oracle():
