@@ -400,11 +400,13 @@ def density(a):
 def graph(a):
     """One particle on a 128 x 128 open square lattice (q = 2, 16384
     nodes), 4096 noisy realisations (J = 1 + 0.1 N(0, 1) per bond,
-    eps ~ U[-0.5, 0.5]), complex128, dt = 0.05, 10 Taylor terms per step,
-    one pass per term.  Algorithmic bytes per node, realisation and term:
-    the previous term (16; neighbours counted as cache hits), the on-site
-    energy (8), width couplings (8 each), the partial sum in and out (32)
-    and the term out (16, not on the last term)."""
+    eps ~ U[-0.5, 0.5]), dt = 0.05, 10 Taylor terms per step, one pass per
+    term; complex128 with FP64 tables, then complex64 with FP32 tables.
+    Algorithmic bytes per node, realisation and term (e = 16 or 8 bytes per
+    amplitude, f = 8 or 4 per real): the previous term (e; neighbours
+    counted as cache hits), the on-site energy (f), width couplings (f
+    each), the partial sum in and out (2e) and the term out (e, not on the
+    last term)."""
     import torch
     from paper_1612_00746_amd import ell_tables, graph_evolve, lattice_edges
     side, R, order, dt = 128, 4096, 10, 0.05
@@ -412,31 +414,38 @@ def graph(a):
     g = np.random.default_rng(71)
     edges = lattice_edges((side, side))
     nbr, hop = ell_tables(n, edges, 1.0 + 0.1 * g.standard_normal((R, len(edges))))
+    eps = g.uniform(-0.5, 0.5, (R, n))
     width = nbr.shape[0]
     dev = "cuda"
-    nbr_d, hop_d = torch.from_numpy(nbr).to(dev), torch.from_numpy(hop).to(dev)
-    del hop
-    eps_d = torch.from_numpy(g.uniform(-0.5, 0.5, (R, n))).to(dev)
-    psi = torch.zeros((R, n), dtype=torch.complex128, device=dev)
-    psi[:, n // 2 + side // 2] = 1.0
-    ws = torch.empty(3 * R * n * 16, dtype=torch.uint8, device=dev)
-    graph_evolve(nbr_d, hop_d, eps_d, psi, dt, order, max(1, a.warmup), ws)
-    torch.cuda.synchronize()
-    steps = max(1, a.steps)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    graph_evolve(nbr_d, hop_d, eps_d, psi, dt, order, steps, ws)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    per_term = 16 + 8 + 8 * width + 32 + 16
-    bytes_step = (order * per_term - 16) * R * n
-    norm = float(torch.linalg.vector_norm(psi[0]).item())
-    print(json.dumps({"metric": "graph walk node-updates/s", "workload": "128 x 128 lattice, 4096 realisations, c128",
-                      "order": order, "width": width, "ms_per_step": round(ms, 4),
-                      "value": R * n / (ms * 1e-3), "unit": "node-updates/s",
-                      "achieved_GBps": round(bytes_step / (ms * 1e-3) / 1e9, 1),
-                      "frac_hbm": round(bytes_step / (ms * 1e-3) / 8e12, 4), "norm_r0": norm}))
+    nbr_d = torch.from_numpy(nbr).to(dev)
+    for dtype in ("c128", "c64"):
+        c64 = dtype == "c64"
+        rt = torch.float32 if c64 else torch.float64
+        hop_d = torch.from_numpy(hop).to(dev).to(rt)
+        eps_d = torch.from_numpy(eps).to(dev).to(rt)
+        psi = torch.zeros((R, n), dtype=torch.complex64 if c64 else torch.complex128, device=dev)
+        psi[:, n // 2 + side // 2] = 1.0
+        e, f = (8, 4) if c64 else (16, 8)
+        ws = torch.empty(3 * R * n * e, dtype=torch.uint8, device=dev)
+        graph_evolve(nbr_d, hop_d, eps_d, psi, dt, order, max(1, a.warmup), ws)
+        torch.cuda.synchronize()
+        steps = max(1, a.steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph_evolve(nbr_d, hop_d, eps_d, psi, dt, order, steps, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        per_term = e + f + f * width + 2 * e + e
+        bytes_step = (order * per_term - e) * R * n
+        norm = float(torch.linalg.vector_norm(psi[0].to(torch.complex128)).item())
+        print(json.dumps({"metric": "graph walk node-updates/s", "workload": "128 x 128 lattice, 4096 realisations",
+                          "dtype": dtype, "order": order, "width": width, "ms_per_step": round(ms, 4),
+                          "value": R * n / (ms * 1e-3), "unit": "node-updates/s",
+                          "achieved_GBps": round(bytes_step / (ms * 1e-3) / 1e9, 1),
+                          "frac_hbm": round(bytes_step / (ms * 1e-3) / 8e12, 4), "norm_r0": norm}), flush=True)
+        del hop_d, eps_d, psi, ws
+        torch.cuda.empty_cache()
 
 
 def three_walkers(a):

@@ -242,32 +242,36 @@ ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
  * set of neighbours; a q-dimensional lattice, q > 1, is one such graph), R
  * statically noisy realisations sharing one topology, advanced n_steps
  * times by the order-n Taylor polynomial of exp(-i H dt) (Eqs. 5-7), one
- * pass over the batch per term.  Stateless: no plan, complex128, FP64.
+ * pass over the batch per term.  Two particles on a graph are one particle
+ * on the pair graph (the binding builds its tables).  Stateless: no plan.
+ * dtype CTQW_C128: complex128 states, FP64 tables and arithmetic;
+ * CTQW_C64: complex64 states, FP32 tables and arithmetic, plain sums.
  *   nbr     device int32 [width][n_nodes]: neighbour of node i in slot k is
  *           nbr[k * n_nodes + i]; a value outside [0, n_nodes) (use -1)
  *           marks an empty slot, so nodes may have different degrees.
- *   hop     device double [R][width][n_nodes]: H_r[i, nbr[k][i]] =
+ *   hop     device real [R][width][n_nodes]: H_r[i, nbr[k][i]] =
  *           hop[(r * width + k) * n_nodes + i].  H_r is Hermitian only if
  *           the caller gives both directions of every bond the same value
  *           (not checked).  nbr and hop may be NULL when width == 0.
- *   onsite  device double [R][n_nodes]: H_r[i, i].
- *   psi     device complex128 [R][n_nodes] (interleaved re, im), advanced
- *           in place.
- *   workspace  device memory of ctqw_graph_workspace(n_nodes, R) bytes.
+ *   onsite  device real [R][n_nodes]: H_r[i, i].
+ *   psi     device complex [R][n_nodes] (interleaved re, im), advanced in
+ *           place.
+ *   workspace  device memory of ctqw_graph_workspace(n_nodes, R, dtype)
+ *           bytes.
  *   norms   device double [n_steps][R] or NULL: the squared FP64 2-norm
  *           of each realisation after each step (the per-step norm check
  *           of Alg. 3; a fixed summation order, so reruns give the same
  *           bits).  The library raises no alarm on this path: the caller
  *           reads the norms.
- * order: 1..64 terms (fixed).  Enqueued on hip_stream
- * (hipStream_t, NULL = default); psi, the tables and the workspace must stay
- * valid until the work has run.  Errors: INVALID_ARG (non-positive sizes,
- * NULL, non-finite dt, order out of range, workspace too small), DEVICE.   */
-ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int64_t* bytes);
-ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const double* hop,
-                              const double* onsite, int32_t R, double dt, int32_t order, int64_t n_steps,
-                              void* psi, void* workspace, int64_t workspace_bytes, double* norms,
-                              void* hip_stream);
+ * order: 1..64 terms (fixed).  Enqueued on hip_stream (hipStream_t, NULL =
+ * default); psi, the tables and the workspace must stay valid until the
+ * work has run.  Errors: INVALID_ARG (non-positive sizes, unknown dtype,
+ * NULL, non-finite dt, order out of range, workspace too small), DEVICE.  */
+ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int32_t dtype, int64_t* bytes);
+ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const void* hop,
+                              const void* onsite, int32_t R, int32_t dtype, double dt, int32_t order,
+                              int64_t n_steps, void* psi, void* workspace, int64_t workspace_bytes,
+                              double* norms, void* hip_stream);
 
 /* Device bytes the caller must provide: each of the two state buffers and
  * the workspace, for the current parameters and launch shape.             */

@@ -463,28 +463,33 @@ def pair_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: np.ndarray,
 
 def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, workspace=None, norms=None) -> None:
     """ctqw_graph_evolve on device tensors: one particle on a general graph,
-    R realisations advanced in place.  nbr int32 [width, n], hop float64
-    [R, width, n], onsite float64 [R, n], psi complex128 [R, n], all
-    contiguous on one device; norms (optional) float64 [n_steps, R]
-    receives each step's squared norms.  Enqueued on that device's current
-    stream."""
+    R realisations advanced in place.  nbr int32 [width, n]; psi complex128
+    [R, n] with hop float64 [R, width, n] and onsite float64 [R, n], or
+    psi complex64 with float32 tables; all contiguous on one device.  norms
+    (optional) float64 [n_steps, R] receives each step's squared norms.
+    Enqueued on that device's current stream."""
     import torch
     lib = L.load()
     R, n = psi.shape
     width = nbr.shape[0]
-    for t, dt_, shp in ((nbr, torch.int32, (width, n)), (hop, torch.float64, (R, width, n)),
-                        (onsite, torch.float64, (R, n)), (psi, torch.complex128, (R, n))):
+    if psi.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError("psi must be complex64 or complex128")
+    c128 = psi.dtype == torch.complex128
+    real = torch.float64 if c128 else torch.float32
+    for t, dt_, shp in ((nbr, torch.int32, (width, n)), (hop, real, (R, width, n)), (onsite, real, (R, n)),
+                        (psi, psi.dtype, (R, n))):
         if t.dtype != dt_ or tuple(t.shape) != shp or not t.is_contiguous() or t.device != psi.device:
             raise ValueError(f"expected a contiguous {dt_} tensor of shape {shp} on {psi.device}")
     if norms is not None and (norms.dtype != torch.float64 or tuple(norms.shape) != (int(n_steps), R)
                               or not norms.is_contiguous() or norms.device != psi.device):
         raise ValueError(f"norms must be a contiguous float64 tensor of shape ({n_steps}, {R}) on {psi.device}")
+    dtype = C128 if c128 else C64
     b = C.c_int64()
-    L.check(lib.ctqw_graph_workspace(n, R, C.byref(b)))
+    L.check(lib.ctqw_graph_workspace(n, R, dtype, C.byref(b)))
     if workspace is None:
         workspace = torch.empty(b.value, dtype=torch.uint8, device=psi.device)
     stream = torch.cuda.current_stream(psi.device).cuda_stream
     p = lambda t: C.c_void_p(t.data_ptr()) if t.numel() else None  # noqa: E731
-    L.check(lib.ctqw_graph_evolve(n, width, p(nbr), p(hop), p(onsite), R, float(dt), int(order), int(n_steps),
+    L.check(lib.ctqw_graph_evolve(n, width, p(nbr), p(hop), p(onsite), R, dtype, float(dt), int(order), int(n_steps),
                                   p(psi), p(workspace), workspace.numel() * workspace.element_size(),
                                   p(norms) if norms is not None else None, C.c_void_p(stream)))

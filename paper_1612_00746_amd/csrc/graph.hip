@@ -5,7 +5,8 @@
 //     Phi^(j) = (-i dt / j) H Phi^(j-1),   psi(t + dt) = sum_j Phi^(j),
 // with H psi gathered through an ELL neighbour table.  The topology is the
 // same for every realisation, the couplings and on-site energies are each
-// realisation's own.  Complex128, FP64 arithmetic.
+// realisation's own.  Complex128 with FP64 tables, or complex64 with FP32
+// tables (plain sums); the optional per-step norms are FP64 either way.
 //
 // Work mapping: one thread per (node, realisation); nodes along x
 // (coalesced reads of the ELL slots, the couplings, the on-site energies and
@@ -21,42 +22,62 @@
 namespace ctqw {
 namespace {
 
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<double> { using type = double2; };
+
+__device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
 __global__ __launch_bounds__(256) void graph_term_kernel(GraphTermArgs a) {
+    using C = typename Cplx<T>::type;
     const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= a.n) return;
     const int64_t n = a.n;
+    const T* hop = static_cast<const T*>(a.hop);
+    const T* onsite = static_cast<const T*>(a.onsite);
+    const T cf = static_cast<T>(a.c);
     for (int64_t r = blockIdx.y; r < a.R; r += gridDim.y) {
-        const double2* x = a.src + r * n;
-        const double2 xi = x[i];
-        const double e = a.onsite[r * n + i];
-        double hr = e * xi.x, hi = e * xi.y;
-        const double* h = a.hop + r * (int64_t)a.width * n;
+        const C* x = static_cast<const C*>(a.src) + r * n;
+        const C xi = x[i];
+        const T e = onsite[r * n + i];
+        T hr = e * xi.x, hi = e * xi.y;
+        const T* h = hop + r * (int64_t)a.width * n;
         for (int32_t k = 0; k < a.width; ++k) {
             const int32_t j = a.nbr[(int64_t)k * n + i];
             if (j < 0 || j >= a.n) continue;
-            const double c = h[(int64_t)k * n + i];
-            const double2 xj = x[j];
-            hr = fma(c, xj.x, hr);
-            hi = fma(c, xj.y, hi);
+            const T c = h[(int64_t)k * n + i];
+            const C xj = x[j];
+            hr = fma_r(c, xj.x, hr);
+            hi = fma_r(c, xj.y, hi);
         }
         // (-i c) (hr + i hi) = c hi - i c hr
-        const double2 t = make_double2(a.c * hi, -a.c * hr);
-        if (a.t_out) a.t_out[r * n + i] = t;
-        const double2 s = a.acc_in[r * n + i];
-        a.acc_out[r * n + i] = make_double2(s.x + t.x, s.y + t.y);
+        C t;
+        t.x = cf * hi;
+        t.y = -cf * hr;
+        if (a.t_out) static_cast<C*>(a.t_out)[r * n + i] = t;
+        const C s = static_cast<const C*>(a.acc_in)[r * n + i];
+        C o;
+        o.x = s.x + t.x;
+        o.y = s.y + t.y;
+        static_cast<C*>(a.acc_out)[r * n + i] = o;
     }
 }
 
 // Squared FP64 norm of each realisation: block r strides over its nodes,
 // then a fixed shared-memory tree, so the result does not depend on timing.
-__global__ __launch_bounds__(256) void graph_norm_kernel(const double2* psi, int32_t n, double* out) {
+template <typename T>
+__global__ __launch_bounds__(256) void graph_norm_kernel(const void* psi, int32_t n, double* out) {
+    using C = typename Cplx<T>::type;
     __shared__ double part[256];
     const int64_t r = blockIdx.x;
-    const double2* x = psi + r * (int64_t)n;
+    const C* x = static_cast<const C*>(psi) + r * (int64_t)n;
     double acc = 0.0;
     for (int32_t i = (int32_t)threadIdx.x; i < n; i += 256) {
-        const double2 v = x[i];
-        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+        const C v = x[i];
+        const double re = v.x, im = v.y;
+        acc = fma(re, re, fma(im, im, acc));
     }
     part[threadIdx.x] = acc;
     __syncthreads();
@@ -69,14 +90,20 @@ __global__ __launch_bounds__(256) void graph_norm_kernel(const double2* psi, int
 
 }  // namespace
 
-hipError_t launch_graph_norms(const double2* psi, int32_t n, int32_t R, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(graph_norm_kernel, dim3((unsigned)R), dim3(256), 0, s, psi, n, out);
+hipError_t launch_graph_norms(const void* psi, int32_t n, int32_t R, double* out, int dtype, hipStream_t s) {
+    if (dtype == 1)
+        hipLaunchKernelGGL(graph_norm_kernel<double>, dim3((unsigned)R), dim3(256), 0, s, psi, n, out);
+    else
+        hipLaunchKernelGGL(graph_norm_kernel<float>, dim3((unsigned)R), dim3(256), 0, s, psi, n, out);
     return hipGetLastError();
 }
 
-hipError_t launch_graph_term(const GraphTermArgs& a, hipStream_t s) {
+hipError_t launch_graph_term(const GraphTermArgs& a, int dtype, hipStream_t s) {
     const dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)std::min<int32_t>(a.R, 65535));
-    hipLaunchKernelGGL(graph_term_kernel, grid, dim3(256), 0, s, a);
+    if (dtype == 1)
+        hipLaunchKernelGGL(graph_term_kernel<double>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(graph_term_kernel<float>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1279,20 +1279,21 @@ ctqw_status ctqw_density_matrix(ctqw_plan* p, int32_t group, void* rho, int64_t 
     return CTQW_OK;
 }
 
-ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int64_t* bytes) {
+ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int32_t dtype, int64_t* bytes) {
     if (!bytes) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL argument");
     if (n_nodes < 1 || R < 1)
         return fail(nullptr, CTQW_ERR_INVALID_ARG, "n_nodes and R must be positive (got %d, %d)", n_nodes, R);
-    // two term buffers and the partial sum, complex128
-    *bytes = 3 * (int64_t)n_nodes * (int64_t)R * 16;
+    if (dtype != CTQW_C64 && dtype != CTQW_C128) return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+    // two term buffers and the partial sum
+    *bytes = 3 * (int64_t)n_nodes * (int64_t)R * (dtype == CTQW_C128 ? 16 : 8);
     return CTQW_OK;
 }
 
-ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const double* hop,
-                              const double* onsite, int32_t R, double dt, int32_t order, int64_t n_steps, void* psi,
+ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const void* hop, const void* onsite,
+                              int32_t R, int32_t dtype, double dt, int32_t order, int64_t n_steps, void* psi,
                               void* workspace, int64_t workspace_bytes, double* norms, void* hip_stream) {
     int64_t need = 0;
-    ctqw_status st = ctqw_graph_workspace(n_nodes, R, &need);
+    ctqw_status st = ctqw_graph_workspace(n_nodes, R, dtype, &need);
     if (st != CTQW_OK) return st;
     if (width < 0) return fail(nullptr, CTQW_ERR_INVALID_ARG, "width must be >= 0 (got %d)", width);
     if (!onsite || !psi || !workspace || (width > 0 && (!nbr || !hop)))
@@ -1306,10 +1307,12 @@ ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr
         return fail(nullptr, CTQW_ERR_INVALID_ARG, "workspace too small (%lld < %lld bytes)",
                     (long long)workspace_bytes, (long long)need);
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const int64_t cnt = (int64_t)n_nodes * R;
-    double2* T[2] = {static_cast<double2*>(workspace), static_cast<double2*>(workspace) + cnt};
-    double2* acc = static_cast<double2*>(workspace) + 2 * cnt;
-    double2* x = static_cast<double2*>(psi);
+    const int dt_ = dtype == CTQW_C128 ? 1 : 0;
+    const int64_t esz = dt_ ? 16 : 8;
+    const int64_t bytes = (int64_t)n_nodes * R * esz;
+    char* ws = static_cast<char*>(workspace);
+    void* T[2] = {ws, ws + bytes};
+    void* acc = ws + 2 * bytes;
     for (int64_t step = 0; step < n_steps; ++step) {
         GraphTermArgs a{};
         a.nbr = nbr;
@@ -1318,20 +1321,20 @@ ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr
         a.n = n_nodes;
         a.width = width;
         a.R = R;
-        a.src = x;
-        a.acc_in = x;
+        a.src = psi;
+        a.acc_in = psi;
         for (int32_t j = 1; j <= order; ++j) {
             const bool last = j == order;
             a.t_out = last ? nullptr : T[(j - 1) & 1];
             // the last term may write the state: it reads only the previous term and the sum
-            a.acc_out = (last && order > 1) ? x : acc;
+            a.acc_out = (last && order > 1) ? psi : acc;
             a.c = dt / (double)j;
-            HIP_TRY(nullptr, launch_graph_term(a, s));
+            HIP_TRY(nullptr, launch_graph_term(a, dt_, s));
             a.src = a.t_out;
             a.acc_in = acc;
         }
-        if (order == 1) HIP_TRY(nullptr, hipMemcpyAsync(x, acc, cnt * 16, hipMemcpyDeviceToDevice, s));
-        if (norms) HIP_TRY(nullptr, launch_graph_norms(x, n_nodes, R, norms + step * (int64_t)R, s));
+        if (order == 1) HIP_TRY(nullptr, hipMemcpyAsync(psi, acc, bytes, hipMemcpyDeviceToDevice, s));
+        if (norms) HIP_TRY(nullptr, launch_graph_norms(psi, n_nodes, R, norms + step * (int64_t)R, dt_, s));
     }
     return CTQW_OK;
 }

@@ -434,22 +434,23 @@ def test_ell_tables_reject_bad_bonds():
 
 @pytest.mark.parametrize("kw,status", [
     (dict(n_nodes=0), 1), (dict(R=0), 1), (dict(width=-1), 1), (dict(order=0), 1), (dict(order=65), 1),
-    (dict(n_steps=-1), 1), (dict(dt=float("nan")), 1), (dict(ws=10), 1), (dict(psi=None), 1),
+    (dict(n_steps=-1), 1), (dict(dt=float("nan")), 1), (dict(ws=10), 1), (dict(psi=None), 1), (dict(dtype=2), 1),
 ])
 def test_graph_evolve_validation(kw, status):
     """Invalid requests are refused on the host, before any device work."""
     from paper_1612_00746_amd import _lib as L
     lib = L.load()
     a = dict(n_nodes=8, width=2, nbr=C.c_void_p(16), hop=C.c_void_p(16), onsite=C.c_void_p(16), R=2, dt=0.1,
-             order=4, n_steps=1, psi=C.c_void_p(16), ws=C.c_void_p(16), ws_bytes=3 * 8 * 2 * 16)
+             order=4, n_steps=1, psi=C.c_void_p(16), ws=C.c_void_p(16), ws_bytes=3 * 8 * 2 * 16, dtype=1)
     if "ws" in kw:
         a["ws_bytes"] = kw.pop("ws")
     a.update(kw)
-    st = lib.ctqw_graph_evolve(a["n_nodes"], a["width"], a["nbr"], a["hop"], a["onsite"], a["R"], a["dt"],
-                               a["order"], a["n_steps"], a["psi"], a["ws"], a["ws_bytes"], None, None)
+    st = lib.ctqw_graph_evolve(a["n_nodes"], a["width"], a["nbr"], a["hop"], a["onsite"], a["R"], a["dtype"],
+                               a["dt"], a["order"], a["n_steps"], a["psi"], a["ws"], a["ws_bytes"], None, None)
     assert st == status
     b = C.c_int64()
-    assert lib.ctqw_graph_workspace(8, 2, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 16
+    assert lib.ctqw_graph_workspace(8, 2, 1, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 16
+    assert lib.ctqw_graph_workspace(8, 2, 0, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 8
 
 
 @pytest.mark.parametrize("statistics", ["distinguishable", "boson"])

@@ -21,7 +21,7 @@ def random_states(R, n, seed):
     return psi / np.linalg.norm(psi, axis=1, keepdims=True)
 
 
-def run_case(n, edges, R, dt, order, steps, seed):
+def run_case(n, edges, R, dt, order, steps, seed, dtype="c128"):
     import torch
     from paper_1612_00746_amd import ell_tables, graph_evolve
     g = np.random.default_rng(seed)
@@ -30,12 +30,14 @@ def run_case(n, edges, R, dt, order, steps, seed):
     psi0 = random_states(R, n, seed + 1)
     nbr, hop = ell_tables(n, np.array(edges, dtype=np.int64).reshape(-1, 2), J)
     dev = "cuda"
-    psi = torch.from_numpy(psi0.copy()).to(dev)
+    c64 = dtype == "c64"
+    psi = torch.from_numpy(psi0.astype(np.complex64) if c64 else psi0.copy()).to(dev)
+    rt = np.float32 if c64 else np.float64
     norms = torch.full((steps, R), -1.0, dtype=torch.float64, device=dev)
-    graph_evolve(torch.from_numpy(nbr).to(dev), torch.from_numpy(np.ascontiguousarray(hop)).to(dev),
-                 torch.from_numpy(eps).to(dev), psi, dt, order, steps, norms=norms)
+    graph_evolve(torch.from_numpy(nbr).to(dev), torch.from_numpy(np.ascontiguousarray(hop, dtype=rt)).to(dev),
+                 torch.from_numpy(np.ascontiguousarray(eps, dtype=rt)).to(dev), psi, dt, order, steps, norms=norms)
     torch.cuda.synchronize()
-    got = psi.cpu().numpy()
+    got = psi.cpu().numpy().astype(np.complex128)
     n2 = norms.cpu().numpy()
     worst = 0.0
     for r in range(R):
@@ -44,7 +46,7 @@ def run_case(n, edges, R, dt, order, steps, seed):
         worst = max(worst, float(np.max(np.abs(got[r] - ref))))
         # the per-step squared norms follow the oracle's states step by step
         want = np.array([np.vdot(v, v).real for v in snaps[1:]])
-        assert np.max(np.abs(n2[:, r] - want)) <= 1e-13, (r, n2[:, r], want)
+        assert np.max(np.abs(n2[:, r] - want)) <= (2e-6 if c64 else 1e-13), (r, n2[:, r], want)
     return worst, got, psi0
 
 
@@ -159,3 +161,45 @@ def test_two_particles_on_a_lattice(statistics, side1, side2, order, steps):
         worst = max(worst, float(np.max(np.abs(got[r] - ref))))
     say(f"  max |psi - oracle| = {worst:.2e}")
     assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("shape,order,steps", [((17, 16), 8, 40), ((6, 5, 4), 6, 25)])
+def test_complex64_lattice_against_the_oracle(shape, order, steps):
+    """complex64 states with FP32 tables and plain sums: within 2e-6 of the
+    oracle's FP64 Taylor map (tens of steps of FP32 rounding at unit norm),
+    per-step FP64 norms of the complex64 state within 2e-6 of the oracle's."""
+    n = int(np.prod(shape))
+    edges = G.lattice_bonds(shape, len(shape) == 3)
+    say(f"case: graph lattice {shape}, complex64, order {order}, {steps} steps")
+    worst, _, _ = run_case(n, edges, 4, 0.05, order, steps, 72, dtype="c64")
+    say(f"  max |psi - oracle| = {worst:.2e}")
+    assert worst <= 2e-6
+
+
+def test_complex64_two_bosons_on_a_lattice():
+    """Two bosons with U on a 15 x 15 lattice in complex64, 10 steps."""
+    import torch
+    from paper_1612_00746_amd import graph_evolve, lattice_edges, pair_tables
+    n, R, order, steps = 225, 2, 10, 10
+    g = np.random.default_rng(73)
+    edges = lattice_edges((15, 15))
+    J = 1.0 + 0.1 * g.standard_normal((R, len(edges)))
+    eps = g.uniform(-0.5, 0.5, (R, n))
+    U = g.uniform(0.5, 2.0, R)
+    nbr, hop, onsite = pair_tables(n, edges, J, eps, U, "boson")
+    D = nbr.shape[1]
+    say(f"case: two bosons on 15 x 15 in complex64, D={D}")
+    psi0 = random_states(R, D, 74)
+    psi = torch.from_numpy(psi0.astype(np.complex64)).cuda()
+    graph_evolve(torch.from_numpy(nbr).cuda(), torch.from_numpy(hop.astype(np.float32)).cuda(),
+                 torch.from_numpy(onsite.astype(np.float32)).cuda(), psi, 0.04, order, steps)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy().astype(np.complex128)
+    bonds = [tuple(e) for e in edges.tolist()]
+    worst = 0.0
+    for r in range(R):
+        H = G.pair_hamiltonian(n, bonds, J[r], eps[r], U[r], "boson")
+        ref, _, _ = P.evolve_taylor(H, psi0[r], 0.04, steps, order=order)
+        worst = max(worst, float(np.max(np.abs(got[r] - ref))))
+    say(f"  max |psi - oracle| = {worst:.2e}")
+    assert worst <= 2e-6
