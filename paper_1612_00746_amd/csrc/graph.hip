@@ -8,9 +8,11 @@
 // realisation's own.  Complex128 with FP64 tables, or complex64 with FP32
 // tables (plain sums); the optional per-step norms are FP64 either way.
 //
-// Work mapping: one thread per (node, realisation); nodes along x
-// (coalesced reads of the ELL slots, the couplings, the on-site energies and
-// the state), realisations along y, strided over the grid's second dimension.
+// Work mapping: one thread per node and group of realisations (four for
+// complex64, one for complex128); nodes
+// along x (coalesced reads of the ELL slots, the couplings, the on-site
+// energies and the state), realisation groups along y, strided over the
+// grid's second dimension.
 // Per node, term and realisation the pass reads the previous term at the
 // node and its neighbours (the neighbours mostly from cache), width
 // couplings and slot indices, the on-site energy and the partial sum, and
@@ -29,39 +31,70 @@ template <> struct Cplx<double> { using type = double2; };
 __device__ inline float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Realisations per thread: they share the slot indices, and their gathers
+// are independent loads in flight together.  Measured on the 128 x 128
+// lattice with 4096 realisations: four per thread is 14 % faster for
+// complex64 (8-byte gathers) and 19 % slower for complex128, which keeps one.
+template <typename T> struct RealsPerThread;
+template <> struct RealsPerThread<float> { static constexpr int value = 4; };
+template <> struct RealsPerThread<double> { static constexpr int value = 1; };
+
 template <typename T>
 __global__ __launch_bounds__(256) void graph_term_kernel(GraphTermArgs a) {
     using C = typename Cplx<T>::type;
+    constexpr int Q = RealsPerThread<T>::value;
     const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= a.n) return;
     const int64_t n = a.n;
     const T* hop = static_cast<const T*>(a.hop);
     const T* onsite = static_cast<const T*>(a.onsite);
+    const C* src = static_cast<const C*>(a.src);
     const T cf = static_cast<T>(a.c);
-    for (int64_t r = blockIdx.y; r < a.R; r += gridDim.y) {
-        const C* x = static_cast<const C*>(a.src) + r * n;
-        const C xi = x[i];
-        const T e = onsite[r * n + i];
-        T hr = e * xi.x, hi = e * xi.y;
-        const T* h = hop + r * (int64_t)a.width * n;
+    const int64_t groups = ((int64_t)a.R + Q - 1) / Q;
+    for (int64_t g = blockIdx.y; g < groups; g += gridDim.y) {
+        const int64_t r0 = g * Q;
+        const int nr = (int)((int64_t)a.R - r0 < Q ? (int64_t)a.R - r0 : Q);
+        T hr[Q], hi[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            hr[q] = T(0);
+            hi[q] = T(0);
+            if (q < nr) {
+                const C xi = src[(r0 + q) * n + i];
+                const T e = onsite[(r0 + q) * n + i];
+                hr[q] = e * xi.x;
+                hi[q] = e * xi.y;
+            }
+        }
         for (int32_t k = 0; k < a.width; ++k) {
             const int32_t j = a.nbr[(int64_t)k * n + i];
             if (j < 0 || j >= a.n) continue;
-            const T c = h[(int64_t)k * n + i];
-            const C xj = x[j];
-            hr = fma_r(c, xj.x, hr);
-            hi = fma_r(c, xj.y, hi);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (q < nr) {
+                    const T c = hop[((r0 + q) * a.width + k) * n + i];
+                    const C xj = src[(r0 + q) * n + j];
+                    hr[q] = fma_r(c, xj.x, hr[q]);
+                    hi[q] = fma_r(c, xj.y, hi[q]);
+                }
+            }
         }
-        // (-i c) (hr + i hi) = c hi - i c hr
-        C t;
-        t.x = cf * hi;
-        t.y = -cf * hr;
-        if (a.t_out) static_cast<C*>(a.t_out)[r * n + i] = t;
-        const C s = static_cast<const C*>(a.acc_in)[r * n + i];
-        C o;
-        o.x = s.x + t.x;
-        o.y = s.y + t.y;
-        static_cast<C*>(a.acc_out)[r * n + i] = o;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (q < nr) {
+                const int64_t o = (r0 + q) * n + i;
+                // (-i c) (hr + i hi) = c hi - i c hr
+                C t;
+                t.x = cf * hi[q];
+                t.y = -cf * hr[q];
+                if (a.t_out) static_cast<C*>(a.t_out)[o] = t;
+                const C s = static_cast<const C*>(a.acc_in)[o];
+                C out;
+                out.x = s.x + t.x;
+                out.y = s.y + t.y;
+                static_cast<C*>(a.acc_out)[o] = out;
+            }
+        }
     }
 }
 
@@ -99,7 +132,9 @@ hipError_t launch_graph_norms(const void* psi, int32_t n, int32_t R, double* out
 }
 
 hipError_t launch_graph_term(const GraphTermArgs& a, int dtype, hipStream_t s) {
-    const dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)std::min<int32_t>(a.R, 65535));
+    const int q = dtype == 1 ? RealsPerThread<double>::value : RealsPerThread<float>::value;
+    const int32_t groups = (int32_t)(((int64_t)a.R + q - 1) / q);
+    const dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)std::min<int32_t>(groups, 65535));
     if (dtype == 1)
         hipLaunchKernelGGL(graph_term_kernel<double>, grid, dim3(256), 0, s, a);
     else
