@@ -267,6 +267,16 @@ ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
  * default); psi, the tables and the workspace must stay valid until the
  * work has run.  Errors: INVALID_ARG (non-positive sizes, unknown dtype,
  * NULL, non-finite dt, order out of range, workspace too small), DEVICE.  */
+/* A-priori Taylor orders for ctqw_graph_evolve, computed on the host from
+ * host copies of its tables (same layouts, FP64): orders[r] is the smallest
+ * n >= 1 with x^(n+1)/(n+1)! / (1 - x/(n+2)) <= tol, x = |dt| * G_r and
+ * G_r = max_i (|onsite_r[i]| + sum over filled slots |hop_r[k][i]|), the
+ * Gershgorin bound on ||H_r||_2 (the chain path's rule, Alg. 3's order
+ * chosen before the step).  Errors: INVALID_ARG, NOT_CONVERGED (a
+ * realisation needs more than max_order <= 64 terms).                    */
+ctqw_status ctqw_graph_orders(int32_t n_nodes, int32_t width, const int32_t* nbr, const double* hop,
+                              const double* onsite, int32_t R, double dt, double tol, int32_t max_order,
+                              int32_t* orders);
 ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int32_t dtype, int64_t* bytes);
 ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const void* hop,
                               const void* onsite, int32_t R, int32_t dtype, double dt, int32_t order,

@@ -493,3 +493,22 @@ def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, wor
     L.check(lib.ctqw_graph_evolve(n, width, p(nbr), p(hop), p(onsite), R, dtype, float(dt), int(order), int(n_steps),
                                   p(psi), p(workspace), workspace.numel() * workspace.element_size(),
                                   p(norms) if norms is not None else None, C.c_void_p(stream)))
+
+
+def graph_orders(nbr: np.ndarray, hop: np.ndarray, onsite: np.ndarray, dt: float, tol: float,
+                 max_order: int = 64) -> np.ndarray:
+    """ctqw_graph_orders on host tables (the layouts of graph_evolve, FP64):
+    each realisation's a-priori Taylor order for the tolerance tol."""
+    lib = L.load()
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    hop = np.ascontiguousarray(hop, dtype=np.float64)
+    onsite = np.ascontiguousarray(np.atleast_2d(onsite), dtype=np.float64)
+    R, n = onsite.shape
+    width = nbr.shape[0]
+    if nbr.shape != (width, n) or hop.shape != (R, width, n):
+        raise ValueError("tables must be nbr [width, n], hop [R, width, n], onsite [R, n]")
+    out = np.zeros(R, dtype=np.int32)
+    p = lambda a: C.c_void_p(a.ctypes.data) if a.size else None  # noqa: E731
+    L.check(lib.ctqw_graph_orders(n, width, p(nbr), p(hop), p(onsite), R, float(dt), float(tol), int(max_order),
+                                  C.c_void_p(out.ctypes.data)))
+    return out

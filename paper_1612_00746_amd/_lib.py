@@ -104,6 +104,8 @@ SIGNATURES = {
     "ctqw_density_workspace": (C.c_int, [PlanP, C.c_int32, i64p]),
     "ctqw_set_telegraph": (C.c_int, [PlanP, C.c_double, C.c_double, C.c_uint64]),
     "ctqw_density_matrix": (C.c_int, [PlanP, C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64]),
+    "ctqw_graph_orders": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                                    C.c_double, C.c_int32, C.c_void_p]),
     "ctqw_graph_workspace": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, i64p]),
     "ctqw_graph_evolve": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                     C.c_double, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,

@@ -1289,6 +1289,47 @@ ctqw_status ctqw_graph_workspace(int32_t n_nodes, int32_t R, int32_t dtype, int6
     return CTQW_OK;
 }
 
+ctqw_status ctqw_graph_orders(int32_t n_nodes, int32_t width, const int32_t* nbr, const double* hop,
+                              const double* onsite, int32_t R, double dt, double tol, int32_t max_order,
+                              int32_t* orders) {
+    if (n_nodes < 1 || R < 1 || width < 0)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "n_nodes, R must be positive and width >= 0");
+    if (!onsite || !orders || (width > 0 && (!nbr || !hop))) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL argument");
+    if (!std::isfinite(dt) || !(tol > 0.0) || !std::isfinite(tol))
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "dt must be finite and tol positive");
+    if (max_order < 1 || max_order > 64) return fail(nullptr, CTQW_ERR_INVALID_ARG, "max_order must be in 1..64");
+    const int64_t n = n_nodes;
+    for (int64_t r = 0; r < R; ++r) {
+        // Gershgorin: ||H_r||_2 <= max_i (|H_ii| + sum_k |H_i,nbr(k,i)|)
+        double G = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double row = std::fabs(onsite[r * n + i]);
+            for (int64_t k = 0; k < width; ++k) {
+                const int32_t j = nbr[k * n + i];
+                if (j >= 0 && j < n_nodes) row += std::fabs(hop[(r * width + k) * n + i]);
+            }
+            if (!std::isfinite(row)) return fail(nullptr, CTQW_ERR_INVALID_ARG, "non-finite table entry");
+            G = std::max(G, row);
+        }
+        const double x = std::fabs(dt) * G;
+        // smallest n with x^(n+1)/(n+1)! / (1 - x/(n+2)) <= tol
+        double term = x;   // x^(n+1)/(n+1)! for n = 0
+        int32_t ord = 0;
+        for (int32_t k = 1; k <= max_order; ++k) {
+            term *= x / (double)(k + 1);
+            if (x < k + 2 && term / (1.0 - x / (k + 2)) <= tol) {
+                ord = k;
+                break;
+            }
+        }
+        if (ord == 0)
+            return fail(nullptr, CTQW_ERR_NOT_CONVERGED, "realisation %lld needs more than %d terms (x = %g)",
+                        (long long)r, max_order, x);
+        orders[r] = ord;
+    }
+    return CTQW_OK;
+}
+
 ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr, const void* hop, const void* onsite,
                               int32_t R, int32_t dtype, double dt, int32_t order, int64_t n_steps, void* psi,
                               void* workspace, int64_t workspace_bytes, double* norms, void* hip_stream) {

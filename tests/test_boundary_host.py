@@ -476,3 +476,41 @@ def test_pair_tables_rebuild_the_oracle_pair_hamiltonian(statistics):
                     M[i, nbr[k, i]] += hop[r, k, i]
         ref = G.pair_hamiltonian(12, bonds, J[r], eps[r], U[r], statistics).toarray()
         assert np.allclose(M, ref, atol=1e-15)
+
+
+def _rule_order(x, tol):
+    n = 1
+    while True:
+        if x < n + 2 and x ** (n + 1) / math.factorial(n + 1) / (1 - x / (n + 2)) <= tol:
+            return n
+        n += 1
+
+
+@pytest.mark.parametrize("statistics", [None, "distinguishable", "boson"])
+def test_graph_orders_follow_the_gershgorin_rule(statistics):
+    """Orders of a noisy 5 x 4 lattice (one particle, or two with U)
+    against the documented rule evaluated on the oracle's dense H
+    (x = dt * largest absolute row sum)."""
+    from paper_1612_00746_amd import ell_tables, graph_orders, lattice_edges, pair_tables
+    from oracle import graph as G
+    g = np.random.default_rng(11)
+    edges = lattice_edges((5, 4))
+    bonds = [tuple(e) for e in edges.tolist()]
+    R, n, dt, tol = 4, 20, 0.07, 1e-9
+    J = (1 + 0.3 * g.standard_normal((R, len(edges)))) * g.uniform(0.5, 2.0, (R, 1))
+    eps, U = g.uniform(-1, 1, (R, n)), g.uniform(0, 3, R)
+    if statistics is None:
+        nbr, hop = ell_tables(n, edges, J)
+        onsite = eps
+        Hs = [G.hamiltonian(n, bonds, J[r], eps[r]) for r in range(R)]
+    else:
+        nbr, hop, onsite = pair_tables(n, edges, J, eps, U, statistics)
+        Hs = [G.pair_hamiltonian(n, bonds, J[r], eps[r], U[r], statistics) for r in range(R)]
+    got = graph_orders(nbr, hop, onsite, dt, tol)
+    want = [_rule_order(dt * float(np.abs(H.toarray()).sum(axis=1).max()), tol) for H in Hs]
+    assert list(got) == want
+    assert len(set(want)) >= 2
+    from paper_1612_00746_amd import CtqwError
+    with pytest.raises(CtqwError) as e:
+        graph_orders(nbr, hop, onsite, dt, tol, max_order=min(want) - 1)
+    assert e.value.status == 5

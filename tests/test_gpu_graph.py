@@ -203,3 +203,36 @@ def test_complex64_two_bosons_on_a_lattice():
         worst = max(worst, float(np.max(np.abs(got[r] - ref))))
     say(f"  max |psi - oracle| = {worst:.2e}")
     assert worst <= 2e-6
+
+
+def test_a_priori_orders_meet_the_tolerance():
+    """With each realisation's a-priori order (ctqw_graph_orders) the
+    evolution stays within steps * tol of the exact one (the oracle's
+    eigendecomposition), realisation by realisation run at its own order,
+    on two bosons with U on a 6 x 5 lattice."""
+    import torch
+    from paper_1612_00746_amd import graph_evolve, graph_orders, lattice_edges, pair_tables
+    n, R, dt, tol, steps = 30, 3, 0.05, 1e-10, 20
+    g = np.random.default_rng(75)
+    edges = lattice_edges((6, 5))
+    J = (1.0 + 0.1 * g.standard_normal((R, len(edges)))) * np.array([[0.6], [1.0], [1.8]])
+    eps = g.uniform(-0.5, 0.5, (R, n))
+    U = g.uniform(0.5, 2.0, R)
+    nbr, hop, onsite = pair_tables(n, edges, J, eps, U, "boson")
+    orders = graph_orders(nbr, hop, onsite, dt, tol)
+    say(f"case: a-priori graph orders {list(orders)} for tol {tol}")
+    assert len(set(orders.tolist())) >= 2
+    D = nbr.shape[1]
+    psi0 = random_states(R, D, 76)
+    bonds = [tuple(e) for e in edges.tolist()]
+    nbr_d = torch.from_numpy(nbr).cuda()
+    for r in range(R):
+        psi = torch.from_numpy(psi0[r:r + 1].copy()).cuda()
+        graph_evolve(nbr_d, torch.from_numpy(np.ascontiguousarray(hop[r:r + 1])).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(onsite[r:r + 1])).cuda(), psi, dt, int(orders[r]), steps)
+        torch.cuda.synchronize()
+        H = G.pair_hamiltonian(n, bonds, J[r], eps[r], U[r], "boson")
+        exact = P.EDPropagator(H).evolve(psi0[r], dt * steps)
+        err = float(np.linalg.norm(psi.cpu().numpy()[0] - exact))
+        say(f"  r={r} order {orders[r]}: ||psi - exact|| = {err:.2e} (bound {steps * tol:.1e})")
+        assert err <= steps * tol + 1e-12
