@@ -12,7 +12,8 @@ Pins in tests/test_oracle_pins.py: the clean lattice spectra against the
 closed forms (sums of 2 cos(pi k / (N + 1)) over the axes, open; sums of
 2 cos(2 pi k / N), periodic), node degrees, symmetry, the two-node closed
 form; for two particles, the non-interacting spectra (sums of one-particle
-eigenvalues) and, on a chain, the pinned many-particle chain Hamiltonian.
+eigenvalues: ordered pairs, pairs i <= j for bosons, i < j for fermions)
+and, on a chain, the pinned many-particle chain Hamiltonian.
 """
 
 from __future__ import annotations
@@ -56,12 +57,28 @@ def hamiltonian(n, bonds, J, eps):
     return H.tocsr()
 
 
+FERMION = "fermion"
+
+
+def antisymmetrizer(n):
+    """Isometry from the two-fermion states to the n^2 grid: column k, for
+    the k-th pair a < b in lexicographic order, is (|a b> - |b a>) / sqrt 2
+    (row-major grid index a * n + b)."""
+    A, B = np.triu_indices(n, 1)
+    k = np.arange(len(A))
+    rows = np.concatenate([A * n + B, B * n + A])
+    vals = np.concatenate([np.full(len(A), 1 / np.sqrt(2)), np.full(len(A), -1 / np.sqrt(2))])
+    return sp.csr_matrix((vals, (rows, np.concatenate([k, k]))), shape=(n * n, len(A)))
+
+
 def pair_hamiltonian(n, bonds, J, eps, U, statistics):
     """Two particles on the graph (Eq. 1 with m = 2): the one-particle H
     acting on either particle, H1 x 1 + 1 x H1, plus U on the states with
     both particles on one node (on-site interaction).  Distinguishable:
     the n^2 grid in row-major order; bosons: S^T H S with the symmetrising
-    isometry of ``basis.symmetrizer`` (sorted pairs, lexicographic)."""
+    isometry of ``basis.symmetrizer`` (sorted pairs, lexicographic);
+    fermions: the same with the antisymmetrising isometry (pairs a < b,
+    lexicographic), where U drops out since no node holds two."""
     from .basis import BOSON, symmetrizer
     H1 = hamiltonian(n, bonds, J, eps)
     one = sp.identity(n, format="csr")
@@ -70,5 +87,8 @@ def pair_hamiltonian(n, bonds, J, eps, U, statistics):
     H = (H + sp.diags(U * double)).tocsr()
     if statistics == BOSON:
         S = symmetrizer(n, 2)
+        H = (S.T @ H @ S).tocsr()
+    elif statistics == FERMION:
+        S = antisymmetrizer(n)
         H = (S.T @ H @ S).tocsr()
     return H

@@ -15,6 +15,7 @@ import mpmath
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 import scipy.special as ss
 
 from oracle import basis as B
@@ -551,3 +552,45 @@ def test_graph_pair_on_a_chain_is_the_chain_hamiltonian(statistics, periodic):
     ref = Hm.hamiltonian(N, 2, Jb, eps, U, statistics, Hm.PERIODIC if periodic else Hm.OPEN, Hm.ONSITE).toarray()
     got = G.pair_hamiltonian(N, bonds, J, eps, U, statistics).toarray()
     assert np.allclose(got, ref, atol=1e-15)
+
+
+def test_graph_two_fermion_non_interacting_spectrum():
+    """Two fermions, noisy 3 x 4 lattice (plaquettes, so exchange signs
+    matter): the eigenvalues are e_i + e_j over pairs i < j of distinct
+    one-particle eigenvalues, and U has no effect.  Dropping the exchange
+    sign of the antisymmetriser (the boson-like isometry on pairs a < b)
+    gives another spectrum."""
+    g = np.random.default_rng(18)
+    bonds = G.lattice_bonds((3, 4))
+    J, eps = 1 + 0.2 * g.standard_normal(len(bonds)), g.uniform(-0.5, 0.5, 12)
+    e = np.linalg.eigvalsh(G.hamiltonian(12, bonds, J, eps).toarray())
+    i, j = np.triu_indices(12, 1)
+    want = np.sort(e[i] + e[j])
+    for U in (0.0, 2.7):
+        H = G.pair_hamiltonian(12, bonds, J, eps, U, G.FERMION).toarray()
+        assert H.shape == (66, 66)
+        assert np.allclose(np.linalg.eigvalsh(H), want, atol=1e-12)
+    S = abs(G.antisymmetrizer(12))
+    H1 = G.hamiltonian(12, bonds, J, eps)
+    one = sp.identity(12, format="csr")
+    wrong = (S.T @ (sp.kron(H1, one) + sp.kron(one, H1)) @ S).toarray()
+    assert not np.allclose(np.linalg.eigvalsh(wrong), want, atol=1e-6)
+
+
+def test_graph_two_fermion_evolution_is_antisymmetric_on_the_grid():
+    """Evolving the antisymmetric grid state with the distinguishable pair
+    H keeps psi(a, b) = -psi(b, a), and equals the fermion-sector evolution
+    mapped back through the antisymmetriser."""
+    g = np.random.default_rng(19)
+    bonds = G.lattice_bonds((3, 3), periodic=True)
+    J, eps = 1 + 0.3 * g.standard_normal(len(bonds)), g.uniform(-1, 1, 9)
+    S = G.antisymmetrizer(9)
+    c = g.standard_normal(S.shape[1]) + 1j * g.standard_normal(S.shape[1])
+    c /= np.linalg.norm(c)
+    Hd = G.pair_hamiltonian(9, bonds, J, eps, 0.0, B.DISTINGUISHABLE)
+    Hf = G.pair_hamiltonian(9, bonds, J, eps, 0.0, G.FERMION)
+    full, _, _ = P.evolve_taylor(Hd, S @ c, 0.02, 40, tol=1e-16)
+    sector, _, _ = P.evolve_taylor(Hf, c, 0.02, 40, tol=1e-16)
+    grid = full.reshape(9, 9)
+    assert np.allclose(grid, -grid.T, atol=1e-13)
+    assert np.allclose(full, S @ sector, atol=1e-13)
