@@ -421,8 +421,12 @@ def pair_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: np.ndarray,
     bond; in the boson sector a move between a doubly occupied node pair
     (a, a) and a pair (a, c) carries sqrt(2) J, split over the two slots of
     the diagonal state.  On-site energies add, and U acts on double
-    occupation.  J [R, E], eps [R, n], U [R].  Returns nbr int32 [2 width,
-    D], hop float64 [R, 2 width, D] and onsite float64 [R, D]."""
+    occupation.  Fermions: the pairs a < b in lexicographic order, each the
+    normalised antisymmetric state; a move onto the other particle's node is
+    absent, and one that carries the mover past the other particle's node
+    (so the pair's order flips) carries -J; U drops out.  J [R, E], eps
+    [R, n], U [R].  Returns nbr int32 [2 width, D], hop float64 [R, 2 width,
+    D] and onsite float64 [R, D]."""
     J = np.atleast_2d(np.asarray(J, dtype=np.float64))
     eps = np.atleast_2d(np.asarray(eps, dtype=np.float64))
     U = np.atleast_1d(np.asarray(U, dtype=np.float64))
@@ -438,6 +442,10 @@ def pair_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: np.ndarray,
         A, B = np.triu_indices(n)
         # position of the sorted pair (a, b), a <= b, in lexicographic order
         index = lambda a, b: (lambda lo, hi: lo * n - lo * (lo - 1) // 2 + (hi - lo))(np.minimum(a, b), np.maximum(a, b))  # noqa: E731
+    elif statistics == "fermion":
+        A, B = np.triu_indices(n, 1)
+        # position of the pair (lo, hi), lo < hi, in lexicographic order
+        index = lambda a, b: (lambda lo, hi: lo * n - lo * (lo + 1) // 2 + (hi - lo - 1))(np.minimum(a, b), np.maximum(a, b))  # noqa: E731
     else:
         raise ValueError(f"unknown statistics {statistics!r}")
     D = len(A)
@@ -448,11 +456,15 @@ def pair_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: np.ndarray,
         for half, (mover, still) in enumerate(((A, B), (B, A))):
             c = nbr1[k, mover]
             ok = c >= 0
+            if statistics == "fermion":
+                ok &= c != still
             cc = np.where(ok, c, 0)
             tgt = np.where(ok, index(cc, still) if half == 0 else index(still, cc), -1)
             f = np.ones(D)
             if statistics == "boson":
                 f = np.where(A == B, 1 / np.sqrt(2), np.where(c == still, np.sqrt(2), 1.0))
+            elif statistics == "fermion":
+                f = np.where((c < still) == (mover < still), 1.0, -1.0)
             nbr[half * w + k] = tgt
             bond[half * w + k] = np.where(ok, bond1[k, mover], -1)
             fac[half * w + k] = np.where(ok, f, 0.0)

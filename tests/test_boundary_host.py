@@ -453,7 +453,7 @@ def test_graph_evolve_validation(kw, status):
     assert lib.ctqw_graph_workspace(8, 2, 0, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 8
 
 
-@pytest.mark.parametrize("statistics", ["distinguishable", "boson"])
+@pytest.mark.parametrize("statistics", ["distinguishable", "boson", "fermion"])
 def test_pair_tables_rebuild_the_oracle_pair_hamiltonian(statistics):
     """Two particles on a 3 x 4 lattice with noise and U: the pair-graph
     tables, read back as a matrix (ELL slots summed, on-site on the
@@ -486,7 +486,7 @@ def _rule_order(x, tol):
         n += 1
 
 
-@pytest.mark.parametrize("statistics", [None, "distinguishable", "boson"])
+@pytest.mark.parametrize("statistics", [None, "distinguishable", "boson", "fermion"])
 def test_graph_orders_follow_the_gershgorin_rule(statistics):
     """Orders of a noisy 5 x 4 lattice (one particle, or two with U)
     against the documented rule evaluated on the oracle's dense H

@@ -127,14 +127,14 @@ def test_zero_steps_leave_the_state():
     assert np.array_equal(psi.cpu().numpy(), psi0)
 
 
-@pytest.mark.parametrize("statistics", ["distinguishable", "boson"])
+@pytest.mark.parametrize("statistics", ["distinguishable", "boson", "fermion"])
 @pytest.mark.parametrize("side1,side2,order,steps", [(6, 5, 8, 30), (15, 15, 10, 10)])
 def test_two_particles_on_a_lattice(statistics, side1, side2, order, steps):
     """Two interacting walkers on a q = 2 lattice (15 x 15 is the paper's
-    capacity example: 50625 distinguishable or 25425 boson pair states),
-    run as one particle on the pair graph: within 1e-12 of the oracle's
-    Taylor map of its own two-particle H (Kronecker sum plus U, symmetrised
-    for bosons)."""
+    capacity example: 50625 distinguishable, 25425 boson or 25200 fermion
+    pair states), run as one particle on the pair graph: within 1e-12 of
+    the oracle's Taylor map of its own two-particle H (Kronecker sum plus
+    U, symmetrised for bosons, antisymmetrised for fermions)."""
     import torch
     from paper_1612_00746_amd import graph_evolve, lattice_edges, pair_tables
     n = side1 * side2
