@@ -243,7 +243,9 @@ ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
  * statically noisy realisations sharing one topology, advanced n_steps
  * times by the order-n Taylor polynomial of exp(-i H dt) (Eqs. 5-7), one
  * pass over the batch per term.  Two particles on a graph are one particle
- * on the pair graph (the binding builds its tables).  Stateless: no plan.
+ * on the pair graph (the binding builds its tables: distinguishable, boson
+ * or fermion pairs; a fermion move that flips the pair's order carries a
+ * negative weight, so hop values may take either sign).  Stateless: no plan.
  * dtype CTQW_C128: complex128 states, FP64 tables and arithmetic;
  * CTQW_C64: complex64 states, FP32 tables and arithmetic, plain sums.
  *   nbr     device int32 [width][n_nodes]: neighbour of node i in slot k is
