@@ -49,7 +49,7 @@ typedef enum {
 } ctqw_status;
 
 /* Particle statistics (Sec. 1 of the paper: walks depend on statistics). */
-typedef enum { CTQW_DISTINGUISHABLE = 0, CTQW_BOSON = 1 } ctqw_statistics;
+typedef enum { CTQW_DISTINGUISHABLE = 0, CTQW_BOSON = 1, CTQW_FERMION = 2 } ctqw_statistics;
 /* Open chain (N-1 bonds) or ring (N bonds, bond N-1 joins node N-1 to 0). */
 typedef enum { CTQW_OPEN = 0, CTQW_PERIODIC = 1 } ctqw_boundary;
 /* Interaction energy V(x) added to the diagonal of H:
@@ -144,7 +144,9 @@ typedef struct {
  * problem, computes the state layout.  No device is touched.
  * Errors: INVALID_ARG (NULL, m not in 1..3, N < 2, periodic with N < 3,
  * non-finite or non-positive dt, order and tol both unset, bad enums),
- * UNSUPPORTED (m == 3, bosons with m != 2 or periodic), OUT_OF_MEMORY.   */
+ * UNSUPPORTED (m == 3 unless distinguishable with one lattice size
+ * N <= 1024; bosons or fermions with m != 2 or on a ring; R > 65535),
+ * OUT_OF_MEMORY.                                                           */
 ctqw_status ctqw_plan_create(const ctqw_problem* problem, ctqw_plan** out);
 ctqw_status ctqw_plan_destroy(ctqw_plan* plan);
 

@@ -15,12 +15,12 @@ from typing import Optional, Sequence
 import numpy as np
 
 from . import _lib as L
-from ._lib import (ACC_KAHAN, ACC_PLAIN, BOSON, C64, C128, DISTINGUISHABLE, INT_NEAREST,  # noqa: F401
+from ._lib import (ACC_KAHAN, ACC_PLAIN, BOSON, C64, C128, DISTINGUISHABLE, FERMION, INT_NEAREST,  # noqa: F401
                    INT_ONSITE, OBS_OCCUPATION, OBS_PAIR, OPEN, PERIODIC, RK4_ORDER, CtqwError)
 
 __all__ = ["Plan", "CtqwError", "make_problem"]
 
-_STAT = {"distinguishable": DISTINGUISHABLE, "boson": BOSON}
+_STAT = {"distinguishable": DISTINGUISHABLE, "boson": BOSON, "fermion": FERMION}
 _BC = {"open": OPEN, "periodic": PERIODIC}
 _INT = {"onsite": INT_ONSITE, "nearest": INT_NEAREST}
 _DT = {"c64": C64, "c128": C128}

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libctqw.so")
 # enums / flags (mirror include/ctqw.h)
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_NOT_CONVERGED, \
     ERR_NUMERICAL, ERR_STATE = range(8)
-DISTINGUISHABLE, BOSON = 0, 1
+DISTINGUISHABLE, BOSON, FERMION = 0, 1, 2
 OPEN, PERIODIC = 0, 1
 INT_ONSITE, INT_NEAREST = 0, 1
 C64, C128 = 0, 1

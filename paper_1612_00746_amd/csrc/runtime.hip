@@ -526,9 +526,9 @@ ctqw_status grid_for(ctqw_plan* p, StepConfig& c, int* n_waves, int64_t n_items 
         *n_waves = (int)n_items;
         return CTQW_OK;
     }
-    // claims count in units of 64 (one per lane) in an int32 counter
-    if (n_items >= (int64_t(1) << 25))
-        return fail(p, CTQW_ERR_UNSUPPORTED, "persistent launch takes at most 2^25 work items per step");
+    // one claim per group plus one final claim per block in an int32 counter
+    if (n_items >= (int64_t(1) << 30))
+        return fail(p, CTQW_ERR_UNSUPPORTED, "persistent launch takes at most 2^30 work items per step");
     int per_cu = 0;
     if (p->chunk) HIP_TRY(p, chunk_occupancy(c, &per_cu));
     else HIP_TRY(p, step_occupancy(c, &per_cu));
@@ -948,8 +948,10 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
     if (!pr || !out) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL problem or output pointer");
     *out = nullptr;
     if (pr->m < 1 || pr->m > 3) return fail(nullptr, CTQW_ERR_INVALID_ARG, "m must be 1, 2 or 3 (got %d)", pr->m);
-    if (pr->statistics != CTQW_DISTINGUISHABLE && pr->statistics != CTQW_BOSON)
+    if (pr->statistics != CTQW_DISTINGUISHABLE && pr->statistics != CTQW_BOSON && pr->statistics != CTQW_FERMION)
         return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown statistics %d", pr->statistics);
+    if (pr->statistics == CTQW_FERMION)
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "fermions on the chain path are not built (use the pair graph)");
     if (pr->interaction != CTQW_INT_ONSITE && pr->interaction != CTQW_INT_NEAREST)
         return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown interaction %d", pr->interaction);
     if (pr->boundary != CTQW_OPEN && pr->boundary != CTQW_PERIODIC)

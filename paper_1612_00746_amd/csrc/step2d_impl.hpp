@@ -665,13 +665,13 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 // then read by one CU at about the same time).  Regular: block b takes
 // group b and the hardware hands out the blocks.  Persistent (a grid of
 // resident blocks): block b starts on group b and then claims the next
-// groups from a counter that the host zeroes before the launch.  Wave 0
-// makes the claim with all lanes adding 1 at the same address, which the
-// compiler folds into one atomic add of 64 from one lane (a claim is
-// counter / 64); lane 0 passes it to the block through LDS (two slots used
-// alternately, so a slot is rewritten only after every wave has passed the
-// next barrier) and every wave reads it back with readfirstlane, so the loop
-// bound is uniform over the block and every wave meets every barrier.
+// groups from a counter that the host zeroes before the launch.  Lane 0 of
+// wave 0 alone adds 1 to the counter (one claim per add, whatever the
+// compiler does with atomics of several lanes) and passes the old value to
+// the block through LDS (two slots used alternately, so a slot is rewritten
+// only after every wave has passed the next barrier); every wave reads it
+// back with readfirstlane, so the loop bound is uniform over the block and
+// every wave meets every barrier.
 // Claims grow monotonically and each block leaves after at most one claim
 // past the last group.  Static assignments of items to waves (round-robin,
 // longest-processing-time) ran 20 % slower: the resident waves do not all
@@ -714,10 +714,7 @@ __global__ void __launch_bounds__(256, (min_blocks_per_cu<T, NT, P, CHUNK>())) s
             }
         }
         if (!a.persistent) break;
-        if (wv == 0) {
-            const int t = atomicAdd(a.claim, 1);
-            if (lane == 0) next_group[it & 1] = __builtin_amdgcn_readfirstlane(t) / 64;
-        }
+        if (wv == 0 && lane == 0) next_group[it & 1] = atomicAdd(a.claim, 1);
         __syncthreads();
         g = n_blocks + __builtin_amdgcn_readfirstlane(next_group[it & 1]);
     }

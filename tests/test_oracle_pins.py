@@ -446,6 +446,88 @@ def test_density_matrix_properties():
     assert np.allclose(mixed @ mixed, mixed / 2, atol=1e-15) and not np.allclose(mixed @ mixed, mixed)
 
 
+def test_density_matrix_orientation():
+    """Eq. 2 puts the ket on the left: rho = |psi><psi|, rho[a, b] = psi_a
+    conj(psi_b).  The mistake rho^T = conj(rho) passes every check above;
+    these fail for it: a known off-diagonal phase (psi = (1, i)/sqrt(2)
+    gives rho[0, 1] = -i/2), rho |psi> = |psi> for a complex pure state, and
+    <phi|rho|phi> = (1/R) sum_r |<phi|psi_r>|^2 for a complex phi."""
+    from oracle import observables as O
+    rho = O.density_matrix([np.array([1.0, 1j]) / math.sqrt(2.0)])
+    assert abs(rho[0, 1] - (-0.5j)) < 1e-15 and abs(rho[1, 0] - 0.5j) < 1e-15
+    g = np.random.default_rng(17)
+    v = g.standard_normal(9) + 1j * g.standard_normal(9)
+    v /= np.linalg.norm(v)
+    pure = O.density_matrix([v])
+    assert np.max(np.abs(pure @ v - v)) < 1e-15
+    assert np.max(np.abs(pure.T @ v - v)) > 1e-2        # the transposed matrix fails
+    states = []
+    for _ in range(5):
+        s = g.standard_normal(9) + 1j * g.standard_normal(9)
+        states.append(s / np.linalg.norm(s))
+    rho = O.density_matrix(states)
+    phi = g.standard_normal(9) + 1j * g.standard_normal(9)
+    lhs = np.vdot(phi, rho @ phi)
+    rhs = math.fsum(abs(np.vdot(phi, s)) ** 2 for s in states) / len(states)
+    assert abs(lhs.imag) < 1e-14 and abs(lhs.real - rhs) < 1e-13
+    assert abs(np.vdot(phi, rho.T @ phi).real - rhs) > 1e-3
+
+
+def _tele_case():
+    """Two distinguishable walkers on a 7-node chain (49 states) with noisy
+    baselines, for the telegraph pins."""
+    g = np.random.default_rng(23)
+    N = 7
+    Jbar = 1 + 0.1 * g.standard_normal(N - 1)
+    eps = g.uniform(-0.3, 0.3, N)
+    U = 0.8
+    build = lambda J: Hm.hamiltonian(N, 2, J, eps, U)  # noqa: E731
+    psi0 = B.product_state(N, [2, 4])
+    return N, Jbar, eps, U, build, psi0
+
+
+def test_telegraph_evolve_reductions():
+    """Eq. 1 with switching terms reduces to the static problem: rate 0 is
+    the static evolution at Jbar + a s_init (s_init the initial signs), and
+    amplitude 0 the static evolution at Jbar, both against
+    ``evolve_taylor`` of the same order (pins that evolve applies the
+    signs to the hoppings, scaled by a, and nothing else)."""
+    from oracle import telegraph as T
+    N, Jbar, eps, U, build, psi0 = _tele_case()
+    dt, steps, order, a, seed, r = 0.05, 12, 10, 0.3, 9, 2
+    s_init = T.sign_history(seed, r, N - 1, 1, 0.0)[0]
+    assert set(np.unique(s_init)) == {-1.0, 1.0}            # both signs present: a real test
+    got = T.evolve(build, Jbar, psi0, dt, steps, order, a, 0.0, seed, r)
+    ref, _, _ = P.evolve_taylor(build(Jbar + a * s_init), psi0, dt, steps, order=order)
+    assert np.max(np.abs(got - ref)) < 1e-15
+    got0 = T.evolve(build, Jbar, psi0, dt, steps, order, 0.0, 5.0, seed, r)
+    ref0, _, _ = P.evolve_taylor(build(Jbar), psi0, dt, steps, order=order)
+    assert np.max(np.abs(got0 - ref0)) < 1e-15
+    # and a static flip pattern is not a no-op: J differs from Jbar by a
+    assert np.max(np.abs(got - ref0)) > 1e-3
+
+
+def test_telegraph_flip_applies_at_the_start_of_its_step():
+    """Flip probability 1 (infinite rate): the signs in force during step 0
+    are already the flipped initial signs, then they alternate.  Two steps
+    equal one exact step at Jbar - a s_init followed by one at Jbar + a s_init
+    (each step against scipy's Pade expm of the dense H, order 30 so the
+    Taylor remainder is far below rounding)."""
+    from oracle import telegraph as T
+    N, Jbar, eps, U, build, psi0 = _tele_case()
+    dt, a, seed, r = 0.05, 0.25, 4, 1
+    assert T.flip_probability(math.inf, dt) == 1.0
+    s_init = T.sign_history(seed, r, N - 1, 1, 0.0)[0]
+    got = T.evolve(build, Jbar, psi0, dt, 2, 30, a, math.inf, seed, r)
+    H0 = build(Jbar - a * s_init).toarray()
+    H1 = build(Jbar + a * s_init).toarray()
+    ref = sla.expm(-1j * dt * H1) @ (sla.expm(-1j * dt * H0) @ psi0)
+    assert np.max(np.abs(got - ref)) < 1e-14
+    # the reading "flip at the end of the step" gives the other order
+    wrong = sla.expm(-1j * dt * H0) @ (sla.expm(-1j * dt * H1) @ psi0)
+    assert np.max(np.abs(wrong - ref)) > 1e-6
+
+
 def test_telegraph_sign_process():
     """The switching signs: rate 0 keeps the initial signs, flip
     probability 1 alternates them every step, the initial signs are about
