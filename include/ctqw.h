@@ -138,6 +138,11 @@ typedef struct {
                                 fraction of it that needs no more bands than
                                 unaligned boundaries is taken (0: bands as
                                 wide as the halo allows) */
+    int32_t terms_per_pass;  /* three particles: Taylor terms chained per pass
+                                over the state, 1..3 (0: 3 for complex64, 2
+                                for complex128); a step of n terms is
+                                ceil(n / K) passes, the last taking the
+                                remaining terms.  Ignored for m < 3.       */
 } ctqw_launch;
 
 /* Create a plan from a problem statement.  Host only: validates the
@@ -245,9 +250,9 @@ ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
  * statically noisy realisations sharing one topology, advanced n_steps
  * times by the order-n Taylor polynomial of exp(-i H dt) (Eqs. 5-7), one
  * pass over the batch per term.  Two particles on a graph are one particle
- * on the pair graph (the binding builds its tables: distinguishable, boson
- * or fermion pairs; a fermion move that flips the pair's order carries a
- * negative weight, so hop values may take either sign).  Stateless: no plan.
+ * on the pair graph (ctqw_graph_tables builds its tables: distinguishable,
+ * boson or fermion pairs; a fermion move that flips the pair's order carries
+ * a negative weight, so hop values may take either sign).  Stateless: no plan.
  * dtype CTQW_C128: complex128 states, FP64 tables and arithmetic;
  * CTQW_C64: complex64 states, FP32 tables and arithmetic, plain sums.
  *   nbr     device int32 [width][n_nodes]: neighbour of node i in slot k is
@@ -271,6 +276,36 @@ ctqw_status ctqw_layout(const ctqw_plan* plan, int64_t* offsets);
  * default); psi, the tables and the workspace must stay valid until the
  * work has run.  Errors: INVALID_ARG (non-positive sizes, unknown dtype,
  * NULL, non-finite dt, order out of range, workspace too small), DEVICE.  */
+/* Tables of ctqw_graph_evolve from an undirected bond list (Sec. 2: each
+ * node couples to its own neighbours; Eq. 1 with equal rates both ways),
+ * built on the host.  edges: int32 [n_edges][2] node pairs (no self-loops,
+ * no repeated bonds); J: [R][n_edges] bond couplings, eps: [R][n_nodes]
+ * on-site energies, U: [R] on-site interaction (m == 2; NULL for m == 1).
+ *   m = 1: states are the nodes; every bond fills one slot of both of its
+ *          nodes, in bond order (first endpoint first); width = the
+ *          largest degree.
+ *   m = 2: one particle on the pair graph.  States: ordered pairs (a, b) at
+ *          a * n + b (DISTINGUISHABLE); pairs a <= b in lexicographic order,
+ *          each the normalised symmetric state (BOSON); pairs a < b, each the
+ *          normalised antisymmetric state (FERMION).  Either particle moves
+ *          along one of its node's slots (width = 2 x the one-particle
+ *          width: slots of the first particle, then of the second).  Bosons:
+ *          a move between (a, a) and (a, c) carries sqrt(2) J, split as
+ *          J / sqrt(2) over the two slots of the diagonal state.  Fermions: a
+ *          move onto the other particle's node is absent, and one that
+ *          carries the mover past the other particle (the pair's order
+ *          flips) carries -J.  On-site energies add; U sits on the states
+ *          with both particles on one node (none for fermions).
+ * Outputs (host, caller-allocated): n_states, width; then, unless nbr, hop
+ * and onsite are all NULL (a size query), nbr int32 [width][n_states] (-1
+ * in empty slots), hop double [R][width][n_states] (0 in empty slots),
+ * onsite double [R][n_states].  Errors: INVALID_ARG (sizes, NULL, a node
+ * out of range, self-loop, repeated bond, non-finite parameter),
+ * UNSUPPORTED (tables beyond 2^31 entries).                               */
+ctqw_status ctqw_graph_tables(int32_t n_nodes, int32_t n_edges, const int32_t* edges, int32_t m, int32_t statistics,
+                              int32_t R, const double* J, const double* eps, const double* U, int32_t* n_states,
+                              int32_t* width, int32_t* nbr, double* hop, double* onsite);
+
 /* A-priori Taylor orders for ctqw_graph_evolve, computed on the host from
  * host copies of its tables (same layouts, FP64): orders[r] is the smallest
  * n >= 1 with x^(n+1)/(n+1)! / (1 - x/(n+2)) <= tol, x = |dt| * G_r and
@@ -286,6 +321,25 @@ ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr
                               const void* onsite, int32_t R, int32_t dtype, double dt, int32_t order,
                               int64_t n_steps, void* psi, void* workspace, int64_t workspace_bytes,
                               double* norms, void* hip_stream);
+
+/* ctqw_graph_evolve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments and kernels without the workspace, whose
+ * role -- two term buffers and the partial sum, ctqw_graph_workspace bytes
+ * -- is taken by a fixed array of CTQW_GRAPH_STATIC_BYTES in device memory
+ * that the library holds on each device it runs on until the process
+ * ends.  The call allocates nothing (no hipMalloc, no allocating library
+ * routine).  Every call on one device shares that device's array, so
+ * calls that overlap on one device (other streams, other host threads)
+ * race; the caller serialises them.  The stream's device (the current
+ * device for the NULL stream) is the one used.
+ * Errors: as ctqw_graph_evolve; UNSUPPORTED (checked before any device
+ * call) when ctqw_graph_workspace(n_nodes, R, dtype) exceeds
+ * CTQW_GRAPH_STATIC_BYTES; DEVICE if the array's address cannot be found. */
+#define CTQW_GRAPH_STATIC_BYTES (64ll << 20)
+ctqw_status ctqw_graph_evolve_static(int32_t n_nodes, int32_t width, const int32_t* nbr, const void* hop,
+                                     const void* onsite, int32_t R, int32_t dtype, double dt, int32_t order,
+                                     int64_t n_steps, void* psi, double* norms, void* hip_stream);
 
 /* Device bytes the caller must provide: each of the two state buffers and
  * the workspace, for the current parameters and launch shape.             */

@@ -10,6 +10,10 @@ N^m-dimensional space, one amplitude per tuple of occupied nodes.
   x_1 <= ... <= x_m (lexicographic order), namely the normalised symmetric
   combination of all distinct permutations of that tuple.  ``symmetrizer``
   returns the explicit isometry S from this sector into the full N^m space.
+* Fermions: the exchange-antisymmetric sector.  One basis state per
+  strictly increasing tuple x_1 < ... < x_m (lexicographic order), the
+  normalised combination of all permutations P of the tuple with the sign
+  of P; ``antisymmetrizer`` returns the isometry into the full space.
 
 Test infrastructure only; see the package docstring.
 """
@@ -24,6 +28,7 @@ import scipy.sparse as sp
 
 DISTINGUISHABLE = "distinguishable"
 BOSON = "boson"
+FERMION = "fermion"
 
 
 def basis_states(N: int, m: int, statistics: str = DISTINGUISHABLE) -> np.ndarray:
@@ -36,6 +41,9 @@ def basis_states(N: int, m: int, statistics: str = DISTINGUISHABLE) -> np.ndarra
     if statistics == BOSON:
         rows = list(itertools.combinations_with_replacement(range(N), m))
         return np.asarray(rows, dtype=np.int64).reshape(len(rows), m)
+    if statistics == FERMION:
+        rows = list(itertools.combinations(range(N), m))
+        return np.asarray(rows, dtype=np.int64).reshape(len(rows), m)
     raise ValueError(f"unknown statistics {statistics!r}")
 
 
@@ -44,6 +52,8 @@ def dimension(N: int, m: int, statistics: str = DISTINGUISHABLE) -> int:
         return N ** m
     if statistics == BOSON:
         return math.comb(N + m - 1, m)
+    if statistics == FERMION:
+        return math.comb(N, m)
     raise ValueError(f"unknown statistics {statistics!r}")
 
 
@@ -75,10 +85,36 @@ def symmetrizer(N: int, m: int) -> sp.csr_matrix:
     return sp.csr_matrix((vals, (rows, cols)), shape=(N ** m, sym.shape[0]))
 
 
+def permutation_sign(seq) -> int:
+    """Sign of the permutation that sorts a sequence of distinct values
+    (by counting inversions)."""
+    seq = list(seq)
+    inv = sum(1 for i in range(len(seq)) for j in range(i + 1, len(seq)) if seq[i] > seq[j])
+    return -1 if inv % 2 else 1
+
+
+def antisymmetrizer(N: int, m: int) -> sp.csr_matrix:
+    """Isometry A (N^m x D_fermion) whose column k is the normalised
+    antisymmetric state of the k-th increasing tuple t: 1/sqrt(m!) times the
+    sign of P at each permuted tuple P(t); A^T A is the identity."""
+    fer = basis_states(N, m, FERMION)
+    rows, cols, vals = [], [], []
+    w = 1.0 / math.sqrt(math.factorial(m))
+    for k, t in enumerate(fer):
+        for p in itertools.permutations(tuple(int(v) for v in t)):
+            rows.append(int(full_index(np.asarray([p]), N)[0]))
+            cols.append(k)
+            vals.append(w * permutation_sign(p))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(N ** m, fer.shape[0]))
+
+
 def product_state(N: int, sites, statistics: str = DISTINGUISHABLE) -> np.ndarray:
     """Initial state with particle a on node sites[a] (complex128, in the
     basis of ``basis_states``).  For bosons the normalised symmetric state
-    of that occupation."""
+    of that occupation; for fermions the normalised antisymmetric state
+    (the Slater determinant of the occupied nodes, particle a on sites[a]),
+    whose coefficient on the sorted tuple is the sign of the permutation
+    that sorts ``sites``."""
     sites = [int(s) for s in sites]
     m = len(sites)
     if any(s < 0 or s >= N for s in sites):
@@ -88,8 +124,10 @@ def product_state(N: int, sites, statistics: str = DISTINGUISHABLE) -> np.ndarra
     if statistics == DISTINGUISHABLE:
         psi[int(full_index(np.asarray([sites]), N)[0])] = 1.0
         return psi
+    if statistics == FERMION and len(set(sites)) != m:
+        raise ValueError("two fermions on one node")
     key = tuple(sorted(sites))
-    states = basis_states(N, m, BOSON)
+    states = basis_states(N, m, statistics)
     hit = np.nonzero((states == np.asarray(key)).all(axis=1))[0]
-    psi[int(hit[0])] = 1.0
+    psi[int(hit[0])] = float(permutation_sign(sites)) if statistics == FERMION else 1.0
     return psi

@@ -17,7 +17,8 @@ where V counts interacting pairs,
     on-site:           V(x) = U * #{a<b : x_a == x_b}
     nearest-neighbour: V(x) = U * #{a<b : |x_a - x_b| == 1}
 (the nearest-neighbour form uses the chain distance, also across the
-periodic bond).  Bosons use H_S = S^T H S with S from ``basis.symmetrizer``.
+periodic bond).  Bosons use H_S = S^T H S with S from ``basis.symmetrizer``,
+fermions H_A = A^T H A with A from ``basis.antisymmetrizer``.
 
 Test infrastructure only; see the package docstring.
 """
@@ -27,7 +28,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .basis import BOSON, DISTINGUISHABLE, basis_states, symmetrizer
+from .basis import BOSON, DISTINGUISHABLE, FERMION, antisymmetrizer, basis_states, symmetrizer
 
 OPEN = "open"
 PERIODIC = "periodic"
@@ -106,6 +107,9 @@ def hamiltonian(N: int, m: int, J, eps, U: float, statistics: str = DISTINGUISHA
     if statistics == BOSON:
         S = symmetrizer(N, m)
         return (S.T @ H @ S).tocsr()
+    if statistics == FERMION:
+        A = antisymmetrizer(N, m)
+        return (A.T @ H @ A).tocsr()
     raise ValueError(f"unknown statistics {statistics!r}")
 
 

@@ -367,121 +367,63 @@ def lattice_edges(shape: Sequence[int], periodic: bool = False) -> np.ndarray:
     return np.concatenate(out).astype(np.int32)
 
 
-def _ell_topology(n_nodes: int, edges: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
-    """Slots of an undirected bond list: nbr int32 [width, n] (-1 empty) and
-    the bond that fills each slot, int64 [width, n] (-1 empty)."""
-    edges = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
-    if len(edges) and (edges.min() < 0 or edges.max() >= n_nodes):
-        raise ValueError("bond endpoint out of range")
-    if np.any(edges[:, 0] == edges[:, 1]):
-        raise ValueError("self-loops belong to the on-site energies")
-    key = np.minimum(edges[:, 0], edges[:, 1]) * n_nodes + np.maximum(edges[:, 0], edges[:, 1])
-    if len(np.unique(key)) != len(key):
-        raise ValueError("repeated bond")
-    ends = np.concatenate([edges[:, 0], edges[:, 1]])       # node that owns the slot
-    other = np.concatenate([edges[:, 1], edges[:, 0]])
-    bond = np.concatenate([np.arange(len(edges))] * 2)
-    order = np.argsort(bond * 2 + np.repeat([0, 1], len(edges)), kind="stable")   # bond order, a-end first
-    ends, other, bond = ends[order], other[order], bond[order]
-    deg = np.bincount(ends, minlength=n_nodes)
-    width = int(deg.max()) if len(edges) else 0
-    slot = np.zeros(len(ends), dtype=np.int64)
-    fill = np.zeros(n_nodes, dtype=np.int64)
-    for t, a in enumerate(ends):
-        slot[t] = fill[a]
-        fill[a] += 1
-    nbr = np.full((width, n_nodes), -1, dtype=np.int32)
-    nbr[slot, ends] = other
-    bond_of = np.full((width, n_nodes), -1, dtype=np.int64)
-    bond_of[slot, ends] = bond
-    return nbr, bond_of
+def graph_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: Optional[np.ndarray] = None,
+                 U: Optional[np.ndarray] = None, m: int = 1,
+                 statistics: str = "distinguishable") -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """ctqw_graph_tables: the ELL tables of ctqw_graph_evolve for m = 1 or
+    2 particles on the graph with the undirected bonds `edges` (int [E, 2]),
+    built by the library from J [R, E], eps [R, n] (zeros if None) and, for
+    two particles, U [R] and the statistics.  Returns nbr int32 [width,
+    states], hop float64 [R, width, states] and onsite float64 [R, states]."""
+    lib = L.load()
+    edges = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2), dtype=np.int32)
+    J = np.ascontiguousarray(np.atleast_2d(np.asarray(J, dtype=np.float64)))
+    R = J.shape[0]
+    if J.shape[1] != len(edges):
+        raise ValueError("J must be [R, E]")
+    eps = np.zeros((R, n_nodes)) if eps is None else np.asarray(eps, dtype=np.float64)
+    eps = np.ascontiguousarray(np.atleast_2d(eps))
+    if eps.shape != (R, n_nodes):
+        raise ValueError("eps must be [R, n]")
+    if m == 2:
+        U = np.ascontiguousarray(np.atleast_1d(np.asarray(U, dtype=np.float64)))
+        if U.shape != (R,):
+            raise ValueError("U must be [R]")
+    ns, w = C.c_int32(), C.c_int32()
+    p = lambda a: C.c_void_p(a.ctypes.data) if a is not None and a.size else None  # noqa: E731
+    stat = _STAT[statistics]
+    L.check(lib.ctqw_graph_tables(int(n_nodes), len(edges), p(edges), int(m), stat, R, None, None, None,
+                                  C.byref(ns), C.byref(w), None, None, None))
+    D, W = ns.value, w.value
+    nbr = np.full((W, D), -1, dtype=np.int32)
+    hop = np.zeros((R, W, D))
+    onsite = np.zeros((R, D))
+    L.check(lib.ctqw_graph_tables(int(n_nodes), len(edges), p(edges), int(m), stat, R, p(J), p(eps),
+                                  p(U) if m == 2 else None, C.byref(ns), C.byref(w), C.c_void_p(nbr.ctypes.data),
+                                  C.c_void_p(hop.ctypes.data), C.c_void_p(onsite.ctypes.data)))
+    return nbr, hop, onsite
 
 
 def ell_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
-    """Neighbour and coupling tables of ctqw_graph_evolve from an undirected
-    bond list: edges int [E, 2] (no self-loops, no repeated bonds), J [R, E]
-    the bond couplings of each realisation.  Each bond fills one slot of
-    both of its nodes, slots in bond order; width = the largest degree.
-    Returns nbr int32 [width, n] (-1 in empty slots) and hop float64
-    [R, width, n]."""
-    J = np.atleast_2d(np.asarray(J, dtype=np.float64))
-    if J.shape[1] != len(np.asarray(edges).reshape(-1, 2)):
-        raise ValueError("J must be [R, E]")
-    nbr, bond_of = _ell_topology(n_nodes, edges)
-    hop = np.where(bond_of >= 0, J[:, np.maximum(bond_of, 0)], 0.0)
-    return nbr, np.ascontiguousarray(hop)
+    """One particle: nbr int32 [width, n] and hop float64 [R, width, n] of
+    ctqw_graph_tables for the bond list `edges` and couplings J [R, E]."""
+    nbr, hop, _ = graph_tables(n_nodes, edges, J)
+    return nbr, hop
 
 
 def pair_tables(n_nodes: int, edges: np.ndarray, J: np.ndarray, eps: np.ndarray, U: np.ndarray,
                 statistics: str = "distinguishable") -> tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """Two particles on a graph (Sec. 2 with m = 2) as one particle on the
-    pair graph, for ctqw_graph_evolve.  States: (a, b) at a * n + b
-    (distinguishable) or the pairs a <= b in lexicographic order, each the
-    normalised symmetric state (bosons).  Either particle moves along a
-    bond; in the boson sector a move between a doubly occupied node pair
-    (a, a) and a pair (a, c) carries sqrt(2) J, split over the two slots of
-    the diagonal state.  On-site energies add, and U acts on double
-    occupation.  Fermions: the pairs a < b in lexicographic order, each the
-    normalised antisymmetric state; a move onto the other particle's node is
-    absent, and one that carries the mover past the other particle's node
-    (so the pair's order flips) carries -J; U drops out.  J [R, E], eps
-    [R, n], U [R].  Returns nbr int32 [2 width, D], hop float64 [R, 2 width,
-    D] and onsite float64 [R, D]."""
-    J = np.atleast_2d(np.asarray(J, dtype=np.float64))
-    eps = np.atleast_2d(np.asarray(eps, dtype=np.float64))
-    U = np.atleast_1d(np.asarray(U, dtype=np.float64))
-    n = int(n_nodes)
-    if J.shape[1] != len(np.asarray(edges).reshape(-1, 2)) or eps.shape != (J.shape[0], n) or U.shape != (J.shape[0],):
-        raise ValueError("J must be [R, E], eps [R, n] and U [R]")
-    nbr1, bond1 = _ell_topology(n, edges)
-    w = nbr1.shape[0]
-    if statistics == "distinguishable":
-        A, B = np.divmod(np.arange(n * n), n)
-        index = lambda a, b: a * n + b  # noqa: E731
-    elif statistics == "boson":
-        A, B = np.triu_indices(n)
-        # position of the sorted pair (a, b), a <= b, in lexicographic order
-        index = lambda a, b: (lambda lo, hi: lo * n - lo * (lo - 1) // 2 + (hi - lo))(np.minimum(a, b), np.maximum(a, b))  # noqa: E731
-    elif statistics == "fermion":
-        A, B = np.triu_indices(n, 1)
-        # position of the pair (lo, hi), lo < hi, in lexicographic order
-        index = lambda a, b: (lambda lo, hi: lo * n - lo * (lo + 1) // 2 + (hi - lo - 1))(np.minimum(a, b), np.maximum(a, b))  # noqa: E731
-    else:
-        raise ValueError(f"unknown statistics {statistics!r}")
-    D = len(A)
-    nbr = np.full((2 * w, D), -1, dtype=np.int32)
-    bond = np.full((2 * w, D), -1, dtype=np.int64)
-    fac = np.zeros((2 * w, D))
-    for k in range(w):
-        for half, (mover, still) in enumerate(((A, B), (B, A))):
-            c = nbr1[k, mover]
-            ok = c >= 0
-            if statistics == "fermion":
-                ok &= c != still
-            cc = np.where(ok, c, 0)
-            tgt = np.where(ok, index(cc, still) if half == 0 else index(still, cc), -1)
-            f = np.ones(D)
-            if statistics == "boson":
-                f = np.where(A == B, 1 / np.sqrt(2), np.where(c == still, np.sqrt(2), 1.0))
-            elif statistics == "fermion":
-                f = np.where((c < still) == (mover < still), 1.0, -1.0)
-            nbr[half * w + k] = tgt
-            bond[half * w + k] = np.where(ok, bond1[k, mover], -1)
-            fac[half * w + k] = np.where(ok, f, 0.0)
-    hop = np.where(bond >= 0, J[:, np.maximum(bond, 0)], 0.0) * fac
-    onsite = eps[:, A] + eps[:, B] + U[:, None] * (A == B)
-    return nbr, np.ascontiguousarray(hop), np.ascontiguousarray(onsite)
+    """Two particles on a graph as one particle on the pair graph:
+    ctqw_graph_tables with m = 2 (J [R, E], eps [R, n], U [R]).  Returns
+    nbr int32 [2 width, D], hop float64 [R, 2 width, D] and onsite float64
+    [R, D]."""
+    return graph_tables(n_nodes, edges, J, eps, U, m=2, statistics=statistics)
 
 
-def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, workspace=None, norms=None) -> None:
-    """ctqw_graph_evolve on device tensors: one particle on a general graph,
-    R realisations advanced in place.  nbr int32 [width, n]; psi complex128
-    [R, n] with hop float64 [R, width, n] and onsite float64 [R, n], or
-    psi complex64 with float32 tables; all contiguous on one device.  norms
-    (optional) float64 [n_steps, R] receives each step's squared norms.
-    Enqueued on that device's current stream."""
+def _graph_args(nbr, hop, onsite, psi, n_steps, norms):
+    """Check the device tensors of graph_evolve(_static); returns (R, n,
+    width, dtype)."""
     import torch
-    lib = L.load()
     R, n = psi.shape
     width = nbr.shape[0]
     if psi.dtype not in (torch.complex64, torch.complex128):
@@ -495,7 +437,19 @@ def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, wor
     if norms is not None and (norms.dtype != torch.float64 or tuple(norms.shape) != (int(n_steps), R)
                               or not norms.is_contiguous() or norms.device != psi.device):
         raise ValueError(f"norms must be a contiguous float64 tensor of shape ({n_steps}, {R}) on {psi.device}")
-    dtype = C128 if c128 else C64
+    return R, n, width, (C128 if c128 else C64)
+
+
+def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, workspace=None, norms=None) -> None:
+    """ctqw_graph_evolve on device tensors: one particle on a general graph,
+    R realisations advanced in place.  nbr int32 [width, n]; psi complex128
+    [R, n] with hop float64 [R, width, n] and onsite float64 [R, n], or
+    psi complex64 with float32 tables; all contiguous on one device.  norms
+    (optional) float64 [n_steps, R] receives each step's squared norms.
+    Enqueued on that device's current stream."""
+    import torch
+    lib = L.load()
+    R, n, width, dtype = _graph_args(nbr, hop, onsite, psi, n_steps, norms)
     b = C.c_int64()
     L.check(lib.ctqw_graph_workspace(n, R, dtype, C.byref(b)))
     if workspace is None:
@@ -505,6 +459,21 @@ def graph_evolve(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, wor
     L.check(lib.ctqw_graph_evolve(n, width, p(nbr), p(hop), p(onsite), R, dtype, float(dt), int(order), int(n_steps),
                                   p(psi), p(workspace), workspace.numel() * workspace.element_size(),
                                   p(norms) if norms is not None else None, C.c_void_p(stream)))
+
+
+def graph_evolve_static(nbr, hop, onsite, psi, dt: float, order: int, n_steps: int, norms=None) -> None:
+    """ctqw_graph_evolve_static: graph_evolve without a workspace, the
+    library's fixed device array (GRAPH_STATIC_BYTES per device) taking its
+    place, for callers that cannot allocate.  Calls that overlap on one
+    device race on that array."""
+    import torch
+    lib = L.load()
+    R, n, width, dtype = _graph_args(nbr, hop, onsite, psi, n_steps, norms)
+    stream = torch.cuda.current_stream(psi.device).cuda_stream
+    p = lambda t: C.c_void_p(t.data_ptr()) if t.numel() else None  # noqa: E731
+    L.check(lib.ctqw_graph_evolve_static(n, width, p(nbr), p(hop), p(onsite), R, dtype, float(dt), int(order),
+                                         int(n_steps), p(psi), p(norms) if norms is not None else None,
+                                         C.c_void_p(stream)))
 
 
 def graph_orders(nbr: np.ndarray, hop: np.ndarray, onsite: np.ndarray, dt: float, tol: float,

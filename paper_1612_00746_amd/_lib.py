@@ -26,6 +26,7 @@ OBS_OCCUPATION, OBS_PAIR = 1, 2
 LOSS_ONE_BODY, LOSS_PRODUCT = 0, 1
 DIST_NONE, DIST_UNIFORM, DIST_NORMAL = 0, 1, 2
 RK4_ORDER = 4
+GRAPH_STATIC_BYTES = 64 << 20
 
 
 class Problem(C.Structure):
@@ -75,6 +76,7 @@ class Launch(C.Structure):
         ("waves_per_cu", C.c_int32),
         ("chunked", C.c_int32),
         ("band_align", C.c_int32),
+        ("terms_per_pass", C.c_int32),
     ]
 
 
@@ -107,9 +109,14 @@ SIGNATURES = {
     "ctqw_graph_orders": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
                                     C.c_double, C.c_int32, C.c_void_p]),
     "ctqw_graph_workspace": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, i64p]),
+    "ctqw_graph_tables": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, i32p, i32p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "ctqw_graph_evolve": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                     C.c_double, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                     C.c_void_p]),
+    "ctqw_graph_evolve_static": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                           C.c_int32, C.c_double, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
+                                           C.c_void_p]),
     "ctqw_stats": (C.c_int, [PlanP, C.POINTER(StepStats)]),
     "ctqw_realization_norms": (C.c_int, [PlanP, dp, dp]),
     "ctqw_get_launch": (C.c_int, [PlanP, C.POINTER(Launch)]),

@@ -59,9 +59,13 @@ __global__ void init_sites_kernel(InitArgs a) {
     }
     int x1 = s[0], x2 = s[1];
     if (rd.flags & RF_TRIANGLE) {
-        if (x1 > x2) { const int t = x1; x1 = x2; x2 = t; }
+        // bosons: phi(x1, x2) = phi(x2, x1) = 1/sqrt 2 (1 on the diagonal);
+        // fermions: phi(x1, x2) = -phi(x2, x1) = 1/sqrt 2 for particle 1 on x1
+        const bool swapped = x1 > x2;
+        if (swapped) { const int t = x1; x1 = x2; x2 = t; }
         C v;
         v.x = (x1 == x2) ? 1.0 : 0.70710678118654752440;
+        if ((rd.flags & RF_FERMION) && swapped) v.x = -v.x;
         v.y = 0;
         psi[tri_index(x1, x2, rd.N)] = v;
     } else {

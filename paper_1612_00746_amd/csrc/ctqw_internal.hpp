@@ -10,8 +10,9 @@ namespace ctqw {
 // Bits of RealDev::flags.
 enum : int32_t {
     RF_PERIODIC = 1,   // ring: bond N-1 joins node N-1 and node 0
-    RF_TRIANGLE = 2,   // two bosons stored as the upper triangle x1 <= x2
+    RF_TRIANGLE = 2,   // two bosons or fermions stored as the upper triangle x1 <= x2
     RF_NEAREST = 4,    // interaction on pairs at chain distance 1
+    RF_FERMION = 8,    // triangle of two fermions: the diagonal x1 == x2 is held at 0
 };
 
 // One realisation, as the kernels see it.  The walk of m = 1 or 2 particles
@@ -164,26 +165,49 @@ hipError_t launch_rescale(const RescaleArgs& a, hipStream_t stream);
 hipError_t launch_fill_zero(void* p, int64_t bytes, hipStream_t stream);
 
 // ------------------------------------------------------- three particles
-struct Step3Args {
-    const void* phi_in;      // psi for the first pass, else Phi^(j-1)
-    void* phi_out;           // Phi^(j) (unused on the last pass)
-    void* acc;               // running sum = the new state
-    void* comp;              // Kahan compensation (complex64)
+// Three particles, K terms chained per pass: one work item is a tile of the
+// (x2, x3) plane swept over the x1 planes.  The tile's window is 64 x3
+// columns from z0 and (rows per block) x2 rows from y0 (either may start
+// below 0 on a ring); only [zlo, zhi) x [ylo, yhi) is written, the rest is
+// halo that the neighbouring tiles write.
+struct Item3Dev {
+    int32_t real;
+    int32_t z0, zlo, zhi;
+    int32_t y0, ylo, yhi;
+    int32_t x0;              // first swept plane (-K on a ring)
+    int32_t nplanes;         // swept planes
+    int32_t plane_lo, plane_hi;   // output planes (absolute)
+    int32_t pad;
+};
+
+// One pass of K levels: X = Psi_s (psi, scaled by the load scale, on the
+// first pass), base = the partial sum before the pass (psi on the first);
+// writes the partial sum after it (the new state on the last pass) and
+// Psi_{s+K} (before the last pass).
+struct Step3cArgs {
+    const void* x_in;
+    const void* base_in;
+    void* sum_out;
+    void* seed_out;          // null on the last pass
     const RealDev* reals;
+    const Item3Dev* items;
     const void* Jt;          // dt-scaled tables (dtype of the state)
     const void* Et;
     const double* scale;
-    double* norm_part;
+    double* norm_part;       // [n_items] (last pass)
     double* tail_part;
     double dt;
-    double inv_j;            // 1 / j
+    double coef[4];          // 1/(s+j)! for j = 1..K, 0 past the order
+    double tail_coef;        // 1/n!
+    int32_t tail_level;      // level of the order's last term (last pass), else 0
     int32_t first;
     int32_t last;
-    int64_t R;
-    int64_t blocks_per_real;
+    int32_t n_items;
 };
-hipError_t launch_term3d(const Step3Args& a, int kahan, int dtype, int N, hipStream_t stream);
-int64_t term3d_blocks_per_real(int N);
+// Terms per pass of the compiled three-particle kernels: 1..3.  Rows of the
+// x2 window of one block for a (dtype, K), 0 if not compiled.
+int step3c_rows_per_block(int dtype, int K);
+hipError_t launch_step3c(const Step3cArgs& a, int dtype, int K, hipStream_t stream);
 
 struct Obs3Args {
     const void* psi;
@@ -268,4 +292,9 @@ struct AdjReduceArgs {
 };
 hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t stream);
 
+}  // namespace ctqw
+
+namespace ctqw {
+// Record the message returned by ctqw_last_error(NULL) and return status.
+int report_error(int status, const char* message);
 }  // namespace ctqw

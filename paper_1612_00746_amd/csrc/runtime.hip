@@ -47,7 +47,7 @@ struct Region {
 struct Layout {
     Region reals, items, order, item_first, claim, Jd, Ed, Jf, Ef, scale, norm_part,
         tail_part, norm2, tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites,
-        s3, M3, occ3, chunk, tbase, tsign, tstep;
+        s3, items3, M3, occ3, chunk, tbase, tsign, tstep;
     int64_t total = 0;
 };
 
@@ -74,6 +74,8 @@ struct ctqw_plan {
     int64_t obs_per_snapshot = 0;
     // work items
     std::vector<ItemDev> items;
+    std::vector<Item3Dev> items3;    // three particles: plane tiles
+    int k3 = 0;                      // three particles: terms per pass
     std::vector<int32_t> item_first, item_order;
     // fused steps: runs of item_order with one Taylor order each, largest
     // order first: {order, first, end}
@@ -140,6 +142,15 @@ ctqw_status fail(ctqw_plan* p, ctqw_status s, const char* fmt, ...) {
     return s;
 }
 
+}  // namespace
+
+int ctqw::report_error(int status, const char* message) {
+    g_last_error = message;
+    return status;
+}
+
+namespace {
+
 #define HIP_TRY(p, call)                                                                  \
     do {                                                                                  \
         hipError_t e_ = (call);                                                           \
@@ -154,7 +165,7 @@ int n_bonds(const ctqw_problem& pr, int N) { return pr.boundary == CTQW_PERIODIC
 int64_t amplitudes(const ctqw_problem& pr, int N) {
     if (pr.m == 1) return N;
     if (pr.m == 3) return (int64_t)N * N * N;
-    if (pr.statistics == CTQW_BOSON) return (int64_t)N * (N + 1) / 2;
+    if (pr.statistics == CTQW_BOSON || pr.statistics == CTQW_FERMION) return (int64_t)N * (N + 1) / 2;
     return (int64_t)N * N;
 }
 
@@ -186,6 +197,43 @@ T* at(ctqw_plan* p, const Region& r) {
     return reinterpret_cast<T*>(p->ws + r.off);
 }
 
+// Windows of W consecutive indices covering [0, N) with a halo of h on each
+// side (the same rule as the column bands below, without the row fields):
+// {window start, first output, end of output}.  Boundaries inside the
+// chain are moved down to multiples of `align` where that leaves an output.
+bool bands_1d(int N, int h, int W, bool periodic, int align, std::vector<std::array<int32_t, 3>>& out) {
+    if (W - 2 * h <= 0) return false;
+    int lo = 0;
+    while (lo < N) {
+        auto aligned = [&](int c) {
+            const int a = (c / align) * align;
+            return a > lo ? a : c;
+        };
+        int w0, hi;
+        if (periodic) {
+            w0 = lo - h;
+            const int end = w0 + W - h;
+            hi = end >= N ? N : aligned(end);
+        } else {
+            w0 = std::max(0, lo - h);
+            if (w0 + W > N) w0 = std::max(0, N - W);
+            const int w1 = std::min(N, w0 + W);
+            hi = (w1 == N) ? N : aligned(w1 - h);
+        }
+        if (hi <= lo) return false;
+        out.push_back({w0, lo, hi});
+        lo = hi;
+    }
+    return true;
+}
+
+// Terms per pass of the three-particle kernel: the launch's choice, else 3
+// (complex64) or 2 (complex128), never more than the order.
+int terms3(const ctqw_plan* p, int order) {
+    int K = p->launch.terms_per_pass > 0 ? p->launch.terms_per_pass : (p->prob.dtype == CTQW_C128 ? 2 : 3);
+    return std::max(1, std::min(K, order));
+}
+
 // Column bands of one realisation for halo h (= its Taylor order) and a
 // window of W columns.  Band boundaries inside the chain are moved down to
 // multiples of `align` columns where that leaves the band an output column,
@@ -199,7 +247,7 @@ bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, int align, b
                 std::vector<ItemDev>& out) {
     const int rows = pr.m == 1 ? 1 : N;
     const bool periodic = pr.boundary == CTQW_PERIODIC;
-    const bool tri = pr.m == 2 && pr.statistics == CTQW_BOSON;
+    const bool tri = pr.m == 2 && pr.statistics != CTQW_DISTINGUISHABLE;
     if (W - 2 * h <= 0) return false;
     int lo = 0;
     while (lo < N) {
@@ -262,12 +310,49 @@ ctqw_status build_tables(ctqw_plan* p) {
     std::vector<ItemDev> items;
     std::vector<int32_t> first(pr.R + 1, 0);
     int64_t n_parts = 0;
+    std::vector<Item3Dev> items3;
+    int k3 = 0;
     if (pr.m == 3) {
-        // one norm partial per block of the three-particle term kernel
-        const int64_t bpr = term3d_blocks_per_real(p->N[0]);
-        if (bpr * pr.R > INT32_MAX) return fail(p, CTQW_ERR_OUT_OF_MEMORY, "too many norm partials");
-        for (int64_t r = 0; r <= pr.R; ++r) first[r] = (int32_t)(r * bpr);
-        n_parts = bpr * pr.R;
+        // tiles of the (x2, x3) plane swept over x1, halo = terms per pass;
+        // one norm partial per tile
+        k3 = terms3(p, maxn);
+        const int rows = step3c_rows_per_block(dtype, k3);
+        if (rows <= 0) return fail(p, CTQW_ERR_UNSUPPORTED, "%d terms per pass are not compiled", k3);
+        const bool periodic = pr.boundary == CTQW_PERIODIC;
+        for (int64_t r = 0; r < pr.R; ++r) {
+            const int N = p->N[r];
+            std::vector<std::array<int32_t, 3>> yb, zb, trial;
+            if (!bands_1d(N, k3, rows, periodic, 1, yb) || !bands_1d(N, k3, 64, periodic, 1, zb))
+                return fail(p, CTQW_ERR_UNSUPPORTED, "%d terms per pass leave a tile no output", k3);
+            // x3 band boundaries on whole cache lines where that adds no band
+            for (int a = std::max(1, p->launch.band_align / amp_bytes); a > 1; a /= 2) {
+                trial.clear();
+                if (bands_1d(N, k3, 64, periodic, a, trial) && trial.size() <= zb.size()) {
+                    zb.swap(trial);
+                    break;
+                }
+            }
+            first[r] = (int32_t)items3.size();
+            for (const auto& y : yb)
+                for (const auto& zz : zb) {
+                    Item3Dev t{};
+                    t.real = (int32_t)r;
+                    t.z0 = zz[0];
+                    t.zlo = zz[1];
+                    t.zhi = zz[2];
+                    t.y0 = y[0];
+                    t.ylo = y[1];
+                    t.yhi = y[2];
+                    t.x0 = periodic ? -k3 : 0;
+                    t.nplanes = periodic ? N + 2 * k3 : N;
+                    t.plane_lo = 0;
+                    t.plane_hi = N;
+                    items3.push_back(t);
+                }
+            if (items3.size() > (size_t)INT32_MAX) return fail(p, CTQW_ERR_OUT_OF_MEMORY, "too many tiles");
+        }
+        first[pr.R] = (int32_t)items3.size();
+        n_parts = (int64_t)items3.size();
     } else {
         for (int64_t r = 0; r < pr.R; ++r) {
             first[r] = (int32_t)items.size();
@@ -296,7 +381,7 @@ ctqw_status build_tables(ctqw_plan* p) {
     // cost, and each run of one (order, variant) is a launch of that depth.
     // Paired 16-byte access (complex64, two columns per lane, full grid)
     // needs an even chain length and an even window start and output range.
-    const bool pairs = !chunk && P == 2 && dtype == 0 && !(pr.m == 2 && pr.statistics == CTQW_BOSON);
+    const bool pairs = !chunk && P == 2 && dtype == 0 && !(pr.m == 2 && pr.statistics != CTQW_DISTINGUISHABLE);
     std::vector<int32_t> ord(items.size());
     std::vector<int64_t> cost(items.size());
     std::vector<int32_t> iord(items.size()), ivec(items.size());
@@ -316,7 +401,8 @@ ctqw_status build_tables(ctqw_plan* p) {
     std::vector<int32_t> igrp(items.size());
     {
         // (measured: a gain at two columns per lane, a loss at one)
-        const bool two_ok = !chunk && dtype == 0 && P == 2 && !(pr.m == 2 && pr.statistics == CTQW_BOSON) && pr.m != 3;
+        const bool two_ok =
+            !chunk && dtype == 0 && P == 2 && !(pr.m == 2 && pr.statistics != CTQW_DISTINGUISHABLE) && pr.m != 3;
         std::vector<int32_t> present;
         for (size_t k = 0; k < items.size(); ++k) present.push_back(iord[k]);
         std::sort(present.begin(), present.end(), std::greater<int32_t>());
@@ -345,6 +431,8 @@ ctqw_status build_tables(ctqw_plan* p) {
         if (two) p->order_runs.back()[4] = 1;
     }
     p->all_vec = all_vec;
+    p->items3.swap(items3);
+    p->k3 = k3;
     p->items.swap(items);
     p->item_first.swap(first);
     p->item_order.swap(ord);
@@ -382,9 +470,11 @@ ctqw_status build_tables(ctqw_plan* p) {
     align_region(L, L.obs, p->obs_per_snapshot * 8);
     align_region(L, L.sites, R * pr.m * 4);
     if (pr.m == 3) {
-        // term buffers (two for Phi, one for the compensation) and marginals
+        // tiles, pass buffers (the partial sum and two for the last term of
+        // a pass, used alternately) and the two-body marginals
         const int64_t sb = p->state_off.back() * (pr.dtype == CTQW_C128 ? 16 : 8);
         const int64_t NN = (int64_t)p->max_N * p->max_N;
+        align_region(L, L.items3, (int64_t)p->items3.size() * (int64_t)sizeof(Item3Dev));
         align_region(L, L.s3, 3 * ((sb + 255) & ~int64_t(255)));
         align_region(L, L.M3, R * 3 * NN * 8);
         align_region(L, L.occ3, G * NN * 8);
@@ -430,7 +520,8 @@ ctqw_status upload_tables(ctqw_plan* p) {
         d.param_off = p->param_off[r];
         d.row_param_off = pr.m == 1 ? p->zero_block : p->param_off[r];
         d.flags = (pr.boundary == CTQW_PERIODIC ? RF_PERIODIC : 0) |
-                  (pr.m == 2 && pr.statistics == CTQW_BOSON ? RF_TRIANGLE : 0) |
+                  (pr.m == 2 && pr.statistics != CTQW_DISTINGUISHABLE ? RF_TRIANGLE : 0) |
+                  (pr.m == 2 && pr.statistics == CTQW_FERMION ? RF_FERMION : 0) |
                   (pr.interaction == CTQW_INT_NEAREST ? RF_NEAREST : 0);
         d.U = pr.m == 1 ? 0.0 : p->U[r];
         // remainder estimate: ||sum_{j>n} Phi^(j)|| <= ||Phi^(n)|| (x/(n+1)) / (1 - x/(n+2))
@@ -467,6 +558,8 @@ ctqw_status upload_tables(ctqw_plan* p) {
     hipStream_t s = p->stream;
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.reals.off, reals.data(), L.reals.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.items.off, p->items.data(), L.items.bytes, h2d, s));
+    if (L.items3.bytes > 0)
+        HIP_TRY(p, hipMemcpyAsync(p->ws + L.items3.off, p->items3.data(), L.items3.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.order.off, p->item_order.data(), L.order.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.item_first.off, p->item_first.data(), L.item_first.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.Jd.off, Jd.data(), L.Jd.bytes, h2d, s));
@@ -503,7 +596,7 @@ StepConfig step_config(ctqw_plan* p) {
     StepConfig c{};
     c.dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
     c.kahan = (c.dtype == 0 && p->prob.accumulation == CTQW_ACC_KAHAN) ? 1 : 0;
-    c.triangle = (p->prob.m == 2 && p->prob.statistics == CTQW_BOSON) ? 1 : 0;
+    c.triangle = (p->prob.m == 2 && p->prob.statistics != CTQW_DISTINGUISHABLE) ? 1 : 0;
     c.cols_per_lane = p->chunk ? 1 : p->launch.cols_per_lane;
     c.levels = p->chunk ? p->chunk : p->levels;
     c.waves_per_block = p->launch.waves_per_block;
@@ -581,8 +674,12 @@ ctqw_status enqueue_finalize(ctqw_plan* p) {
     return CTQW_OK;
 }
 
-// Three particles: n one-term passes from psi[cur] into psi[1-cur] (the sum),
-// Phi ping-ponging through two workspace buffers.
+// Three particles: ceil(n / K) passes of the chained kernel from psi[cur]
+// into psi[1-cur].  Pass q continues the series from the last term of pass
+// q-1 (two workspace buffers, alternately) and the partial sum, which
+// alternates between the workspace and the output so that the last pass
+// writes the output and no pass updates its own input; the last pass takes
+// the remaining n - qK terms.
 ctqw_status enqueue_telegraph(ctqw_plan* p);
 
 ctqw_status enqueue_step3(ctqw_plan* p) {
@@ -595,30 +692,43 @@ ctqw_status enqueue_step3(ctqw_plan* p) {
     const int dtype = pr.dtype == CTQW_C128 ? 1 : 0;
     const int64_t sb = (p->state_off.back() * (dtype ? 16 : 8) + 255) & ~int64_t(255);
     uint8_t* s3 = p->ws + L.s3.off;
-    Step3Args a{};
-    a.acc = p->psi[1 - p->cur];
-    a.comp = s3 + 2 * sb;
+    uint8_t* acc_tmp = s3;
+    uint8_t* seed_buf[2] = {s3 + sb, s3 + 2 * sb};
+    const void* in = p->psi[p->cur];
+    void* out = p->psi[1 - p->cur];
+    const int n = p->levels, K = p->k3;
+    const int passes = (n + K - 1) / K;
+    auto acc_buf = [&](int q) -> void* { return ((passes - 1 - q) & 1) == 0 ? out : static_cast<void*>(acc_tmp); };
+    auto inv_fact = [](int k) {
+        double prod = 1.0;
+        for (int i = 2; i <= k; ++i) prod *= i;
+        return 1.0 / prod;
+    };
+    Step3cArgs a{};
     a.reals = at<RealDev>(p, L.reals);
+    a.items = at<Item3Dev>(p, L.items3);
     a.Jt = dtype ? static_cast<const void*>(at<double>(p, L.Jd)) : static_cast<const void*>(at<float>(p, L.Jf));
     a.Et = dtype ? static_cast<const void*>(at<double>(p, L.Ed)) : static_cast<const void*>(at<float>(p, L.Ef));
     a.scale = at<double>(p, L.scale);
     a.norm_part = at<double>(p, L.norm_part);
     a.tail_part = at<double>(p, L.tail_part);
     a.dt = pr.dt;
-    a.R = pr.R;
-    a.blocks_per_real = term3d_blocks_per_real(p->N[0]);
-    const int kahan = (!dtype && pr.accumulation == CTQW_ACC_KAHAN) ? 1 : 0;
+    a.n_items = (int32_t)p->items3.size();
+    a.tail_coef = inv_fact(n);
     ctqw_status st;
     if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
-    const void* in = p->psi[p->cur];
-    for (int j = 1; j <= p->levels; ++j) {
-        a.phi_in = in;
-        a.phi_out = s3 + (j & 1) * sb;
-        a.inv_j = 1.0 / j;
-        a.first = j == 1;
-        a.last = j == p->levels;
-        HIP_TRY(p, launch_term3d(a, kahan, dtype, p->N[0], p->stream));
-        in = a.phi_out;
+    for (int q = 0; q < passes; ++q) {
+        const int s0 = q * K;
+        const int Kq = std::min(K, n - s0);
+        a.x_in = q == 0 ? in : seed_buf[(q - 1) & 1];
+        a.base_in = q == 0 ? in : acc_buf(q - 1);
+        a.sum_out = acc_buf(q);
+        a.seed_out = q == passes - 1 ? nullptr : seed_buf[q & 1];
+        for (int j = 0; j < 4; ++j) a.coef[j] = j < Kq ? inv_fact(s0 + j + 1) : 0.0;
+        a.first = q == 0;
+        a.last = q == passes - 1;
+        a.tail_level = a.last ? Kq : 0;
+        HIP_TRY(p, launch_step3c(a, dtype, Kq, p->stream));
     }
     if (p->timing && (st = record_event(p, 1)) != CTQW_OK) return st;
     if ((st = enqueue_finalize(p)) != CTQW_OK) return st;
@@ -923,7 +1033,7 @@ ctqw_status read_status(ctqw_plan* p, int32_t* st) {
 
 extern "C" {
 
-const char* ctqw_version(void) { return "ctqw-mi355x 0.3 (gfx950)"; }
+const char* ctqw_version(void) { return "ctqw-mi355x 0.4 (gfx950)"; }
 
 const char* ctqw_status_string(ctqw_status s) {
     switch (s) {
@@ -950,8 +1060,6 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
     if (pr->m < 1 || pr->m > 3) return fail(nullptr, CTQW_ERR_INVALID_ARG, "m must be 1, 2 or 3 (got %d)", pr->m);
     if (pr->statistics != CTQW_DISTINGUISHABLE && pr->statistics != CTQW_BOSON && pr->statistics != CTQW_FERMION)
         return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown statistics %d", pr->statistics);
-    if (pr->statistics == CTQW_FERMION)
-        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "fermions on the chain path are not built (use the pair graph)");
     if (pr->interaction != CTQW_INT_ONSITE && pr->interaction != CTQW_INT_NEAREST)
         return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown interaction %d", pr->interaction);
     if (pr->boundary != CTQW_OPEN && pr->boundary != CTQW_PERIODIC)
@@ -987,6 +1095,11 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
     if (pr->statistics == CTQW_BOSON && pr->m == 2 && pr->boundary == CTQW_PERIODIC)
         return fail(nullptr, CTQW_ERR_UNSUPPORTED, "bosons on a ring are not built (use distinguishable "
                                                    "particles with a symmetrised start)");
+    if (pr->statistics == CTQW_FERMION && pr->m != 2 && pr->m != 1)
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "fermions are built for m == 2");
+    if (pr->statistics == CTQW_FERMION && pr->m == 2 && pr->boundary == CTQW_PERIODIC)
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "fermions on a ring are not built on the chain path (the wrap "
+                                                   "bond crosses the stored triangle; use the pair graph)");
 
     ctqw_plan* p = new (std::nothrow) ctqw_plan();
     if (!p) return fail(nullptr, CTQW_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -1058,6 +1171,7 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         p->launch.waves_per_cu = 0;
         p->launch.chunked = 0;
         p->launch.band_align = 128;
+        p->launch.terms_per_pass = 0;
         p->order.assign(R, 0);
         p->xbound.assign(R, 0.0);
     } catch (const std::bad_alloc&) {
@@ -1273,11 +1387,132 @@ ctqw_status ctqw_density_matrix(ctqw_plan* p, int32_t group, void* rho, int64_t 
     a.A = workspace;
     a.D = D;
     a.R_g = Rg;
-    a.triangle = (p->prob.m == 2 && p->prob.statistics == CTQW_BOSON) ? 1 : 0;
+    a.triangle = (p->prob.m == 2 && p->prob.statistics != CTQW_DISTINGUISHABLE) ? 1 : 0;
     HIP_TRY(p, launch_density_gather(a, dtype, p->stream));
     const int e = density_herk(&p->blas, p->stream, dtype, D, Rg, workspace, rho, ld);
     if (e != 0) return fail(p, CTQW_ERR_DEVICE, "Hermitian rank-k update failed (rocBLAS status %d)", e);
     if (!lower_only) HIP_TRY(p, launch_density_mirror(rho, D, ld, dtype, p->stream));
+    return CTQW_OK;
+}
+
+ctqw_status ctqw_graph_tables(int32_t n_nodes, int32_t n_edges, const int32_t* edges, int32_t m, int32_t statistics,
+                              int32_t R, const double* J, const double* eps, const double* U, int32_t* n_states,
+                              int32_t* width, int32_t* nbr, double* hop, double* onsite) {
+    if (n_nodes < 1 || n_edges < 0 || R < 0)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "n_nodes must be positive, n_edges and R >= 0");
+    if (m != 1 && m != 2) return fail(nullptr, CTQW_ERR_INVALID_ARG, "m must be 1 or 2 (got %d)", m);
+    if (statistics != CTQW_DISTINGUISHABLE && statistics != CTQW_BOSON && statistics != CTQW_FERMION)
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "unknown statistics %d", statistics);
+    if (!n_states || !width || (n_edges > 0 && !edges))
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL argument");
+    const int64_t n = n_nodes;
+    // One-particle slots: each bond fills one slot of both of its nodes, in
+    // bond order, the first endpoint's slot first.
+    std::vector<int32_t> deg(n, 0);
+    std::vector<std::pair<int64_t, int64_t>> seen;
+    seen.reserve(n_edges);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        const int64_t a = edges[2 * e], b = edges[2 * e + 1];
+        if (a < 0 || a >= n || b < 0 || b >= n) return fail(nullptr, CTQW_ERR_INVALID_ARG, "bond %lld: node out of range", (long long)e);
+        if (a == b) return fail(nullptr, CTQW_ERR_INVALID_ARG, "bond %lld is a self-loop (use the on-site energies)", (long long)e);
+        seen.emplace_back(std::min(a, b), std::max(a, b));
+        ++deg[a];
+        ++deg[b];
+    }
+    {
+        std::vector<std::pair<int64_t, int64_t>> sorted_b(seen);
+        std::sort(sorted_b.begin(), sorted_b.end());
+        if (std::adjacent_find(sorted_b.begin(), sorted_b.end()) != sorted_b.end())
+            return fail(nullptr, CTQW_ERR_INVALID_ARG, "repeated bond");
+    }
+    const int32_t w1 = n_edges ? *std::max_element(deg.begin(), deg.end()) : 0;
+    std::vector<int32_t> nbr1((size_t)w1 * n, -1), bond1((size_t)w1 * n, -1), fill(n, 0);
+    for (int64_t e = 0; e < n_edges; ++e) {
+        const int32_t a = edges[2 * e], b = edges[2 * e + 1];
+        int32_t k = fill[a]++;
+        nbr1[(size_t)k * n + a] = b;
+        bond1[(size_t)k * n + a] = (int32_t)e;
+        k = fill[b]++;
+        nbr1[(size_t)k * n + b] = a;
+        bond1[(size_t)k * n + b] = (int32_t)e;
+    }
+    // States: one node (m = 1); ordered pairs a * n + b (distinguishable);
+    // pairs a <= b (bosons) or a < b (fermions) in lexicographic order.
+    const bool boson = m == 2 && statistics == CTQW_BOSON, fermion = m == 2 && statistics == CTQW_FERMION;
+    int64_t D = m == 1 ? n : (boson ? n * (n + 1) / 2 : (fermion ? n * (n - 1) / 2 : n * n));
+    const int64_t W = m == 1 ? w1 : 2 * (int64_t)w1;
+    if (D < 1 || D > INT32_MAX || W * D > INT32_MAX)
+        return fail(nullptr, CTQW_ERR_UNSUPPORTED, "%lld states x %lld slots exceed the 32-bit tables", (long long)D, (long long)W);
+    *n_states = (int32_t)D;
+    *width = (int32_t)W;
+    if (!nbr && !hop && !onsite) return CTQW_OK;   // sizes only
+    if (!nbr || !hop || !onsite || (R > 0 && ((n_edges > 0 && !J) || !eps || (m == 2 && !U))))
+        return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL table or parameter array");
+    for (int64_t k = 0; k < (int64_t)R * n_edges; ++k)
+        if (!std::isfinite(J[k])) return fail(nullptr, CTQW_ERR_INVALID_ARG, "non-finite hopping");
+    for (int64_t k = 0; k < (int64_t)R * n; ++k)
+        if (!std::isfinite(eps[k])) return fail(nullptr, CTQW_ERR_INVALID_ARG, "non-finite on-site energy");
+    if (m == 2)
+        for (int64_t r = 0; r < R; ++r)
+            if (!std::isfinite(U[r])) return fail(nullptr, CTQW_ERR_INVALID_ARG, "non-finite U");
+    auto index = [&](int64_t a, int64_t b) -> int64_t {
+        if (!boson && !fermion) return a * n + b;
+        const int64_t lo = std::min(a, b), hi = std::max(a, b);
+        return boson ? lo * n - lo * (lo - 1) / 2 + (hi - lo) : lo * n - lo * (lo + 1) / 2 + (hi - lo - 1);
+    };
+    // state k -> its nodes (A, B)
+    std::vector<int32_t> SA(D), SB(D);
+    {
+        int64_t k = 0;
+        if (m == 1) {
+            for (int64_t a = 0; a < n; ++a) { SA[k] = (int32_t)a; SB[k] = (int32_t)a; ++k; }
+        } else {
+            for (int64_t a = 0; a < n; ++a)
+                for (int64_t b = boson ? a : (fermion ? a + 1 : 0); b < n; ++b) { SA[k] = (int32_t)a; SB[k] = (int32_t)b; ++k; }
+        }
+    }
+    // slot (half, k) of state s: the particle `mover` (A for half 0, B for 1)
+    // steps along its node's slot k; factor f multiplies the bond's J
+    std::vector<int32_t> sbond((size_t)W * D, -1);
+    std::vector<double> sfac((size_t)W * D, 0.0);
+    for (int64_t st = 0; st < D; ++st) {
+        const int64_t A = SA[st], B = SB[st];
+        for (int half = 0; half < (m == 1 ? 1 : 2); ++half) {
+            const int64_t mover = half == 0 ? A : B, still = half == 0 ? B : A;
+            for (int32_t k = 0; k < w1; ++k) {
+                const size_t slot = (size_t)(half * w1 + k) * D + st;
+                const int64_t c = nbr1[(size_t)k * n + mover];
+                if (c < 0) continue;
+                if (fermion && c == still) continue;          // no two fermions on one node
+                int64_t tgt;
+                double f = 1.0;
+                if (m == 1) {
+                    tgt = c;
+                } else {
+                    tgt = half == 0 ? index(c, still) : index(still, c);
+                    if (boson) f = (A == B) ? 1.0 / std::sqrt(2.0) : (c == still ? std::sqrt(2.0) : 1.0);
+                    // a fermion move that carries the mover past the other particle flips the pair's order
+                    if (fermion) f = ((c < still) == (mover < still)) ? 1.0 : -1.0;
+                }
+                nbr[slot] = (int32_t)tgt;
+                sbond[slot] = bond1[(size_t)k * n + mover];
+                sfac[slot] = f;
+            }
+        }
+    }
+    for (size_t slot = 0; slot < (size_t)W * D; ++slot)
+        if (sbond[slot] < 0) nbr[slot] = -1;
+    for (int64_t r = 0; r < R; ++r) {
+        double* h = hop + (size_t)r * W * D;
+        for (size_t slot = 0; slot < (size_t)W * D; ++slot)
+            h[slot] = sbond[slot] >= 0 ? J[(size_t)r * n_edges + sbond[slot]] * sfac[slot] : 0.0;
+        double* o = onsite + (size_t)r * D;
+        const double* er = eps + (size_t)r * n;
+        for (int64_t st = 0; st < D; ++st) {
+            if (m == 1) o[st] = er[SA[st]];
+            else o[st] = er[SA[st]] + er[SB[st]] + (SA[st] == SB[st] ? U[r] : 0.0);
+        }
+    }
     return CTQW_OK;
 }
 
@@ -1397,7 +1632,7 @@ ctqw_status ctqw_work_items(const ctqw_plan* p, int64_t* items, int64_t* waves) 
     const int64_t n = p->prob.m == 3 ? p->n_parts : (int64_t)p->items.size();
     if (items) *items = n;
     if (waves) {
-        *waves = p->prob.m == 3 ? n * 4 : n;
+        *waves = p->prob.m == 3 ? n * 8 : n;
         if (p->prob.m != 3 && p->launch.persistent && p->bound) {
             // the persistent grid: resident waves of the device (the
             // largest of the per-order launches)
@@ -1442,6 +1677,8 @@ ctqw_status ctqw_set_launch(ctqw_plan* p, const ctqw_launch* l) {
         return fail(p, CTQW_ERR_INVALID_ARG, "bad persistent / use_graph / waves_per_cu / chunked");
     if (l->band_align != 0 && l->band_align != 64 && l->band_align != 128 && l->band_align != 256)
         return fail(p, CTQW_ERR_INVALID_ARG, "band_align must be 0, 64, 128 or 256 bytes");
+    if (l->terms_per_pass < 0 || l->terms_per_pass > 3)
+        return fail(p, CTQW_ERR_INVALID_ARG, "terms_per_pass must be 0 (default) or 1..3");
     const ctqw_launch old = p->launch;
     p->launch = *l;
     if (p->params_set) {
@@ -1508,6 +1745,10 @@ ctqw_status ctqw_init_product_state(ctqw_plan* p, const int32_t* sites, int32_t 
             for (int a = 0; a < pr.m; ++a)
                 if (sites[a] >= p->N[r])
                     return fail(p, CTQW_ERR_INVALID_ARG, "start site %d out of range for N = %d", sites[a], p->N[r]);
+    if (pr.statistics == CTQW_FERMION && pr.m == 2)
+        for (int64_t k = 0; k < cnt; k += 2)
+            if (sites[k] == sites[k + 1])
+                return fail(p, CTQW_ERR_INVALID_ARG, "two fermions on node %d", sites[k]);
     HIP_TRY(p, hipMemcpyAsync(p->ws + p->lay.sites.off, sites, cnt * 4, hipMemcpyHostToDevice, p->stream));
     InitArgs a{};
     a.psi = p->psi[0];
@@ -1662,6 +1903,7 @@ bool cache_lookup(const char* path, const std::string& key, ctqw_launch* out, do
             parse_int_field(s, "persistent", &l.persistent) && parse_int_field(s, "waves_per_cu", &l.waves_per_cu)) {
             if (!parse_int_field(s, "chunked", &l.chunked)) l.chunked = 0;
             if (!parse_int_field(s, "band_align", &l.band_align)) l.band_align = 0;
+            if (!parse_int_field(s, "terms_per_pass", &l.terms_per_pass)) l.terms_per_pass = 0;
             *out = l;
             const size_t at = s.find("\"ms\": ");
             *ms = at == std::string::npos ? NAN : atof(s.c_str() + at + 6);
@@ -1677,9 +1919,9 @@ void cache_append(const char* path, const std::string& key, const ctqw_launch& l
     if (!f) return;
     fprintf(f,
             "{\"key\": \"%s\", \"cols_per_lane\": %d, \"waves_per_block\": %d, \"persistent\": %d, "
-            "\"waves_per_cu\": %d, \"chunked\": %d, \"band_align\": %d, \"ms\": %.6f}\n",
+            "\"waves_per_cu\": %d, \"chunked\": %d, \"band_align\": %d, \"terms_per_pass\": %d, \"ms\": %.6f}\n",
             key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, l.chunked, l.band_align,
-            ms);
+            l.terms_per_pass, ms);
     fclose(f);
 }
 
@@ -1712,14 +1954,6 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
     if (steps < 1) return fail(p, CTQW_ERR_INVALID_ARG, "steps must be >= 1");
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
-    if (p->prob.m == 3) {
-        // one launch shape only: report its time
-        double ms = 0.0;
-        if ((st = time_steps(p, steps, &ms)) != CTQW_OK) return st;
-        if (best_out) *best_out = p->launch;
-        if (best_ms_out) *best_ms_out = ms;
-        return CTQW_OK;
-    }
     const char* path = cache_path ? cache_path : getenv("CTQW_TUNE_CACHE");
     const std::string key = tune_key(p);
     const ctqw_launch orig = p->launch;
@@ -1739,7 +1973,30 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
             }
         }
     }
-    if (!cached) {
+    if (!cached && p->prob.m == 3) {
+        // three particles: terms per pass and the x3 band alignment
+        for (int K : {3, 2, 1})
+            for (int align : {128, 0}) {
+                ctqw_launch c = orig;
+                c.terms_per_pass = K;
+                c.band_align = align;
+                p->launch = c;
+                if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
+                if ((st = upload_tables(p)) != CTQW_OK) return st;
+                double ms = INFINITY;
+                if ((st = time_steps(p, steps, &ms)) != CTQW_OK) return st;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        if (!std::isfinite(best_ms)) {
+            p->launch = orig;
+            build_tables(p);
+            return fail(p, CTQW_ERR_UNSUPPORTED, "no launch shape fits the bound workspace");
+        }
+        if (path && *path) cache_append(path, key, best, best_ms);
+    } else if (!cached) {
         for (int align : {128, 64, 0})
         for (int chunked : {0, 1})
         for (int P : {1, 2})
@@ -1847,6 +2104,8 @@ ctqw_status ctqw_forward_ckpt(ctqw_plan* p, int64_t n_steps, int64_t ckpt_every,
     if (p->group_N.size() != 1)
         return fail(p, CTQW_ERR_UNSUPPORTED, "gradients with respect to shared baselines need one lattice size");
     if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "gradients are built for one and two particles");
+    if (p->prob.m == 2 && p->prob.statistics == CTQW_FERMION)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "gradients are built for distinguishable particles and bosons");
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
     const GradLayout g = grad_layout(p, n_steps, ckpt_every);
@@ -2026,6 +2285,8 @@ ctqw_status ctqw_loss(ctqw_plan* p, int32_t kind, const double* site_w, void* gw
         return fail(p, CTQW_ERR_INVALID_ARG, "unknown loss kind %d", kind);
     if (p->group_N.size() != 1) return fail(p, CTQW_ERR_UNSUPPORTED, "the loss needs one lattice size");
     if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "the loss is built for one and two particles");
+    if (p->prob.m == 2 && p->prob.statistics == CTQW_FERMION)
+        return fail(p, CTQW_ERR_UNSUPPORTED, "the loss is built for distinguishable particles and bosons");
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
     const GradLayout g = grad_layout(p, 0, 1);

@@ -34,6 +34,10 @@
 // row-major: the diagonal uses the mirrored neighbours phi(q, q-1) =
 // phi(q-1, q) and phi(q+1, q) = phi(q, q+1), i.e. doubled couplings to the
 // row above and the column to the right, with the lower triangle held at 0.
+// Two fermions (open chain) use the same layout for the antisymmetric
+// phi: the diagonal is held at 0 as well, and since every neighbour of an
+// element above it that lies across the diagonal is a diagonal element,
+// no coupling changes.
 //
 // Complex64 state can accumulate the terms with Kahan compensation.  The
 // squared norm of the new state and of the last term are accumulated in FP64
@@ -233,6 +237,9 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     const int nrows = it.nrows;
     const bool periodic = (rd.flags & RF_PERIODIC) != 0;
     const bool nearest = (rd.flags & RF_NEAREST) != 0;
+    // two fermions in the triangle: the diagonal stays 0 and no coupling
+    // doubles (the mirrored neighbours across it are the diagonal itself)
+    const bool fermi = TRI && (rd.flags & RF_FERMION) != 0;
     // J and eps below are scaled by dt (host tables).
     const T* __restrict__ Jc = jpar<T>(a) + rd.param_off;
     const T* __restrict__ Ec = epar<T>(a) + rd.param_off;
@@ -522,7 +529,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
                             T cu = Ju, crt = jr[p];
-                            if (TRI && zone && col[p] == qa) { cu = Ju + Ju; crt = crt + crt; }
+                            if (TRI && zone && col[p] == qa && !fermi) { cu = Ju + Ju; crt = crt + crt; }
                             const T mr = fr[j - 1][sm][p], mi = fi[j - 1][sm][p];
                             T hr = dg[w][p] * mr;
                             T hi = dg[w][p] * mi;
@@ -540,7 +547,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const bool low = TRI && zone && col[p] < qa;
+                        const bool low = TRI && zone && (col[p] < qa || (fermi && col[p] == qa));
                         const T hr = hrv[p], hi = hiv[p];
                         // A_j = H B_{j-1} (from the imaginary-role array), B_j = H A_{j-1}
                         T pr_ = hi;

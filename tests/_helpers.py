@@ -86,11 +86,17 @@ def oracle_H(N, m, statistics, boundary, interaction, J, eps, U):
 
 
 def gpu_to_oracle(psi_r, N, m, statistics):
-    """GPU layout of one realisation -> oracle basis coefficients."""
+    """GPU layout of one realisation -> oracle basis coefficients.  The GPU
+    stores phi(x1, x2) on x1 <= x2 for bosons and fermions (the fermions'
+    diagonal is 0); the normalised basis coefficient is sqrt(2) phi off the
+    diagonal (bosons: phi on it; fermions have no diagonal states)."""
     psi_r = np.asarray(psi_r, dtype=np.complex128)
     if m == 2 and statistics == B.BOSON:
         st = B.basis_states(N, 2, B.BOSON)
         return psi_r * np.where(st[:, 0] < st[:, 1], math.sqrt(2.0), 1.0)
+    if m == 2 and statistics == B.FERMION:
+        tri = B.basis_states(N, 2, B.BOSON)
+        return psi_r[tri[:, 0] < tri[:, 1]] * math.sqrt(2.0)
     return psi_r
 
 
@@ -99,4 +105,15 @@ def oracle_to_gpu(c, N, m, statistics):
     if m == 2 and statistics == B.BOSON:
         st = B.basis_states(N, 2, B.BOSON)
         return c / np.where(st[:, 0] < st[:, 1], math.sqrt(2.0), 1.0)
+    if m == 2 and statistics == B.FERMION:
+        tri = B.basis_states(N, 2, B.BOSON)
+        out = np.zeros(len(tri), dtype=np.complex128)
+        out[tri[:, 0] < tri[:, 1]] = c / math.sqrt(2.0)
+        return out
     return c
+
+
+def gpu_tri_diagonal(psi_r, N):
+    """The diagonal entries phi(x, x) of the triangle layout."""
+    tri = B.basis_states(N, 2, B.BOSON)
+    return np.asarray(psi_r)[tri[:, 0] == tri[:, 1]]

@@ -426,10 +426,32 @@ def test_ell_tables_rebuild_the_oracle_hamiltonian():
 
 
 def test_ell_tables_reject_bad_bonds():
-    from paper_1612_00746_amd import ell_tables
-    for edges in ([(0, 0)], [(0, 1), (1, 0)], [(0, 5)]):
-        with pytest.raises(ValueError):
+    """ctqw_graph_tables refuses self-loops, repeated bonds (either
+    orientation) and nodes out of range with INVALID_ARG."""
+    from paper_1612_00746_amd import CtqwError, ell_tables
+    for edges in ([(0, 0)], [(0, 1), (1, 0)], [(0, 5)], [(-1, 2)]):
+        with pytest.raises(CtqwError) as e:
             ell_tables(4, np.array(edges), np.ones((1, len(edges))))
+        assert e.value.status == 1
+
+
+def test_graph_tables_sizes_and_one_particle_onsite():
+    """The size query returns the state count and width of each case
+    (n, n^2, n(n+1)/2, n(n-1)/2 states; width = largest degree, doubled for
+    pairs), and one particle's on-site table is eps itself."""
+    from paper_1612_00746_amd import _lib as L
+    from paper_1612_00746_amd import graph_tables, lattice_edges
+    lib = L.load()
+    edges = np.ascontiguousarray(lattice_edges((3, 4)), dtype=np.int32)
+    n = 12
+    for m, stat, D in ((1, 0, n), (2, 0, n * n), (2, 1, n * (n + 1) // 2), (2, 2, n * (n - 1) // 2)):
+        ns, w = C.c_int32(), C.c_int32()
+        assert lib.ctqw_graph_tables(n, len(edges), C.c_void_p(edges.ctypes.data), m, stat, 0, None, None, None,
+                                     C.byref(ns), C.byref(w), None, None, None) == 0
+        assert ns.value == D and w.value == 4 * m
+    eps = np.random.default_rng(3).uniform(-1, 1, (2, n))
+    nbr, hop, onsite = graph_tables(n, edges, np.ones((2, len(edges))), eps)
+    assert np.array_equal(onsite, eps)
 
 
 @pytest.mark.parametrize("kw,status", [
@@ -514,3 +536,42 @@ def test_graph_orders_follow_the_gershgorin_rule(statistics):
     with pytest.raises(CtqwError) as e:
         graph_orders(nbr, hop, onsite, dt, tol, max_order=min(want) - 1)
     assert e.value.status == 5
+
+
+def test_graph_static_refuses_oversized_scratch_without_a_device():
+    """ctqw_graph_evolve_static checks the scratch size before any device
+    call: a problem needing more than CTQW_GRAPH_STATIC_BYTES is refused
+    with UNSUPPORTED and a message naming the limit (runs without a GPU)."""
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    n, R = 1 << 16, 64           # 3 * n * R * 16 bytes = 192 MiB > 64 MiB
+    st = lib.ctqw_graph_evolve_static(n, 0, None, None, 1, R, L.C128, 0.05, 4, 1, 1, None, None)
+    assert st == L.ERR_UNSUPPORTED
+    msg = lib.ctqw_last_error(None).decode()
+    assert "static buffer" in msg and str(L.GRAPH_STATIC_BYTES) in msg
+    # just inside the limit the size check passes and the NULL state is refused instead
+    n_ok = L.GRAPH_STATIC_BYTES // (3 * 16)
+    st = lib.ctqw_graph_evolve_static(n_ok, 0, None, None, 1, 1, L.C128, 0.05, 4, 1, None, None, None)
+    assert st == L.ERR_INVALID_ARG
+    import re
+    hdr = open(HEADER).read()
+    m = re.search(r"#define CTQW_GRAPH_STATIC_BYTES \((\d+)ll << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == L.GRAPH_STATIC_BYTES
+
+
+def test_fermion_plans_validate_and_use_the_triangle_layout():
+    """Two fermions on an open chain: accepted, stored on the triangle
+    x1 <= x2 (N(N+1)/2 amplitudes, the diagonal held at 0); on a ring or
+    with three particles: UNSUPPORTED; one fermion is one walker."""
+    from paper_1612_00746_amd import CtqwError, Plan, make_problem
+    pr, _ = make_problem(2, 3, 9, 0.05, statistics="fermion", interaction="nearest", taylor_tol=1e-12)
+    p = Plan(pr)
+    assert list(np.diff(p.layout())) == [45, 45, 45]
+    for kw in (dict(m=2, boundary="periodic"), dict(m=3)):
+        m = kw.pop("m")
+        pr, _ = make_problem(m, 1, 9, 0.05, statistics="fermion", taylor_tol=1e-12, **kw)
+        with pytest.raises(CtqwError) as e:
+            Plan(pr)
+        assert e.value.status == 2
+    pr, _ = make_problem(1, 2, 9, 0.05, statistics="fermion", taylor_tol=1e-12)
+    assert list(np.diff(Plan(pr).layout())) == [9, 9]

@@ -313,11 +313,16 @@ def test_boson_kernel_matches_distinguishable_symmetrised():
 
 # ------------------------------------------------------------- complex64
 
+C64_BARS = {"kahan": 2e-7, "plain": 1e-6}   # amplitude bars after 200 steps (about 2.5x the measured errors)
+
+
 @pytest.mark.parametrize("acc", ["kahan", "plain"])
 def test_c64_against_oracle(acc):
-    """complex64 state, FP32 stencil: error against the FP64 exact evolution
-    after 200 steps of dt = 0.05 stays below 2e-5 (max-abs amplitude);
-    the measured error is printed."""
+    """complex64 state, FP32 stencil: max-abs amplitude error against the
+    FP64 exact evolution after 200 steps of dt = 0.05 stays below 2e-7 with
+    the compensated sum (measured 7.9e-8 / 8.2e-8) and 1e-6 with plain
+    summation (measured 4.8e-7 / 3.0e-7), so a compensated sum that lost
+    its compensation fails its bar; the measured error is printed."""
     say(f"case: c64 {acc} m=2 dist N=[64,100] and bosons N=70, 200 steps")
     for stat, Ns in (("distinguishable", [64, 100]), ("boson", [70])):
         reals = random_reals(Ns, seed=10)
@@ -325,10 +330,10 @@ def test_c64_against_oracle(acc):
         plan = gpu_plan(m=2, statistics=stat, boundary="open", interaction="onsite", dtype="c64",
                         accumulation=acc, reals=reals, dt=0.05, tol=1e-7, sites=[30, 33])
         plan.propagate(200)
-        err = compare_final(plan, reals, 2, sb, "open", "onsite", [30, 33], 10.0, 2e-5)
+        err = compare_final(plan, reals, 2, sb, "open", "onsite", [30, 33], 10.0, C64_BARS[acc])
         n2, _ = plan.realization_norms()
         say(f"  {stat} {acc}: err {err:.3e}, |norm-1| max {np.max(np.abs(np.sqrt(n2) - 1)):.2e}")
-        assert np.max(np.abs(np.sqrt(n2) - 1)) < 1e-5
+        assert np.max(np.abs(np.sqrt(n2) - 1)) < (3e-7 if acc == "kahan" else 5e-6)
 
 
 def test_compensated_sum_against_plain():

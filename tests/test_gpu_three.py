@@ -1,6 +1,10 @@
-"""GPU parity for three distinguishable walkers (one Taylor term per pass):
-against the oracle's exact evolution on small lattices, and on the full
-N = 256 lattice against the oracle on the window the walkers can reach."""
+"""GPU parity for three distinguishable walkers (K Taylor terms chained per
+pass over the state, K = 1, 2, 3, the last pass taking the remaining
+terms): against the oracle's exact evolution on small lattices, against
+its Taylor map on lattices that span several tiles in both plane
+directions, on the three-walker workload's parameters for one output
+interval, and on the full N = 256 lattice against the oracle on the window
+the walkers can reach."""
 
 import numpy as np
 import pytest
@@ -9,7 +13,7 @@ from oracle import basis as B
 from oracle import hamiltonian as Hm
 from oracle import observables as O
 from oracle import propagate as P
-from workloads import C5
+from workloads import C5, scaled
 
 from _helpers import gpu_plan, say
 
@@ -22,15 +26,16 @@ def reals3(N, R, seed, boundary="open"):
     return [(N, 1 + 0.2 * g.standard_normal(nb), g.uniform(-1, 1, N), float(g.uniform(0.5, 1.5))) for _ in range(R)]
 
 
+@pytest.mark.parametrize("K", [1, 2, 3])
 @pytest.mark.parametrize("N,boundary,interaction", [(7, "open", "nearest"), (10, "open", "nearest"),
                                                     (6, "periodic", "onsite"), (5, "periodic", "nearest")])
-def test_three_walkers_c128_against_ed(N, boundary, interaction):
-    say(f"case: m=3 N={N} {boundary} {interaction} c128, 40 steps")
+def test_three_walkers_c128_against_ed(N, boundary, interaction, K):
+    say(f"case: m=3 N={N} {boundary} {interaction} c128, K={K}, 40 steps")
     R, dt, steps = 3, 0.02, 40
     reals = reals3(N, R, 1, boundary)
     sites = [1, N // 2, N - 2]
     plan = gpu_plan(m=3, statistics="distinguishable", boundary=boundary, interaction=interaction, dtype="c128",
-                    reals=reals, dt=dt, tol=1e-14, observables=3, sites=sites)
+                    reals=reals, dt=dt, tol=1e-14, observables=3, sites=sites, launch={"terms_per_pass": K})
     out = plan.propagate(steps, 20, 3)
     psi = plan.state_numpy()
     st = B.basis_states(N, 3)
@@ -44,9 +49,95 @@ def test_three_walkers_c128_against_ed(N, boundary, interaction):
     occ_e, pair_e = O.ensemble_mean(occ), O.ensemble_mean(pair)
     e_occ = np.max(np.abs(out[-1][:N] - occ_e))
     e_pair = np.max(np.abs(out[-1][N:].reshape(N, N) - pair_e))
-    say(f"  amplitude {worst:.2e}, occupation {e_occ:.2e}, pair {e_pair:.2e}")
+    n2, _ = plan.realization_norms()
+    say(f"  order {int(plan.orders().max())}: amplitude {worst:.2e}, occupation {e_occ:.2e}, pair {e_pair:.2e}, "
+        f"|norm^2 - 1| {np.max(np.abs(n2 - 1)):.1e}")
     assert worst <= 1e-10 and e_occ <= 1e-10 and e_pair <= 1e-10
     assert abs(out[0][:N].sum() - 3) < 1e-12
+    assert np.max(np.abs(n2 - 1)) < 1e-12
+
+
+@pytest.mark.parametrize("N,boundary,K", [(70, "open", 3), (41, "open", 2), (37, "periodic", 3)])
+def test_three_walkers_several_tiles_c128(N, boundary, K):
+    """Lattices spanning several tiles along x2 and x3 (a tile is 64 x3
+    columns by 16-24 x2 rows at complex128) with a ragged last tile: the
+    state after 12 steps equals the oracle's Taylor map of the same order,
+    amplitude by amplitude (1e-12), from a random complex start state; the
+    FP64 norms follow the oracle's."""
+    R, dt, steps = 2, 0.02, 12
+    reals = reals3(N, R, 7, boundary)
+    say(f"case: m=3 several tiles N={N} {boundary} K={K} c128, {steps} steps")
+    g = np.random.default_rng(11)
+    D = N ** 3
+    psi0 = g.standard_normal((R, D)) + 1j * g.standard_normal((R, D))
+    psi0 /= np.linalg.norm(psi0, axis=1, keepdims=True)
+    plan = gpu_plan(m=3, statistics="distinguishable", boundary=boundary, interaction="nearest", dtype="c128",
+                    reals=reals, dt=dt, tol=1e-14, launch={"terms_per_pass": K})
+    plan.set_state_numpy(psi0.reshape(-1))
+    n = int(plan.orders().max())
+    plan.propagate(steps)
+    psi = plan.state_numpy().reshape(R, D)
+    n2, _ = plan.realization_norms()
+    worst = 0.0
+    for r, (_, J, eps, U) in enumerate(reals):
+        H = Hm.hamiltonian(N, 3, J, eps, U, B.DISTINGUISHABLE, boundary, "nearest")
+        ref, _, _ = P.evolve_taylor(H, psi0[r], dt, steps, order=n)
+        worst = max(worst, float(np.max(np.abs(psi[r] - ref))))
+        assert abs(n2[r] - np.vdot(ref, ref).real) < 1e-12
+    say(f"  order {n}: max |psi - oracle map| = {worst:.2e}")
+    assert worst <= 1e-12
+
+
+def test_three_walker_workload_one_output_interval_c64():
+    """The three-walker workload's parameters (nearest-neighbour U = 1,
+    eps ~ U[-1, 1], J = 1, dt = 0.02, tolerance 1e-7, complex64, start at the
+    centre) on a reduced lattice N = 48, for one output interval of 50 steps,
+    against the oracle's exact evolution: amplitudes within 2e-6, ensemble
+    occupation and pair correlation within 1e-6, norms within 1e-6."""
+    w = scaled(C5(), N=48, R=3, start=(23, 24, 25))
+    reals = w.all_realizations()
+    steps = 50
+    say(f"case: {w.name} reduced to N=48 R=3, {steps} steps c64")
+    plan = gpu_plan(m=3, statistics="distinguishable", boundary="open", interaction="nearest", dtype="c64",
+                    reals=reals, dt=w.dt, tol=w.tol, observables=3, sites=list(w.start))
+    out = plan.propagate(steps, steps, 3)
+    psi = plan.state_numpy()
+    st = B.basis_states(w.N, 3)
+    worst, occ, pair = 0.0, [], []
+    D = w.N ** 3
+    for r, (N, J, eps, U) in enumerate(reals):
+        H = Hm.hamiltonian(N, 3, J, eps, U, B.DISTINGUISHABLE, "open", "nearest")
+        ref, _, _ = P.evolve_taylor(H, B.product_state(N, list(w.start)), w.dt, steps, tol=1e-15)
+        worst = max(worst, float(np.max(np.abs(psi[r * D:(r + 1) * D] - ref))))
+        occ.append(O.occupation(ref, st, N))
+        pair.append(O.pair_correlation(ref, st, N))
+    e_occ = float(np.max(np.abs(out[-1][:w.N] - O.ensemble_mean(occ))))
+    e_pair = float(np.max(np.abs(out[-1][w.N:].reshape(w.N, w.N) - O.ensemble_mean(pair))))
+    n2, _ = plan.realization_norms()
+    say(f"  order {int(plan.orders().max())}: amplitude {worst:.2e}, occupation {e_occ:.2e}, pair {e_pair:.2e}, "
+        f"|norm - 1| {np.max(np.abs(np.sqrt(n2) - 1)):.1e}")
+    assert worst <= 2e-6 and e_occ <= 1e-6 and e_pair <= 1e-6
+    assert np.max(np.abs(np.sqrt(n2) - 1)) <= 1e-6
+
+
+def test_three_walker_autotune_picks_a_pass_depth():
+    """The autotuner times 1, 2 and 3 terms per pass for three walkers and
+    applies the fastest; the tuned plan still matches the oracle."""
+    N, R, dt, steps = 9, 2, 0.02, 10
+    reals = reals3(N, R, 5)
+    sites = [2, 4, 6]
+    say("case: m=3 autotune N=9 c128")
+    plan = gpu_plan(m=3, statistics="distinguishable", boundary="open", interaction="nearest", dtype="c128",
+                    reals=reals, dt=dt, tol=1e-14)
+    best, ms = plan.autotune(steps=2)
+    assert best.terms_per_pass in (1, 2, 3) and ms > 0
+    plan.init_product_state(sites)
+    plan.propagate(steps)
+    psi = plan.state_numpy()
+    for r, (n, J, eps, U) in enumerate(reals):
+        H = Hm.hamiltonian(N, 3, J, eps, U, B.DISTINGUISHABLE, "open", "nearest")
+        ref = P.EDPropagator(H).evolve(B.product_state(N, sites), dt * steps)
+        assert np.max(np.abs(psi[r * N ** 3:(r + 1) * N ** 3] - ref)) <= 1e-10
 
 
 @pytest.mark.parametrize("acc", ["kahan", "plain"])

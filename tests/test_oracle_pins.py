@@ -122,6 +122,31 @@ def test_product_form_bosons():
     assert np.max(np.abs(psi - expect)) < 1e-12
 
 
+@pytest.mark.parametrize("sites", [(3, 6), (6, 3)])
+def test_product_form_fermions(sites):
+    """U = 0 fermions: the Slater determinant of the evolved orbitals; in the
+    antisymmetric basis c_{x<y} = phi_1(x) phi_2(y) - phi_2(x) phi_1(y) with
+    phi_a = exp(-i H1 t)|s_a> (particle a started on sites[a]: swapping the
+    start sites flips the sign), and the full-grid state A c is
+    antisymmetric under exchange."""
+    g = rng(12)
+    N = 10
+    J = 1 + g.uniform(-0.3, 0.3, N - 1)
+    eps = g.uniform(-0.5, 0.5, N)
+    t = 2.1
+    U1 = one_particle_orbitals(J, eps, t)
+    f1, f2 = U1[:, sites[0]], U1[:, sites[1]]
+    det = np.outer(f1, f2) - np.outer(f2, f1)
+    psi = P.EDPropagator(Hm.hamiltonian(N, 2, J, eps, 0.0, B.FERMION)).evolve(
+        B.product_state(N, list(sites), B.FERMION), t)
+    states = B.basis_states(N, 2, B.FERMION)
+    assert np.max(np.abs(psi - det[states[:, 0], states[:, 1]])) < 1e-12
+    full = (B.antisymmetrizer(N, 2) @ psi).reshape(N, N)
+    assert np.max(np.abs(full + full.T)) < 1e-15
+    assert np.max(np.abs(np.diag(full))) == 0.0
+    assert abs(np.linalg.norm(psi) - 1) < 1e-13
+
+
 def test_two_site_boson_closed_form():
     """N = 2, two bosons: basis (0,0), (0,1), (1,1) and
     H = [[2e0+U, sqrt2 J, 0], [sqrt2 J, e0+e1, sqrt2 J], [0, sqrt2 J, 2e1+U]]."""
@@ -155,6 +180,19 @@ def second_quantised(N, m, J, eps, U, statistics, boundary, interaction):
         H[k, k] += diag
         for bi, (i, j) in enumerate(bonds):
             for src, dst in ((i, j), (j, i)):
+                if statistics == B.FERMION:
+                    # c+_dst c_src on the normal-ordered state c+_x1 ... c+_xm |0>:
+                    # Jordan-Wigner sign (-1)^(occupied nodes strictly between)
+                    if occ[src] == 0 or occ[dst] == 1:
+                        continue
+                    lo, hi = min(src, dst), max(src, dst)
+                    sign = (-1) ** int(occ[lo + 1:hi].sum())
+                    new = occ.copy()
+                    new[src] -= 1
+                    new[dst] += 1
+                    t = tuple(int(v) for v in np.nonzero(new)[0])
+                    H[index[t], k] += J[bi] * sign
+                    continue
                 if statistics == B.DISTINGUISHABLE:
                     for a in range(m):
                         if s[a] == src:
@@ -180,6 +218,10 @@ def second_quantised(N, m, J, eps, U, statistics, boundary, interaction):
     (3, B.BOSON, Hm.OPEN, Hm.ONSITE),
     (2, B.DISTINGUISHABLE, Hm.PERIODIC, Hm.NEAREST),
     (2, B.BOSON, Hm.PERIODIC, Hm.ONSITE),
+    (2, B.FERMION, Hm.OPEN, Hm.NEAREST),
+    (2, B.FERMION, Hm.OPEN, Hm.ONSITE),
+    (2, B.FERMION, Hm.PERIODIC, Hm.NEAREST),
+    (3, B.FERMION, Hm.PERIODIC, Hm.NEAREST),
 ])
 def test_hamiltonian_matches_second_quantised(m, statistics, boundary, interaction):
     g = rng(3)
