@@ -90,7 +90,10 @@ def cpu_baseline(w, budget_s: float = 10.0):
     each propagated step by step for `budget_s` seconds; the rate is the
     summed updates over the summed per-process seconds times the cores."""
     import multiprocessing as mp
-    cores = min(host_cores(), 16)
+    # one process per core of the host's CPU share (the GPU box gives one GPU
+    # 16 cores, whatever the affinity mask shows)
+    available = host_cores()
+    cores = min(available, 16)
     sizes = w.lattice_sizes()
     sample = list(range(min(cores, w.R)))
     jobs = [(int(sizes[r]),) + w.realization(r, int(sizes[r])) + (w.dt, w.tol, budget_s) for r in sample]
@@ -101,7 +104,8 @@ def cpu_baseline(w, budget_s: float = 10.0):
     wall = time.perf_counter() - t0
     updates = sum(r[0] for r in res)
     per_proc_rate = updates / sum(r[1] for r in res)
-    return {"value": per_proc_rate * cores, "unit": "amplitude-updates/s", "cores": cores, "kind": "oracle",
+    return {"value": per_proc_rate * cores, "unit": "amplitude-updates/s", "cores": cores,
+            "cores_in_affinity_mask": available, "kind": "oracle",
             "sample": f"realisations 0..{len(sample) - 1} (N = {[int(sizes[r]) for r in sample]}), "
                       f"{sum(r[2] for r in res)} steps in total of the FP64 CSR Taylor oracle (tol {w.tol:g}), "
                       f"{budget_s:g} s of propagation per process, {cores} processes",
@@ -238,6 +242,76 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
     print(f"wrote {out}")
 
 
+def kernel_summary(out, title, workload, commands, match, trace_dir, fetch_dir=None, write_dir=None,
+                   counters_dir=None, per_step_dispatches=1, algorithmic_bytes_per_step=None):
+    """A rocprofv3 summary of the kernels whose name contains `match`:
+    duration statistics from the kernel trace; optionally FETCH_SIZE /
+    WRITE_SIZE per dispatch scaled by the same counters of the 4 GiB copy
+    probe of the run (HBM bytes per step), and the average of every other
+    counter found under `counters_dir` (e.g. SQ_WAVE_CYCLES, SQ_BUSY_CYCLES,
+    SQ_ACTIVE_INST_VALU).  Per-step figures sum `per_step_dispatches`
+    dispatches' averages."""
+    def find(d, suffix):
+        for root, _, files in os.walk(d):
+            for f in files:
+                if f.endswith(suffix):
+                    return os.path.join(root, f)
+        raise FileNotFoundError(f"{suffix} under {d}")
+    stats = [r for r in _rows(find(trace_dir, "kernel_stats.csv")) if match in r["Name"]]
+    if not stats:
+        raise SystemExit(f"no kernel matching {match!r} in the trace")
+    step_ns = sum(float(r["AverageNs"]) * int(r["Calls"]) for r in stats) / (
+        sum(int(r["Calls"]) for r in stats) / per_step_dispatches)
+    lines = [f"# {title}", "", *workload, "", "Commands (from the repository root, TMPDIR=/tmp):", "",
+             *[f"    {c}" for c in commands], "",
+             "| kernel | dispatches | average | min / max |", "|---|---|---|---|",
+             *[f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} ms | "
+               f"{float(r['MinNs']) / 1e6:.4f} / {float(r['MaxNs']) / 1e6:.4f} ms |" for r in stats], "",
+             "| per step | value |", "|---|---|",
+             f"| kernel time per step ({per_step_dispatches} dispatches) | {step_ns / 1e6:.4f} ms |"]
+    if algorithmic_bytes_per_step:
+        lines.append(f"| algorithmic bytes per step | {algorithmic_bytes_per_step / 1e9:.3f} GB |")
+        lines.append(f"| algorithmic GB/s (fraction of 8 TB/s) | {algorithmic_bytes_per_step / step_ns:.1f} "
+                     f"({algorithmic_bytes_per_step / step_ns / HBM_PEAK_GBS:.4f}) |")
+    if fetch_dir and write_dir:
+        def counter(d, name):
+            rows = [r for r in _rows(find(d, "counter_collection.csv")) if r["Counter_Name"] == name]
+            k = [float(r["Counter_Value"]) for r in rows if match in r["Kernel_Name"]]
+            c = [float(r["Counter_Value"]) for r in rows
+                 if "copyBuffer" in r["Kernel_Name"] and int(r["Grid_Size"]) >= 100000]
+            if not k or not c:
+                raise SystemExit(f"{name}: kernel or copy probe dispatches missing in {d}")
+            return sum(k) / len(k), sum(c) / len(c)
+        fk, fc = counter(fetch_dir, "FETCH_SIZE")
+        wk, wc = counter(write_dir, "WRITE_SIZE")
+        probe = 4096 << 20
+        fb = fk * 1024.0 * probe / (fc * 1024.0) * per_step_dispatches
+        wb = wk * 1024.0 * probe / (wc * 1024.0) * per_step_dispatches
+        lines += [f"| FETCH_SIZE per dispatch (copy probe: {fc:.0f} KiB for 4 GiB) | {fk:.0f} KiB |",
+                  f"| WRITE_SIZE per dispatch (copy probe: {wc:.0f} KiB for 4 GiB) | {wk:.0f} KiB |",
+                  f"| HBM bytes read per step | {fb / 1e9:.3f} GB |",
+                  f"| HBM bytes written per step | {wb / 1e9:.3f} GB |"]
+        if algorithmic_bytes_per_step:
+            lines.append(f"| counted / algorithmic bytes | {(fb + wb) / algorithmic_bytes_per_step:.3f} |")
+    if counters_dir:
+        rows = [r for r in _rows(find(counters_dir, "counter_collection.csv")) if match in r["Kernel_Name"]]
+        names = sorted({r["Counter_Name"] for r in rows})
+        avg = {n: sum(float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == n) /
+               max(1, sum(1 for r in rows if r["Counter_Name"] == n)) for n in names}
+        lines += ["", "| counter (average per dispatch) | value |", "|---|---|",
+                  *[f"| {n} | {avg[n]:.6g} |" for n in names]]
+        if "SQ_ACTIVE_INST_VALU" in avg and "SQ_WAVE_CYCLES" in avg and avg["SQ_WAVE_CYCLES"] > 0:
+            lines.append(f"| SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES | {avg['SQ_ACTIVE_INST_VALU'] / avg['SQ_WAVE_CYCLES']:.4f} |")
+        if "SQ_BUSY_CYCLES" in avg and "SQ_WAVE_CYCLES" in avg and avg["SQ_BUSY_CYCLES"] > 0:
+            lines.append(f"| SQ_WAVE_CYCLES / SQ_BUSY_CYCLES (waves resident per busy cycle) | "
+                         f"{avg['SQ_WAVE_CYCLES'] / avg['SQ_BUSY_CYCLES']:.3f} |")
+    lines.append("")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines))
+    print(f"wrote {out}")
+
+
 # ---------------------------------------------------------------- GPU side
 
 def build_plan(w, dtype, accumulation, launch, tol):
@@ -280,6 +354,34 @@ def time_plan(plan, steps, warmup):
     if launches != steps:
         raise RuntimeError(f"timed {launches} step kernels for {steps} steps")
     return wall, kern_ms / launches
+
+
+def sample_errors(w, sample, steps, runs):
+    """Max-abs amplitude error after `steps` steps of the sampled
+    realisations for each (dtype, tol) in `runs`, against the complex128 GPU
+    path at tolerance 1e-14 (itself held to 1e-10 of the FP64 oracle by the
+    tests).  Small plans of the sample alone; launch shapes do not change
+    the results."""
+    from paper_1612_00746_amd import Plan, make_problem
+    sizes = w.lattice_sizes()
+    reals = w.all_realizations(sample)
+    Ns = [int(sizes[r]) for r in sample]
+    J = np.concatenate([r[1] for r in reals])
+    eps = np.concatenate([r[2] for r in reals])
+    U = np.array([r[3] for r in reals])
+
+    def final(dtype, tol):
+        pr, keep = make_problem(2, len(sample), Ns, w.dt, statistics=w.statistics, dtype=dtype,
+                                accumulation="kahan", taylor_tol=tol)
+        p = Plan(pr)
+        p._keep.append(keep)
+        p.set_params(J, eps, U)
+        p.bind()
+        p.init_product_state(np.array([[n // 2 - 1, n // 2] for n in Ns], dtype=np.int32))
+        p.propagate(steps)
+        return p.state_numpy().astype(np.complex128)
+    ref = final("c128", 1e-14)
+    return [float(np.max(np.abs(final(dt, tol) - ref))) for dt, tol in runs]
 
 
 def rk4_compare(a):
@@ -402,11 +504,13 @@ def graph(a):
     nodes), 4096 noisy realisations (J = 1 + 0.1 N(0, 1) per bond,
     eps ~ U[-0.5, 0.5]), dt = 0.05, 10 Taylor terms per step, one pass per
     term; complex128 with FP64 tables, then complex64 with FP32 tables.
-    Algorithmic bytes per node, realisation and term (e = 16 or 8 bytes per
-    amplitude, f = 8 or 4 per real): the previous term (e; neighbours
-    counted as cache hits), the on-site energy (f), width couplings (f
-    each), the partial sum in and out (2e) and the term out (e, not on the
-    last term)."""
+    The roofline fraction counts the algorithmic bytes of a step, read psi
+    and write psi once (2e per node and realisation, e = 16 or 8 bytes per
+    amplitude), over the step time.  The bytes the one-term passes move are
+    reported beside it: per node, realisation and term the previous term (e;
+    neighbours counted as cache hits), the on-site energy (f = 8 or 4 bytes
+    per real), width couplings (f each), the partial sum in and out (2e)
+    and the term out (e, not on the last term)."""
     import torch
     from paper_1612_00746_amd import ell_tables, graph_evolve, lattice_edges
     side, R, order, dt = 128, 4096, 10, 0.05
@@ -437,13 +541,19 @@ def graph(a):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         per_term = e + f + f * width + 2 * e + e
-        bytes_step = (order * per_term - e) * R * n
+        moved = (order * per_term - e) * R * n
+        alg = 2 * e * R * n
         norm = float(torch.linalg.vector_norm(psi[0].to(torch.complex128)).item())
         print(json.dumps({"metric": "graph walk node-updates/s", "workload": "128 x 128 lattice, 4096 realisations",
                           "dtype": dtype, "order": order, "width": width, "ms_per_step": round(ms, 4),
                           "value": R * n / (ms * 1e-3), "unit": "node-updates/s",
-                          "achieved_GBps": round(bytes_step / (ms * 1e-3) / 1e9, 1),
-                          "frac_hbm": round(bytes_step / (ms * 1e-3) / 8e12, 4), "norm_r0": norm}), flush=True)
+                          "roofline": {"bound": "hbm", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(alg / (ms * 1e-3) / 8e12, 4),
+                                       "bytes_per_update_algorithmic": 2 * e,
+                                       "bytes_per_update_moved": round(moved / (R * n), 1),
+                                       "moved_GBps": round(moved / (ms * 1e-3) / 1e9, 1)},
+                          "norm_r0": norm}), flush=True)
         del hop_d, eps_d, psi, ws
         torch.cuda.empty_cache()
 
@@ -502,6 +612,54 @@ def three_walkers(a):
     torch.cuda.empty_cache()
 
 
+def adjoint(a):
+    """Seconds per gradient of the gradient workload: two bosons on N = 256,
+    U = 1, 512 realisations, loss = probability that both are in nodes
+    192..255 after 400 steps of dt = 0.05, gradients with respect to the 255
+    baseline hoppings and 256 on-site energies, checkpoints every 32 steps
+    (the forward run with checkpoints, then the adjoint: recomputation of
+    each segment and the Horner recursion with the FP64 contractions);
+    complex64 and complex128.  Timed with HIP events on the plan's stream
+    around the whole gradient call, after one untimed gradient."""
+    import torch
+    from paper_1612_00746_amd import Plan, make_problem
+    from workloads import C4
+    for dtype in ("c64", "c128"):
+        w = C4(dtype)
+        reals = w.all_realizations()
+        J = np.concatenate([r[1] for r in reals])
+        eps = np.concatenate([r[2] for r in reals])
+        U = np.array([r[3] for r in reals])
+        pr, keep = make_problem(2, w.R, w.N, w.dt, statistics="boson", dtype=dtype, taylor_tol=w.tol)
+        plan = Plan(pr)
+        plan._keep.append(keep)
+        plan.set_params(J, eps, U)
+        plan.bind()
+        sw = (np.arange(w.N) >= 192).astype(float)
+        times = []
+        for k in range(3):
+            plan.init_product_state(list(w.start))
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(torch.cuda.current_stream())
+            loss, gJ, gE = plan.gradient(w.n_steps, 32, sw, "product")
+            e1.record(torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            if k:
+                times.append(e0.elapsed_time(e1) * 1e-3)
+        sec = float(np.median(times))
+        amps = w.R * w.N * (w.N + 1) // 2
+        print(json.dumps({"metric": "seconds per gradient", "value": round(sec, 4), "unit": "s",
+                          "higher_is_better": False, "dtype": dtype,
+                          "config": {"workload": w.name, "realisations": w.R, "sites": w.N, "steps": w.n_steps,
+                                     "checkpoint_every": 32, "taylor_order": int(plan.orders().max()),
+                                     "amplitudes": amps},
+                          "loss": loss, "grad_norm": float(np.linalg.norm(np.concatenate([gJ, gE]))),
+                          "forward_equivalent_steps_per_s": round(w.n_steps / sec, 1)}), flush=True)
+        del plan
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -512,8 +670,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (for scaling HBM counters)")
+    ap.add_argument("--copy-probe-mib", type=int, default=4096,
+                    help="a plain device copy of this size, timed as the practical HBM roof (0: skip)")
     ap.add_argument("--regular", action="store_true", help="one block per item group instead of the persistent grid")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep --cols-per-lane, --waves-per-block and --waves-per-cu")
@@ -523,6 +681,17 @@ def main():
                     help="write the step kernel's rocprofv3 summary under profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line recorded in the profile summary (repeatable)")
+    ap.add_argument("--kernel-summary", metavar="OUT",
+                    help="write a rocprofv3 summary of the kernels matching --match to OUT and exit")
+    ap.add_argument("--match", default="", help="kernel-name substring for --kernel-summary")
+    ap.add_argument("--title", default="", help="title of the --kernel-summary")
+    ap.add_argument("--workload-line", action="append", default=[], help="workload description line (repeatable)")
+    ap.add_argument("--trace-dir", help="--kernel-summary: rocprofv3 --kernel-trace --stats output directory")
+    ap.add_argument("--fetch-dir", help="--kernel-summary: rocprofv3 --pmc FETCH_SIZE output directory")
+    ap.add_argument("--write-dir", help="--kernel-summary: rocprofv3 --pmc WRITE_SIZE output directory")
+    ap.add_argument("--counters-dir", help="--kernel-summary: rocprofv3 --pmc output with other counters")
+    ap.add_argument("--per-step", type=int, default=1, help="--kernel-summary: matching dispatches per step")
+    ap.add_argument("--alg-bytes", type=float, default=0.0, help="--kernel-summary: algorithmic bytes per step")
     ap.add_argument("--rk4-compare", action="store_true",
                     help="time Alg. 2 (RK4) against the adaptive Taylor step at equal per-step accuracy on the batch")
     ap.add_argument("--graph", action="store_true",
@@ -533,12 +702,18 @@ def main():
                     help="time the ensemble density matrix of 1000 two-boson states on N = 128 (complex64)")
     ap.add_argument("--three-walkers", action="store_true",
                     help="time the three-walker path instead (64 x 256^3 amplitudes, complex64)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time one gradient of the gradient workload (512 x two bosons, N = 256, 400 steps)")
     ap.add_argument("--terms-per-pass", type=int, default=0,
                     help="three walkers: Taylor terms chained per pass (0: the library's default)")
     a = ap.parse_args()
     if a.profile_summary:
         profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane,
                         waves_per_block=a.waves_per_block, waves_per_cu=a.waves_per_cu)
+        return
+    if a.kernel_summary:
+        kernel_summary(a.kernel_summary, a.title or a.match, a.workload_line, a.profile_command, a.match,
+                       a.trace_dir, a.fetch_dir, a.write_dir, a.counters_dir, a.per_step, a.alg_bytes or None)
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: realisations are independent, and a multi-GPU run would "
@@ -548,6 +723,9 @@ def main():
 
     if a.three_walkers:
         three_walkers(a)
+        return
+    if a.adjoint:
+        adjoint(a)
         return
     if a.rk4_compare:
         rk4_compare(a)
@@ -577,14 +755,17 @@ def main():
         n = a.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        dt_copy = (time.perf_counter() - t0) / 5
+        dt_copy = e0.elapsed_time(e1) * 1e-3 / 5
         copy_probe = {"bytes_read": n * 4, "bytes_written": n * 4,
-                      "gbs": round(2 * n * 4 / dt_copy / 1e9, 1)}
+                      "gbs": round(2 * n * 4 / dt_copy / 1e9, 1),
+                      "frac_of_peak": round(2 * n * 4 / dt_copy / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"copy probe: {copy_probe}")
         del src, dst
     sizes = w.lattice_sizes()
@@ -630,8 +811,19 @@ def main():
 
     fp64 = None
     if not a.no_fp64:
+        # Equal accuracy: the complex128 comparator runs at the loosest
+        # tolerance whose measured error on a sample of the batch (the
+        # smallest and largest chains and two more, 50 steps) is at most the
+        # complex64 path's on the same sample.
+        g = np.random.default_rng(5)
+        sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *g.choice(w.R, 2, replace=False).tolist()})
+        cands = [1e-4, 1e-5, 1e-6, 1e-7, 1e-8]
+        errs = sample_errors(w, sample, 50, [("c64", w.tol)] + [("c128", t) for t in cands])
+        e32, e64s = errs[0], dict(zip(cands, errs[1:]))
+        tol64 = next((t for t in cands if e64s[t] <= e32), cands[-1])
+        log(f"equal accuracy: c64 error {e32:.2e}; c128 errors {e64s} -> tol {tol64:g}")
         log("building the complex128 plan ...")
-        p64 = build_plan(w, "c128", "plain", {"cols_per_lane": 1, "persistent": 0, "waves_per_block": 4}, w.tol)
+        p64 = build_plan(w, "c128", "plain", {"cols_per_lane": 1, "persistent": 0, "waves_per_block": 4}, tol64)
         wall64, kern64 = time_plan(p64, max(2, a.steps // 2), 2)
         log(f"complex128: kernel {kern64:.3f} ms")
         s64 = max(2, a.steps // 2)
@@ -639,7 +831,12 @@ def main():
                 "ms_per_step": round(1e3 * wall64 / s64, 4),
                 "kernel_ms": round(kern64, 4),
                 "hbm_gbs_algorithmic": round(amps * 32.0 / (kern64 * 1e-3) / 1e9, 1),
-                "taylor_order": int(p64.orders().max()), "launch": "regular, one per Taylor order and step"}
+                "taylor_tol": tol64,
+                "taylor_order": [int(p64.orders().min()), int(p64.orders().max())],
+                "launch": "regular, one per Taylor order and step",
+                "equal_accuracy": {"sample": sample, "steps": 50, "reference": "complex128 GPU path at tol 1e-14",
+                                   "c64_max_abs_err": e32, "c128_max_abs_err": e64s[tol64],
+                                   "c128_err_by_tol": {f"{t:g}": e for t, e in e64s.items()}}}
         del p64
         torch.cuda.empty_cache()
 

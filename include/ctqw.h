@@ -385,17 +385,21 @@ ctqw_status ctqw_groups(const ctqw_plan* plan, int32_t* n_groups, int32_t* sizes
 /* Ensemble-averaged density matrix of one group (Eq. 2; the paper updates
  * it with one Hermitian rank-1 update per realisation):
  *     rho_g = (1/R_g) sum_{r in g} |psi_r><psi_r|,
- * D_g x D_g complex of the plan's dtype in the basis of ctqw_layout (bosons:
- * the normalised symmetric basis, coefficient sqrt(2) phi off the
- * diagonal), column-major with leading dimension ld >= D_g, written to the
- * caller's device memory rho.  lower_only != 0: only the lower triangle is
- * written; else the full Hermitian matrix.  workspace: device memory of at
- * least ctqw_density_workspace(group) bytes (the group's states gathered
- * with the load scale into a D_g x R_g matrix); rho = A A^H / R_g is one
- * rocBLAS cherk / zherk on the matrix cores.  Enqueued on the plan's
- * stream.  Errors: INVALID_ARG (NULL, group out of range, ld or workspace
- * too small), UNSUPPORTED (D_g or ld >= 2^31, R_g > 65535), STATE (not
- * bound), DEVICE.                                                         */
+ * D_g x D_g complex of the plan's dtype in the basis of ctqw_layout (bosons
+ * and fermions: the triangle basis, coefficient sqrt(2) phi off the
+ * diagonal; the fermions' diagonal rows and columns are zero), column-major
+ * with leading dimension ld >= D_g, written to the caller's device memory
+ * rho.  lower_only != 0: only the lower triangle is written (the upper one
+ * is left as it was); else the full Hermitian matrix.  workspace: device
+ * memory of at least ctqw_density_workspace(group) bytes, which receives
+ * the group's states (load scale and basis weights applied) as real and
+ * imaginary planes padded with zeros to whole tiles (128 rows complex64, 64
+ * complex128) and stages (16 / 8 realisations); the lower triangle of
+ * rho = A A^H / R_g is then formed tile by tile on the matrix cores
+ * (FP32 MFMA for complex64, FP64 MFMA for complex128).  Enqueued on the
+ * plan's stream.  Errors: INVALID_ARG (NULL, group out of range, ld or
+ * workspace too small), UNSUPPORTED (D_g or ld >= 2^31, R_g > 65535),
+ * STATE (not bound), DEVICE.                                              */
 ctqw_status ctqw_density_workspace(const ctqw_plan* plan, int32_t group, int64_t* bytes);
 ctqw_status ctqw_density_matrix(ctqw_plan* plan, int32_t group, void* rho, int64_t ld, int32_t lower_only,
                                 void* workspace, int64_t workspace_bytes);

@@ -61,7 +61,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
                 raise RuntimeError(f"hipcc failed for {obj}")
             objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lrocblas"]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         print(res.stdout + res.stderr, file=sys.stderr)

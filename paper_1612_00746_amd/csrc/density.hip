@@ -1,14 +1,12 @@
 // Ensemble-averaged density matrix of one lattice-size group (Eq. 2):
 //   rho = (1/R_g) sum_{r in g} |psi_r><psi_r|,
-// in the basis of the state layout (bosons: the normalised symmetric basis,
+// in the basis of the state layout (bosons and fermions: the triangle basis,
 // whose coefficients are sqrt(2) phi off the diagonal).  The group's states
-// are gathered into a D x R_g column-major matrix A (load scale and basis
-// weights applied), then rho = A A^H / R_g is one Hermitian rank-R_g update
-// (a plain library contraction: rocBLAS cherk / zherk, on the matrix cores);
-// a last kernel mirrors the lower triangle when the full matrix is asked for.
+// are gathered into split real / imaginary planes (load scale and basis
+// weights applied, zero padding to whole tiles and stages), the lower
+// triangle of rho = A A^H / R_g is formed on the matrix cores (herk.hip),
+// and a last kernel mirrors it when the full matrix is asked for.
 #include "density.hpp"
-
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 
@@ -17,9 +15,17 @@ namespace {
 
 template <typename C>
 __global__ void gather_group_kernel(DensityArgs a) {
-    const int64_t k = blockIdx.y;   // member index in the group
+    using T = decltype(C{}.x);
+    const int64_t k = blockIdx.y;   // member index in the group (padded)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.D) return;
+    if (i >= a.Dp) return;
+    T* re = reinterpret_cast<T*>(a.A) + k * a.Dp + i;
+    T* im = re + a.Rp * a.Dp;
+    if (i >= a.D || k >= a.R_g) {
+        *re = T(0);
+        *im = T(0);
+        return;
+    }
     const int32_t r = a.members[k];
     const RealDev rd = a.reals[r];
     const C* psi = reinterpret_cast<const C*>(a.psi) + rd.state_off;
@@ -34,10 +40,9 @@ __global__ void gather_group_kernel(DensityArgs a) {
         const int x2 = x1 + (int)(i - row0);
         if (x2 != x1) w *= 1.4142135623730950488;
     }
-    C v = psi[i];
-    v.x = static_cast<decltype(v.x)>(v.x * w);
-    v.y = static_cast<decltype(v.y)>(v.y * w);
-    reinterpret_cast<C*>(a.A)[i + a.D * k] = v;
+    const C v = psi[i];
+    *re = static_cast<T>(v.x * w);
+    *im = static_cast<T>(v.y * w);
 }
 
 // rho[j][i] = conj(rho[i][j]) for i > j (column-major, ld): the upper
@@ -77,8 +82,8 @@ __global__ __launch_bounds__(256) void mirror_kernel(void* rho, int64_t D, int64
 }  // namespace
 
 hipError_t launch_density_gather(const DensityArgs& a, int dtype, hipStream_t s) {
-    if (a.R_g <= 0 || a.R_g > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((a.D + 255) / 256), (unsigned)a.R_g);
+    if (a.R_g <= 0 || a.Rp > 65535 || a.Rp < a.R_g || a.Dp < a.D) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.Dp + 255) / 256), (unsigned)a.Rp);
     if (dtype == 1)
         hipLaunchKernelGGL(gather_group_kernel<double2>, grid, dim3(256), 0, s, a);
     else
@@ -95,35 +100,6 @@ hipError_t launch_density_mirror(void* rho, int64_t D, int64_t ld, int dtype, hi
     else
         hipLaunchKernelGGL(mirror_kernel<float2>, grid, dim3(256), 0, s, rho, D, ld);
     return hipGetLastError();
-}
-
-// rho (lower triangle) = A A^H / R_g with A: D x R_g, column-major.
-int density_herk(void** handle, hipStream_t s, int dtype, int64_t D, int64_t R_g, const void* A, void* rho,
-                 int64_t ld) {
-    if (!*handle) {
-        rocblas_handle h = nullptr;
-        if (rocblas_create_handle(&h) != rocblas_status_success) return -1;
-        *handle = h;
-    }
-    rocblas_handle h = static_cast<rocblas_handle>(*handle);
-    if (rocblas_set_stream(h, s) != rocblas_status_success) return -2;
-    rocblas_status st;
-    if (dtype == 1) {
-        const double alpha = 1.0 / (double)R_g, beta = 0.0;
-        st = rocblas_zherk(h, rocblas_fill_lower, rocblas_operation_none, (rocblas_int)D, (rocblas_int)R_g, &alpha,
-                           static_cast<const rocblas_double_complex*>(A), (rocblas_int)D, &beta,
-                           static_cast<rocblas_double_complex*>(rho), (rocblas_int)ld);
-    } else {
-        const float alpha = (float)(1.0 / (double)R_g), beta = 0.0f;
-        st = rocblas_cherk(h, rocblas_fill_lower, rocblas_operation_none, (rocblas_int)D, (rocblas_int)R_g, &alpha,
-                           static_cast<const rocblas_float_complex*>(A), (rocblas_int)D, &beta,
-                           static_cast<rocblas_float_complex*>(rho), (rocblas_int)ld);
-    }
-    return st == rocblas_status_success ? 0 : (int)st;
-}
-
-void density_release(void* handle) {
-    if (handle) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
 }
 
 }  // namespace ctqw

@@ -118,12 +118,10 @@ struct ctqw_plan {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
     }
-    void* blas = nullptr;            // rocBLAS handle of the density-matrix update (lazy)
     double tele_amp = 0.0, tele_rate = 0.0;   // switching hopping noise (0: static)
     uint64_t tele_seed = 0;
     ~ctqw_plan() {
         drop_graphs();
-        density_release(blas);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
@@ -1358,7 +1356,10 @@ ctqw_status ctqw_density_workspace(const ctqw_plan* p, int32_t group, int64_t* b
     if (group < 0 || group >= (int32_t)p->group_N.size())
         return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "group %d out of range", group);
     const int64_t Rg = p->group_first[group + 1] - p->group_first[group];
-    *bytes = group_dim(p, group) * Rg * (p->prob.dtype == CTQW_C128 ? 16 : 8);
+    const int dtype = p->prob.dtype == CTQW_C128 ? 1 : 0;
+    const int64_t tile = herk_tile(dtype), stage = herk_stage(dtype);
+    const int64_t Dp = (group_dim(p, group) + tile - 1) / tile * tile, Rp = (Rg + stage - 1) / stage * stage;
+    *bytes = 2 * Dp * Rp * (dtype ? 8 : 4);   // real and imaginary planes, zero padded
     return CTQW_OK;
 }
 
@@ -1388,9 +1389,21 @@ ctqw_status ctqw_density_matrix(ctqw_plan* p, int32_t group, void* rho, int64_t 
     a.D = D;
     a.R_g = Rg;
     a.triangle = (p->prob.m == 2 && p->prob.statistics != CTQW_DISTINGUISHABLE) ? 1 : 0;
+    const int64_t tile = herk_tile(dtype), stage = herk_stage(dtype);
+    a.Dp = (D + tile - 1) / tile * tile;
+    a.Rp = (Rg + stage - 1) / stage * stage;
     HIP_TRY(p, launch_density_gather(a, dtype, p->stream));
-    const int e = density_herk(&p->blas, p->stream, dtype, D, Rg, workspace, rho, ld);
-    if (e != 0) return fail(p, CTQW_ERR_DEVICE, "Hermitian rank-k update failed (rocBLAS status %d)", e);
+    HerkArgs h{};
+    h.G = workspace;
+    h.rho = rho;
+    h.D = D;
+    h.Dp = a.Dp;
+    h.ld = ld;
+    h.Rp = (int32_t)a.Rp;
+    const int64_t T = a.Dp / tile;
+    h.n_tiles = T * (T + 1) / 2;
+    h.inv_R = 1.0 / (double)Rg;
+    HIP_TRY(p, launch_herk(h, dtype, p->stream));
     if (!lower_only) HIP_TRY(p, launch_density_mirror(rho, D, ld, dtype, p->stream));
     return CTQW_OK;
 }

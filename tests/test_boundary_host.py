@@ -372,22 +372,24 @@ def test_switching_noise_orders_and_validation():
 
 
 def test_density_matrix_arguments_are_checked():
-    """Workspace size of a group's density matrix (D x R_g amplitudes),
-    group range and the state of the plan (not bound) are checked on the
-    host."""
+    """Workspace size of a group's density matrix (real and imaginary
+    planes of D x R_g padded to whole 128-row tiles and 16-realisation
+    stages for complex64), group range and the state of the plan (not
+    bound) are checked on the host."""
     import ctypes as C2
     plan = make(R=3, n_sites=[6, 8, 6], dtype="c64", taylor_tol=1e-7)
     J, eps, U = draw(8, 3, 7)
     plan.set_params(np.concatenate([J[0:5], J[7:14], J[14:19]]), np.concatenate([eps[0:6], eps[8:16], eps[16:22]]), U)
     ws = C2.c_int64()
     assert plan.lib.ctqw_density_workspace(plan.h, 0, C2.byref(ws)) == 0
-    assert ws.value == 36 * 2 * 8            # N = 6: D = 36, two realisations, complex64
+    assert ws.value == 2 * 128 * 16 * 4      # N = 6: D = 36 -> 128 rows, two realisations -> 16, two FP32 planes
     assert plan.lib.ctqw_density_workspace(plan.h, 1, C2.byref(ws)) == 0
-    assert ws.value == 64 * 1 * 8
+    assert ws.value == 2 * 128 * 16 * 4
     assert plan.lib.ctqw_density_workspace(plan.h, 2, C2.byref(ws)) == 1
-    buf = C2.create_string_buffer(4096)
-    assert plan.lib.ctqw_density_matrix(plan.h, 0, buf, 36, 0, buf, 4096) == 7   # STATE: not bound
-    assert plan.lib.ctqw_density_matrix(plan.h, 0, buf, 20, 0, buf, 4096) == 1   # ld below D
+    buf = C2.create_string_buffer(16384)
+    assert plan.lib.ctqw_density_matrix(plan.h, 0, buf, 36, 0, buf, 16384) == 7   # STATE: not bound
+    assert plan.lib.ctqw_density_matrix(plan.h, 0, buf, 20, 0, buf, 16384) == 1   # ld below D
+    assert plan.lib.ctqw_density_matrix(plan.h, 0, buf, 36, 0, buf, 16383) == 1   # workspace too small
 
 
 # ---------------------------------------------------------------- general graphs
