@@ -356,6 +356,33 @@ def time_plan(plan, steps, warmup):
     return wall, kern_ms / launches
 
 
+def run_copy_probe(mib):
+    """A plain device-to-device copy of `mib` MiB (torch), timed with HIP
+    events: the practical HBM roof beside the 8 TB/s peak, and the kernel
+    whose FETCH_SIZE / WRITE_SIZE counters scale those of the step kernels
+    in a rocprofv3 counter run.  None when mib <= 0."""
+    if mib <= 0:
+        return None
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    dt_copy = e0.elapsed_time(e1) * 1e-3 / 5
+    out = {"bytes_read": n * 4, "bytes_written": n * 4, "gbs": round(2 * n * 4 / dt_copy / 1e9, 1),
+           "frac_of_peak": round(2 * n * 4 / dt_copy / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"copy probe: {out}")
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def sample_errors(w, sample, steps, runs):
     """Max-abs amplitude error after `steps` steps of the sampled
     realisations for each (dtype, tol) in `runs`, against the complex128 GPU
@@ -572,6 +599,7 @@ def three_walkers(a):
     from paper_1612_00746_amd import Plan, make_problem
     from workloads import C5
     w = C5()
+    probe = run_copy_probe(a.copy_probe_mib)
     sizes = w.lattice_sizes()
     reals = w.all_realizations()
     J = np.concatenate([r[1] for r in reals])
@@ -607,6 +635,7 @@ def three_walkers(a):
                      "bytes_per_update_moved": impl_bytes,
                      "moved_GBps": round(amps * impl_bytes / (kern_ms * 1e-3) / 1e9, 1)},
         "norm_range": [st.min_norm, st.max_norm],
+        "copy_probe": probe,
     }))
     del plan
     torch.cuda.empty_cache()
@@ -748,26 +777,7 @@ def main():
         log(f"cpu baseline: {cpu['value']:.3e} updates/s on {cpu['cores']} cores ({cpu['seconds']} s)")
 
     import torch
-    copy_probe = None
-    if a.copy_probe_mib > 0:
-        # A plain device-to-device copy of known size: its HBM counters per
-        # dispatch give the scale between counter units and bytes moved.
-        n = a.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        e1.record()
-        torch.cuda.synchronize()
-        dt_copy = e0.elapsed_time(e1) * 1e-3 / 5
-        copy_probe = {"bytes_read": n * 4, "bytes_written": n * 4,
-                      "gbs": round(2 * n * 4 / dt_copy / 1e9, 1),
-                      "frac_of_peak": round(2 * n * 4 / dt_copy / 1e9 / HBM_PEAK_GBS, 4)}
-        log(f"copy probe: {copy_probe}")
-        del src, dst
+    copy_probe = run_copy_probe(a.copy_probe_mib)
     sizes = w.lattice_sizes()
     amps = int(np.sum(sizes.astype(np.int64) ** 2))
     launch = {"cols_per_lane": a.cols_per_lane, "persistent": 0 if a.regular else 1,

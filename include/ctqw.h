@@ -58,11 +58,12 @@ typedef enum { CTQW_OPEN = 0, CTQW_PERIODIC = 1 } ctqw_boundary;
 typedef enum { CTQW_INT_ONSITE = 0, CTQW_INT_NEAREST = 1 } ctqw_interaction;
 /* State precision: interleaved complex FP32 or FP64 (torch.complex64/128). */
 typedef enum { CTQW_C64 = 0, CTQW_C128 = 1 } ctqw_dtype;
-/* Summation of the Taylor terms within one step.  KAHAN: compensated
- * accumulation of sum_j Phi^(j) in a word pair (a, c) worth a - c: Kahan's
- * update adds the leading term Phi^(1) to psi exactly, the later (smaller)
- * terms are collected in c, and a - c is rounded once on output.  PLAIN:
- * ordinary accumulation.  The FP64 state always uses PLAIN.              */
+/* Summation of the Taylor terms within one step.  KAHAN (compensated):
+ * the terms Phi^(j), j >= 1, which are smaller than psi by x = dt ||H|| or
+ * more, are summed apart from psi and added to it once, so the new state
+ * takes one rounding per step (per pass for chained passes) instead of one
+ * per term.  PLAIN: each term is added to the running sum as it comes.  The
+ * FP64 state always uses PLAIN.                                           */
 typedef enum { CTQW_ACC_KAHAN = 0, CTQW_ACC_PLAIN = 1 } ctqw_accumulation;
 
 /* Observables (bit mask).  OCCUPATION: <n_i> = sum_x p(x) #{a : x_a = i},

@@ -250,8 +250,10 @@ class Plan:
         self._check(self.lib.ctqw_density_workspace(self.h, group, C.byref(ws_bytes)))
         psi_a = self._buffers[0]
         ctype = torch.complex128 if self.dtype == "c128" else torch.complex64
-        esz = 16 if self.dtype == "c128" else 8
-        D = int(round((ws_bytes.value // esz) / self.group_sizes(group)))
+        Ng = int(self.groups()[group])
+        r = next(k for k, n in enumerate(self.Ns) if n == Ng)
+        off = self.layout()
+        D = int(off[r + 1] - off[r])          # amplitudes of one realisation of the group
         # the full matrix is written element by element; lower_only leaves the upper at zero
         alloc = torch.zeros if lower_only else torch.empty
         rho = alloc((D, D), dtype=ctype, device=psi_a.device)

@@ -23,7 +23,8 @@
 // tile's column block, MFMA columns from its row block -- so that each
 // lane's accumulators hold consecutive rows of rho in column-major order
 // and the conjugated values are stored 256 contiguous bytes per half-wave.
-// Tiles on the diagonal store only their lower part.
+// Tiles on the diagonal store only their lower part; diagonal entries are
+// stored with imaginary part 0 (rho is Hermitian).
 #include "density.hpp"
 
 namespace ctqw {
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(256, 2) herk_c64_kernel(HerkArgs a) {
                 if (gr < a.D && gc < a.D && (P != Q || gr >= gc)) {
                     float2 v;
                     v.x = accR[i][j][e] * inv;
-                    v.y = -accI[i][j][e] * inv;
+                    v.y = gr == gc ? 0.0f : -accI[i][j][e] * inv;   // Hermitian: real diagonal
                     rho[gr + (int64_t)a.ld * gc] = v;
                 }
             }
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(256, 2) herk_c128_kernel(HerkArgs a) {
         }
     }
 
-    // accumulator e of a lane: MFMA row m = 4 (lane / 16) + e, column n = lane % 16
+    // accumulator e of a lane: MFMA row m = 4 e + lane / 16, column n = lane % 16
     const double inv = a.inv_R;
     double2* rho = static_cast<double2*>(a.rho);
 #pragma unroll
@@ -242,13 +243,13 @@ __global__ void __launch_bounds__(256, 2) herk_c128_kernel(HerkArgs a) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int m = 4 * kslot + e;
+                const int m = 4 * e + kslot;
                 const int64_t gc = q0 + 32 * wr + 16 * i + m;
                 const int64_t gr = p0 + 32 * wc + 16 * j + row;
                 if (gr < a.D && gc < a.D && (P != Q || gr >= gc)) {
                     double2 v;
                     v.x = accR[i][j][e] * inv;
-                    v.y = -accI[i][j][e] * inv;
+                    v.y = gr == gc ? 0.0 : -accI[i][j][e] * inv;    // Hermitian: real diagonal
                     rho[gr + (int64_t)a.ld * gc] = v;
                 }
             }

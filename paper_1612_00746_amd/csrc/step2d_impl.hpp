@@ -17,7 +17,7 @@
 //    loads row i, level j works on row i - j from level j-1 on rows i-j-1,
 //    i-j, i-j+1 (all already in registers), and row i - n is complete and
 //    stored.  Each level keeps a three-row window; the partial sums of the
-//    rows in flight (and their Kahan compensations) sit in an (n+1)-row
+//    rows in flight (and the separate sums of their terms) sit in an (n+1)-row
 //    window.  Windows start at zero and rows outside the sweep stay zero, so
 //    the pipeline fills and drains without per-level tests (the bond above
 //    the first row and below the last row of an open chain is 0).
@@ -39,9 +39,11 @@
 // element above it that lies across the diagonal is a diagonal element,
 // no coupling changes.
 //
-// Complex64 state can accumulate the terms with Kahan compensation.  The
-// squared norm of the new state and of the last term are accumulated in FP64
-// per item (the paper checks the norm every step, Alg. 3).
+// Complex64 state can sum the terms j >= 1 apart from psi and add them to it
+// once per step (compensated accumulation: one rounding of the state per
+// step instead of one per term).  The squared norm of the new state and of
+// the last term are accumulated in FP64 per item (the paper checks the norm
+// every step, Alg. 3).
 #pragma once
 #include "ctqw_internal.hpp"
 
@@ -340,7 +342,7 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 
     T fr[NT][3][P], fi[NT][3][P];   // Psi_j rows, j < NT
     T ar[WA][P], ai[WA][P];         // partial sums of the rows in flight
-    T cr[WA][P], ci[WA][P];         // compensation words (KAHAN)
+    T cr[WA][P], ci[WA][P];         // sum of the terms j >= 1 of the rows in flight (KAHAN)
     T dg[WA][P];                    // dt * diagonal of H on the rows in flight
     T ju[WA];                       // dt * bond above each row in flight (uniform)
     C pre[PF][P];                   // rows being fetched
@@ -555,19 +557,14 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         if (TRI && low) { pr_ = T(0); pi_ = T(0); }
                         if (j < NT) { fr[j % NT][sm][p] = pr_; fi[j % NT][sm][p] = pi_; }
                         if (KAHAN && j == 1) {
-                            // Kahan's update on the leading term: (a, c) with
-                            // a - c = psi + Phi^(1) exactly.
-                            const T yr = cr_j * pr_, yi = ci_j * pi_;   // fused step: cr_1, ci_1 = +-1
-                            const T tr = ar[w][p] + yr, ti = ai[w][p] + yi;
-                            cr[w][p] = (tr - ar[w][p]) - yr;
-                            ci[w][p] = (ti - ai[w][p]) - yi;
-                            ar[w][p] = tr;
-                            ai[w][p] = ti;
+                            // The terms are summed apart from psi (they are
+                            // smaller than psi by x = dt ||H|| or more) and
+                            // added to it once, when the row is complete.
+                            cr[w][p] = cr_j * pr_;   // fused step: cr_1, ci_1 = +-1
+                            ci[w][p] = ci_j * pi_;
                         } else if (KAHAN) {
-                            // Later terms are smaller than the leading one by
-                            // x/2 or more: they are collected in the low word.
-                            cr[w][p] -= cr_j * pr_;
-                            ci[w][p] -= ci_j * pi_;
+                            cr[w][p] = fma_t(cr_j, pr_, cr[w][p]);
+                            ci[w][p] = fma_t(ci_j, pi_, ci[w][p]);
                         } else {
                             ar[w][p] += cr_j * pr_;
                             ai[w][p] += ci_j * pi_;
@@ -610,8 +607,8 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                         C vo[P];
 #pragma unroll
                         for (int p = 0; p < P; ++p) {
-                            vo[p].x = KAHAN ? ar[w][p] - cr[w][p] : ar[w][p];
-                            vo[p].y = KAHAN ? ai[w][p] - ci[w][p] : ai[w][p];
+                            vo[p].x = KAHAN ? ar[w][p] + cr[w][p] : ar[w][p];
+                            vo[p].y = KAHAN ? ai[w][p] + ci[w][p] : ai[w][p];
                         }
                         if constexpr (BUF) {
                             const __amdgpu_buffer_rsrc_t rs =

@@ -101,17 +101,50 @@ __device__ __forceinline__ S load_uniform3(const S* table, int index) {
 }
 
 __device__ __forceinline__ int wrap3(int x, int n) { int r = x % n; return r < 0 ? r + n : r; }
-__device__ __forceinline__ bool related(int a, int b, int N, bool periodic, int want) {
-    int d = a - b;
-    d = d < 0 ? -d : d;
-    if (periodic && N - d < d) d = N - d;
-    return d == want;
-}
 __host__ __device__ constexpr int m3(int x) { return ((x % 3) + 3) % 3; }
 // (-i)^j = sr + i si with (sr, si) applied after the swap of roles: for odd
 // j the real part of (-i)^j y is si_j * Im y, the imaginary part sr_j * Re y.
 __host__ __device__ constexpr float rot_re(int j) { return (j % 4 == 0 || j % 4 == 1) ? 1.0f : -1.0f; }
 __host__ __device__ constexpr float rot_im(int j) { return (j % 4 == 0 || j % 4 == 3) ? 1.0f : -1.0f; }
+
+// Chain distance |a - b| (the shorter way round on a ring) == want, without branches.
+__device__ __forceinline__ bool related_u(int a, int b, int N, bool periodic, int want) {
+    const int d = a > b ? a - b : b - a;
+    const int e = N - d;
+    return ((periodic && e < d) ? e : d) == want;
+}
+
+// The complex64 stencil of one amplitude and level, h = (dt H y)(x):
+//   h = d m + Ju u + Jd v + Ja a + Jb b + jl m(lane - 1) + jr m(lane + 1)
+// (m: this amplitude; u, v: the planes above and below; a, b: the rows
+// above and below; Ju, Jd, Ja, Jb wave-uniform bonds; jl, jr the lane's
+// x3 bonds), accumulated in this order for the real and imaginary parts.
+// The x3 neighbours are read from the adjacent lanes by the FMA itself
+// (DPP wave_shr / wave_shl, bound_ctrl: lanes 0 and 63 read 0).  A DPP read
+// of a VGPR must follow the VALU write of that register by two wait
+// states: the DPP instructions come after ten VALU instructions of the
+// block and read inputs of the block.
+__device__ __forceinline__ void stencil3_c64(float& hr, float& hi, float d, float mr, float mi, float ur, float ui,
+                                             float vr, float vi, float ar, float ai, float br, float bi, float Ju,
+                                             float Jd, float Ja, float Jb, float jl, float jr) {
+    asm("v_mul_f32 %0, %2, %3\n\t"
+        "v_mul_f32 %1, %2, %4\n\t"
+        "v_fmac_f32 %0, %13, %5\n\t"
+        "v_fmac_f32 %1, %13, %6\n\t"
+        "v_fmac_f32 %0, %14, %7\n\t"
+        "v_fmac_f32 %1, %14, %8\n\t"
+        "v_fmac_f32 %0, %15, %9\n\t"
+        "v_fmac_f32 %1, %15, %10\n\t"
+        "v_fmac_f32 %0, %16, %11\n\t"
+        "v_fmac_f32 %1, %16, %12\n\t"
+        "v_fmac_f32_dpp %0, %3, %17 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %4, %17 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %0, %3, %18 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %4, %18 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(hr), "=&v"(hi)
+        : "v"(d), "v"(mr), "v"(mi), "v"(ur), "v"(ui), "v"(vr), "v"(vi), "v"(ar), "v"(ai), "v"(br), "v"(bi),
+          "s"(Ju), "s"(Jd), "s"(Ja), "s"(Jb), "v"(jl), "v"(jr));
+}
 
 __device__ __forceinline__ float fma3(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma3(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -184,6 +217,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
     int soff[S];     // byte offset of the row in a plane (0 off the chain)
     bool yin[S];     // row on the chain: loads read it, else zero
     bool yout[S];    // output row: stores write it
+    uint32_t voff_ld[S], voff_st[S];   // the lane's column offset, past the plane off the chain / the output
     T jrow[S + 1];   // jrow[s]: dt * bond between rows s-1 and s of the strip
     T drow[S];       // per lane: dt * (eps[x2] + eps[x3] + interaction of (x2, x3))
     int ywr[S];
@@ -195,6 +229,8 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
         yout[s] = y >= it.ylo && y < it.yhi;
         ywr[s] = yin[s] ? yw : 0;
         soff[s] = ywr[s] * N * (int)sizeof(C);
+        voff_ld[s] = yin[s] ? voff_in : kPastRow;
+        voff_st[s] = yout[s] ? voff_out : kPastRow;
     }
 #pragma unroll
     for (int s = 0; s <= S; ++s) {
@@ -209,7 +245,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         T d = e3 + (yin[s] ? Eu_t[ywr[s]] : T(0));
-        if (zin && yin[s] && related(ywr[s], zw, N, periodic, want)) d += Udt;
+        if (zin && yin[s] && related_u(ywr[s], zw, N, periodic, want)) d += Udt;
         drow[s] = d;
     }
 
@@ -234,29 +270,35 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
 
     const int nplanes = it.nplanes;
     const int plo = it.plane_lo - it.x0, phi = it.plane_hi - it.x0;   // output planes (sweep index)
-    auto plane_w = [&](int p) { const int x = it.x0 + p; return periodic ? wrap3(x, N) : x; };
-    // the sweep's plane p lies on the chain (open chains: no plane outside [0, N))
-    auto plane_live = [&](int p) {
-        const int x = it.x0 + p;
-        return p >= 0 && p < nplanes && (periodic || (x >= 0 && x < N));
-    };
+    // Plane p of the sweep is x1 = x0 + p (wrapped on a ring); open chains
+    // sweep exactly [0, N).  A plane is addressed through one buffer
+    // resource (length 0 -- loads read zero, stores are dropped -- where `ok`
+    // is false), the row as scalar offset and the column as lane offset.
+    auto live = [&](int p) { return p >= 0 && p < nplanes; };
     auto plane_out = [&](int p) { return p >= plo && p < phi && p >= 0; };
-    // Row s of plane p of an array: a buffer resource over the plane with the
-    // row as scalar offset; its length is 0 (loads read zero, stores are
-    // dropped) where `ok` is false.
-    auto rsrc = [&](const char* base, int p, bool ok) {
-        const int64_t off = (int64_t)(ok ? plane_w(p) : 0) * NN * (int64_t)sizeof(C);
+    auto rsrc = [&](const char* base, int xw, bool ok) {
+        const int64_t off = (int64_t)(ok ? xw : 0) * NN * (int64_t)sizeof(C);
         return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base + off), 0, ok ? plane_bytes : 0,
                                                  kBufferWord3);
     };
-    auto fetch = [&](const char* base, int p, C (&dst)[S]) {
-        const bool live = plane_live(p);
+    auto fetch = [&](const char* base, int xw, bool ok, C (&dst)[S]) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc(base, xw, ok);
 #pragma unroll
-        for (int s = 0; s < S; ++s) dst[s] = load_c(rsrc(base, p, live && yin[s]), voff_in, soff[s], (C*)nullptr);
+        for (int s = 0; s < S; ++s) dst[s] = load_c(rs, voff_ld[s], soff[s], (C*)nullptr);
     };
+    // x1 of sweep position p + k, |k| <= 3, from x1 of p (wrapped once on a
+    // ring, whose N >= 3)
+    const int Nwrap = periodic ? N : 0;
+    auto shift = [&](int x, int k) {
+        int y = x + k;
+        y += y < 0 ? Nwrap : 0;
+        y -= y >= N ? Nwrap : 0;
+        return y;
+    };
+    int xc = periodic ? wrap3(it.x0, N) : it.x0;   // x1 of sweep position i (advanced per step)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        fetch(x_base, k, pre[k]);
+        fetch(x_base, shift(xc, k), live(k), pre[k]);
         __builtin_amdgcn_sched_barrier(0);
     }
 
@@ -278,13 +320,15 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                     yr[0][w][s] = FIRST ? pre[w][s].x * sc : pre[w][s].x;
                     yi[0][w][s] = FIRST ? pre[w][s].y * sc : pre[w][s].y;
                 }
-                fetch(x_base, i + 3, pre[w]);
+                fetch(x_base, shift(xc, 3), live(i + 3), pre[w]);
+                // bond above plane i (0 at an open chain's first plane and past the sweep)
 #pragma unroll
                 for (int k = 0; k < KT; ++k) jq[k] = jq[k + 1];
-                const int x1 = plane_w(i);
-                const bool has_up = plane_live(i) && (periodic || x1 > 0);
-                const T jup = Ju_t[has_up ? (periodic ? wrap3(x1 - 1, N) : x1 - 1) : 0];   // index in range either way
-                jq[KT] = has_up ? jup : T(0);
+                {
+                    const bool has_up = live(i) && (periodic || xc > 0);
+                    const T jup = Ju_t[has_up ? shift(xc, -1) : 0];   // index in range either way
+                    jq[KT] = has_up ? jup : T(0);
+                }
                 // partial sum of plane i - 1, used when it completes (step i - 1 + KT)
                 const int wb = m3(u - 1);
                 if constexpr (FIRST) {
@@ -294,10 +338,10 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                         bi[wb][s] = yi[0][wb][s];
                     }
                 } else {
-                    const bool live = plane_live(i - 1);
+                    const __amdgpu_buffer_rsrc_t rs = rsrc(b_base, shift(xc, -1), live(i - 1));
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        const C v = load_c(rsrc(b_base, i - 1, live && yin[s]), voff_in, soff[s], (C*)nullptr);
+                        const C v = load_c(rs, voff_ld[s], soff[s], (C*)nullptr);
                         br[wb][s] = v.x;
                         bi[wb][s] = v.y;
                     }
@@ -316,27 +360,36 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                 const T cr = static_cast<T>(rot_re(j)) * cj, ci = static_cast<T>(rot_im(j)) * cj;
                 const int p = i - j;
                 const bool seed_ok = !LAST && j == KT && plane_out(p);
+                __amdgpu_buffer_rsrc_t rs_seed;
+                if constexpr (!LAST)
+                    if (j == KT) rs_seed = rsrc(q_base, shift(xc, -KT), seed_ok);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     const T mr = yr[j - 1][sm][s], mi = yi[j - 1][sm][s];
-                    T hr = dg[sm][s] * mr;
-                    T hi = dg[sm][s] * mi;
-                    hr = fma3(Jup, yr[j - 1][su][s], hr);
-                    hi = fma3(Jup, yi[j - 1][su][s], hi);
-                    hr = fma3(Jdn, yr[j - 1][sd][s], hr);
-                    hi = fma3(Jdn, yi[j - 1][sd][s], hi);
                     const T ar = s > 0 ? yr[j - 1][sm][s > 0 ? s - 1 : 0] : up_e.x;
                     const T ai = s > 0 ? yi[j - 1][sm][s > 0 ? s - 1 : 0] : up_e.y;
                     const T br_ = s < S - 1 ? yr[j - 1][sm][s < S - 1 ? s + 1 : 0] : dn_e.x;
                     const T bi_ = s < S - 1 ? yi[j - 1][sm][s < S - 1 ? s + 1 : 0] : dn_e.y;
-                    hr = fma3(jrow[s], ar, hr);
-                    hi = fma3(jrow[s], ai, hi);
-                    hr = fma3(jrow[s + 1], br_, hr);
-                    hi = fma3(jrow[s + 1], bi_, hi);
-                    hr = fma3(jl, lane_from_left(mr), hr);
-                    hi = fma3(jl, lane_from_left(mi), hi);
-                    hr = fma3(jr, lane_from_right(mr), hr);
-                    hi = fma3(jr, lane_from_right(mi), hi);
+                    T hr, hi;
+                    if constexpr (sizeof(T) == 4) {
+                        stencil3_c64(hr, hi, dg[sm][s], mr, mi, yr[j - 1][su][s], yi[j - 1][su][s], yr[j - 1][sd][s],
+                                     yi[j - 1][sd][s], ar, ai, br_, bi_, Jup, Jdn, jrow[s], jrow[s + 1], jl, jr);
+                    } else {
+                        hr = dg[sm][s] * mr;
+                        hi = dg[sm][s] * mi;
+                        hr = fma3(Jup, yr[j - 1][su][s], hr);
+                        hi = fma3(Jup, yi[j - 1][su][s], hi);
+                        hr = fma3(Jdn, yr[j - 1][sd][s], hr);
+                        hi = fma3(Jdn, yi[j - 1][sd][s], hi);
+                        hr = fma3(jrow[s], ar, hr);
+                        hi = fma3(jrow[s], ai, hi);
+                        hr = fma3(jrow[s + 1], br_, hr);
+                        hi = fma3(jrow[s + 1], bi_, hi);
+                        hr = fma3(jl, lane_from_left(mr), hr);
+                        hi = fma3(jl, lane_from_left(mi), hi);
+                        hr = fma3(jr, lane_from_right(mr), hr);
+                        hi = fma3(jr, lane_from_right(mi), hi);
+                    }
                     if (j < KT) {
                         yr[j][sm][s] = hr;
                         yi[j][sm][s] = hi;
@@ -358,8 +411,8 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                         }
                     } else if (j == KT) {
                         // Psi_{s+K} with its true phase, for the next pass
-                        store_c(static_cast<T>(rot_re(KT)) * xr, static_cast<T>(rot_im(KT)) * xi,
-                                rsrc(q_base, p, seed_ok && yout[s]), voff_out, soff[s]);
+                        store_c(static_cast<T>(rot_re(KT)) * xr, static_cast<T>(rot_im(KT)) * xi, rs_seed,
+                                voff_st[s], soff[s]);
                     }
                 }
             }
@@ -368,12 +421,13 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                 const int p = i - KT;
                 const int w = m3(u - KT);
                 const bool ok = plane_out(p);
+                const __amdgpu_buffer_rsrc_t rs = rsrc(s_base, shift(xc, -KT), ok);
                 double pn = 0.0;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
                     const T orr = br[w][s] + tr[w][s];
                     const T oi = bi[w][s] + ti[w][s];
-                    store_c(orr, oi, rsrc(s_base, p, ok && yout[s]), voff_out, soff[s]);
+                    store_c(orr, oi, rs, voff_st[s], soff[s]);
                     if constexpr (LAST) {
                         const double dr = orr, di = oi;
                         pn = __builtin_fma(yout[s] ? dr : 0.0, dr, __builtin_fma(yout[s] ? di : 0.0, di, pn));
@@ -387,13 +441,15 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
             // plane i - 3, whose last use was level 3 of this step)
             {
                 const int w = u;
-                const bool xin = plane_live(i);
-                const int x1 = xin ? plane_w(i) : 0;
-                const T e1 = xin ? Eu_t[x1] : T(0);
-                const T u13 = (xin && zin && related(x1, zw, N, periodic, want)) ? Udt : T(0);
+                // (evaluated without branches: every index is in range either way)
+                const bool xin = live(i);
+                const int x1 = xin ? xc : 0;
+                const T e1v = Eu_t[x1];
+                const T e1 = xin ? e1v : T(0);
+                const T u13 = (xin & zin & related_u(x1, zw, N, periodic, want)) ? Udt : T(0);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const T u12 = (xin && yin[s] && related(x1, ywr[s], N, periodic, want)) ? Udt : T(0);
+                    const T u12 = (xin & yin[s] & related_u(x1, ywr[s], N, periodic, want)) ? Udt : T(0);
                     dg[w][s] = drow[s] + (e1 + u12) + u13;
                 }
             }
@@ -413,6 +469,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                     ew[((j * (W + 2) + wv + 1) * 2 + 1) * 64 + lane] = l;
                 }
             }
+            xc = shift(xc, 1);
         }
     }
 
