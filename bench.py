@@ -526,6 +526,69 @@ def density(a):
                       "trace": tr}))
 
 
+def density_sweep(a):
+    """The paper's post-processing-rate experiment (Sec. 4, Fig. 5: the
+    ensemble density matrix formed every 10, 25, 100, 250 or 1500 of 1500
+    steps) on the two-boson workload's shape: 1000 realisations, N = 128
+    (D = 8256), complex64.  For each rate the run is timed with HIP events
+    on the plan's stream: the whole run, and the density-matrix calls alone
+    (gather + MFMA rank-1000 update + mirror); the share of the run spent
+    on <rho> is reported beside the paper's ~90 % at the most frequent
+    output."""
+    import torch
+    from paper_1612_00746_amd import Plan, make_problem
+    from workloads import C2
+    w = C2("c64")
+    reals = w.all_realizations()
+    J = np.concatenate([r[1] for r in reals])
+    eps = np.concatenate([r[2] for r in reals])
+    U = np.array([r[3] for r in reals])
+    pr, keep = make_problem(2, w.R, w.N, w.dt, statistics="boson", dtype="c64", accumulation="kahan",
+                            taylor_tol=w.tol, observables=1)
+    plan = Plan(pr)
+    plan._keep.append(keep)
+    plan.set_launch(use_graph=1)
+    plan.set_params(J, eps, U)
+    plan.bind()
+    total_steps = 1500
+    rows = []
+    plan.init_product_state(np.array(w.start_sites(w.N), dtype=np.int32))
+    plan.propagate(10)
+    plan.density_matrix(0)                     # warm-up of every kernel
+    torch.cuda.synchronize()
+    for every in (10, 25, 100, 250, 1500):
+        plan.init_product_state(np.array(w.start_sites(w.N), dtype=np.int32))
+        rho_ms = 0.0
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        done = 0
+        n_rho = 0
+        while done < total_steps:
+            plan.propagate(every)
+            done += every
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rho = plan.density_matrix(0)
+            e1.record()
+            e1.synchronize()
+            rho_ms += e0.elapsed_time(e1)
+            n_rho += 1
+            del rho
+        t1.record()
+        torch.cuda.synchronize()
+        run_ms = t0.elapsed_time(t1)
+        rows.append({"output_every": every, "density_matrices": n_rho, "run_ms": round(run_ms, 2),
+                     "rho_ms": round(rho_ms, 2), "rho_share": round(rho_ms / run_ms, 4)})
+        log(f"every {every}: run {run_ms:.1f} ms, rho {rho_ms:.1f} ms ({100 * rho_ms / run_ms:.1f} %)")
+    print(json.dumps({"experiment": "post-processing rate (the paper's Fig. 5 protocol)",
+                      "workload": "1000 x two bosons, N = 128, D = 8256, complex64, 1500 steps of dt = 0.05",
+                      "rates": rows,
+                      "paper_context": "post-processing about 90 % of the run at frequent output, "
+                                       "cublasCher > 99.3 % of that (K40, complex single)"}))
+    del plan
+    torch.cuda.empty_cache()
+
+
 def graph(a):
     """One particle on a 128 x 128 open square lattice (q = 2, 16384
     nodes), 4096 noisy realisations (J = 1 + 0.1 N(0, 1) per bond,
@@ -723,6 +786,8 @@ def main():
     ap.add_argument("--alg-bytes", type=float, default=0.0, help="--kernel-summary: algorithmic bytes per step")
     ap.add_argument("--rk4-compare", action="store_true",
                     help="time Alg. 2 (RK4) against the adaptive Taylor step at equal per-step accuracy on the batch")
+    ap.add_argument("--density-sweep", action="store_true",
+                    help="the post-processing-rate experiment: <rho> every 10 ... 1500 of 1500 steps")
     ap.add_argument("--graph", action="store_true",
                     help="time one particle on a 128 x 128 lattice, 4096 realisations (complex128)")
     ap.add_argument("--telegraph", action="store_true",
@@ -761,6 +826,9 @@ def main():
         return
     if a.density:
         density(a)
+        return
+    if a.density_sweep:
+        density_sweep(a)
         return
     if a.graph:
         graph(a)

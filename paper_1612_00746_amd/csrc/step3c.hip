@@ -62,8 +62,14 @@ constexpr int kStoreNT = 2;   // stores are read again only by the next pass
 constexpr uint32_t kPastRow = 0x80000000u;
 
 // Loads and stores of one amplitude per lane through a buffer resource over
-// one plane: soff (wave-uniform) selects the row, off (per lane) the column;
-// an offset at or past the resource's length reads 0 and drops the store.
+// one plane: loads take the row as soff (wave-uniform) and the column as off
+// (per lane); stores take row and column in off and a zero scalar offset.
+// An offset at or past the resource's length reads 0 and drops the store.
+// (A 16-byte store reads its data registers after it issues: a VALU write
+// of them must wait one cycle.  The compiler inserts that wait only for
+// stores whose scalar offset is not a register; with a register there the
+// store was seen to write the following instruction's results in some
+// lanes.  A zero scalar offset keeps the wait.)
 __device__ __forceinline__ float2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t off, int soff, float2*) {
     const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, soff, 0);
     return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
@@ -72,19 +78,19 @@ __device__ __forceinline__ double2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t of
     const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, soff, 0);
     return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
 }
-__device__ __forceinline__ void store_c(float re, float im, __amdgpu_buffer_rsrc_t rs, uint32_t off, int soff) {
+__device__ __forceinline__ void store_c(float re, float im, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
     u32x2 v;
     v.x = __float_as_uint(re);
     v.y = __float_as_uint(im);
-    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)off, soff, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)off, 0, kStoreNT);
 }
-__device__ __forceinline__ void store_c(double re, double im, __amdgpu_buffer_rsrc_t rs, uint32_t off, int soff) {
+__device__ __forceinline__ void store_c(double re, double im, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
     u32x4 v;
     v.x = (unsigned)__double2loint(re);
     v.y = (unsigned)__double2hiint(re);
     v.z = (unsigned)__double2loint(im);
     v.w = (unsigned)__double2hiint(im);
-    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, soff, kStoreNT);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, kStoreNT);
 }
 
 template <typename T> using UPtr = const __attribute__((address_space(4))) T*;
@@ -217,7 +223,8 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
     int soff[S];     // byte offset of the row in a plane (0 off the chain)
     bool yin[S];     // row on the chain: loads read it, else zero
     bool yout[S];    // output row: stores write it
-    uint32_t voff_ld[S], voff_st[S];   // the lane's column offset, past the plane off the chain / the output
+    uint32_t voff_ld[S];   // the lane's column offset, past the plane off the chain
+    uint32_t voff_st[S];   // the lane's row and column offset, past the plane off the output
     T jrow[S + 1];   // jrow[s]: dt * bond between rows s-1 and s of the strip
     T drow[S];       // per lane: dt * (eps[x2] + eps[x3] + interaction of (x2, x3))
     int ywr[S];
@@ -230,7 +237,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
         ywr[s] = yin[s] ? yw : 0;
         soff[s] = ywr[s] * N * (int)sizeof(C);
         voff_ld[s] = yin[s] ? voff_in : kPastRow;
-        voff_st[s] = yout[s] ? voff_out : kPastRow;
+        voff_st[s] = (yout[s] && voff_out != kPastRow) ? voff_out + (uint32_t)soff[s] : kPastRow;
     }
 #pragma unroll
     for (int s = 0; s <= S; ++s) {
@@ -412,7 +419,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                     } else if (j == KT) {
                         // Psi_{s+K} with its true phase, for the next pass
                         store_c(static_cast<T>(rot_re(KT)) * xr, static_cast<T>(rot_im(KT)) * xi, rs_seed,
-                                voff_st[s], soff[s]);
+                                voff_st[s]);
                     }
                 }
             }
@@ -427,7 +434,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                 for (int s = 0; s < S; ++s) {
                     const T orr = br[w][s] + tr[w][s];
                     const T oi = bi[w][s] + ti[w][s];
-                    store_c(orr, oi, rs, voff_st[s], soff[s]);
+                    store_c(orr, oi, rs, voff_st[s]);
                     if constexpr (LAST) {
                         const double dr = orr, di = oi;
                         pn = __builtin_fma(yout[s] ? dr : 0.0, dr, __builtin_fma(yout[s] ? di : 0.0, di, pn));

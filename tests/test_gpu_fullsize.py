@@ -85,11 +85,19 @@ def test_c2_full_configuration_sampled_against_the_oracle(dtype):
     compared amplitude by amplitude with the oracle's Taylor route at
     tolerance 1e-15 (within steps x 1e-15 of the exact evolution), and the
     final ensemble occupation of the sample with the oracle's.  complex128:
-    1e-10.  complex64 (tolerance 1e-7, compensated sum): amplitude 2e-6,
-    occupation 1e-6 and |norm - 1| 1e-6 (FP32 bars derived from the
-    arithmetic: parameters rounded to FP32 and one rounding per step);
-    also against the oracle's map at the realisations' own orders, which
-    leaves rounding alone."""
+    1e-10.  complex64 (tolerance 1e-7, compensated sum) splits its error in
+    two.  Representation: the kernels hold dt*J, dt*eps and dt*U in FP32 and
+    form each diagonal entry as an FP32 sum of them, i.e. they evolve with a
+    Hamiltonian H32 that differs from H by rounding alone; the oracle
+    evolves the sample with H32 too, and |psi_H32 - psi_H| (measured
+    0.3e-6 to 1.0e-6) is a property of FP32 storage, not of the kernels.
+    Arithmetic: against the oracle's H32 evolution the kernels may differ
+    by their roundings only: one rounding of each component of the state
+    per step (2^-24 relative) plus the rounding of the summed terms, at
+    |psi| <= 0.3, accumulating as a random walk over 1000 steps:
+    sqrt(1000) * 1.2 * 6e-8 * 0.3 = 7e-7, held to 1.5e-6.  So the bars are
+    amplitude <= 1.5e-6 against the H32 evolution and <= |psi_H32 - psi_H|
+    + 1.5e-6 against the exact one; occupation 1e-6 and |norm - 1| 1e-6."""
     import torch
     from oracle import observables as O
     from workloads import C2
@@ -112,28 +120,50 @@ def test_c2_full_configuration_sampled_against_the_oracle(dtype):
     off = plan.layout()
     sample = sorted(np.random.default_rng(50).choice(w.R, 6, replace=False).tolist())
     st = B.basis_states(w.N, 2, B.BOSON)
-    worst, worst_same, occ_o, occ_g = 0.0, 0.0, [], []
+    worst, worst32, excess, occ_o, occ_g = 0.0, 0.0, -1.0, [], []
     for r in sample:
         N, J, eps, U = reals[r]
         H = oracle_H(N, 2, B.BOSON, "open", "onsite", J, eps, U)
         psi0 = B.product_state(N, list(w.start), B.BOSON)
         ref, _, _ = P.evolve_taylor(H, psi0, w.dt, w.n_steps, tol=1e-15)
         got = gpu_to_oracle(psi[off[r]:off[r + 1]].cpu().numpy(), N, 2, B.BOSON)
-        worst = max(worst, float(np.max(np.abs(got - ref))))
+        err = float(np.max(np.abs(got - ref)))
+        worst = max(worst, err)
         if dtype == "c64":
-            same, _, _ = P.evolve_taylor(H, psi0, w.dt, w.n_steps, order=int(orders[r]))
-            worst_same = max(worst_same, float(np.max(np.abs(got - same))))
+            ref32, _, _ = P.evolve_taylor(fp32_boson_onsite_H(N, J, eps, U, w.dt, st), psi0, w.dt, w.n_steps,
+                                          tol=1e-15)
+            rep = float(np.max(np.abs(ref32 - ref)))
+            e32 = float(np.max(np.abs(got - ref32)))
+            worst32 = max(worst32, e32)
+            excess = max(excess, err - rep)
+            say(f"  r={r}: |psi - oracle| {err:.2e}, |psi - oracle(H32)| {e32:.2e}, "
+                f"|oracle(H32) - oracle| {rep:.2e}")
         occ_o.append(O.occupation(ref, st, N))
         occ_g.append(O.occupation(got, st, N))
     e_occ = float(np.max(np.abs(O.ensemble_mean(occ_g) - O.ensemble_mean(occ_o))))
     say(f"  orders {int(orders.min())}-{int(orders.max())}; sample {sample}: amplitude {worst:.2e}"
-        + (f" (same-order map {worst_same:.2e})" if dtype == "c64" else "")
+        + (f" (against the H32 evolution {worst32:.2e}, beyond the representation {excess:.2e})"
+           if dtype == "c64" else "")
         + f", occupation {e_occ:.2e}, max |norm - 1| over all {w.R}: {drift:.2e}")
     if dtype == "c128":
         assert worst <= 1e-10 and e_occ <= 1e-10 and drift <= 1e-10
     else:
-        assert worst <= 2e-6 and e_occ <= 1e-6 and drift <= 1e-6
-        assert worst_same <= 2e-6
+        assert worst32 <= 1.5e-6 and excess <= 1.5e-6 and e_occ <= 1e-6 and drift <= 1e-6
+
+
+def fp32_boson_onsite_H(N, J, eps, U, dt, states):
+    """The two-boson on-site Hamiltonian as FP32 tables of dt-scaled
+    parameters represent it: hoppings fl(dt J)/dt, diagonal entries
+    fl(fl(dt eps_a) + fl(dt eps_b)) (plus fl(dt U), rounded again, on a
+    doubly occupied node) over dt."""
+    import scipy.sparse as sp
+    f32 = lambda x: np.asarray(x, dtype=np.float32).astype(np.float64)
+    Jr = f32(np.asarray(J) * dt) / dt
+    Er = f32(np.asarray(eps) * dt)
+    H = oracle_H(N, 2, B.BOSON, "open", "onsite", Jr, np.zeros(N), 0.0)
+    d = f32(Er[states[:, 0]] + Er[states[:, 1]])
+    d = np.where(states[:, 0] == states[:, 1], f32(d + f32(U * dt)), d)
+    return (H - sp.diags(H.diagonal()) + sp.diags(d / dt)).tocsr()
 
 
 def test_c4_full_lattice_gradient_against_the_oracle():

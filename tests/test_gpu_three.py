@@ -88,6 +88,37 @@ def test_three_walkers_several_tiles_c128(N, boundary, K):
     assert worst <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_three_walkers_middle_passes_every_lane(K, dtype):
+    """One step of order 3K (a first, a middle and a last pass) on a 70-site
+    chain whose tiles hold amplitudes in all 64 lanes and all rows: every
+    amplitude equals the oracle's Taylor map of that order (complex128
+    1e-12; complex64 5e-9 on amplitudes of size ~1e-3).  A middle pass both
+    reads the partial sum and writes the next pass's seed; a store whose
+    data registers were overwritten before it read them once showed up here
+    as wrong real parts in four-lane groups."""
+    N, dt, order = 70, 0.02, 3 * K
+    reals = reals3(N, 1, 7, "open")
+    say(f"case: m=3 middle passes N={N} K={K} order={order} {dtype}")
+    g = np.random.default_rng(11)
+    D = N ** 3
+    psi0 = g.standard_normal(D) + 1j * g.standard_normal(D)
+    psi0 /= np.linalg.norm(psi0)
+    plan = gpu_plan(m=3, statistics="distinguishable", boundary="open", interaction="nearest", dtype=dtype,
+                    reals=reals, dt=dt, order=order, launch={"terms_per_pass": K})
+    plan.set_state_numpy(psi0)
+    plan.propagate(1)
+    psi = plan.state_numpy()
+    _, J, eps, U = reals[0]
+    H = Hm.hamiltonian(N, 3, J, eps, U, B.DISTINGUISHABLE, "open", "nearest")
+    ref, _, _ = P.evolve_taylor(H, psi0, dt, 1, order=order)
+    err = np.abs(psi - ref)
+    say(f"  max |psi - oracle map| = {err.max():.2e}, entries above the bar: "
+        f"{int((err > (1e-12 if dtype == 'c128' else 5e-9)).sum())}")
+    assert err.max() <= (1e-12 if dtype == "c128" else 5e-9)
+
+
 def test_three_walker_workload_one_output_interval_c64():
     """The three-walker workload's parameters (nearest-neighbour U = 1,
     eps ~ U[-1, 1], J = 1, dt = 0.02, tolerance 1e-7, complex64, start at the
