@@ -127,10 +127,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def shape_tag(cols_per_lane, waves_per_block, grid_waves) -> str:
-    """Launch shape of the step kernel: columns per lane, waves per block and
-    the waves of the (persistent) grid."""
-    return f"cols_per_lane={cols_per_lane} waves_per_block={waves_per_block} grid_waves={grid_waves}"
+def shape_tag(cols_per_lane, waves_per_block, grid_waves, band_align=128, band_mode=0) -> str:
+    """Launch shape of the step kernel: columns per lane, waves per block,
+    the waves of the (persistent) grid and the column-band layout."""
+    return (f"cols_per_lane={cols_per_lane} waves_per_block={waves_per_block} grid_waves={grid_waves} "
+            f"band_align={band_align} band_mode={band_mode}")
 
 
 def recorded_traffic(launch, grid_waves):
@@ -144,7 +145,8 @@ def recorded_traffic(launch, grid_waves):
     fields = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(keys))
     if fields.get("kernel-source-sha256", "").strip() != kernel_source_hash():
         return None
-    tag = shape_tag(launch.get("cols_per_lane", 1), launch.get("waves_per_block", 4), grid_waves)
+    tag = shape_tag(launch.get("cols_per_lane", 1), launch.get("waves_per_block", 4), grid_waves,
+                    launch.get("band_align", 128), launch.get("band_mode", 0))
     if fields.get("launch-shape", "").strip() != tag:
         return None
     try:
@@ -159,7 +161,7 @@ def _rows(path):
 
 
 def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols_per_lane=1, waves_per_block=4,
-                    waves_per_cu=0):
+                    waves_per_cu=0, band_align=128, band_mode=0):
     """Write the step kernels' rocprofv3 summary: duration statistics from
     the kernel trace, FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the
     same counters read for the 4 GiB device copy of the same run.  A step
@@ -209,7 +211,9 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         "N uniform in {64, 96, ..., 1024}, U ~ U[0, 4], J ~ N(1, 0.1^2), dt = 0.05,",
         "Taylor tolerance 1e-7 (6 or 7 terms per realisation), complex64 with the",
         f"compensated sum; persistent launches, {cols_per_lane} column(s) per lane, {waves_per_block} wave(s) per block,",
-        f"{waves_per_cu or 'all'} resident waves per CU, 128-byte band boundaries, captured step loop;",
+        f"{waves_per_cu or 'all'} resident waves per CU, "
+        + (f"band windows on {band_align}-byte boundaries (outputs on 32-byte ones)" if band_mode
+           else f"{band_align}-byte band boundaries") + ", captured step loop;",
         "adjacent Taylor orders share one launch (each item at its own order).",
         "",
         "Commands (from the repository root, TMPDIR=/tmp):",
@@ -232,7 +236,7 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         f"| HBM bytes written per step | {write_b / 1e9:.3f} GB |",
         "",
         f"kernel-source-sha256: {kernel_source_hash()}",
-        "launch-shape: " + shape_tag(cols_per_lane, waves_per_block, grid_waves),
+        "launch-shape: " + shape_tag(cols_per_lane, waves_per_block, grid_waves, band_align, band_mode),
         f"traffic-bytes: {int(round(fetch_b + write_b))}",
         "",
     ]
@@ -527,9 +531,9 @@ def density(a):
 
 
 def density_sweep(a):
-    """The paper's post-processing-rate experiment (Sec. 4, Fig. 5: the
-    ensemble density matrix formed every 10, 25, 100, 250 or 1500 of 1500
-    steps) on the two-boson workload's shape: 1000 realisations, N = 128
+    """The paper's post-processing-rate runs (Sec. 4: the ensemble density
+    matrix formed once every 10, 25, 100, 250 or 1500 of 1500 steps, 1000
+    realisations) on the two-boson workload's shape: 1000 realisations, N = 128
     (D = 8256), complex64.  For each rate the run is timed with HIP events
     on the plan's stream: the whole run, and the density-matrix calls alone
     (gather + MFMA rank-1000 update + mirror); the share of the run spent
@@ -580,7 +584,7 @@ def density_sweep(a):
         rows.append({"output_every": every, "density_matrices": n_rho, "run_ms": round(run_ms, 2),
                      "rho_ms": round(rho_ms, 2), "rho_share": round(rho_ms / run_ms, 4)})
         log(f"every {every}: run {run_ms:.1f} ms, rho {rho_ms:.1f} ms ({100 * rho_ms / run_ms:.1f} %)")
-    print(json.dumps({"experiment": "post-processing rate (the paper's Fig. 5 protocol)",
+    print(json.dumps({"experiment": "post-processing rate (the rates of Sec. 4)",
                       "workload": "1000 x two bosons, N = 128, D = 8256, complex64, 1500 steps of dt = 0.05",
                       "rates": rows,
                       "paper_context": "post-processing about 90 % of the run at frequent output, "
@@ -716,7 +720,7 @@ def adjoint(a):
     import torch
     from paper_1612_00746_amd import Plan, make_problem
     from workloads import C4
-    for dtype in ("c64", "c128"):
+    for dtype in a.adjoint_dtypes.split(","):
         w = C4(dtype)
         reals = w.all_realizations()
         J = np.concatenate([r[1] for r in reals])
@@ -769,6 +773,9 @@ def main():
                     help="keep --cols-per-lane, --waves-per-block and --waves-per-cu")
     ap.add_argument("--waves-per-block", type=int, default=4)
     ap.add_argument("--waves-per-cu", type=int, default=0, help="persistent grid: resident waves per CU (0: all)")
+    ap.add_argument("--band-align", type=int, default=128, help="column-band alignment in bytes (with --no-autotune)")
+    ap.add_argument("--band-mode", type=int, default=0,
+                    help="0: band boundaries aligned; 1: band windows aligned (with --no-autotune)")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the step kernel's rocprofv3 summary under profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
@@ -798,12 +805,14 @@ def main():
                     help="time the three-walker path instead (64 x 256^3 amplitudes, complex64)")
     ap.add_argument("--adjoint", action="store_true",
                     help="time one gradient of the gradient workload (512 x two bosons, N = 256, 400 steps)")
+    ap.add_argument("--adjoint-dtypes", default="c64,c128", help="--adjoint: comma-separated state types")
     ap.add_argument("--terms-per-pass", type=int, default=0,
                     help="three walkers: Taylor terms chained per pass (0: the library's default)")
     a = ap.parse_args()
     if a.profile_summary:
         profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane,
-                        waves_per_block=a.waves_per_block, waves_per_cu=a.waves_per_cu)
+                        waves_per_block=a.waves_per_block, waves_per_cu=a.waves_per_cu, band_align=a.band_align,
+                        band_mode=a.band_mode)
         return
     if a.kernel_summary:
         kernel_summary(a.kernel_summary, a.title or a.match, a.workload_line, a.profile_command, a.match,
@@ -849,7 +858,8 @@ def main():
     sizes = w.lattice_sizes()
     amps = int(np.sum(sizes.astype(np.int64) ** 2))
     launch = {"cols_per_lane": a.cols_per_lane, "persistent": 0 if a.regular else 1,
-              "waves_per_block": a.waves_per_block, "waves_per_cu": a.waves_per_cu, "use_graph": 1}
+              "waves_per_block": a.waves_per_block, "waves_per_cu": a.waves_per_cu, "use_graph": 1,
+              "band_align": a.band_align, "band_mode": a.band_mode}
     log("building the complex64 plan ...")
     plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
     tuned = None
@@ -863,12 +873,13 @@ def main():
             best, best_ms = plan.autotune(os.path.join(td, "tune.jsonl"), steps=3)
         tuned = {"cols_per_lane": best.cols_per_lane, "waves_per_block": best.waves_per_block,
                  "persistent": best.persistent, "waves_per_cu": best.waves_per_cu, "chunked": best.chunked,
-                 "band_align": best.band_align,
+                 "band_align": best.band_align, "band_mode": best.band_mode,
                  "ms": round(best_ms, 4)}
         log(f"autotune: {tuned}")
         launch = {"cols_per_lane": best.cols_per_lane, "persistent": 0 if a.regular else 1,
                   "waves_per_block": best.waves_per_block, "waves_per_cu": best.waves_per_cu,
-                  "chunked": best.chunked, "band_align": best.band_align, "use_graph": 1}
+                  "chunked": best.chunked, "band_align": best.band_align, "band_mode": best.band_mode,
+                  "use_graph": 1}
         plan.set_launch(**launch)
         plan.bind()
         sizes0 = w.lattice_sizes()

@@ -144,6 +144,15 @@ typedef struct {
                                 for complex128); a step of n terms is
                                 ceil(n / K) passes, the last taking the
                                 remaining terms.  Ignored for m < 3.       */
+    int32_t band_mode;       /* full grids on open chains, band_align > 0:
+                                0 (default): band boundaries on multiples of
+                                band_align bytes (above);
+                                1: each band's window of columns starts on
+                                a multiple of band_align bytes, so its rows
+                                are read as whole cache lines, and its
+                                output ends on a 32-byte boundary (two bands
+                                then store parts of one line).  Other
+                                layouts ignore it.                         */
 } ctqw_launch;
 
 /* Create a plan from a problem statement.  Host only: validates the

@@ -77,6 +77,7 @@ class Launch(C.Structure):
         ("chunked", C.c_int32),
         ("band_align", C.c_int32),
         ("terms_per_pass", C.c_int32),
+        ("band_mode", C.c_int32),
     ]
 
 

@@ -10,13 +10,37 @@
 // the same stencil with the opposite sign.  dA/dtheta = -i dt dH/dtheta, so
 // the contribution is 2 dt Im <u_i | dH/dtheta | v_i>.
 //
-// The kernels work on the whole batch: `apply_kernel` computes
-// y = s (-i) (dt H) x + c z for every stored amplitude (s = +1 for A, -1 for
-// A^dagger); `contract_*` accumulate Im <u| E |v> for every bond operator E
-// (hopping across one bond for every particle) and every site operator (the
-// occupation of one node) into per-realisation FP64 sums.  Bosons are stored
-// as the symmetric function on x1 <= x2 and read with mirrored indices, so
-// all inner products are full-grid inner products.
+// One kernel does the work of a level: a row sweep (`sweep_kernel`) that
+// computes y = cz z + s (-i) (dt H) (xs x) for every stored amplitude (s = +1
+// for A, -1 for A^dagger) and, given v, accumulates Im <u| E |v> with
+// u = xs x for every bond operator E (hopping across one bond, for every
+// particle) and every site operator (the occupation of one node) into FP64
+// sums.  A backward step is n - 1 such sweeps for v_1 .. v_{n-1} and n for
+// the Horner chain, each contracting its input u_L with v_L while it forms
+// u_{L-1} (lambda_k at L = 0); u_{n-1} = lambda / n! is the first sweep's
+// scaled input, so no vector holds it.
+//
+// Work item: a band of 62 output columns of one realisation, held by one
+// wave (one column per lane, one halo column on either side: the stencil and
+// the bonds reach one column over), swept down the rows.  Rows q - 1, q,
+// q + 1 of x and rows q, q + 1 of v are in registers; column neighbours come
+// from the adjacent lanes.  Loads and stores run along rows, one amplitude
+// per lane.
+//
+// Contractions.  Full grid (distinguishable particles; one particle is the
+// one-row case): the column parts of bond c and site c are sums over the
+// rows, kept per lane; the row parts of bond q and site q are sums over the
+// columns, reduced across the wave at every row into one partial per band.
+// Bosons are stored as the symmetric function phi(x1, x2) on x1 <= x2; the
+// full-grid sums are then twice the column part, and the column part of
+// bond b (pairs (q, b), (q, b + 1) over all q) splits into the stored pairs
+// of row q <= b in columns b, b + 1 and, mirrored, the pairs of rows b,
+// b + 1 in every column c >= b + 1: a horizontal part summed per lane and a
+// vertical part summed per row, as for the full grid, with the vertical
+// pairs and the row sites taken only where both entries are stored off the
+// diagonal (site b: column b over rows q <= b, plus row b over columns
+// c > b).  The stencil at a stored diagonal entry (q, q) reads its mirrored
+// neighbours (q + 1, q) = (q, q + 1) and (q, q - 1) = (q - 1, q).
 #include "ctqw_internal.hpp"
 
 namespace ctqw {
@@ -32,170 +56,183 @@ __device__ __forceinline__ int64_t index_of(const RealDev& rd, int q, int c) {
     return (int64_t)q * rd.N + c;
 }
 
-template <typename C>
-__device__ __forceinline__ C ld(const C* __restrict__ base, const RealDev& rd, int q, int c) {
-    return base[rd.state_off + index_of(rd, q, c)];
-}
+// Lane l receives lane l + 1's value (lane 63: 0) / lane l - 1's (lane 0: 0).
+__device__ __forceinline__ float from_right(float x) { return __builtin_amdgcn_update_dpp(0.0f, x, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ double from_right(double x) { return __builtin_amdgcn_update_dpp(0.0, x, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ float from_left(float x) { return __builtin_amdgcn_update_dpp(0.0f, x, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ double from_left(double x) { return __builtin_amdgcn_update_dpp(0.0, x, 0x138, 0xF, 0xF, true); }
 
-// (dt H x)(q, c) with the dt-scaled tables of the step kernel.
-template <typename T, typename C>
-__device__ __forceinline__ void apply_h(const C* __restrict__ x, const RealDev& rd, const T* __restrict__ Jt,
-                                        const T* __restrict__ Et, T Udt, int q, int c, T& hr, T& hi) {
-    const int N = rd.N, rows = rd.rows;
-    const bool periodic = (rd.flags & RF_PERIODIC) != 0;
-    const T* Jc = Jt + rd.param_off;
-    const T* Ec = Et + rd.param_off;
-    const T* Jr = Jt + rd.row_param_off;
-    const T* Er = Et + rd.row_param_off;
-    const C s = ld(x, rd, q, c);
-    T d = Er[q] + Ec[c];
-    if (rows > 1) {
-        int dd = q - c;
-        dd = dd < 0 ? -dd : dd;
-        if (periodic && N - dd < dd) dd = N - dd;
-        if (dd == ((rd.flags & RF_NEAREST) ? 1 : 0)) d += Udt;
-    }
-    hr = d * s.x;
-    hi = d * s.y;
-    // column neighbours (bond c-1 joins c-1 and c, bond c joins c and c+1)
-    if (c > 0 || periodic) {
-        const int cl = c > 0 ? c - 1 : N - 1;
-        const C v = ld(x, rd, q, cl);
-        const T j = Jc[cl];
-        hr += j * v.x;
-        hi += j * v.y;
-    }
-    if (c < N - 1 || periodic) {
-        const int cr = c < N - 1 ? c + 1 : 0;
-        const C v = ld(x, rd, q, cr);
-        const T j = Jc[c];
-        hr += j * v.x;
-        hi += j * v.y;
-    }
-    if (rows > 1) {
-        if (q > 0 || periodic) {
-            const int qu = q > 0 ? q - 1 : rows - 1;
-            const C v = ld(x, rd, qu, c);
-            const T j = Jr[qu];
-            hr += j * v.x;
-            hi += j * v.y;
-        }
-        if (q < rows - 1 || periodic) {
-            const int qd = q < rows - 1 ? q + 1 : 0;
-            const C v = ld(x, rd, qd, c);
-            const T j = Jr[q];
-            hr += j * v.x;
-            hi += j * v.y;
-        }
-    }
-}
-
-// y = s * (-i) * (dt H x) + cz * z  over every stored amplitude; x may be
-// null (then only cz * z), z may be null (cz ignored).
+// Im(conj(u) v) in FP64.
 template <typename T>
-__global__ void apply_kernel(AdjApplyArgs a) {
-    using C = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
-    const int r = blockIdx.z;
-    const RealDev rd = a.reals[r];
-    const int q = blockIdx.y;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= rd.rows || c >= rd.N) return;
-    if ((rd.flags & RF_TRIANGLE) && c < q) return;
-    const C* x = reinterpret_cast<const C*>(a.x);
-    const C* z = reinterpret_cast<const C*>(a.z);
-    C* y = reinterpret_cast<C*>(a.y);
-    T yr = T(0), yi = T(0);
-    if (x) {
-        T hr, hi;
-        apply_h<T, C>(x, rd, reinterpret_cast<const T*>(a.Jt), reinterpret_cast<const T*>(a.Et),
-                      static_cast<T>(rd.U * a.dt), q, c, hr, hi);
-        // s (-i)(hr + i hi) = s (hi - i hr)
-        const T sg = static_cast<T>(a.sign);
-        yr = sg * hi;
-        yi = -sg * hr;
-    }
-    const int64_t o = rd.state_off + index_of(rd, q, c);
-    if (z) {
-        const C zv = z[o];
-        const T cz = static_cast<T>(a.cz);
-        yr += cz * zv.x;
-        yi += cz * zv.y;
-    }
-    C out;
-    out.x = yr;
-    out.y = yi;
-    y[o] = out;
+__device__ __forceinline__ double im_uv(T ur, T ui, T vr, T vi) {
+    return (double)ur * (double)vi - (double)ui * (double)vr;
 }
 
-// Im( conj(u) v ) in FP64.
-template <typename C>
-__device__ __forceinline__ double im_uv(const C& u, const C& v) {
-    return (double)u.x * (double)v.y - (double)u.y * (double)v.x;
-}
-
-// Column parts: thread per column b of realisation r, summing over all rows
-//   bond b: Im conj(u(q,b)) v(q,b+1) + Im conj(u(q,b+1)) v(q,b)
-//   site b: Im conj(u(q,b)) v(q,b)
-// (the only parts for one particle; doubled for the symmetric boson function).
-template <typename C>
-__global__ void contract_cols_kernel(AdjContractArgs a) {
-    const int r = blockIdx.y;
-    const RealDev rd = a.reals[r];
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= rd.N) return;
-    const C* u = reinterpret_cast<const C*>(a.u);
-    const C* v = reinterpret_cast<const C*>(a.v);
-    const bool periodic = (rd.flags & RF_PERIODIC) != 0;
-    const bool has_bond = periodic || b < rd.N - 1;
-    const int b1 = b + 1 < rd.N ? b + 1 : 0;
-    double sb = 0.0, ss = 0.0;
-    for (int q = 0; q < rd.rows; ++q) {
-        const C ub = ld(u, rd, q, b), vb = ld(v, rd, q, b);
-        ss += im_uv(ub, vb);
-        if (has_bond) {
-            const C ub1 = ld(u, rd, q, b1), vb1 = ld(v, rd, q, b1);
-            sb += im_uv(ub, vb1) + im_uv(ub1, vb);
-        }
-    }
-    const double f = (rd.flags & RF_TRIANGLE) ? 2.0 : 1.0;
-    const int64_t o = a.site_off[r] + b;
-    a.gJ[o] += f * sb;
-    a.gE[o] += f * ss;
-}
-
-// Row parts for distinguishable particles: one wave per row q,
-//   bond q: sum_c Im conj(u(q,c)) v(q+1,c) + Im conj(u(q+1,c)) v(q,c)
-//   site q: sum_c Im conj(u(q,c)) v(q,c)
-template <typename C>
-__global__ void contract_rows_kernel(AdjContractArgs a) {
-    const int r = blockIdx.y;
-    const RealDev rd = a.reals[r];
-    const int lane = threadIdx.x & 63;
-    const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (q >= rd.rows) return;
-    const C* u = reinterpret_cast<const C*>(a.u);
-    const C* v = reinterpret_cast<const C*>(a.v);
-    const bool periodic = (rd.flags & RF_PERIODIC) != 0;
-    const bool has_bond = periodic || q < rd.rows - 1;
-    const int q1 = q + 1 < rd.rows ? q + 1 : 0;
-    double sb = 0.0, ss = 0.0;
-    for (int c = lane; c < rd.N; c += 64) {
-        const C uq = ld(u, rd, q, c), vq = ld(v, rd, q, c);
-        ss += im_uv(uq, vq);
-        if (has_bond) {
-            const C uq1 = ld(u, rd, q1, c), vq1 = ld(v, rd, q1, c);
-            sb += im_uv(uq, vq1) + im_uv(uq1, vq);
-        }
-    }
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        sb += __shfl_xor(sb, off, 64);
-        ss += __shfl_xor(ss, off, 64);
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T, bool CONTRACT>
+__global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) {
+    using C = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    const int r = blockIdx.y;
+    const int w = blockIdx.x;
+    const RealDev rd = a.reals[r];
+    const int N = rd.N, rows = rd.rows;
+    if (w * kSweepOut >= N) return;   // whole block, before the barrier
+    const int lane = threadIdx.x & 63;
+    const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool periodic = (rd.flags & RF_PERIODIC) != 0;
+    const bool tri = (rd.flags & RF_TRIANGLE) != 0;
+    const T* Jc = reinterpret_cast<const T*>(a.Jt) + rd.param_off;
+    const T* Ec = reinterpret_cast<const T*>(a.Et) + rd.param_off;
+    const T* Jr = reinterpret_cast<const T*>(a.Jt) + rd.row_param_off;
+    const T* Er = reinterpret_cast<const T*>(a.Et) + rd.row_param_off;
+    const T Udt = static_cast<T>(rd.U * a.dt);
+    const int want = (rd.flags & RF_NEAREST) ? 1 : 0;
+
+    // this lane's column: window [w * 62 - 1, w * 62 + 63), output [w * 62, w * 62 + 62)
+    const int c = w * kSweepOut - 1 + lane;
+    const bool inb = periodic || (c >= 0 && c < N);
+    const int cw = periodic ? wrapi(c, N) : (inb ? c : 0);
+    const bool out = c >= w * kSweepOut && c < w * kSweepOut + kSweepOut && c < N && lane > 0 && lane < 63;
+    const T jl = (inb && (periodic || c > 0)) ? Jc[periodic ? wrapi(cw - 1, N) : cw - 1] : T(0);
+    const T jr = (inb && (periodic || c < N - 1)) ? Jc[cw] : T(0);
+    const T ec = inb ? Ec[cw] : T(0);
+    const bool has_bond_c = periodic || c < N - 1;
+
+    const C* X = reinterpret_cast<const C*>(a.x);
+    const C* Z = reinterpret_cast<const C*>(a.z);
+    const C* V = reinterpret_cast<const C*>(a.v);
+    C* Y = reinterpret_cast<C*>(a.y);
+    const T xs = static_cast<T>(a.xs), cz = static_cast<T>(a.cz), sg = static_cast<T>(a.sign);
+    // lanes whose amplitude (q, c) is stored
+    auto stored = [&](int q) { return inb && (!tri || cw >= q); };
+    auto ld = [&](const C* base, int q) -> C {
+        C v;
+        v.x = T(0);
+        v.y = T(0);
+        if (!base) return v;
+        if (periodic) q = wrapi(q, rows);
+        else if (q < 0 || q >= rows) return v;
+        if (!stored(q)) return v;
+        return base[rd.state_off + index_of(rd, q, cw)];
+    };
+    // rows holding a stored amplitude of this window, split into one segment per wave
+    const int q_end = tri ? min(rows, w * kSweepOut + 63) : rows;
+    const int q0 = (int)(((int64_t)q_end * seg) / kSweepSegs);
+    const int q1 = (int)(((int64_t)q_end * (seg + 1)) / kSweepSegs);
+
+    // Rows q - 1, q, q + 1 of x, q and q + 1 of v and q of z in registers; the
+    // next kSweepAhead rows of each in a ring of loads in flight.
+    C xm = ld(X, q0 - 1), x0 = ld(X, q0), xp = ld(X, q0 + 1);
+    C v0 = CONTRACT ? ld(V, q0) : C{}, vp = CONTRACT ? ld(V, q0 + 1) : C{};
+    C zq = ld(Z, q0);
+    C xr[kSweepAhead], vr_[kSweepAhead], zr[kSweepAhead];
+#pragma unroll
+    for (int k = 0; k < kSweepAhead; ++k) {
+        xr[k] = ld(X, q0 + 2 + k);
+        vr_[k] = CONTRACT ? ld(V, q0 + 2 + k) : C{};
+        zr[k] = ld(Z, q0 + 1 + k);
     }
-    if (lane == 0) {
-        const int64_t o = a.site_off[r] + q;
-        a.gJ2[o] += sb;
-        a.gE2[o] += ss;
+    double bond_col = 0.0, site_col = 0.0;
+    const double f = tri ? 2.0 : 1.0;
+    double* gV = a.gV + ((int64_t)r * a.nb + w) * a.row_stride;
+    double* gR = a.gR + ((int64_t)r * a.nb + w) * a.row_stride;
+    for (int qb = q0; qb < q1; qb += kSweepAhead) {
+#pragma unroll
+        for (int k = 0; k < kSweepAhead; ++k) {
+            const int q = qb + k;
+            if (q >= q1) break;
+            const T mr = xs * x0.x, mi = xs * x0.y;
+            const T ur_ = xs * xm.x, ui_ = xs * xm.y;      // row q - 1
+            const T dr_ = xs * xp.x, di_ = xs * xp.y;      // row q + 1
+            const T rr = from_right(mr), ri = from_right(mi);
+            const T lr = from_left(mr), li = from_left(mi);
+            const bool diag = tri && cw == q;
+            // neighbours below and to the left; mirrored on the stored diagonal
+            const T br = diag ? rr : dr_, bi = diag ? ri : di_;
+            const T ar = diag ? ur_ : lr, ai = diag ? ui_ : li;
+            const bool up = rows > 1 && (periodic || q > 0);
+            const bool dn = rows > 1 && (periodic || q < rows - 1);
+            const T Jup = up ? Jr[periodic ? wrapi(q - 1, rows) : q - 1] : T(0);
+            const T Jdn = dn ? Jr[q] : T(0);
+            T d = Er[q] + ec;
+            if (rows > 1) {
+                int dd = q - cw;
+                dd = dd < 0 ? -dd : dd;
+                if (periodic && N - dd < dd) dd = N - dd;
+                if (dd == want) d += Udt;
+            }
+            T hr = d * mr, hi = d * mi;
+            hr = fma(Jup, ur_, hr);
+            hi = fma(Jup, ui_, hi);
+            hr = fma(Jdn, br, hr);
+            hi = fma(Jdn, bi, hi);
+            hr = fma(jl, ar, hr);
+            hi = fma(jl, ai, hi);
+            hr = fma(jr, rr, hr);
+            hi = fma(jr, ri, hi);
+            const bool st = out && stored(q);
+            if (st) {
+                // s (-i)(hr + i hi) = s (hi - i hr)
+                C yv;
+                yv.x = fma(cz, zq.x, sg * hi);
+                yv.y = fma(cz, zq.y, -sg * hr);
+                Y[rd.state_off + index_of(rd, q, cw)] = yv;
+            }
+            if constexpr (CONTRACT) {
+                const T vr = from_right(v0.x), vi = from_right(v0.y);
+                double vert = 0.0, rsite = 0.0;
+                if (st) {
+                    const double s0 = im_uv(mr, mi, v0.x, v0.y);
+                    site_col += s0;
+                    if (has_bond_c) bond_col += im_uv(mr, mi, vr, vi) + im_uv(rr, ri, v0.x, v0.y);
+                    if (rows > 1) {
+                        rsite = diag ? 0.0 : s0;
+                        if (dn && (!tri || cw >= q + 1))
+                            vert = im_uv(mr, mi, vp.x, vp.y) + im_uv(dr_, di_, v0.x, v0.y);
+                    }
+                }
+                if (rows > 1) {
+                    vert = wave_sum(vert);
+                    rsite = wave_sum(rsite);
+                    if (lane == 0) {
+                        gV[q] += f * vert;
+                        gR[q] += f * rsite;
+                    }
+                }
+                v0 = vp;
+                vp = vr_[k];
+                vr_[k] = ld(V, q + 2 + kSweepAhead);
+            }
+            xm = x0;
+            x0 = xp;
+            xp = xr[k];
+            xr[k] = ld(X, q + 2 + kSweepAhead);
+            zq = zr[k];
+            zr[k] = ld(Z, q + 1 + kSweepAhead);
+        }
+    }
+    if constexpr (CONTRACT) {
+        // column parts of the segments, summed in segment order
+        __shared__ double part[2][kSweepSegs][64];
+        part[0][seg][lane] = bond_col;
+        part[1][seg][lane] = site_col;
+        __syncthreads();
+        if (seg == 0 && out) {
+            double sb = 0.0, ss = 0.0;
+#pragma unroll
+            for (int k = 0; k < kSweepSegs; ++k) {
+                sb += part[0][k][lane];
+                ss += part[1][k][lane];
+            }
+            const int64_t o = a.site_off[r] + cw;
+            a.gJ[o] += f * sb;
+            a.gE[o] += f * ss;
+        }
     }
 }
 
@@ -237,53 +274,67 @@ __global__ void weights_kernel(AdjWeightArgs a) {
     if (threadIdx.x == 0) a.row_loss[a.site_off[r] + q] = red[0];
 }
 
-// Sum over realisations (index order) of the per-realisation gradients:
-// out_J[b] = 2 dt sum_r (gJ[r][b] + gJ2[r][b]), out_E likewise; and the loss
-// (1/R) sum_r sum_q row_loss[r][q].  One thread per site b (plus thread 0 of
-// block 0 for the loss).
-__global__ void adj_reduce_kernel(AdjReduceArgs a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum over realisations of the per-realisation gradients:
+// out_J[b] = 2 dt sum_r (gJ[r][b] + sum_w gV[r][w][b]) (the column part, then
+// the row parts of the bands in band order), out_E likewise with gE, gR; and
+// the loss (1/R) sum_r sum_q row_loss[r][q].  Block b < N: site b, thread t
+// summing realisations t, t + 256, ... in order, then a fixed tree over the
+// threads (deterministic).  Block N: the loss, the same way.
+__global__ void __launch_bounds__(256) adj_reduce_kernel(AdjReduceArgs a) {
+    const int b = blockIdx.x;
+    const int t = threadIdx.x;
+    __shared__ double red[2][256];
+    double s0 = 0.0, s1 = 0.0;
     if (b < a.N) {
-        double sj = 0.0, se = 0.0;
-        for (int64_t r = 0; r < a.R; ++r) {
+        for (int64_t r = t; r < a.R; r += 256) {
             const int64_t o = a.site_off[r] + b;
-            sj += a.gJ[o] + a.gJ2[o];
-            se += a.gE[o] + a.gE2[o];
+            double vj = 0.0, ve = 0.0;
+            for (int w = 0; w < a.nb; ++w) {
+                vj += a.gV[(r * a.nb + w) * a.row_stride + b];
+                ve += a.gR[(r * a.nb + w) * a.row_stride + b];
+            }
+            s0 += a.gJ[o] + vj;
+            s1 += a.gE[o] + ve;
         }
-        a.out[b] = 2.0 * a.dt * sj;
-        a.out[a.N + b] = 2.0 * a.dt * se;
-    }
-    if (b == 0) {
-        double l = 0.0;
-        for (int64_t r = 0; r < a.R; ++r) {
+    } else {
+        for (int64_t r = t; r < a.R; r += 256) {
             double lr = 0.0;
             for (int q = 0; q < a.rows; ++q) lr += a.row_loss[a.site_off[r] + q];
-            l += lr;
+            s0 += lr;
         }
-        a.out[2 * a.N] = l / (double)a.R;
+    }
+    red[0][t] = s0;
+    red[1][t] = s1;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (t < k) {
+            red[0][t] += red[0][t + k];
+            red[1][t] += red[1][t + k];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (b < a.N) {
+            a.out[b] = 2.0 * a.dt * red[0][0];
+            a.out[a.N + b] = 2.0 * a.dt * red[1][0];
+        } else {
+            a.out[2 * a.N] = red[0][0] / (double)a.R;
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_adj_apply(const AdjApplyArgs& a, hipStream_t s) {
-    if (a.R > 65535 || a.max_rows > 65535) return hipErrorInvalidValue;
-    const dim3 g((a.max_N + 63) / 64, a.max_rows, (unsigned)a.R);
-    if (a.dtype == 1) hipLaunchKernelGGL(apply_kernel<double>, g, dim3(64), 0, s, a);
-    else hipLaunchKernelGGL(apply_kernel<float>, g, dim3(64), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_contract(const AdjContractArgs& a, hipStream_t s) {
-    if (a.R > 65535) return hipErrorInvalidValue;
-    const dim3 gc((a.max_N + 255) / 256, (unsigned)a.R);
-    const dim3 gr((a.max_rows + 3) / 4, (unsigned)a.R);
+hipError_t launch_adj_sweep(const AdjSweepArgs& a, hipStream_t s) {
+    if (a.R > 65535 || a.nb < 1 || a.nb > 65535) return hipErrorInvalidValue;
+    const dim3 g((unsigned)a.nb, (unsigned)a.R);
+    const bool con = a.v != nullptr;
     if (a.dtype == 1) {
-        hipLaunchKernelGGL(contract_cols_kernel<double2>, gc, dim3(256), 0, s, a);
-        if (a.rows_part) hipLaunchKernelGGL(contract_rows_kernel<double2>, gr, dim3(256), 0, s, a);
+        if (con) hipLaunchKernelGGL((sweep_kernel<double, true>), g, dim3(64 * kSweepSegs), 0, s, a);
+        else hipLaunchKernelGGL((sweep_kernel<double, false>), g, dim3(64 * kSweepSegs), 0, s, a);
     } else {
-        hipLaunchKernelGGL(contract_cols_kernel<float2>, gc, dim3(256), 0, s, a);
-        if (a.rows_part) hipLaunchKernelGGL(contract_rows_kernel<float2>, gr, dim3(256), 0, s, a);
+        if (con) hipLaunchKernelGGL((sweep_kernel<float, true>), g, dim3(64 * kSweepSegs), 0, s, a);
+        else hipLaunchKernelGGL((sweep_kernel<float, false>), g, dim3(64 * kSweepSegs), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -297,7 +348,7 @@ hipError_t launch_adj_weights(const AdjWeightArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(adj_reduce_kernel, dim3((a.N + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(adj_reduce_kernel, dim3((unsigned)a.N + 1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ enum : int32_t {
     RF_TRIANGLE = 2,   // two bosons or fermions stored as the upper triangle x1 <= x2
     RF_NEAREST = 4,    // interaction on pairs at chain distance 1
     RF_FERMION = 8,    // triangle of two fermions: the diagonal x1 == x2 is held at 0
+    RF_NO_EPS = 16,    // all on-site energies are 0: the diagonal of H is the interaction alone
 };
 
 // One realisation, as the kernels see it.  The walk of m = 1 or 2 particles
@@ -228,39 +229,36 @@ struct Obs3Args {
 hipError_t launch_obs3(const Obs3Args& a, int dtype, hipStream_t stream);
 
 // ---------------------------------------------------------------- adjoint
-struct AdjApplyArgs {
-    const void* x;       // may be null
+// Backward sweeps: bands of kSweepOut output columns (a wave of 64 lanes
+// with one halo column on either side); a block of kSweepSegs waves splits
+// the band's rows into consecutive segments, each wave keeping the next
+// kSweepAhead rows of its inputs in flight.
+constexpr int kSweepOut = 62;
+constexpr int kSweepSegs = 4;
+constexpr int kSweepAhead = 4;
+struct AdjSweepArgs {
+    const void* x;       // input vector (never null)
+    double xs;           // scale of x (u = xs x)
     const void* z;       // may be null
-    void* y;
+    double cz;
+    int sign;            // +1: A = -i dt H; -1: A^dagger
+    void* y;             // output: cz z + s (-i) (dt H) u
+    const void* v;       // contraction partner of u; null: no contraction
     const RealDev* reals;
     const void* Jt;      // dt-scaled tables of the step kernel (dtype of the state)
     const void* Et;
     double dt;
-    double cz;
-    int sign;            // +1: A = -i dt H; -1: A^dagger
-    int64_t R;
-    int max_N;
-    int max_rows;
-    int dtype;
-};
-hipError_t launch_adj_apply(const AdjApplyArgs& a, hipStream_t stream);
-
-struct AdjContractArgs {
-    const void* u;
-    const void* v;
-    const RealDev* reals;
     const int64_t* site_off;
     double* gJ;          // column parts (bond b / site b) per realisation
     double* gE;
-    double* gJ2;         // row parts (distinguishable particles)
-    double* gE2;
+    double* gV;          // row parts per band: [R][nb][row_stride]
+    double* gR;
     int64_t R;
-    int max_N;
-    int max_rows;
-    int rows_part;
+    int nb;              // bands per realisation (ceil(max N / kSweepOut))
+    int row_stride;
     int dtype;
 };
-hipError_t launch_adj_contract(const AdjContractArgs& a, hipStream_t stream);
+hipError_t launch_adj_sweep(const AdjSweepArgs& a, hipStream_t stream);
 
 struct AdjWeightArgs {
     const void* psi;
@@ -280,8 +278,10 @@ hipError_t launch_adj_weights(const AdjWeightArgs& a, hipStream_t stream);
 struct AdjReduceArgs {
     const double* gJ;
     const double* gE;
-    const double* gJ2;
-    const double* gE2;
+    const double* gV;
+    const double* gR;
+    int nb;
+    int row_stride;
     const double* row_loss;
     const int64_t* site_off;
     double* out;         // [2N + 1]: dL/dJ, dL/deps, loss

@@ -196,9 +196,10 @@ T* at(ctqw_plan* p, const Region& r) {
 }
 
 // Windows of W consecutive indices covering [0, N) with a halo of h on each
-// side (the same rule as the column bands below, without the row fields):
-// {window start, first output, end of output}.  Boundaries inside the
-// chain are moved down to multiples of `align` where that leaves an output.
+// side (the same rule as the output-aligned column bands below, without the
+// row fields): {window start, first output, end of output}.  Boundaries
+// inside the chain are moved down to multiples of `align` where that leaves
+// an output; on an open chain the last window may run past the end.
 bool bands_1d(int N, int h, int W, bool periodic, int align, std::vector<std::array<int32_t, 3>>& out) {
     if (W - 2 * h <= 0) return false;
     int lo = 0;
@@ -213,10 +214,8 @@ bool bands_1d(int N, int h, int W, bool periodic, int align, std::vector<std::ar
             const int end = w0 + W - h;
             hi = end >= N ? N : aligned(end);
         } else {
-            w0 = std::max(0, lo - h);
-            if (w0 + W > N) w0 = std::max(0, N - W);
-            const int w1 = std::min(N, w0 + W);
-            hi = (w1 == N) ? N : aligned(w1 - h);
+            w0 = std::max(0, lo - h);   // the last window may run past the chain's end
+            hi = (w0 + W >= N) ? N : aligned(w0 + W - h);
         }
         if (hi <= lo) return false;
         out.push_back({w0, lo, hi});
@@ -233,21 +232,33 @@ int terms3(const ctqw_plan* p, int order) {
 }
 
 // Column bands of one realisation for halo h (= its Taylor order) and a
-// window of W columns.  Band boundaries inside the chain are moved down to
-// multiples of `align` columns where that leaves the band an output column,
-// so that the stores of neighbouring bands do not share cache lines (the
-// caller halves the alignment while it would add a band).
+// window of W columns.  A band computes its whole window and stores its
+// output columns [lo, hi), which lie at least h columns inside the window
+// (or at the chain's ends).  Two layouts:
+//  * output-aligned (window_aligned = false): band boundaries inside the
+//    chain are moved down to multiples of `align` columns where that leaves
+//    the band an output column, so that the stores of neighbouring bands do
+//    not share cache lines (the caller halves the alignment while it would
+//    add a band); the window starts h columns before the output;
+//  * window-aligned (full grids on open chains): each window starts on a
+//    multiple of `align` columns, so a row of the window is read as whole
+//    cache lines, and the output ends on a multiple of `out_gran` columns;
+//    neighbouring bands then store parts of one line.
+// On an open chain the last window is not moved back inside the chain:
+// its columns past the end are lanes without data, which load nothing.
 // Returns false if the halo leaves no output column.
 // With `pairs` (lanes holding two adjacent columns) the window starts on an
 // even column where the chain allows, so that the lanes' column pairs are
 // read and written as one 16-byte access.
 bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, int align, bool pairs,
-                std::vector<ItemDev>& out) {
+                std::vector<ItemDev>& out, bool window_aligned = false, int out_gran = 1) {
     const int rows = pr.m == 1 ? 1 : N;
     const bool periodic = pr.boundary == CTQW_PERIODIC;
     const bool tri = pr.m == 2 && pr.statistics != CTQW_DISTINGUISHABLE;
     if (W - 2 * h <= 0) return false;
+    window_aligned = window_aligned && !periodic && !tri && align > 1;
     int lo = 0;
+    int next_w0 = 0;
     while (lo < N) {
         ItemDev it{};
         it.real = r;
@@ -255,7 +266,13 @@ bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, int align, b
             const int a = (c / align) * align;
             return a > lo ? a : c;
         };
-        if (periodic) {
+        if (window_aligned) {
+            const int w0 = next_w0;   // a multiple of align, at most lo - h
+            it.w0 = w0;
+            it.lo = lo;
+            it.hi = w0 + W >= N ? N : ((w0 + W - h) / out_gran) * out_gran;
+            if (it.hi < N) next_w0 = std::max(0, ((it.hi - h) / align) * align);
+        } else if (periodic) {
             int w0 = lo - h;
             if (pairs && (w0 & 1)) --w0;
             it.w0 = w0;
@@ -265,11 +282,10 @@ bool make_bands(const ctqw_problem& pr, int r, int N, int h, int W, int align, b
         } else {
             int w0 = std::max(0, lo - h);
             if (pairs && (w0 & 1)) --w0;
-            if (w0 + W > N) w0 = std::max(0, N - W);
-            const int w1 = std::min(N, w0 + W);
+            const int w1 = w0 + W;
             it.w0 = w0;
             it.lo = lo;
-            it.hi = (w1 == N) ? N : aligned(w1 - h);
+            it.hi = (w1 >= N) ? N : aligned(w1 - h);
         }
         if (it.hi <= it.lo) return false;
         if (periodic && rows > 1) {
@@ -361,11 +377,20 @@ ctqw_status build_tables(ctqw_plan* p) {
             if (!make_bands(pr, (int)r, p->N[r], halo, band_W, 1, pairs_r, plain))
                 return fail(p, CTQW_ERR_UNSUPPORTED, "Taylor order %d too deep for a %d-column band", halo, band_W);
             const std::vector<ItemDev>* use = &plain;
-            for (int a = align; a > 1; a /= 2) {
-                trial.clear();
-                if (make_bands(pr, (int)r, p->N[r], halo, band_W, a, pairs_r, trial) && trial.size() <= plain.size()) {
+            if (p->launch.band_mode == 1 && align > 1) {
+                // window-aligned bands; outputs end on 32-byte boundaries
+                const int gran = std::max(1, std::min(align, 32 / amp_bytes));
+                if (make_bands(pr, (int)r, p->N[r], halo, band_W, align, pairs_r, trial, true, gran) &&
+                    trial.size() <= plain.size() + 1)
                     use = &trial;
-                    break;
+            } else {
+                for (int a = align; a > 1; a /= 2) {
+                    trial.clear();
+                    if (make_bands(pr, (int)r, p->N[r], halo, band_W, a, pairs_r, trial) &&
+                        trial.size() <= plain.size()) {
+                        use = &trial;
+                        break;
+                    }
                 }
             }
             items.insert(items.end(), use->begin(), use->end());
@@ -521,6 +546,12 @@ ctqw_status upload_tables(ctqw_plan* p) {
                   (pr.m == 2 && pr.statistics != CTQW_DISTINGUISHABLE ? RF_TRIANGLE : 0) |
                   (pr.m == 2 && pr.statistics == CTQW_FERMION ? RF_FERMION : 0) |
                   (pr.interaction == CTQW_INT_NEAREST ? RF_NEAREST : 0);
+        {
+            // no on-site energies: the diagonal of H is the interaction alone
+            bool zero = true;
+            for (int i = 0; i < p->N[r] && zero; ++i) zero = p->Epad[p->param_off[r] + i] == 0.0;
+            if (zero) d.flags |= RF_NO_EPS;
+        }
         d.U = pr.m == 1 ? 0.0 : p->U[r];
         // remainder estimate: ||sum_{j>n} Phi^(j)|| <= ||Phi^(n)|| (x/(n+1)) / (1 - x/(n+2))
         d.tail_factor = (x < n + 2) ? (x / (n + 1)) / (1.0 - x / (n + 2)) : INFINITY;
@@ -1170,6 +1201,7 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         p->launch.chunked = 0;
         p->launch.band_align = 128;
         p->launch.terms_per_pass = 0;
+        p->launch.band_mode = 0;
         p->order.assign(R, 0);
         p->xbound.assign(R, 0.0);
     } catch (const std::bad_alloc&) {
@@ -1692,6 +1724,8 @@ ctqw_status ctqw_set_launch(ctqw_plan* p, const ctqw_launch* l) {
         return fail(p, CTQW_ERR_INVALID_ARG, "band_align must be 0, 64, 128 or 256 bytes");
     if (l->terms_per_pass < 0 || l->terms_per_pass > 3)
         return fail(p, CTQW_ERR_INVALID_ARG, "terms_per_pass must be 0 (default) or 1..3");
+    if (l->band_mode != 0 && l->band_mode != 1)
+        return fail(p, CTQW_ERR_INVALID_ARG, "band_mode must be 0 (output-aligned) or 1 (window-aligned)");
     const ctqw_launch old = p->launch;
     p->launch = *l;
     if (p->params_set) {
@@ -1917,6 +1951,7 @@ bool cache_lookup(const char* path, const std::string& key, ctqw_launch* out, do
             if (!parse_int_field(s, "chunked", &l.chunked)) l.chunked = 0;
             if (!parse_int_field(s, "band_align", &l.band_align)) l.band_align = 0;
             if (!parse_int_field(s, "terms_per_pass", &l.terms_per_pass)) l.terms_per_pass = 0;
+            if (!parse_int_field(s, "band_mode", &l.band_mode)) l.band_mode = 0;
             *out = l;
             const size_t at = s.find("\"ms\": ");
             *ms = at == std::string::npos ? NAN : atof(s.c_str() + at + 6);
@@ -1932,9 +1967,10 @@ void cache_append(const char* path, const std::string& key, const ctqw_launch& l
     if (!f) return;
     fprintf(f,
             "{\"key\": \"%s\", \"cols_per_lane\": %d, \"waves_per_block\": %d, \"persistent\": %d, "
-            "\"waves_per_cu\": %d, \"chunked\": %d, \"band_align\": %d, \"terms_per_pass\": %d, \"ms\": %.6f}\n",
+            "\"waves_per_cu\": %d, \"chunked\": %d, \"band_align\": %d, \"terms_per_pass\": %d, "
+            "\"band_mode\": %d, \"ms\": %.6f}\n",
             key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, l.chunked, l.band_align,
-            l.terms_per_pass, ms);
+            l.terms_per_pass, l.band_mode, ms);
     fclose(f);
 }
 
@@ -2010,6 +2046,7 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
         }
         if (path && *path) cache_append(path, key, best, best_ms);
     } else if (!cached) {
+        for (int mode : {0, 1})
         for (int align : {128, 64, 0})
         for (int chunked : {0, 1})
         for (int P : {1, 2})
@@ -2018,6 +2055,7 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
                     for (int cap : {0, 8, 16}) {
                         if (!pers && cap) continue;
                         if (chunked && (P != 1 || p->prob.m == 3)) continue;   // passes run one column per lane
+                        if (mode && (align != 128 || chunked)) continue;        // window-aligned: 128-byte windows
                         ctqw_launch c = orig;
                         c.cols_per_lane = P;
                         c.waves_per_block = wpb;
@@ -2025,6 +2063,7 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
                         c.waves_per_cu = cap;
                         c.chunked = chunked;
                         c.band_align = align;
+                        c.band_mode = mode;
                         p->launch = c;
                         if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
                         if ((st = upload_tables(p)) != CTQW_OK) return st;
@@ -2061,7 +2100,8 @@ namespace {
 struct GradLayout {
     int64_t S = 0, n_ckpt = 0, n_seg = 0, n_v = 0;
     int64_t ckpt = 0, seg = 0, v = 0, u = 0, lam = 0;
-    int64_t gJ = 0, gE = 0, gJ2 = 0, gE2 = 0, row_loss = 0, site_w = 0, out = 0;
+    int64_t gJ = 0, gE = 0, gV = 0, gR = 0, row_loss = 0, site_w = 0, out = 0;
+    int nb = 1;
     int64_t total = 0;
 };
 
@@ -2081,8 +2121,10 @@ GradLayout grad_layout(const ctqw_plan* p, int64_t n_steps, int64_t C) {
     auto dbl = [&](int64_t n) { const int64_t r = o; o += (n * 8 + 255) & ~int64_t(255); return r; };
     g.gJ = dbl(p->site_total);
     g.gE = dbl(p->site_total);
-    g.gJ2 = dbl(p->site_total);
-    g.gE2 = dbl(p->site_total);
+    // row parts of the backward sweeps: one partial per band and row
+    g.nb = std::max(1, (p->max_N + kSweepOut - 1) / kSweepOut);
+    g.gV = dbl((int64_t)p->prob.R * g.nb * p->max_N);
+    g.gR = dbl((int64_t)p->prob.R * g.nb * p->max_N);
     g.row_loss = dbl(p->site_total);
     g.site_w = dbl(p->max_N);
     g.out = dbl(2 * (int64_t)p->max_N + 1);
@@ -2199,42 +2241,32 @@ ctqw_status ctqw_backward(ctqw_plan* p, int32_t kind, const double* site_w, void
     wa.dtype = dtype;
     HIP_TRY(p, launch_adj_weights(wa, s));
 
-    AdjApplyArgs ap{};
-    ap.reals = reals;
-    ap.Jt = dtype ? static_cast<const void*>(at<double>(p, p->lay.Jd)) : static_cast<const void*>(at<float>(p, p->lay.Jf));
-    ap.Et = dtype ? static_cast<const void*>(at<double>(p, p->lay.Ed)) : static_cast<const void*>(at<float>(p, p->lay.Ef));
-    ap.dt = pr.dt;
-    ap.R = pr.R;
-    ap.max_N = N;
-    ap.max_rows = rows;
-    ap.dtype = dtype;
-    auto apply = [&](const void* x, const void* z, double cz, int sign, void* y) -> ctqw_status {
-        AdjApplyArgs a = ap;
+    AdjSweepArgs sa{};
+    sa.reals = reals;
+    sa.Jt = dtype ? static_cast<const void*>(at<double>(p, p->lay.Jd)) : static_cast<const void*>(at<float>(p, p->lay.Jf));
+    sa.Et = dtype ? static_cast<const void*>(at<double>(p, p->lay.Ed)) : static_cast<const void*>(at<float>(p, p->lay.Ef));
+    sa.dt = pr.dt;
+    sa.site_off = site_off;
+    sa.gJ = reinterpret_cast<double*>(G + g.gJ);
+    sa.gE = reinterpret_cast<double*>(G + g.gE);
+    sa.gV = reinterpret_cast<double*>(G + g.gV);
+    sa.gR = reinterpret_cast<double*>(G + g.gR);
+    sa.R = pr.R;
+    sa.nb = g.nb;
+    sa.row_stride = p->max_N;
+    sa.dtype = dtype;
+    // one sweep: y = cz z + s (-i)(dt H)(xs x), contracting xs x with v if given
+    auto sweep = [&](const void* x, double xs, const void* z, double cz, int sign, void* y,
+                     const void* v) -> ctqw_status {
+        AdjSweepArgs a = sa;
         a.x = x;
+        a.xs = xs;
         a.z = z;
         a.cz = cz;
         a.sign = sign;
         a.y = y;
-        HIP_TRY(p, launch_adj_apply(a, s));
-        return CTQW_OK;
-    };
-    AdjContractArgs ca{};
-    ca.reals = reals;
-    ca.site_off = site_off;
-    ca.gJ = reinterpret_cast<double*>(G + g.gJ);
-    ca.gE = reinterpret_cast<double*>(G + g.gE);
-    ca.gJ2 = reinterpret_cast<double*>(G + g.gJ2);
-    ca.gE2 = reinterpret_cast<double*>(G + g.gE2);
-    ca.R = pr.R;
-    ca.max_N = N;
-    ca.max_rows = rows;
-    ca.rows_part = (pr.m == 2 && pr.statistics == CTQW_DISTINGUISHABLE) ? 1 : 0;
-    ca.dtype = dtype;
-    auto contract = [&](const void* u, const void* v) -> ctqw_status {
-        AdjContractArgs a = ca;
-        a.u = u;
         a.v = v;
-        HIP_TRY(p, launch_adj_contract(a, s));
+        HIP_TRY(p, launch_adj_sweep(a, s));
         return CTQW_OK;
     };
 
@@ -2250,29 +2282,36 @@ ctqw_status ctqw_backward(ctqw_plan* p, int32_t kind, const double* site_w, void
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const void* lam = state(g.lam, lc);
+            // v_i = A^i psi_k
             vp[0] = segp[k];
             for (int i = 1; i < n; ++i) {
                 vp[i] = state(g.v, i - 1);
-                if ((st = apply(vp[i - 1], nullptr, 0.0, +1, const_cast<void*>(vp[i]))) != CTQW_OK) return st;
+                if ((st = sweep(vp[i - 1], 1.0, nullptr, 0.0, +1, const_cast<void*>(vp[i]), nullptr)) != CTQW_OK)
+                    return st;
             }
+            // Horner: level L contracts u_L with v_L and forms u_{L-1} = lambda / L! + A^dagger u_L
+            // (lambda_k at L = 0); u_{n-1} = lambda / n! is the first level's scaled input
             int uc = 0;
-            if ((st = apply(nullptr, lam, inv_fact(n), +1, state(g.u, uc))) != CTQW_OK) return st;
-            if ((st = contract(state(g.u, uc), vp[n - 1])) != CTQW_OK) return st;
-            for (int i = n - 2; i >= 0; --i) {
-                if ((st = apply(state(g.u, uc), lam, inv_fact(i + 1), -1, state(g.u, 1 - uc))) != CTQW_OK) return st;
+            const void* u = lam;
+            double us = inv_fact(n);
+            for (int L = n - 1; L >= 0; --L) {
+                void* y = L > 0 ? state(g.u, uc) : state(g.lam, 1 - lc);
+                if ((st = sweep(u, us, lam, inv_fact(L), -1, y, vp[L])) != CTQW_OK) return st;
+                u = y;
+                us = 1.0;
                 uc ^= 1;
-                if ((st = contract(state(g.u, uc), vp[i])) != CTQW_OK) return st;
             }
-            if ((st = apply(state(g.u, uc), lam, 1.0, -1, state(g.lam, 1 - lc))) != CTQW_OK) return st;
             lc ^= 1;
         }
     }
 
     AdjReduceArgs ra{};
-    ra.gJ = ca.gJ;
-    ra.gE = ca.gE;
-    ra.gJ2 = ca.gJ2;
-    ra.gE2 = ca.gE2;
+    ra.gJ = sa.gJ;
+    ra.gE = sa.gE;
+    ra.gV = sa.gV;
+    ra.gR = sa.gR;
+    ra.nb = g.nb;
+    ra.row_stride = p->max_N;
     ra.row_loss = wa.row_loss;
     ra.site_off = site_off;
     ra.out = reinterpret_cast<double*>(G + g.out);
@@ -2334,8 +2373,10 @@ ctqw_status ctqw_loss(ctqw_plan* p, int32_t kind, const double* site_w, void* gw
     AdjReduceArgs ra{};
     ra.gJ = reinterpret_cast<const double*>(G + g.gJ);
     ra.gE = reinterpret_cast<const double*>(G + g.gE);
-    ra.gJ2 = reinterpret_cast<const double*>(G + g.gJ2);
-    ra.gE2 = reinterpret_cast<const double*>(G + g.gE2);
+    ra.gV = reinterpret_cast<const double*>(G + g.gV);
+    ra.gR = reinterpret_cast<const double*>(G + g.gR);
+    ra.nb = g.nb;
+    ra.row_stride = p->max_N;
     ra.row_loss = wa.row_loss;
     ra.site_off = wa.site_off;
     ra.out = reinterpret_cast<double*>(G + g.out);

@@ -128,6 +128,49 @@ __device__ __forceinline__ void stencil_c64_p2(float (&hr)[2], float (&hi)[2], c
           "v"(jr[0]), "v"(jr[1]));
 }
 
+// The same stencils without the diagonal product, for rows where the
+// diagonal of H is zero on every lane (no on-site energies, no interacting
+// column in the band): the sum starts from the bond above.  The DPP reads
+// come after four or eight VALU instructions of the block.
+__device__ __forceinline__ void stencil_c64_p1_nd(float& hr, float& hi, float mr, float mi, float ur, float ui,
+                                                  float vr, float vi, float Ju, float Jd, float jl, float jr) {
+    asm("v_mul_f32 %0, %8, %4\n\t"
+        "v_mul_f32 %1, %8, %5\n\t"
+        "v_fmac_f32 %0, %9, %6\n\t"
+        "v_fmac_f32 %1, %9, %7\n\t"
+        "v_fmac_f32_dpp %0, %2, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %3, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %0, %2, %11 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %3, %11 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(hr), "=&v"(hi)
+        : "v"(mr), "v"(mi), "v"(ur), "v"(ui), "v"(vr), "v"(vi), "s"(Ju), "s"(Jd), "v"(jl), "v"(jr));
+}
+__device__ __forceinline__ void stencil_c64_p2_nd(float (&hr)[2], float (&hi)[2], const float (&mr)[2],
+                                                  const float (&mi)[2], const float (&ur)[2], const float (&ui)[2],
+                                                  const float (&vr)[2], const float (&vi)[2], float Ju, float Jd,
+                                                  const float (&jl)[2], const float (&jr)[2]) {
+    asm("v_mul_f32 %0, %16, %8\n\t"
+        "v_mul_f32 %1, %16, %9\n\t"
+        "v_mul_f32 %2, %16, %10\n\t"
+        "v_mul_f32 %3, %16, %11\n\t"
+        "v_fmac_f32 %0, %17, %12\n\t"
+        "v_fmac_f32 %1, %17, %13\n\t"
+        "v_fmac_f32 %2, %17, %14\n\t"
+        "v_fmac_f32 %3, %17, %15\n\t"
+        "v_fmac_f32_dpp %0, %6, %18 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %1, %7, %18 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32 %2, %19, %4\n\t"
+        "v_fmac_f32 %3, %19, %5\n\t"
+        "v_fmac_f32 %0, %20, %6\n\t"
+        "v_fmac_f32 %1, %20, %7\n\t"
+        "v_fmac_f32_dpp %2, %4, %21 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_fmac_f32_dpp %3, %5, %21 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(hr[0]), "=&v"(hi[0]), "=&v"(hr[1]), "=&v"(hi[1])
+        : "v"(mr[0]), "v"(mi[0]), "v"(mr[1]), "v"(mi[1]), "v"(ur[0]), "v"(ui[0]), "v"(ur[1]), "v"(ui[1]),
+          "v"(vr[0]), "v"(vi[0]), "v"(vr[1]), "v"(vi[1]), "s"(Ju), "s"(Jd), "v"(jl[0]), "v"(jl[1]), "v"(jr[0]),
+          "v"(jr[1]));
+}
+
 // Raw buffer resources: the last descriptor word for gfx9-family buffers
 // without format conversion.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -413,7 +456,10 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
     // block body has no early exit (which keeps the prefetch waits exact).
     const int total = nrows + NT;
 
-    for (int i0 = 0; i0 < total; i0 += WA) {
+    // One unrolled block of WA sweep steps.  ND: every level's rows have a
+    // zero diagonal on every lane, so the stencil skips the diagonal product.
+    auto block = [&](auto nodiag, int i0) {
+        constexpr bool ND = decltype(nodiag)::value;
 #pragma unroll
         for (int u = 0; u < WA; ++u) {
             const int i = i0 + u;
@@ -510,13 +556,23 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                     const bool zone = TRI && qa >= it.w0;
                     T hrv[P], hiv[P];
                     if constexpr (sizeof(T) == 4 && !TRI) {
-                        if constexpr (P == 1)
-                            stencil_c64_p1(hrv[0], hiv[0], dg[w][0], fr[j - 1][sm][0], fi[j - 1][sm][0],
-                                           fr[j - 1][su][0], fi[j - 1][su][0], fr[j - 1][sd][0], fi[j - 1][sd][0], Ju,
-                                           Jd, jl[0], jr[0]);
-                        else
-                            stencil_c64_p2(hrv, hiv, dg[w], fr[j - 1][sm], fi[j - 1][sm], fr[j - 1][su], fi[j - 1][su],
-                                           fr[j - 1][sd], fi[j - 1][sd], Ju, Jd, jl, jr);
+                        if constexpr (ND) {
+                            if constexpr (P == 1)
+                                stencil_c64_p1_nd(hrv[0], hiv[0], fr[j - 1][sm][0], fi[j - 1][sm][0],
+                                                  fr[j - 1][su][0], fi[j - 1][su][0], fr[j - 1][sd][0],
+                                                  fi[j - 1][sd][0], Ju, Jd, jl[0], jr[0]);
+                            else
+                                stencil_c64_p2_nd(hrv, hiv, fr[j - 1][sm], fi[j - 1][sm], fr[j - 1][su],
+                                                  fi[j - 1][su], fr[j - 1][sd], fi[j - 1][sd], Ju, Jd, jl, jr);
+                        } else {
+                            if constexpr (P == 1)
+                                stencil_c64_p1(hrv[0], hiv[0], dg[w][0], fr[j - 1][sm][0], fi[j - 1][sm][0],
+                                               fr[j - 1][su][0], fi[j - 1][su][0], fr[j - 1][sd][0],
+                                               fi[j - 1][sd][0], Ju, Jd, jl[0], jr[0]);
+                            else
+                                stencil_c64_p2(hrv, hiv, dg[w], fr[j - 1][sm], fi[j - 1][sm], fr[j - 1][su],
+                                               fi[j - 1][su], fr[j - 1][sd], fi[j - 1][sd], Ju, Jd, jl, jr);
+                        }
                     } else {
                         T lr[P], li[P], rr[P], ri[P];
 #pragma unroll
@@ -533,10 +589,16 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                             T cu = Ju, crt = jr[p];
                             if (TRI && zone && col[p] == qa && !fermi) { cu = Ju + Ju; crt = crt + crt; }
                             const T mr = fr[j - 1][sm][p], mi = fi[j - 1][sm][p];
-                            T hr = dg[w][p] * mr;
-                            T hi = dg[w][p] * mi;
-                            hr += cu * fr[j - 1][su][p];
-                            hi += cu * fi[j - 1][su][p];
+                            T hr, hi;
+                            if constexpr (ND) {
+                                hr = cu * fr[j - 1][su][p];
+                                hi = cu * fi[j - 1][su][p];
+                            } else {
+                                hr = dg[w][p] * mr;
+                                hi = dg[w][p] * mi;
+                                hr += cu * fr[j - 1][su][p];
+                                hi += cu * fi[j - 1][su][p];
+                            }
                             hr += Jd * fr[j - 1][sd][p];
                             hi += Jd * fi[j - 1][sd][p];
                             hr += jl[p] * lr[p];
@@ -646,6 +708,32 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
                 }
             }
         }
+    };
+    // Without on-site energies the diagonal of H is the interaction alone,
+    // nonzero only on the rows whose interacting columns (the row itself on
+    // site, its neighbours for nearest-neighbour pairs) fall in the band's
+    // window: the levels of other rows skip the diagonal product.  Steps
+    // [d0, d1) (whole blocks) hold a level on such a row; the diagonal of
+    // every row is still formed at level 0, so the slots stay exact.
+    int d0 = 0, d1 = total;
+    if constexpr (!TRI && !CHUNK) {
+        if ((rd.flags & RF_NO_EPS) && !periodic && rows > 1) {
+            const int reach = nearest ? 1 : 0;
+            const int zlo = max(0, it.w0 - reach - it.row0);
+            const int zhi = min(nrows, it.w0 + 64 * P + reach - it.row0);
+            if (Udt == T(0) || zlo >= zhi) {
+                d0 = d1 = 0;
+            } else {
+                d0 = ((zlo + 1) / WA) * WA;
+                d1 = ((zhi + NT + WA - 1) / WA) * WA;
+            }
+        }
+        int i0 = 0;
+        for (; i0 < d0 && i0 < total; i0 += WA) block(std::true_type{}, i0);
+        for (; i0 < d1 && i0 < total; i0 += WA) block(std::false_type{}, i0);
+        for (; i0 < total; i0 += WA) block(std::true_type{}, i0);
+    } else {
+        for (int i0 = 0; i0 < total; i0 += WA) block(std::false_type{}, i0);
     }
     if (!TRI) {
 #pragma unroll

@@ -58,6 +58,44 @@ def test_gradient_matches_finite_differences_c128(stat, kind, boundary):
     assert plan.stats().steps_done == steps
 
 
+@pytest.mark.parametrize("m,stat,boundary,N", [(1, "distinguishable", "open", 150),
+                                                (1, "distinguishable", "periodic", 150),
+                                                (2, "distinguishable", "periodic", 70),
+                                                (2, "boson", "open", 130)])
+def test_gradient_several_bands_c128(m, stat, boundary, N):
+    """Lattices wider than one backward band (62 output columns): the
+    derivative of the loss along two random directions of (Jbar, epsbar)
+    equals the central difference of the oracle's truncated-Taylor loss
+    (relative to |grad| |direction|: 1e-8), and the loss the oracle's."""
+    say(f"case: adjoint c128 m={m} {stat} {boundary} N={N} R=2, 30 steps, ckpt 7")
+    R, dt, steps, order, ckpt = 2, 0.05, 30, 10, 7
+    dJ, deps, U = noise(N, R, 4, boundary)
+    nb = dJ.shape[1]
+    Jbar = 1.0 + 0.05 * np.sin(np.arange(nb))
+    epsbar = 0.1 * np.cos(np.arange(N))
+    sw = np.linspace(-1, 1, N)
+    sites = [N // 3] if m == 1 else [N // 3, N // 3 + 1]
+    reals = [(N, Jbar + dJ[r], epsbar + deps[r], float(U[r])) for r in range(R)]
+    plan = gpu_plan(m=m, statistics=stat, boundary=boundary, interaction="onsite", dtype="c128", reals=reals,
+                    dt=dt, order=order, tol=0.0, sites=sites)
+    loss, gJ, gE = plan.gradient(steps, ckpt, sw, "one_body")
+    ens = G.Ensemble(N, m, stat, dJ, deps, U, sites, boundary=boundary)
+    w = G.diagonal_weights(ens.states, sw, G.ONE_BODY)
+    fn = lambda a, b: G.loss_taylor(ens, a, b, w, dt, steps, order)  # noqa: E731
+    l0 = fn(Jbar, epsbar)
+    g_all = np.concatenate([gJ, gE])
+    rs = np.random.default_rng(5)
+    worst = 0.0
+    for _ in range(2):
+        vJ, vE = rs.normal(size=nb), rs.normal(size=N)
+        fd = G.fd_directional(fn, Jbar, epsbar, vJ, vE, h=1e-5)
+        ad = float(gJ @ vJ + gE @ vE)
+        worst = max(worst, abs(ad - fd) / (np.linalg.norm(g_all) * np.linalg.norm(np.concatenate([vJ, vE]))))
+    say(f"  loss {loss:.12f} (oracle {l0:.12f}); directional error / (|g| |v|) = {worst:.2e}")
+    assert abs(loss - l0) < 1e-12
+    assert worst <= 1e-8
+
+
 def test_gradient_matches_exact_evolution_gradient_reduced_c4():
     """Reduced gradient workload: two bosons on N=32, U=1, J noise 0.1,
     eps noise U[-0.5,0.5], 8 realisations, loss = probability that both are

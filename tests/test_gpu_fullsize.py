@@ -28,13 +28,15 @@ STEPS = 20
 C64_BAR = 2e-7
 
 
-def test_c3_full_size_sampled_against_the_oracle():
+@pytest.mark.parametrize("band_mode", [0, 1], ids=["output-aligned", "window-aligned"])
+def test_c3_full_size_sampled_against_the_oracle(band_mode):
     import torch
     import bench
     from workloads import C3
 
     w = C3("c64")
-    launch = dict(cols_per_lane=2, persistent=1, waves_per_block=1, waves_per_cu=8, use_graph=1, band_align=128)
+    launch = dict(cols_per_lane=2, persistent=1, waves_per_block=1, waves_per_cu=8, use_graph=1, band_align=128,
+                  band_mode=band_mode)
     say(f"case: C3 full size, c64 Kahan, {STEPS} steps, launch {launch}")
     plan = bench.build_plan(w, "c64", "kahan", launch, w.tol)
     sizes = w.lattice_sizes()

@@ -218,6 +218,49 @@ def test_pair_correlation_c128():
         assert np.max(np.abs(got_G - G)) <= C128_BAR
 
 
+# ------------------------------------------------------------ zero on-site energies
+
+@pytest.mark.parametrize("interaction", ["onsite", "nearest"])
+@pytest.mark.parametrize("P_", [1, 2])
+def test_zero_onsite_energies_c128(P_, interaction):
+    """Without on-site energies the diagonal of H is the interaction alone
+    and the step kernel skips the diagonal product on rows whose band has no
+    interacting column.  Chains of several bands with eps = 0 and U != 0
+    against the oracle's Taylor map of the same order (1e-12)."""
+    say(f"case: eps = 0, m=2 dist open N=[150,300,200] c128 P={P_} {interaction}")
+    reals = [(N, J, np.zeros(N), U) for (N, J, _, U) in random_reals([150, 300, 200], seed=3, U=(1.0, 3.0))]
+    plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction=interaction, dtype="c128",
+                    reals=reals, dt=0.05, order=8, tol=0.0, launch={"cols_per_lane": P_}, sites=[70, 75])
+    plan.propagate(30)
+    psi = plan.state_numpy()
+    off = plan.layout()
+    worst = 0.0
+    for k, (N, J, eps, U) in enumerate(reals):
+        H = oracle_H(N, 2, B.DISTINGUISHABLE, "open", interaction, J, eps, U)
+        ref, _, _ = P.evolve_taylor(H, B.product_state(N, [70, 75]), 0.05, 30, order=8)
+        worst = max(worst, float(np.max(np.abs(psi[off[k]:off[k + 1]] - ref))))
+    say(f"  max err vs oracle Taylor map {worst:.3e}")
+    assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("P_", [1, 2])
+def test_zero_onsite_energies_bitwise_c64(P_):
+    """complex64: the diagonal-free rows give the same bits as the full
+    stencil.  A batch with eps = 0 against the same batch with one on-site
+    energy of 1e-300, which makes the kernel keep the diagonal product on
+    every row but rounds to 0 in the FP32 tables."""
+    say(f"case: eps = 0 vs eps with a 1e-300 entry, c64 P={P_}")
+    base = [(N, J, np.zeros(N), U) for (N, J, _, U) in random_reals([150, 300, 64, 520], seed=4, U=(1.0, 3.0))]
+    tiny = [(N, J, np.where(np.arange(N) == N - 1, 1e-300, 0.0), U) for (N, J, _, U) in base]
+    out = []
+    for reals in (base, tiny):
+        plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite", dtype="c64",
+                        reals=reals, dt=0.05, tol=1e-7, launch={"cols_per_lane": P_}, sites=[30, 31])
+        plan.propagate(25)
+        out.append(plan.state_numpy())
+    assert np.array_equal(out[0], out[1])
+
+
 # ------------------------------------------------------------ launch shapes
 
 def test_graph_replays_match_eager_launches():
@@ -431,7 +474,8 @@ _SHAPE_REALS = None
 
 
 def _shape_state(launch):
-    reals = random_reals([100, 200, 37], seed=8)
+    # 520 sites: several bands at either width, the last one past the chain's end
+    reals = random_reals([100, 200, 37, 520], seed=8)
     plan = gpu_plan(m=2, statistics="distinguishable", boundary="open", interaction="onsite",
                     dtype="c64", reals=reals, dt=0.05, tol=1e-7, launch=launch, sites=[30, 31])
     plan.propagate(25)
@@ -447,8 +491,12 @@ def _shape_state(launch):
     {"cols_per_lane": 1, "band_align": 0},
     {"cols_per_lane": 2, "band_align": 64},
     {"cols_per_lane": 2, "persistent": 1, "band_align": 0},
+    {"cols_per_lane": 1, "band_mode": 1},
+    {"cols_per_lane": 2, "band_mode": 1},
+    {"cols_per_lane": 2, "persistent": 1, "waves_per_block": 1, "band_mode": 1},
 ], ids=["P2", "P1-wpb1", "P1-persistent", "P2-persistent-wpb1", "P1-persistent-cap8", "P1-unaligned",
-        "P2-align64", "P2-persistent-unaligned"])
+        "P2-align64", "P2-persistent-unaligned", "P1-window-aligned", "P2-window-aligned",
+        "P2-persistent-window-aligned"])
 def test_launch_shape_bitwise_identical(launch):
     """Bitwise identical whatever the block shape, launch form, band
     boundaries or columns per lane: the complex64 full-grid stencil is one
