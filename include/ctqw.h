@@ -473,16 +473,21 @@ ctqw_status ctqw_gradient(ctqw_plan* plan, int64_t n_steps, int64_t ckpt_every, 
 /* Autotuner.  Times `steps` propagation steps (after one warm-up step) for
  * every launch shape -- columns per lane {1, 2}, waves per block {1, 2, 4},
  * regular or persistent launch, for the persistent form a cap of
- * {auto, 8, 16} resident waves per CU, and all terms in one pass or passes
- * of K terms (one column per lane) -- that fits the bound workspace,
+ * {auto, 8, 16} resident waves per CU, all terms in one pass or passes of
+ * K terms (one column per lane), band alignment {128, 64, 0} bytes and
+ * band layout (output- or window-aligned); for three particles the terms
+ * per pass {3, 2, 1} and the x3 band alignment -- that fits the bound workspace,
  * keeps the fastest (average step-kernel time from HIP events) and applies
  * it with ctqw_set_launch (use_graph is left as set).  With a cache path
  * (or the CTQW_TUNE_CACHE environment variable when cache_path is NULL),
  * a stored result for the same device, library version and problem shape
  * (dtype, accumulation, m, statistics, boundary, lattice sizes, R, Taylor
  * orders) is applied without timing, and new results are appended (one
- * JSON object per line).  The state buffers are overwritten: tune before
- * ctqw_init_product_state / ctqw_set_state.  best / best_ms may be NULL.  */
+ * JSON object per line).  If the CTQW_TUNE_TRACE environment variable
+ * names a file, one line per candidate (its shape and time, or that it does
+ * not fit the bound workspace) is appended to it.  The state buffers are
+ * overwritten: tune before ctqw_init_product_state / ctqw_set_state.
+ * best / best_ms may be NULL.                                              */
 ctqw_status ctqw_autotune(ctqw_plan* plan, const char* cache_path, int32_t steps, ctqw_launch* best,
                           double* best_ms);
 

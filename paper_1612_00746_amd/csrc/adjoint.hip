@@ -74,6 +74,38 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRawBufferWord3 = 0x00020000;   // gfx9-family raw buffer, no format conversion
+constexpr uint32_t kPastEnd = 0x80000000u;    // an offset past every row: loads read 0, stores drop
+
+// One amplitude per lane through a buffer resource over a row.  Stores take
+// a zero scalar offset (a 16-byte store reads its data registers after it
+// issues; the compiler keeps the wait before the next write of them only
+// when the scalar offset is not a register).
+__device__ __forceinline__ float2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t off, float2*) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+    return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
+}
+__device__ __forceinline__ double2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t off, double2*) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
+}
+__device__ __forceinline__ void store_c(float re, float im, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    u32x2 v;
+    v.x = __float_as_uint(re);
+    v.y = __float_as_uint(im);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rs, (int)off, 0, 0);
+}
+__device__ __forceinline__ void store_c(double re, double im, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    u32x4 v;
+    v.x = (unsigned)__double2loint(re);
+    v.y = (unsigned)__double2hiint(re);
+    v.z = (unsigned)__double2loint(im);
+    v.w = (unsigned)__double2hiint(im);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, 0);
+}
+
 template <typename T, bool CONTRACT>
 __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) {
     using C = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
@@ -81,7 +113,13 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
     const int w = blockIdx.x;
     const RealDev rd = a.reals[r];
     const int N = rd.N, rows = rd.rows;
-    if (w * kSweepOut >= N) return;   // whole block, before the barrier
+    // Bands are laid from the chain's end: band w of nbr outputs columns
+    // [hi - 62, hi), hi = N - 62 (nbr - 1 - w), the first band the rest, so
+    // that the narrow band sits where the triangle's columns are shortest.
+    const int nbr = (N + kSweepOut - 1) / kSweepOut;
+    if (w >= nbr) return;   // whole block, before the barrier
+    const int hi_w = N - kSweepOut * (nbr - 1 - w);
+    const int lo_w = max(0, hi_w - kSweepOut);
     const int lane = threadIdx.x & 63;
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool periodic = (rd.flags & RF_PERIODIC) != 0;
@@ -93,11 +131,11 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
     const T Udt = static_cast<T>(rd.U * a.dt);
     const int want = (rd.flags & RF_NEAREST) ? 1 : 0;
 
-    // this lane's column: window [w * 62 - 1, w * 62 + 63), output [w * 62, w * 62 + 62)
-    const int c = w * kSweepOut - 1 + lane;
+    // this lane's column: window [lo_w - 1, lo_w + 63), output [lo_w, hi_w)
+    const int c = lo_w - 1 + lane;
     const bool inb = periodic || (c >= 0 && c < N);
     const int cw = periodic ? wrapi(c, N) : (inb ? c : 0);
-    const bool out = c >= w * kSweepOut && c < w * kSweepOut + kSweepOut && c < N && lane > 0 && lane < 63;
+    const bool out = c >= lo_w && c < hi_w && lane > 0 && lane < 63;
     const T jl = (inb && (periodic || c > 0)) ? Jc[periodic ? wrapi(cw - 1, N) : cw - 1] : T(0);
     const T jr = (inb && (periodic || c < N - 1)) ? Jc[cw] : T(0);
     const T ec = inb ? Ec[cw] : T(0);
@@ -110,18 +148,38 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
     const T xs = static_cast<T>(a.xs), cz = static_cast<T>(a.cz), sg = static_cast<T>(a.sign);
     // lanes whose amplitude (q, c) is stored
     auto stored = [&](int q) { return inb && (!tri || cw >= q); };
-    auto ld = [&](const C* base, int q) -> C {
-        C v;
-        v.x = T(0);
-        v.y = T(0);
-        if (!base) return v;
+    // Row q (wrapped on a ring) through a buffer resource over the row: its
+    // first stored amplitude is (q, q) in the triangle, (q, 0) on the full
+    // grid, and lane c reads column c; a lane without a stored amplitude,
+    // or a row off the grid (resource length 0), reads 0.  No branches.
+    const uint32_t row_bytes = (uint32_t)N * (uint32_t)sizeof(C);
+    const uint32_t col_off = (uint32_t)cw * (uint32_t)sizeof(C);
+    auto row_rsrc = [&](const C* base, int q, uint32_t& voff) {
+        bool live = true;
         if (periodic) q = wrapi(q, rows);
-        else if (q < 0 || q >= rows) return v;
-        if (!stored(q)) return v;
-        return base[rd.state_off + index_of(rd, q, cw)];
+        else {
+            live = q >= 0 && q < rows;
+            q = live ? q : 0;
+        }
+        // triangle row q holds columns q .. N - 1 from index q N - q (q + 1) / 2 + q
+        const int64_t rb = tri ? (int64_t)q * N - ((int64_t)q * (q + 1)) / 2 : (int64_t)q * N;
+        voff = stored(q) ? col_off : kPastEnd;
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<C*>(base) + rd.state_off + rb, 0,
+                                                 live ? (int)row_bytes : 0, kRawBufferWord3);
+    };
+    auto ld = [&](const C* base, int q) -> C {
+        if (!base) {
+            C v;
+            v.x = T(0);
+            v.y = T(0);
+            return v;
+        }
+        uint32_t voff;
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(base, q, voff);
+        return load_c(rs, voff, (C*)nullptr);
     };
     // rows holding a stored amplitude of this window, split into one segment per wave
-    const int q_end = tri ? min(rows, w * kSweepOut + 63) : rows;
+    const int q_end = tri ? min(rows, hi_w) : rows;
     const int q0 = (int)(((int64_t)q_end * seg) / kSweepSegs);
     const int q1 = (int)(((int64_t)q_end * (seg + 1)) / kSweepSegs);
 
@@ -176,25 +234,24 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
             hr = fma(jr, rr, hr);
             hi = fma(jr, ri, hi);
             const bool st = out && stored(q);
-            if (st) {
-                // s (-i)(hr + i hi) = s (hi - i hr)
-                C yv;
-                yv.x = fma(cz, zq.x, sg * hi);
-                yv.y = fma(cz, zq.y, -sg * hr);
-                Y[rd.state_off + index_of(rd, q, cw)] = yv;
+            {
+                // s (-i)(hr + i hi) = s (hi - i hr); lanes without an output drop the store
+                uint32_t voff;
+                const __amdgpu_buffer_rsrc_t rs = row_rsrc(Y, q, voff);
+                store_c(fma(cz, zq.x, sg * hi), fma(cz, zq.y, -sg * hr), rs, st ? voff : kPastEnd);
             }
             if constexpr (CONTRACT) {
                 const T vr = from_right(v0.x), vi = from_right(v0.y);
+                // every lane computes, lanes without an output add zeros
+                const double s0 = im_uv(mr, mi, v0.x, v0.y);
+                const double hb = im_uv(mr, mi, vr, vi) + im_uv(rr, ri, v0.x, v0.y);
+                site_col += st ? s0 : 0.0;
+                bond_col += (st && has_bond_c) ? hb : 0.0;
                 double vert = 0.0, rsite = 0.0;
-                if (st) {
-                    const double s0 = im_uv(mr, mi, v0.x, v0.y);
-                    site_col += s0;
-                    if (has_bond_c) bond_col += im_uv(mr, mi, vr, vi) + im_uv(rr, ri, v0.x, v0.y);
-                    if (rows > 1) {
-                        rsite = diag ? 0.0 : s0;
-                        if (dn && (!tri || cw >= q + 1))
-                            vert = im_uv(mr, mi, vp.x, vp.y) + im_uv(dr_, di_, v0.x, v0.y);
-                    }
+                if (rows > 1) {
+                    const double vb = im_uv(mr, mi, vp.x, vp.y) + im_uv(dr_, di_, v0.x, v0.y);
+                    rsite = (st && !diag) ? s0 : 0.0;
+                    vert = (st && dn && (!tri || cw >= q + 1)) ? vb : 0.0;
                 }
                 if (rows > 1) {
                     vert = wave_sum(vert);

@@ -2004,6 +2004,9 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
     const char* path = cache_path ? cache_path : getenv("CTQW_TUNE_CACHE");
+    // CTQW_TUNE_TRACE: a file that receives one line per timed candidate
+    const char* trace_env = getenv("CTQW_TUNE_TRACE");
+    const char* trace = (trace_env && *trace_env) ? trace_env : nullptr;
     const std::string key = tune_key(p);
     const ctqw_launch orig = p->launch;
     ctqw_launch best = orig;
@@ -2065,12 +2068,16 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
                         c.band_align = align;
                         c.band_mode = mode;
                         p->launch = c;
-                        if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
+                        if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) {
+                            if (trace) cache_append(trace, key + " (does not fit the bound workspace)", c, -1.0);
+                            continue;
+                        }
                         if ((st = upload_tables(p)) != CTQW_OK) return st;
                         double ms = INFINITY;
                         st = time_steps(p, steps, &ms);
                         if (st == CTQW_ERR_UNSUPPORTED) continue;   // block larger than the kernel's bound
                         if (st != CTQW_OK) return st;
+                        if (trace) cache_append(trace, key, c, ms);
                         if (ms < best_ms) {
                             best_ms = ms;
                             best = c;

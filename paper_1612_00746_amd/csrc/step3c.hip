@@ -515,21 +515,21 @@ struct Step3cShape {
 };
 Step3cShape select3c(int dtype, int K, bool first, bool last) {
     using namespace step3c_detail;
-#define CTQW_3C(T, KT, S)                                                               \
-    {first ? (last ? &step3c_kernel<T, KT, S, 8, true, true> : &step3c_kernel<T, KT, S, 8, true, false>) \
-           : (last ? &step3c_kernel<T, KT, S, 8, false, true> : &step3c_kernel<T, KT, S, 8, false, false>), S, 8}
+#define CTQW_3C(T, KT, S, W)                                                            \
+    {first ? (last ? &step3c_kernel<T, KT, S, W, true, true> : &step3c_kernel<T, KT, S, W, true, false>) \
+           : (last ? &step3c_kernel<T, KT, S, W, false, true> : &step3c_kernel<T, KT, S, W, false, false>), S, W}
     if (dtype == 1) {
         switch (K) {
-            case 1: return CTQW_3C(double, 1, 4);
-            case 2: return CTQW_3C(double, 2, 3);
-            case 3: return CTQW_3C(double, 3, 2);
+            case 1: return CTQW_3C(double, 1, 4, 8);
+            case 2: return CTQW_3C(double, 2, 3, 8);
+            case 3: return CTQW_3C(double, 3, 2, 8);
             default: return {nullptr, 0, 0};
         }
     }
     switch (K) {
-        case 1: return CTQW_3C(float, 1, 8);
-        case 2: return CTQW_3C(float, 2, 5);
-        case 3: return CTQW_3C(float, 3, 4);
+        case 1: return CTQW_3C(float, 1, 8, 8);
+        case 2: return CTQW_3C(float, 2, 5, 8);
+        case 3: return CTQW_3C(float, 3, 4, 8);
         default: return {nullptr, 0, 0};
     }
 #undef CTQW_3C
