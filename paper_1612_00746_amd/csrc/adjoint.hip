@@ -74,6 +74,39 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Im(conj(u) v) in the state's precision.
+template <typename T>
+__device__ __forceinline__ T im_t(T ur, T ui, T vr, T vi) {
+    return fma(ur, vi, -(ui * vr));
+}
+
+// Eight values summed over the wave at once: each exchange step hands the
+// partner the half of the values this lane does not keep (xor 32: four,
+// xor 16: two, xor 8: one), then three steps sum the one value left.  Lane
+// l ends with the total of value (l >> 3) (bits 5, 4, 3 of l pick it), in
+// a fixed order of additions.  Ten shuffles instead of 48.
+__device__ __forceinline__ double reduce8(const double (&v)[8], int lane) {
+    const bool b5 = (lane & 32) != 0, b4 = (lane & 16) != 0, b3 = (lane & 8) != 0;
+    double w[4], x[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double send = b5 ? v[k] : v[k + 4];
+        const double keep = b5 ? v[k + 4] : v[k];
+        w[k] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double send = b4 ? w[k] : w[k + 2];
+        const double keep = b4 ? w[k + 2] : w[k];
+        x[k] = keep + __shfl_xor(send, 16, 64);
+    }
+    double y = (b3 ? x[1] : x[0]) + __shfl_xor(b3 ? x[0] : x[1], 8, 64);
+    y += __shfl_xor(y, 4, 64);
+    y += __shfl_xor(y, 2, 64);
+    y += __shfl_xor(y, 1, 64);
+    return y;
+}
+
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRawBufferWord3 = 0x00020000;   // gfx9-family raw buffer, no format conversion
@@ -106,13 +139,14 @@ __device__ __forceinline__ void store_c(double re, double im, __amdgpu_buffer_rs
     __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)off, 0, 0);
 }
 
-template <typename T, bool CONTRACT>
+// PER: ring; LAY: 0 one row (one particle), 1 full grid, 2 triangle (bosons).
+template <typename T, bool CONTRACT, bool PER, int LAY>
 __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) {
     using C = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
     const int r = blockIdx.y;
     const int w = blockIdx.x;
     const RealDev rd = a.reals[r];
-    const int N = rd.N, rows = rd.rows;
+    const int N = rd.N, rows = LAY == 0 ? 1 : rd.rows;
     // Bands are laid from the chain's end: band w of nbr outputs columns
     // [hi - 62, hi), hi = N - 62 (nbr - 1 - w), the first band the rest, so
     // that the narrow band sits where the triangle's columns are shortest.
@@ -122,8 +156,8 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
     const int lo_w = max(0, hi_w - kSweepOut);
     const int lane = threadIdx.x & 63;
     const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const bool periodic = (rd.flags & RF_PERIODIC) != 0;
-    const bool tri = (rd.flags & RF_TRIANGLE) != 0;
+    constexpr bool periodic = PER;
+    constexpr bool tri = LAY == 2;
     const T* Jc = reinterpret_cast<const T*>(a.Jt) + rd.param_off;
     const T* Ec = reinterpret_cast<const T*>(a.Et) + rd.param_off;
     const T* Jr = reinterpret_cast<const T*>(a.Jt) + rd.row_param_off;
@@ -200,10 +234,15 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
     double* gV = a.gV + ((int64_t)r * a.nb + w) * a.row_stride;
     double* gR = a.gR + ((int64_t)r * a.nb + w) * a.row_stride;
     for (int qb = q0; qb < q1; qb += kSweepAhead) {
+        // row parts of the block's rows (bond q, site q per row), summed
+        // over the lanes together after the block
+        static_assert(2 * kSweepAhead == 8, "one reduce8 per block of rows");
+        double rowpart[2 * kSweepAhead];
 #pragma unroll
         for (int k = 0; k < kSweepAhead; ++k) {
+            // rows past the segment run with every output off (no stores, no sums)
             const int q = qb + k;
-            if (q >= q1) break;
+            const bool live = q < q1;
             const T mr = xs * x0.x, mi = xs * x0.y;
             const T ur_ = xs * xm.x, ui_ = xs * xm.y;      // row q - 1
             const T dr_ = xs * xp.x, di_ = xs * xp.y;      // row q + 1
@@ -213,12 +252,13 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
             // neighbours below and to the left; mirrored on the stored diagonal
             const T br = diag ? rr : dr_, bi = diag ? ri : di_;
             const T ar = diag ? ur_ : lr, ai = diag ? ui_ : li;
-            const bool up = rows > 1 && (periodic || q > 0);
-            const bool dn = rows > 1 && (periodic || q < rows - 1);
-            const T Jup = up ? Jr[periodic ? wrapi(q - 1, rows) : q - 1] : T(0);
-            const T Jdn = dn ? Jr[q] : T(0);
-            T d = Er[q] + ec;
-            if (rows > 1) {
+            const int qr = periodic ? wrapi(q, rows) : min(q, rows - 1);   // in range either way
+            const bool up = LAY != 0 && (periodic || q > 0);
+            const bool dn = LAY != 0 && (periodic || q < rows - 1);
+            const T Jup = up ? Jr[periodic ? wrapi(q - 1, rows) : min(max(q - 1, 0), rows - 1)] : T(0);
+            const T Jdn = dn ? Jr[qr] : T(0);
+            T d = Er[qr] + ec;
+            if (LAY != 0) {
                 int dd = q - cw;
                 dd = dd < 0 ? -dd : dd;
                 if (periodic && N - dd < dd) dd = N - dd;
@@ -233,7 +273,7 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
             hi = fma(jl, ai, hi);
             hr = fma(jr, rr, hr);
             hi = fma(jr, ri, hi);
-            const bool st = out && stored(q);
+            const bool st = live && out && stored(q);
             {
                 // s (-i)(hr + i hi) = s (hi - i hr); lanes without an output drop the store
                 uint32_t voff;
@@ -241,26 +281,16 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
                 store_c(fma(cz, zq.x, sg * hi), fma(cz, zq.y, -sg * hr), rs, st ? voff : kPastEnd);
             }
             if constexpr (CONTRACT) {
-                const T vr = from_right(v0.x), vi = from_right(v0.y);
+                // Im conj(u) v in the state's precision per pair, summed in FP64;
                 // every lane computes, lanes without an output add zeros
-                const double s0 = im_uv(mr, mi, v0.x, v0.y);
-                const double hb = im_uv(mr, mi, vr, vi) + im_uv(rr, ri, v0.x, v0.y);
-                site_col += st ? s0 : 0.0;
-                bond_col += (st && has_bond_c) ? hb : 0.0;
-                double vert = 0.0, rsite = 0.0;
-                if (rows > 1) {
-                    const double vb = im_uv(mr, mi, vp.x, vp.y) + im_uv(dr_, di_, v0.x, v0.y);
-                    rsite = (st && !diag) ? s0 : 0.0;
-                    vert = (st && dn && (!tri || cw >= q + 1)) ? vb : 0.0;
-                }
-                if (rows > 1) {
-                    vert = wave_sum(vert);
-                    rsite = wave_sum(rsite);
-                    if (lane == 0) {
-                        gV[q] += f * vert;
-                        gR[q] += f * rsite;
-                    }
-                }
+                const T vr = from_right(v0.x), vi = from_right(v0.y);
+                const T s0 = im_t(mr, mi, v0.x, v0.y);
+                const T hb = im_t(mr, mi, vr, vi) + im_t(rr, ri, v0.x, v0.y);
+                site_col += st ? (double)s0 : 0.0;
+                bond_col += (st && has_bond_c) ? (double)hb : 0.0;
+                const T vb = im_t(mr, mi, vp.x, vp.y) + im_t(dr_, di_, v0.x, v0.y);
+                rowpart[2 * k] = (st && dn && (!tri || cw >= q + 1)) ? (double)vb : 0.0;
+                rowpart[2 * k + 1] = (st && !diag) ? (double)s0 : 0.0;
                 v0 = vp;
                 vp = vr_[k];
                 vr_[k] = ld(V, q + 2 + kSweepAhead);
@@ -271,6 +301,18 @@ __global__ void __launch_bounds__(64 * kSweepSegs) sweep_kernel(AdjSweepArgs a) 
             xr[k] = ld(X, q + 2 + kSweepAhead);
             zq = zr[k];
             zr[k] = ld(Z, q + 1 + kSweepAhead);
+        }
+        if constexpr (CONTRACT) {
+            if (LAY != 0) {
+                // lane 8 j ends with the wave's sum of rowpart[j]
+                const double t = reduce8(rowpart, lane);
+                const int j = lane >> 3;
+                const int q = qb + (j >> 1);
+                if ((lane & 7) == 0 && q < q1) {
+                    if (j & 1) gR[q] += f * t;
+                    else gV[q] += f * t;
+                }
+            }
         }
     }
     if constexpr (CONTRACT) {
@@ -386,13 +428,21 @@ hipError_t launch_adj_sweep(const AdjSweepArgs& a, hipStream_t s) {
     if (a.R > 65535 || a.nb < 1 || a.nb > 65535) return hipErrorInvalidValue;
     const dim3 g((unsigned)a.nb, (unsigned)a.R);
     const bool con = a.v != nullptr;
+    if (a.layout < 0 || a.layout > 2) return hipErrorInvalidValue;
+    using Fn = void (*)(AdjSweepArgs);
+#define CTQW_SWEEP(T, C, PER)                                                                     \
+    (a.layout == 0 ? (Fn)&sweep_kernel<T, C, PER, 0>                                              \
+                   : (a.layout == 1 ? (Fn)&sweep_kernel<T, C, PER, 1> : (Fn)&sweep_kernel<T, C, PER, 2>))
+    Fn fn;
     if (a.dtype == 1) {
-        if (con) hipLaunchKernelGGL((sweep_kernel<double, true>), g, dim3(64 * kSweepSegs), 0, s, a);
-        else hipLaunchKernelGGL((sweep_kernel<double, false>), g, dim3(64 * kSweepSegs), 0, s, a);
+        fn = con ? (a.periodic ? CTQW_SWEEP(double, true, true) : CTQW_SWEEP(double, true, false))
+                 : (a.periodic ? CTQW_SWEEP(double, false, true) : CTQW_SWEEP(double, false, false));
     } else {
-        if (con) hipLaunchKernelGGL((sweep_kernel<float, true>), g, dim3(64 * kSweepSegs), 0, s, a);
-        else hipLaunchKernelGGL((sweep_kernel<float, false>), g, dim3(64 * kSweepSegs), 0, s, a);
+        fn = con ? (a.periodic ? CTQW_SWEEP(float, true, true) : CTQW_SWEEP(float, true, false))
+                 : (a.periodic ? CTQW_SWEEP(float, false, true) : CTQW_SWEEP(float, false, false));
     }
+#undef CTQW_SWEEP
+    hipLaunchKernelGGL(fn, g, dim3(64 * kSweepSegs), 0, s, a);
     return hipGetLastError();
 }
 

@@ -257,6 +257,8 @@ struct AdjSweepArgs {
     int nb;              // bands per realisation (ceil(max N / kSweepOut))
     int row_stride;
     int dtype;
+    int periodic;        // the batch's boundary (1: ring)
+    int layout;          // 0: one row (one particle), 1: full grid, 2: triangle (bosons)
 };
 hipError_t launch_adj_sweep(const AdjSweepArgs& a, hipStream_t stream);
 

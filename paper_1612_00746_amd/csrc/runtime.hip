@@ -2262,6 +2262,8 @@ ctqw_status ctqw_backward(ctqw_plan* p, int32_t kind, const double* site_w, void
     sa.nb = g.nb;
     sa.row_stride = p->max_N;
     sa.dtype = dtype;
+    sa.periodic = pr.boundary == CTQW_PERIODIC ? 1 : 0;
+    sa.layout = pr.m == 1 ? 0 : (pr.statistics == CTQW_DISTINGUISHABLE ? 1 : 2);
     // one sweep: y = cz z + s (-i)(dt H)(xs x), contracting xs x with v if given
     auto sweep = [&](const void* x, double xs, const void* z, double cz, int sign, void* y,
                      const void* v) -> ctqw_status {
