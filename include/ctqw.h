@@ -332,6 +332,41 @@ ctqw_status ctqw_graph_evolve(int32_t n_nodes, int32_t width, const int32_t* nbr
                               int64_t n_steps, void* psi, void* workspace, int64_t workspace_bytes,
                               double* norms, void* hip_stream);
 
+/* One particle on a two-dimensional lattice (q = 2, Sec. 2; the capacity
+ * example of Sec. 3) with every bond and node of every realisation carrying
+ * its own coupling and on-site energy (Eq. 1 with the noise drawn per bond
+ * and per node), advanced by the truncated Taylor series of exp(-i H dt)
+ * (Eqs. 5-7, Alg. 3): all `order` terms of a step are chained in one pass
+ * over the state (a register pipeline down the rows, 64-column bands with
+ * a halo of `order` columns), where ctqw_graph_evolve runs one pass per
+ * term.  The node (x, y) of realisation r is element r * Lx * Ly + y * Lx
+ * + x of every array (the node numbering of a row-major lattice).
+ *   Lx, Ly       lattice size (>= 1); periodic_x / periodic_y: 1 closes the
+ *                axis into a ring (of at least 3 nodes), 0 leaves it open
+ *   Jx, Jy, eps  device arrays [R][Ly][Lx] of the state's real type
+ *                (float for CTQW_C64, double for CTQW_C128): the coupling
+ *                between (x, y) and (x + 1, y), between (x, y) and
+ *                (x, y + 1) (ignored at an open axis's last column / row),
+ *                and the on-site energy; read only
+ *   psi          device state [R][Ly][Lx], complex, updated in place
+ *   workspace    ctqw_lattice_workspace bytes of device memory, 256-byte
+ *                aligned (a second state buffer, the dt-scaled tables and
+ *                the norm partials)
+ *   norms        device double [n_steps][R] or NULL: the squared FP64
+ *                2-norm of each realisation after each step (per band in a
+ *                fixed order, then over the bands in band order)
+ * order: 1..12 (complex64) or 1..10 (complex128); a larger order is
+ * UNSUPPORTED here (ctqw_graph_evolve takes up to 64).  Enqueued on
+ * hip_stream (NULL = default); the call does not synchronise.  Errors:
+ * INVALID_ARG (sizes, NULL, non-finite dt, workspace too small or
+ * misaligned), UNSUPPORTED (order, tables beyond 2^31 entries), DEVICE. */
+ctqw_status ctqw_lattice_workspace(int32_t Lx, int32_t Ly, int32_t R, int32_t dtype, int32_t order,
+                                   int32_t periodic_x, int64_t* bytes);
+ctqw_status ctqw_lattice_evolve(int32_t Lx, int32_t Ly, int32_t periodic_x, int32_t periodic_y, int32_t R,
+                                const void* Jx, const void* Jy, const void* eps, int32_t dtype, double dt,
+                                int32_t order, int64_t n_steps, void* psi, void* workspace,
+                                int64_t workspace_bytes, double* norms, void* hip_stream);
+
 /* ctqw_graph_evolve for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same arguments and kernels without the workspace, whose

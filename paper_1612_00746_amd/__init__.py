@@ -478,6 +478,45 @@ def graph_evolve_static(nbr, hop, onsite, psi, dt: float, order: int, n_steps: i
                                          C.c_void_p(stream)))
 
 
+def lattice_evolve(Jx, Jy, eps, psi, dt: float, order: int, n_steps: int, periodic=(False, False),
+                   workspace=None, norms=None) -> None:
+    """ctqw_lattice_evolve on device tensors: one particle on an Lx x Ly
+    lattice, R realisations advanced in place with all `order` terms of a
+    step in one pass.  psi complex64 [R, Ly, Lx] with Jx, Jy, eps float32
+    [R, Ly, Lx] (or complex128 with float64 tables); Jx[r, y, x] couples
+    (x, y) to (x + 1, y), Jy[r, y, x] couples (x, y) to (x, y + 1).
+    periodic = (x ring, y ring).  norms (optional) float64 [n_steps, R].
+    Enqueued on the device's current stream."""
+    import torch
+    lib = L.load()
+    if psi.dtype not in (torch.complex64, torch.complex128) or psi.dim() != 3:
+        raise ValueError("psi must be a complex64 or complex128 tensor of shape (R, Ly, Lx)")
+    R, Ly, Lx = psi.shape
+    c128 = psi.dtype == torch.complex128
+    real = torch.float64 if c128 else torch.float32
+    for t in (Jx, Jy, eps, psi):
+        if t.dtype not in (real, psi.dtype) or tuple(t.shape) != (R, Ly, Lx) or not t.is_contiguous() \
+                or t.device != psi.device:
+            raise ValueError(f"expected contiguous tensors of shape {(R, Ly, Lx)} on {psi.device}")
+    for t in (Jx, Jy, eps):
+        if t.dtype != real:
+            raise ValueError(f"tables must be {real}")
+    if norms is not None and (norms.dtype != torch.float64 or tuple(norms.shape) != (int(n_steps), R)
+                              or not norms.is_contiguous() or norms.device != psi.device):
+        raise ValueError(f"norms must be a contiguous float64 tensor of shape ({n_steps}, {R}) on {psi.device}")
+    dtype = C128 if c128 else C64
+    px, py = int(bool(periodic[0])), int(bool(periodic[1]))
+    b = C.c_int64()
+    L.check(lib.ctqw_lattice_workspace(Lx, Ly, R, dtype, int(order), px, C.byref(b)))
+    if workspace is None:
+        workspace = torch.empty(b.value, dtype=torch.uint8, device=psi.device)
+    stream = torch.cuda.current_stream(psi.device).cuda_stream
+    p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+    L.check(lib.ctqw_lattice_evolve(Lx, Ly, px, py, R, p(Jx), p(Jy), p(eps), dtype, float(dt), int(order),
+                                    int(n_steps), p(psi), p(workspace), workspace.numel() * workspace.element_size(),
+                                    p(norms) if norms is not None else None, C.c_void_p(stream)))
+
+
 def graph_orders(nbr: np.ndarray, hop: np.ndarray, onsite: np.ndarray, dt: float, tol: float,
                  max_order: int = 64) -> np.ndarray:
     """ctqw_graph_orders on host tables (the layouts of graph_evolve, FP64):

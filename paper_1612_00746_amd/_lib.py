@@ -118,6 +118,10 @@ SIGNATURES = {
     "ctqw_graph_evolve_static": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                            C.c_int32, C.c_double, C.c_int32, C.c_int64, C.c_void_p, C.c_void_p,
                                            C.c_void_p]),
+    "ctqw_lattice_workspace": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, i64p]),
+    "ctqw_lattice_evolve": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_int32, C.c_double, C.c_int32, C.c_int64, C.c_void_p,
+                                      C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ctqw_stats": (C.c_int, [PlanP, C.POINTER(StepStats)]),
     "ctqw_realization_norms": (C.c_int, [PlanP, dp, dp]),
     "ctqw_get_launch": (C.c_int, [PlanP, C.POINTER(Launch)]),

@@ -297,6 +297,27 @@ hipError_t launch_adj_reduce(const AdjReduceArgs& a, hipStream_t stream);
 }  // namespace ctqw
 
 namespace ctqw {
+// One particle on a two-dimensional lattice (lattice.hip).
+constexpr int kLatticeMaxOrderC64 = 12;
+constexpr int kLatticeMaxOrderC128 = 10;
+struct LatticeArgs {
+    const void* Jx;          // [R][Ly][Lx] bond to (x + 1, y), the state's real type
+    const void* Jy;          // [R][Ly][Lx] bond to (x, y + 1)
+    const void* eps;         // [R][Ly][Lx] on-site energies
+    void* tab;               // dt-scaled tables: right bonds, bonds below, energies ([3][R][Ly][Lx])
+    const void* psi_in;      // [R][Ly][Lx]
+    void* psi_out;
+    double* norm_part;       // [R][nb] squared FP64 norm of each item's output
+    int32_t Lx, Ly, R, px, py, nb, n_items;
+    double dt;
+};
+int lattice_max_order(int dtype);
+hipError_t launch_lattice_scale(const LatticeArgs& a, int dtype, hipStream_t stream);
+hipError_t launch_lattice_step(const LatticeArgs& a, int dtype, int order, hipStream_t stream);
+hipError_t launch_lattice_norms(const double* part, int32_t nb, int32_t R, double* out, hipStream_t stream);
+}  // namespace ctqw
+
+namespace ctqw {
 // Record the message returned by ctqw_last_error(NULL) and return status.
 int report_error(int status, const char* message);
 }  // namespace ctqw

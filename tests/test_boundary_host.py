@@ -477,6 +477,42 @@ def test_graph_evolve_validation(kw, status):
     assert lib.ctqw_graph_workspace(8, 2, 0, C.byref(b)) == 0 and b.value == 3 * 8 * 2 * 8
 
 
+@pytest.mark.parametrize("kw,status", [
+    (dict(Lx=0), 1), (dict(Ly=0), 1), (dict(R=0), 1), (dict(order=0), 1), (dict(order=13), 2),
+    (dict(order=11, dtype=1), 2), (dict(px=1, Lx=2), 1), (dict(py=1, Ly=2), 1), (dict(n_steps=-1), 1),
+    (dict(dt=float("inf")), 1), (dict(ws=64), 1), (dict(psi=None), 1), (dict(dtype=3), 1),
+])
+def test_lattice_evolve_validation(kw, status):
+    """Invalid requests to the two-dimensional lattice path are refused on
+    the host before any device work (1: INVALID_ARG, 2: UNSUPPORTED)."""
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    a = dict(Lx=70, Ly=9, px=0, py=0, R=2, tab=C.c_void_p(256), dtype=0, dt=0.05, order=10, n_steps=1,
+             psi=C.c_void_p(256), ws=None, ws_ptr=C.c_void_p(256))
+    a.update(kw)
+    b = C.c_int64()
+    ok = lib.ctqw_lattice_workspace(a["Lx"], a["Ly"], a["R"], a["dtype"], a["order"], a["px"], C.byref(b))
+    ws_bytes = a["ws"] if a["ws"] is not None else (b.value if ok == 0 else 1 << 20)
+    st = lib.ctqw_lattice_evolve(a["Lx"], a["Ly"], a["px"], a["py"], a["R"], a["tab"], a["tab"], a["tab"], a["dtype"],
+                                 a["dt"], a["order"], a["n_steps"], a["psi"], a["ws_ptr"], ws_bytes, None, None)
+    assert st == status
+
+
+def test_lattice_workspace_holds_a_state_the_tables_and_the_partials():
+    """Workspace of the lattice path: a second state buffer, three dt-scaled
+    tables and one FP64 norm partial per band and realisation, each region
+    256-byte aligned (70 columns at order 10: two bands of 64 lanes)."""
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    b = C.c_int64()
+    assert lib.ctqw_lattice_workspace(70, 9, 2, 0, 10, 0, C.byref(b)) == 0
+    n = 70 * 9 * 2
+    up = lambda x: (x + 255) // 256 * 256  # noqa: E731
+    assert b.value == up(up(up(n * 8) + 3 * n * 4) + 2 * 2 * 8)
+    assert lib.ctqw_lattice_workspace(70, 9, 2, 1, 8, 1, C.byref(b)) == 0
+    assert b.value == up(up(up(n * 16) + 3 * n * 8) + 2 * 2 * 8)
+
+
 @pytest.mark.parametrize("statistics", ["distinguishable", "boson", "fermion"])
 def test_pair_tables_rebuild_the_oracle_pair_hamiltonian(statistics):
     """Two particles on a 3 x 4 lattice with noise and U: the pair-graph
