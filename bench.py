@@ -127,11 +127,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def shape_tag(cols_per_lane, waves_per_block, grid_waves, band_align=128, band_mode=0) -> str:
+def shape_tag(cols_per_lane, waves_per_block, grid_waves, band_align=128, band_mode=0, row_segments=0) -> str:
     """Launch shape of the step kernel: columns per lane, waves per block,
-    the waves of the (persistent) grid and the column-band layout."""
+    the waves of the (persistent) grid and the band layout."""
     return (f"cols_per_lane={cols_per_lane} waves_per_block={waves_per_block} grid_waves={grid_waves} "
-            f"band_align={band_align} band_mode={band_mode}")
+            f"band_align={band_align} band_mode={band_mode} row_segments={row_segments}")
 
 
 def recorded_traffic(launch, grid_waves):
@@ -146,7 +146,7 @@ def recorded_traffic(launch, grid_waves):
     if fields.get("kernel-source-sha256", "").strip() != kernel_source_hash():
         return None
     tag = shape_tag(launch.get("cols_per_lane", 1), launch.get("waves_per_block", 4), grid_waves,
-                    launch.get("band_align", 128), launch.get("band_mode", 0))
+                    launch.get("band_align", 128), launch.get("band_mode", 0), launch.get("row_segments", 0))
     if fields.get("launch-shape", "").strip() != tag:
         return None
     try:
@@ -161,7 +161,7 @@ def _rows(path):
 
 
 def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols_per_lane=1, waves_per_block=4,
-                    waves_per_cu=0, band_align=128, band_mode=0):
+                    waves_per_cu=0, band_align=128, band_mode=0, row_segments=0):
     """Write the step kernels' rocprofv3 summary: duration statistics from
     the kernel trace, FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the
     same counters read for the 4 GiB device copy of the same run.  A step
@@ -236,7 +236,8 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         f"| HBM bytes written per step | {write_b / 1e9:.3f} GB |",
         "",
         f"kernel-source-sha256: {kernel_source_hash()}",
-        "launch-shape: " + shape_tag(cols_per_lane, waves_per_block, grid_waves, band_align, band_mode),
+        "launch-shape: " + shape_tag(cols_per_lane, waves_per_block, grid_waves, band_align, band_mode,
+                                     row_segments),
         f"traffic-bytes: {int(round(fetch_b + write_b))}",
         "",
     ]
@@ -530,6 +531,19 @@ def density(a):
                       "trace": tr}))
 
 
+def autotune_launch(plan, a) -> dict:
+    """Unless --no-autotune: time the launch shapes of the plan's step on
+    its batch and keep the fastest (the state is overwritten: callers set
+    their start state afterwards).  Returns the launch in use."""
+    if not a.no_autotune:
+        import tempfile
+        with tempfile.TemporaryDirectory() as td:
+            plan.autotune(os.path.join(td, "tune.jsonl"), steps=3)
+    l = plan.get_launch()
+    return {k: int(getattr(l, k)) for k in ("cols_per_lane", "waves_per_block", "persistent", "waves_per_cu",
+                                            "chunked", "band_align", "band_mode", "row_segments", "use_graph")}
+
+
 def density_sweep(a):
     """The paper's post-processing-rate runs (Sec. 4: the ensemble density
     matrix formed once every 10, 25, 100, 250 or 1500 of 1500 steps, 1000
@@ -551,9 +565,10 @@ def density_sweep(a):
                             taylor_tol=w.tol, observables=1)
     plan = Plan(pr)
     plan._keep.append(keep)
-    plan.set_launch(use_graph=1)
+    plan.set_launch(use_graph=1, row_segments=a.row_segments)
     plan.set_params(J, eps, U)
     plan.bind()
+    tuned = autotune_launch(plan, a)
     total_steps = 1500
     rows = []
     plan.init_product_state(np.array(w.start_sites(w.N), dtype=np.int32))
@@ -586,6 +601,7 @@ def density_sweep(a):
         log(f"every {every}: run {run_ms:.1f} ms, rho {rho_ms:.1f} ms ({100 * rho_ms / run_ms:.1f} %)")
     print(json.dumps({"experiment": "post-processing rate (the rates of Sec. 4)",
                       "workload": "1000 x two bosons, N = 128, D = 8256, complex64, 1500 steps of dt = 0.05",
+                      "launch": tuned, "work_items": plan.work_items()[0],
                       "rates": rows,
                       "paper_context": "post-processing about 90 % of the run at frequent output, "
                                        "cublasCher > 99.3 % of that (K40, complex single)"}))
@@ -609,6 +625,7 @@ def graph(a):
     and the term out (e, not on the last term)."""
     import torch
     from paper_1612_00746_amd import ell_tables, graph_evolve, lattice_edges
+    probe = run_copy_probe(a.copy_probe_mib)
     side, R, order, dt = 128, 4096, 10, 0.05
     n = side * side
     g = np.random.default_rng(71)
@@ -693,7 +710,7 @@ def graph(a):
                                        "bytes_per_update_algorithmic": 2 * e,
                                        "bytes_per_update_with_tables": 2 * e + 3 * f,
                                        "frac_with_tables": round((2 * e + 3 * f) * R * n / (ms * 1e-3) / 8e12, 4)},
-                          "norm_r0": norm}), flush=True)
+                          "copy_probe": probe, "norm_r0": norm}), flush=True)
         del Jx_d, Jy_d, eps_d, psi
         torch.cuda.empty_cache()
 
@@ -775,8 +792,10 @@ def adjoint(a):
         pr, keep = make_problem(2, w.R, w.N, w.dt, statistics="boson", dtype=dtype, taylor_tol=w.tol)
         plan = Plan(pr)
         plan._keep.append(keep)
+        plan.set_launch(row_segments=a.row_segments)
         plan.set_params(J, eps, U)
         plan.bind()
+        tuned = autotune_launch(plan, a)
         sw = (np.arange(w.N) >= 192).astype(float)
         times = []
         for k in range(3):
@@ -795,7 +814,8 @@ def adjoint(a):
                           "higher_is_better": False, "dtype": dtype,
                           "config": {"workload": w.name, "realisations": w.R, "sites": w.N, "steps": w.n_steps,
                                      "checkpoint_every": 32, "taylor_order": int(plan.orders().max()),
-                                     "amplitudes": amps},
+                                     "amplitudes": amps, "launch": tuned,
+                                     "work_items": plan.work_items()[0]},
                           "loss": loss, "grad_norm": float(np.linalg.norm(np.concatenate([gJ, gE]))),
                           "forward_equivalent_steps_per_s": round(w.n_steps / sec, 1)}), flush=True)
         del plan
@@ -822,6 +842,8 @@ def main():
     ap.add_argument("--band-align", type=int, default=128, help="column-band alignment in bytes (with --no-autotune)")
     ap.add_argument("--band-mode", type=int, default=0,
                     help="0: band boundaries aligned; 1: band windows aligned (with --no-autotune)")
+    ap.add_argument("--row-segments", type=int, default=0,
+                    help="two particles: 0 splits few bands' rows, 1 never, k at most k segments (with --no-autotune)")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the step kernel's rocprofv3 summary under profiles/ and exit")
     ap.add_argument("--profile-command", action="append", default=[],
@@ -858,7 +880,7 @@ def main():
     if a.profile_summary:
         profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane,
                         waves_per_block=a.waves_per_block, waves_per_cu=a.waves_per_cu, band_align=a.band_align,
-                        band_mode=a.band_mode)
+                        band_mode=a.band_mode, row_segments=a.row_segments)
         return
     if a.kernel_summary:
         kernel_summary(a.kernel_summary, a.title or a.match, a.workload_line, a.profile_command, a.match,
@@ -905,7 +927,7 @@ def main():
     amps = int(np.sum(sizes.astype(np.int64) ** 2))
     launch = {"cols_per_lane": a.cols_per_lane, "persistent": 0 if a.regular else 1,
               "waves_per_block": a.waves_per_block, "waves_per_cu": a.waves_per_cu, "use_graph": 1,
-              "band_align": a.band_align, "band_mode": a.band_mode}
+              "band_align": a.band_align, "band_mode": a.band_mode, "row_segments": a.row_segments}
     log("building the complex64 plan ...")
     plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
     tuned = None
@@ -920,12 +942,12 @@ def main():
         tuned = {"cols_per_lane": best.cols_per_lane, "waves_per_block": best.waves_per_block,
                  "persistent": best.persistent, "waves_per_cu": best.waves_per_cu, "chunked": best.chunked,
                  "band_align": best.band_align, "band_mode": best.band_mode,
-                 "ms": round(best_ms, 4)}
+                 "row_segments": best.row_segments, "ms": round(best_ms, 4)}
         log(f"autotune: {tuned}")
         launch = {"cols_per_lane": best.cols_per_lane, "persistent": 0 if a.regular else 1,
                   "waves_per_block": best.waves_per_block, "waves_per_cu": best.waves_per_cu,
                   "chunked": best.chunked, "band_align": best.band_align, "band_mode": best.band_mode,
-                  "use_graph": 1}
+                  "row_segments": best.row_segments, "use_graph": 1}
         plan.set_launch(**launch)
         plan.bind()
         sizes0 = w.lattice_sizes()

@@ -153,6 +153,19 @@ typedef struct {
                                 output ends on a 32-byte boundary (two bands
                                 then store parts of one line).  Other
                                 layouts ignore it.                         */
+    int32_t row_segments;    /* two particles, all terms in one pass: a band's
+                                rows are swept in order by one wave, so a
+                                batch with few bands leaves most SIMDs
+                                idle.  0 (default): when the batch has
+                                fewer than 1024 bands, each band's output
+                                rows are split into up to 16 segments
+                                (each at least twice the halo long) to
+                                bring it to about 1024; 1: never split;
+                                2..16: split into up to that many.  A
+                                segment is swept from halo rows before its
+                                first output row to halo rows after its
+                                last (halo = Taylor terms), so the extra
+                                reads are 2 * halo rows per segment.       */
 } ctqw_launch;
 
 /* Create a plan from a problem statement.  Host only: validates the

@@ -44,13 +44,22 @@ struct ItemDev {
     int32_t out_lo, out_hi;  // output rows (absolute)
 };
 
+// Persistent step launches claim work from one list per XCD: the hardware
+// hands a grid's blocks to the eight XCDs of the device in turn (block b to
+// XCD b mod 8), and each XCD has its own L2, so the bands that share halo
+// columns are listed together on one XCD.  A block whose list is empty
+// takes work from the next lists.
+constexpr int kClaimLists = 8;
+
 struct StepArgs {
     const void* psi_in;
     void* psi_out;
     const RealDev* reals;
     const ItemDev* items;
     const int32_t* item_order;   // processing order (largest first)
-    int32_t* claim;              // persistent launch: claim counter, zero at launch
+    int32_t* claim;              // persistent launch: kClaimLists counters, zero at launch
+    const int32_t* list_off;     // persistent launch: kClaimLists + 1 offsets into
+                                 // item_order; list x = [list_off[x], list_off[x + 1])
     int32_t n_items;
     int32_t n_waves;             // persistent launch: waves in the grid
     const double* Jd;

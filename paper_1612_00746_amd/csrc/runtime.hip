@@ -37,6 +37,11 @@ using namespace ctqw;
 namespace {
 
 constexpr int kMaxSites = 32768;
+// Two-particle steps: batches of fewer bands than the device has SIMDs
+// (256 CUs x 4) have their bands' rows split into up to kMaxRowSegments
+// segments.
+constexpr int kSplitTarget = 1024;
+constexpr int kMaxRowSegments = 16;
 thread_local std::string g_last_error;
 
 struct Region {
@@ -45,7 +50,7 @@ struct Region {
 };
 
 struct Layout {
-    Region reals, items, order, item_first, claim, Jd, Ed, Jf, Ef, scale, norm_part,
+    Region reals, items, order, item_first, claim, lists, Jd, Ed, Jf, Ef, scale, norm_part,
         tail_part, norm2, tail2, status, colsum, rowsum, diag, site_off, gmembers, gfirst, gN, gout, obs, sites,
         s3, items3, M3, occ3, chunk, tbase, tsign, tstep;
     int64_t total = 0;
@@ -80,6 +85,10 @@ struct ctqw_plan {
     // fused steps: runs of item_order with one Taylor order each, largest
     // order first: {order, first, end}
     std::vector<std::array<int32_t, 5>> order_runs;   // {order, first, end, paired access, two orders}
+    // persistent launches: per run of order_runs, then for the whole order,
+    // kClaimLists + 1 offsets of the per-XCD claim lists (relative to the
+    // launch's first item)
+    std::vector<int32_t> list_off;
     bool all_vec = false;            // every item takes the paired-access kernel
     bool one_depth = false;          // set while a gradient run needs one polynomial for all
     int64_t n_parts = 0;             // per-step FP64 norm partials
@@ -395,6 +404,47 @@ ctqw_status build_tables(ctqw_plan* p) {
             }
             items.insert(items.end(), use->begin(), use->end());
         }
+        // Few bands: a band's rows are swept in order by one wave, so the
+        // step lasts as long as the longest sweep.  Split each band's output
+        // rows into segments, each swept from `halo` rows before its first
+        // output row to `halo` rows after its last (the rows the pipeline
+        // needs to bring its deepest term up to date).
+        const int seg_cap = p->launch.row_segments == 0
+                                ? ((int64_t)items.size() < kSplitTarget ? kMaxRowSegments : 1)
+                                : p->launch.row_segments;
+        if (!chunk && pr.m == 2 && seg_cap > 1) {
+            const bool periodic = pr.boundary == CTQW_PERIODIC;
+            const int64_t want = p->launch.row_segments == 0
+                                     ? (kSplitTarget + (int64_t)items.size() - 1) / (int64_t)items.size()
+                                     : seg_cap;
+            const int S = (int)std::min<int64_t>(seg_cap, want);
+            std::vector<ItemDev> split;
+            split.reserve(items.size() * S);
+            size_t k = 0;
+            for (int64_t r = 0; r < pr.R; ++r) {
+                first[r] = (int32_t)split.size();
+                for (; k < items.size() && items[k].real == r; ++k) {
+                    const ItemDev& it = items[k];
+                    const int e_lo = std::max(it.out_lo, it.row0);
+                    const int e_hi = std::min(it.out_hi, it.row0 + it.nrows);
+                    const int s = std::min(S, (e_hi - e_lo) / std::max(8, 2 * halo));
+                    if (s <= 1) {
+                        split.push_back(it);
+                        continue;
+                    }
+                    for (int q = 0; q < s; ++q) {
+                        ItemDev t = it;
+                        t.out_lo = e_lo + (int)((int64_t)(e_hi - e_lo) * q / s);
+                        t.out_hi = e_lo + (int)((int64_t)(e_hi - e_lo) * (q + 1) / s);
+                        t.row0 = periodic ? t.out_lo - halo : std::max(it.row0, t.out_lo - halo);
+                        const int stop = periodic ? t.out_hi + halo : std::min(it.row0 + it.nrows, t.out_hi + halo);
+                        t.nrows = stop - t.row0;
+                        split.push_back(t);
+                    }
+                }
+            }
+            items.swap(split);
+        }
         first[pr.R] = (int32_t)items.size();
         n_parts = (int64_t)items.size();
     }
@@ -453,6 +503,53 @@ ctqw_status build_tables(ctqw_plan* p) {
         p->order_runs.back()[2] = (int32_t)k + 1;
         if (two) p->order_runs.back()[4] = 1;
     }
+    // Persistent launches: split each run into one claim list per XCD.
+    // Consecutive items of one realisation (its adjacent bands, which share
+    // halo columns) go to one list as a cluster; clusters are dealt out in
+    // the processing order (largest first) to the list with the least work
+    // so far, and each list keeps that order.
+    {
+        const int XL = kClaimLists;
+        p->list_off.assign((p->order_runs.size() + 1) * (XL + 1), 0);
+        auto split_range = [&](int32_t k0, int32_t k1, int32_t* off) {
+            const int32_t n = k1 - k0;
+            if (!p->launch.persistent || n <= 0) {
+                off[0] = 0;
+                for (int x = 1; x <= XL; ++x) off[x] = n;
+                return;
+            }
+            std::vector<std::vector<int32_t>> lists(XL);
+            std::vector<int64_t> load(XL, 0);
+            for (int32_t k = k0; k < k1;) {
+                const int32_t real = items[ord[k]].real;
+                int32_t e = k;
+                int64_t c = 0;
+                while (e < k1 && items[ord[e]].real == real) c += cost[ord[e++]];
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (int32_t q = k; q < e; ++q) lists[x].push_back(ord[q]);
+                load[x] += c;
+                k = e;
+            }
+            int32_t at_ = 0;
+            off[0] = 0;
+            for (int x = 0; x < XL; ++x) {
+                std::copy(lists[x].begin(), lists[x].end(), ord.begin() + k0 + at_);
+                at_ += (int32_t)lists[x].size();
+                off[x + 1] = at_;
+            }
+        };
+        for (size_t q = 0; q < p->order_runs.size(); ++q)
+            split_range(p->order_runs[q][1], p->order_runs[q][2], &p->list_off[q * (XL + 1)]);
+        // whole order (launches at one depth): the runs' lists when there is
+        // one run, else one list
+        int32_t* whole = &p->list_off[p->order_runs.size() * (XL + 1)];
+        if (p->order_runs.size() == 1) {
+            std::copy(p->list_off.begin(), p->list_off.begin() + (XL + 1), whole);
+        } else {
+            whole[0] = 0;
+            for (int x = 1; x <= XL; ++x) whole[x] = (int32_t)ord.size();
+        }
+    }
     p->all_vec = all_vec;
     p->items3.swap(items3);
     p->k3 = k3;
@@ -471,7 +568,8 @@ ctqw_status build_tables(ctqw_plan* p) {
     align_region(L, L.items, nit * (int64_t)sizeof(ItemDev));
     align_region(L, L.order, nit * 4);
     align_region(L, L.item_first, (R + 1) * 4);
-    align_region(L, L.claim, 4);   // persistent launch: item claim counter
+    align_region(L, L.claim, 4 * kClaimLists);   // persistent launch: claim counters
+    align_region(L, L.lists, (int64_t)p->list_off.size() * 4);
     align_region(L, L.Jd, p->param_total * 8);
     align_region(L, L.Ed, p->param_total * 8);
     align_region(L, L.Jf, p->param_total * 4);
@@ -590,6 +688,8 @@ ctqw_status upload_tables(ctqw_plan* p) {
     if (L.items3.bytes > 0)
         HIP_TRY(p, hipMemcpyAsync(p->ws + L.items3.off, p->items3.data(), L.items3.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.order.off, p->item_order.data(), L.order.bytes, h2d, s));
+    if (L.lists.bytes > 0)
+        HIP_TRY(p, hipMemcpyAsync(p->ws + L.lists.off, p->list_off.data(), L.lists.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.item_first.off, p->item_first.data(), L.item_first.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.Jd.off, Jd.data(), L.Jd.bytes, h2d, s));
     HIP_TRY(p, hipMemcpyAsync(p->ws + L.Ed.off, Ed.data(), L.Ed.bytes, h2d, s));
@@ -786,6 +886,7 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
     a.items = at<ItemDev>(p, L.items);
     a.item_order = at<int32_t>(p, L.order);
     a.claim = at<int32_t>(p, L.claim);
+    a.list_off = at<int32_t>(p, L.lists) + p->order_runs.size() * (kClaimLists + 1);   // whole order
     a.n_items = (int32_t)p->items.size();
     a.n_waves = n_waves;
     a.Jd = at<double>(p, L.Jd);
@@ -801,14 +902,16 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
         if (p->one_depth || p->order_runs.empty()) {
             // one launch at the batch's largest order for every item
             // (paired access only when every item allows it)
-            if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
+            if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4 * kClaimLists, p->stream));
             HIP_TRY(p, launch_step(c, a, p->stream));
             return CTQW_OK;
         }
         // one launch per run of items (one order, or two adjacent orders),
         // each item at its own depth
         const int32_t* order_base = at<int32_t>(p, L.order);
-        for (const auto& run : p->order_runs) {
+        const int32_t* lists_base = at<int32_t>(p, L.lists);
+        for (size_t q = 0; q < p->order_runs.size(); ++q) {
+            const auto& run = p->order_runs[q];
             StepConfig cr = step_config(p);
             cr.levels = run[0];
             cr.vec = run[3];
@@ -816,9 +919,10 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
             const int64_t n = run[2] - run[1];
             if ((st = grid_for(p, cr, &n_waves, n)) != CTQW_OK) return st;
             a.item_order = order_base + run[1];
+            a.list_off = lists_base + q * (kClaimLists + 1);
             a.n_items = (int32_t)n;
             a.n_waves = n_waves;
-            if (cr.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
+            if (cr.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4 * kClaimLists, p->stream));
             HIP_TRY(p, launch_step(cr, a, p->stream));
         }
         return CTQW_OK;
@@ -847,7 +951,7 @@ ctqw_status enqueue_step_kernels(ctqw_plan* p, const void* in, void* out) {
         a.last = q == passes - 1;
         a.tail_level = a.last ? n - s0 : 0;
         a.tail_coef = inv_fact_n;
-        if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4, p->stream));
+        if (c.persistent) HIP_TRY(p, launch_fill_zero(a.claim, 4 * kClaimLists, p->stream));
         HIP_TRY(p, launch_chunk_pass(c, a, p->stream));
     }
     return CTQW_OK;
@@ -1202,6 +1306,7 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         p->launch.band_align = 128;
         p->launch.terms_per_pass = 0;
         p->launch.band_mode = 0;
+        p->launch.row_segments = 0;
         p->order.assign(R, 0);
         p->xbound.assign(R, 0.0);
     } catch (const std::bad_alloc&) {
@@ -1726,6 +1831,8 @@ ctqw_status ctqw_set_launch(ctqw_plan* p, const ctqw_launch* l) {
         return fail(p, CTQW_ERR_INVALID_ARG, "terms_per_pass must be 0 (default) or 1..3");
     if (l->band_mode != 0 && l->band_mode != 1)
         return fail(p, CTQW_ERR_INVALID_ARG, "band_mode must be 0 (output-aligned) or 1 (window-aligned)");
+    if (l->row_segments < 0 || l->row_segments > kMaxRowSegments)
+        return fail(p, CTQW_ERR_INVALID_ARG, "row_segments must be 0 (auto), 1 (never split) or 2..%d", kMaxRowSegments);
     const ctqw_launch old = p->launch;
     p->launch = *l;
     if (p->params_set) {
@@ -1952,6 +2059,7 @@ bool cache_lookup(const char* path, const std::string& key, ctqw_launch* out, do
             if (!parse_int_field(s, "band_align", &l.band_align)) l.band_align = 0;
             if (!parse_int_field(s, "terms_per_pass", &l.terms_per_pass)) l.terms_per_pass = 0;
             if (!parse_int_field(s, "band_mode", &l.band_mode)) l.band_mode = 0;
+            if (!parse_int_field(s, "row_segments", &l.row_segments)) l.row_segments = 0;
             *out = l;
             const size_t at = s.find("\"ms\": ");
             *ms = at == std::string::npos ? NAN : atof(s.c_str() + at + 6);
@@ -1968,9 +2076,9 @@ void cache_append(const char* path, const std::string& key, const ctqw_launch& l
     fprintf(f,
             "{\"key\": \"%s\", \"cols_per_lane\": %d, \"waves_per_block\": %d, \"persistent\": %d, "
             "\"waves_per_cu\": %d, \"chunked\": %d, \"band_align\": %d, \"terms_per_pass\": %d, "
-            "\"band_mode\": %d, \"ms\": %.6f}\n",
+            "\"band_mode\": %d, \"row_segments\": %d, \"ms\": %.6f}\n",
             key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, l.chunked, l.band_align,
-            l.terms_per_pass, l.band_mode, ms);
+            l.terms_per_pass, l.band_mode, l.row_segments, ms);
     fclose(f);
 }
 
@@ -2087,6 +2195,29 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
             p->launch = orig;
             build_tables(p);
             return fail(p, CTQW_ERR_UNSUPPORTED, "no launch shape fits the bound workspace");
+        }
+        // the row split of the best shape: caps other than the default's
+        if (p->prob.m == 2 && !best.chunked) {
+            int64_t n_auto = -1;
+            p->launch = best;
+            if (build_tables(p) == CTQW_OK) n_auto = (int64_t)p->items.size();
+            for (int seg : {1, 2, 4, 8}) {
+                ctqw_launch c = best;
+                c.row_segments = seg;
+                p->launch = c;
+                if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
+                if ((int64_t)p->items.size() == n_auto) continue;   // the same partition as the default
+                if ((st = upload_tables(p)) != CTQW_OK) return st;
+                double ms = INFINITY;
+                st = time_steps(p, steps, &ms);
+                if (st == CTQW_ERR_UNSUPPORTED) continue;
+                if (st != CTQW_OK) return st;
+                if (trace) cache_append(trace, key, c, ms);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
         }
         if (path && *path) cache_append(path, key, best, best_ms);
     }

@@ -752,20 +752,23 @@ __device__ __forceinline__ void process_item(const StepArgs& a, int home, int la
 }
 
 // One kernel serves both launch forms.  Items are taken in groups of one
-// item per wave of the block (consecutive in the processing order, so
-// mostly adjacent bands of one realisation, whose overlapping columns are
-// then read by one CU at about the same time).  Regular: block b takes
-// group b and the hardware hands out the blocks.  Persistent (a grid of
-// resident blocks): block b starts on group b and then claims the next
-// groups from a counter that the host zeroes before the launch.  Lane 0 of
-// wave 0 alone adds 1 to the counter (one claim per add, whatever the
-// compiler does with atomics of several lanes) and passes the old value to
-// the block through LDS (two slots used alternately, so a slot is rewritten
-// only after every wave has passed the next barrier); every wave reads it
-// back with readfirstlane, so the loop bound is uniform over the block and
-// every wave meets every barrier.
-// Claims grow monotonically and each block leaves after at most one claim
-// past the last group.  Static assignments of items to waves (round-robin,
+// item per wave of the block.  Regular: block b takes group b of the
+// processing order and the hardware hands out the blocks.  Persistent (a
+// grid of resident blocks): the processing order is split into kClaimLists
+// lists, list x holding work for the blocks on XCD x (b mod kClaimLists);
+// the adjacent bands of a realisation sit next to each other in one list,
+// so that their overlapping columns are read through one L2 at about the
+// same time.  A block claims the next group of its list from that list's
+// counter (zeroed by the host before the launch); when its list is used up
+// it moves on to the next list, and it leaves after kClaimLists claims in a
+// row past the ends of lists (counters only grow, so every list is then
+// used up).  Lane 0 of wave 0 alone adds 1 to the counter (one claim per
+// add, whatever the compiler does with atomics of several lanes) and passes
+// the old value to the block through LDS (two slots used alternately, so a
+// slot is rewritten only after every wave has passed the next barrier);
+// every wave reads it back with readfirstlane, so the loop's branches are
+// uniform over the block and every wave meets every barrier.
+// Static assignments of items to waves (round-robin,
 // longest-processing-time) ran 20 % slower: the resident waves do not all
 // advance at the same rate, and only claiming at run time follows that.
 // Two columns per lane in complex64 up to 7 terms sit at the 256-VGPR line
@@ -785,30 +788,52 @@ __global__ void __launch_bounds__(256, (min_blocks_per_cu<T, NT, P, CHUNK>())) s
     const int wpb = blockDim.x >> 6;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ int next_group[2];
-    const int n_blocks = a.persistent ? a.n_waves / wpb : 0;
     // One loop for both forms, so the item code is inlined once and both
-    // forms run the same instructions: a regular launch leaves after its
-    // first group.
-    int g = blockIdx.x;
-    for (int it = 0; g * wpb < a.n_items; ++it) {
-        const int k = g * wpb + wv;
-        if (k < a.n_items) {
-            const int home = ((UniformPtr<int32_t>)a.item_order)[k];
-            if constexpr (TWO) {
-                static_assert(NT >= 2 && !CHUNK, "two orders: NT and NT - 1");
-                const int real = ((UniformPtr<int32_t>)(a.items + home))[0];
-                if (load_uniform(a.reals, real).order == NT)
+    // forms run the same instructions: a regular launch runs group
+    // blockIdx.x of the whole order once.
+    int x = (int)(blockIdx.x % kClaimLists);
+    int end = a.n_items;   // end of the current list (regular: of the order)
+    int first = (int)blockIdx.x * wpb;
+    int it = 0;
+    if (a.persistent) first = a.n_items;   // no group yet: claim below
+    // One loop for both forms, so the item code is inlined once and both
+    // forms run the same instructions: a regular launch runs group
+    // blockIdx.x of the whole order and leaves.
+    for (bool started = !a.persistent;;) {
+        if (started) {
+            const int k = first + wv;
+            if (k < end) {
+                const int home = ((UniformPtr<int32_t>)a.item_order)[k];
+                if constexpr (TWO) {
+                    static_assert(NT >= 2 && !CHUNK, "two orders: NT and NT - 1");
+                    const int real = ((UniformPtr<int32_t>)(a.items + home))[0];
+                    if (load_uniform(a.reals, real).order == NT)
+                        process_item<T, NT, P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
+                    else
+                        process_item<T, (TWO ? NT - 1 : NT), P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
+                } else {
                     process_item<T, NT, P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
-                else
-                    process_item<T, (TWO ? NT - 1 : NT), P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
-            } else {
-                process_item<T, NT, P, KAHAN, TRI, CHUNK, VEC>(a, home, lane);
+                }
             }
+            if (!a.persistent) break;
         }
-        if (!a.persistent) break;
-        if (wv == 0 && lane == 0) next_group[it & 1] = atomicAdd(a.claim, 1);
-        __syncthreads();
-        g = n_blocks + __builtin_amdgcn_readfirstlane(next_group[it & 1]);
+        started = true;
+        // Claim the next group of list x, or of the lists after it.
+        // (x, the bounds and the claim are block-uniform; readfirstlane
+        // keeps them, and everything derived from them, in scalar registers)
+        int misses = 0;
+        for (; misses < kClaimLists; ++misses, ++it) {
+            x = __builtin_amdgcn_readfirstlane(x);
+            if (wv == 0 && lane == 0) next_group[it & 1] = atomicAdd(a.claim + x, 1);
+            __syncthreads();
+            const int lo = __builtin_amdgcn_readfirstlane(((UniformPtr<int32_t>)a.list_off)[x]);
+            end = __builtin_amdgcn_readfirstlane(((UniformPtr<int32_t>)a.list_off)[x + 1]);
+            first = lo + __builtin_amdgcn_readfirstlane(next_group[it & 1]) * wpb;
+            if (first < end) break;
+            x = (x + 1 == kClaimLists) ? 0 : x + 1;   // list x is used up
+        }
+        if (misses == kClaimLists) break;
+        ++it;
     }
 }
 

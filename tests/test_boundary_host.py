@@ -139,6 +139,7 @@ def test_orders_above_the_fused_depth_run_in_passes():
         assert plan.work_items()[0] == bands, dtype
         fused = make(R=1, n_sites=N, taylor_order=6, taylor_tol=0.0, dtype=dtype)
         fused.set_params(np.ones(N - 1), np.zeros(N), np.zeros(1))
+        fused.set_launch(row_segments=1)   # the chunked layout has no row segments
         sb_f, ws_f = fused.sizes()
         fused.set_launch(chunked=1)
         sb_c, ws_c = fused.sizes()
@@ -165,9 +166,37 @@ def test_band_partition_covers_columns_once():
     number of bands follows from the window (64 per lane column) and halo."""
     for P, N, expect in [(1, 64, 1), (1, 65, 2), (1, 200, 4), (2, 128, 1), (2, 300, 3)]:
         plan = make(R=1, n_sites=N, taylor_order=7, taylor_tol=0.0)
-        plan.set_launch(cols_per_lane=P)
+        plan.set_launch(cols_per_lane=P, row_segments=1)
         plan.set_params(np.ones(N - 1), np.zeros(N), np.zeros(1))
         assert plan.work_items()[0] == expect, (P, N)
+
+
+def test_few_bands_split_their_rows():
+    """A batch with few bands has each band's rows split into segments of
+    at least twice the halo (the Taylor order) output rows; row_segments
+    caps the count, 1 switches the split off, and the default splits only
+    small batches."""
+    N, n = 200, 7
+    plan = make(R=1, n_sites=N, taylor_order=n, taylor_tol=0.0)
+    plan.set_launch(cols_per_lane=1, row_segments=1)
+    plan.set_params(np.ones(N - 1), np.zeros(N), np.zeros(1))
+    bands = plan.work_items()[0]
+    assert bands == 4
+    for cap in (2, 5, 16):
+        plan.set_launch(row_segments=cap)
+        assert plan.work_items()[0] == bands * min(cap, N // (2 * n)), cap
+    plan.set_launch(row_segments=0)
+    assert plan.work_items()[0] == bands * min(16, N // (2 * n))
+    # three-particle and one-particle plans are never split
+    one = make(R=1, m=1, n_sites=N, taylor_order=n, taylor_tol=0.0)
+    one.set_launch(cols_per_lane=1)
+    one.set_params(np.ones(N - 1), np.zeros(N), np.zeros(1))
+    assert one.work_items()[0] == 4
+    from paper_1612_00746_amd import CtqwError
+    with pytest.raises(CtqwError):
+        plan.set_launch(row_segments=17)
+    with pytest.raises(CtqwError):
+        plan.set_launch(row_segments=-1)
 
 
 def test_bind_requires_valid_buffers_without_touching_device():
@@ -305,7 +334,7 @@ def test_band_boundaries_follow_the_alignment(P, align, dtype):
     match the band rule; alignment never changes the number of items."""
     Ns = [64, 96, 300, 999, 1024]
     plan = make(R=len(Ns), n_sites=Ns, taylor_order=7, taylor_tol=0.0, dtype=dtype)
-    plan.set_launch(cols_per_lane=P, band_align=align)
+    plan.set_launch(cols_per_lane=P, band_align=align, row_segments=1)
     nb = sum(N - 1 for N in Ns)
     J, _, U = draw(1, len(Ns), nb)
     eps = np.zeros(sum(Ns))

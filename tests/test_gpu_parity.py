@@ -494,9 +494,13 @@ def _shape_state(launch):
     {"cols_per_lane": 1, "band_mode": 1},
     {"cols_per_lane": 2, "band_mode": 1},
     {"cols_per_lane": 2, "persistent": 1, "waves_per_block": 1, "band_mode": 1},
+    {"cols_per_lane": 1, "row_segments": 0},
+    {"cols_per_lane": 2, "row_segments": 3},
+    {"cols_per_lane": 1, "persistent": 1, "row_segments": 16},
 ], ids=["P2", "P1-wpb1", "P1-persistent", "P2-persistent-wpb1", "P1-persistent-cap8", "P1-unaligned",
         "P2-align64", "P2-persistent-unaligned", "P1-window-aligned", "P2-window-aligned",
-        "P2-persistent-window-aligned"])
+        "P2-persistent-window-aligned", "P1-row-segments-auto", "P2-row-segments-3",
+        "P1-persistent-row-segments-16"])
 def test_launch_shape_bitwise_identical(launch):
     """Bitwise identical whatever the block shape, launch form, band
     boundaries or columns per lane: the complex64 full-grid stencil is one
@@ -505,8 +509,64 @@ def test_launch_shape_bitwise_identical(launch):
     arithmetic)."""
     say(f"case: launch shape {launch} vs regular with the same columns per lane")
     P_ = launch.get("cols_per_lane", 1)
-    ref = _shape_state({"cols_per_lane": P_})
+    launch = {"row_segments": 1, **launch}
+    ref = _shape_state({"cols_per_lane": P_, "row_segments": 1})
     got = _shape_state(launch)
     assert np.array_equal(got, ref)
     if P_ == 2:
-        assert np.array_equal(got, _shape_state({"cols_per_lane": 1}))
+        assert np.array_equal(got, _shape_state({"cols_per_lane": 1, "row_segments": 1}))
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("statistics,boundary,interaction", [
+    ("distinguishable", "open", "onsite"),
+    ("boson", "open", "onsite"),
+    ("fermion", "open", "nearest"),
+    ("distinguishable", "periodic", "onsite"),
+    ("distinguishable", "periodic", "nearest"),
+])
+def test_row_segments_match_the_unsplit_sweep(statistics, boundary, interaction, dtype):
+    """Splitting a band's rows into segments (each swept from a halo of
+    Taylor-order rows before its first output row to as many after its
+    last) computes every amplitude from the same neighbours with the same
+    coefficients.  The complex64 full-grid stencil is one fixed sequence of
+    FMAs, so there the state is bitwise unchanged; the compiler-generated
+    stencils (triangle, complex128) may contract a row's products
+    differently at another position of the unrolled sweep, so there the
+    states agree to rounding (measured: a few units in the last place of
+    the smallest amplitudes).  Both runs match the FP64 oracle."""
+    say(f"case: row segments {statistics} {boundary} {interaction} {dtype}")
+    reals = random_reals([100, 37, 150], boundary=boundary, seed=21)
+    n_steps, dt, sites = 12, 0.05, [17, 30]
+
+    def run(seg):
+        plan = gpu_plan(m=2, statistics=statistics, boundary=boundary, interaction=interaction, dtype=dtype,
+                        reals=reals, dt=dt, tol=1e-7 if dtype == "c64" else 1e-12,
+                        launch={"row_segments": seg}, sites=sites)
+        items = plan.work_items()[0]
+        plan.propagate(n_steps)
+        return items, plan.state_numpy(), plan.realization_norms(), plan.orders(), plan.layout()
+
+    n1, ref, (lo1, hi1), orders, off = run(1)
+    exact = dtype == "c64" and statistics == "distinguishable"
+    for seg in (0, 5):
+        n, got, (lo, hi), _, _ = run(seg)
+        d = np.max(np.abs(got.astype(np.complex128) - ref.astype(np.complex128)))
+        say(f"  row_segments={seg}: {n} items (unsplit {n1}), max |split - unsplit| = {d:.3e}")
+        assert n > n1
+        if exact:
+            assert np.array_equal(got, ref)
+        else:
+            assert d <= (1e-6 if dtype == "c64" else 1e-13) * np.max(np.abs(ref))
+        # squared norms in FP64; the last term's squares are summed in the
+        # state's precision per segment before widening
+        assert np.allclose(lo, lo1, rtol=1e-12 if exact or dtype == "c128" else 1e-7, atol=0)
+        assert np.allclose(hi, hi1, rtol=1e-5 if dtype == "c64" else 1e-12, atol=1e-300)
+    # the split run against the oracle's map of the same orders
+    for r, (N, J, eps, U) in enumerate(reals):
+        H = oracle_H(N, 2, statistics, boundary, interaction, J, eps, U)
+        c, _, _ = P.evolve_taylor(H, B.product_state(N, sites, statistics), dt, n_steps, order=int(orders[r]))
+        g = gpu_to_oracle(got[off[r]:off[r + 1]], N, 2, statistics)
+        err = np.max(np.abs(g - c))
+        say(f"  r={r} N={N}: split run vs oracle map {err:.2e}")
+        assert err <= (2e-6 if dtype == "c64" else 1e-12)

@@ -1,5 +1,6 @@
-"""Host-side check of the compiled kernels (no GPU): no 12- or 16-byte buffer
-store is followed at once by a vector-ALU write of its data registers.
+"""Host-side checks of the compiled kernels (no GPU): no 12- or 16-byte
+buffer store is followed at once by a vector-ALU write of its data
+registers, and the two-particle step kernels keep their register budgets.
 
 A buffer store of more than 8 bytes reads its data registers after it
 issues, so a VALU write of them must wait one cycle.  The compiler inserts
@@ -9,10 +10,12 @@ kernels therefore give these stores a zero scalar offset, and this test
 reads the gfx950 assembly of the sources that hold them to check that no
 store is left unguarded."""
 
+import functools
 import os
 import re
 import shutil
 import subprocess
+import tempfile
 
 import pytest
 
@@ -72,15 +75,60 @@ def test_scanner_flags_an_unguarded_store():
     assert len(hits) == 1 and "v[16:19]" in hits[0][1]
 
 
-@pytest.mark.parametrize("src", SOURCES)
-def test_no_store_data_overwritten_at_once(src, tmp_path):
+_TMP = tempfile.mkdtemp(prefix="ctqw_isa_")
+
+
+@functools.lru_cache(maxsize=None)
+def _assembly(src: str) -> str:
+    """gfx950 assembly of one translation unit (compiled once per session)."""
     cc = _hipcc()
     if cc is None:
         pytest.skip("hipcc not available")
-    out = tmp_path / (src + ".s")
+    out = os.path.join(_TMP, src + ".s")
     cmd = [cc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
            "-packed-fp32-ops", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "--cuda-device-only", "-S",
-           os.path.join(CSRC, src), "-o", str(out)]
+           os.path.join(CSRC, src), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
-    hits = unguarded_stores(out.read_text())
+    with open(out) as fh:
+        return fh.read()
+
+
+@pytest.mark.parametrize("src", SOURCES)
+def test_no_store_data_overwritten_at_once(src):
+    hits = unguarded_stores(_assembly(src))
     assert not hits, "\n".join(f"{n}: {a} / {b}" for n, a, b in hits[:5])
+
+
+def kernel_resources(asm: str):
+    """{(pipeline depth, kernel name): (VGPRs, scratch bytes per lane)} of
+    the step kernels in an assembly listing."""
+    out = {}
+    for m in re.finditer(r"\.amdhsa_kernel (\S+)(.*?)\.end_amdhsa_kernel", asm, re.S):
+        name, body = m.group(1), m.group(2)
+        depth = re.search(r"step2d_kernelI[fd]Li(\d+)E", name)
+        if not depth:
+            continue
+        vgpr = int(re.search(r"\.amdhsa_next_free_vgpr\s+(\d+)", body).group(1))
+        scratch = int(re.search(r"\.amdhsa_private_segment_fixed_size\s+(\d+)", body).group(1))
+        out[(int(depth.group(1)), name)] = (vgpr, scratch)
+    return out
+
+
+@pytest.mark.parametrize("src", ["step2d_f32k_p2_vec.hip", "step2d_f64_p2_full.hip"])
+def test_step_kernels_keep_their_register_budget(src):
+    """The sweep's occupancy rests on the kernels' register counts: the
+    complex64 two-column kernels up to 7 terms fit 256 VGPRs (two waves per
+    SIMD) and no step kernel spills.  Everything derived from the work
+    item (its realisation, row bases, the claim of the next item) is
+    wave-uniform and must stay in scalar registers: when the compiler
+    loses track of that (a claim index it cannot prove uniform), the
+    uniform values move to VGPRs, the order-7 complex64 kernel spills and
+    the complex128 kernels drop to one wave per SIMD."""
+    res = kernel_resources(_assembly(src))
+    assert res, "no step kernels found"
+    for (depth, name), (vgpr, scratch) in sorted(res.items()):
+        assert scratch == 0, f"{name}: {scratch} bytes of scratch"
+        if src.startswith("step2d_f32k") and depth <= 7:
+            assert vgpr <= 256, f"{name}: {vgpr} VGPRs"
+        if src.startswith("step2d_f64") and depth <= 3:
+            assert vgpr <= 256, f"{name}: {vgpr} VGPRs"
