@@ -116,7 +116,9 @@ def cpu_baseline(w, budget_s: float = 10.0):
 
 KERNEL_SOURCES = ("paper_1612_00746_amd/csrc/step2d_impl.hpp", "paper_1612_00746_amd/csrc/ctqw_internal.hpp",
                   "paper_1612_00746_amd/csrc/step2d_dispatch.hip")
-SUMMARY = os.path.join(ROOT, "profiles", "step2d_kernel_C3_c64_kahan.md")
+# Counter summaries of the complex64 step kernel on the C3 batch, one file
+# per launch shape that was profiled (the autotuner's pick varies by box).
+SUMMARY = os.path.join(ROOT, "profiles", "step2d_kernel_C3_c64_kahan_wpb{wpb}.md")
 
 
 def kernel_source_hash() -> str:
@@ -135,10 +137,10 @@ def shape_tag(cols_per_lane, waves_per_block, grid_waves, band_align=128, band_m
 
 
 def recorded_traffic(launch, grid_waves):
-    """HBM bytes per step from the committed counter summary, if it was taken
-    on the current kernel sources and at this launch shape."""
+    """HBM bytes per step from the committed counter summary of this launch
+    shape, if it was taken on the current kernel sources."""
     try:
-        text = open(SUMMARY).read()
+        text = open(SUMMARY.format(wpb=launch.get("waves_per_block", 4))).read()
     except OSError:
         return None
     keys = ("kernel-source-sha256:", "traffic-bytes:", "launch-shape:")
@@ -160,8 +162,8 @@ def _rows(path):
         return list(csv.DictReader(fh))
 
 
-def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols_per_lane=1, waves_per_block=4,
-                    waves_per_cu=0, band_align=128, band_mode=0, row_segments=0):
+def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=None, cols_per_lane=1, waves_per_block=4,
+                    waves_per_cu=0, band_align=128, band_mode=0, row_segments=0, persistent=1):
     """Write the step kernels' rocprofv3 summary: duration statistics from
     the kernel trace, FETCH_SIZE / WRITE_SIZE per dispatch scaled by what the
     same counters read for the 4 GiB device copy of the same run.  A step
@@ -210,8 +212,9 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         "Workload: 4096 realisations of two distinguishable walkers on open chains,",
         "N uniform in {64, 96, ..., 1024}, U ~ U[0, 4], J ~ N(1, 0.1^2), dt = 0.05,",
         "Taylor tolerance 1e-7 (6 or 7 terms per realisation), complex64 with the",
-        f"compensated sum; persistent launches, {cols_per_lane} column(s) per lane, {waves_per_block} wave(s) per block,",
-        f"{waves_per_cu or 'all'} resident waves per CU, "
+        f"compensated sum; {'persistent' if persistent else 'regular'} launches, {cols_per_lane} column(s) per lane, "
+        f"{waves_per_block} wave(s) per block,",
+        (f"{waves_per_cu or 'all'} resident waves per CU, " if persistent else "one block per group of items, ")
         + (f"band windows on {band_align}-byte boundaries (outputs on 32-byte ones)" if band_mode
            else f"{band_align}-byte band boundaries") + ", captured step loop;",
         "adjacent Taylor orders share one launch (each item at its own order).",
@@ -241,6 +244,7 @@ def profile_summary(trace_dir, fetch_dir, write_dir, commands, out=SUMMARY, cols
         f"traffic-bytes: {int(round(fetch_b + write_b))}",
         "",
     ]
+    out = out or SUMMARY.format(wpb=waves_per_block)
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as fh:
         fh.write("\n".join(lines))
@@ -880,7 +884,7 @@ def main():
     if a.profile_summary:
         profile_summary(*a.profile_summary, commands=a.profile_command, cols_per_lane=a.cols_per_lane,
                         waves_per_block=a.waves_per_block, waves_per_cu=a.waves_per_cu, band_align=a.band_align,
-                        band_mode=a.band_mode, row_segments=a.row_segments)
+                        band_mode=a.band_mode, row_segments=a.row_segments, persistent=0 if a.regular else 1)
         return
     if a.kernel_summary:
         kernel_summary(a.kernel_summary, a.title or a.match, a.workload_line, a.profile_command, a.match,
@@ -933,9 +937,11 @@ def main():
     tuned = None
     if not a.no_autotune:
         # The autotuner times every launch shape on this batch; the batch's
-        # launch form stays persistent with the captured step loop, and the
-        # tuned columns per lane, waves per block, wave cap and chunking are
-        # kept.  The state is overwritten by tuning: start again after it.
+        # launch form stays persistent with the captured step loop (the
+        # workload is defined with one persistent launch per step), and the
+        # tuned columns per lane, waves per block, wave cap, chunking and
+        # band layout are kept.  The state is overwritten by tuning: start
+        # again after it.
         import tempfile
         with tempfile.TemporaryDirectory() as td:
             best, best_ms = plan.autotune(os.path.join(td, "tune.jsonl"), steps=3)

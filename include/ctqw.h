@@ -472,9 +472,10 @@ ctqw_status ctqw_realization_norms(ctqw_plan* plan, double* norm2, double* tail2
 ctqw_status ctqw_get_launch(const ctqw_plan* plan, ctqw_launch* out);
 ctqw_status ctqw_set_launch(ctqw_plan* plan, const ctqw_launch* launch);
 
-/* Number of work items (realisation x column band) of one step and the
- * number of waves that one step launches, for the current launch shape
- * (persistent: the device's resident waves, known once bound; with
+/* Number of work items (realisation x column band, or row segment of a
+ * band) of one step and the number of waves that one step launches, for
+ * the current launch shape (regular: whole blocks of waves_per_block
+ * waves; persistent: the device's resident waves, known once bound; with
  * several orders, the largest of the per-order launches).                */
 ctqw_status ctqw_work_items(const ctqw_plan* plan, int64_t* items, int64_t* waves);
 

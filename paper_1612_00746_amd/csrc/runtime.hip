@@ -1783,6 +1783,17 @@ ctqw_status ctqw_work_items(const ctqw_plan* p, int64_t* items, int64_t* waves) 
     if (items) *items = n;
     if (waves) {
         *waves = p->prob.m == 3 ? n * 8 : n;
+        if (p->prob.m != 3 && !p->launch.persistent) {
+            // regular: whole blocks of waves_per_block waves per launch (the
+            // largest of the per-order launches)
+            const int64_t wpb = p->launch.waves_per_block;
+            auto whole = [&](int64_t k) { return (k + wpb - 1) / wpb * wpb; };
+            *waves = whole(n);
+            if (!p->chunk && !p->order_runs.empty()) {
+                *waves = 0;
+                for (const auto& run : p->order_runs) *waves = std::max<int64_t>(*waves, whole(run[2] - run[1]));
+            }
+        }
         if (p->prob.m != 3 && p->launch.persistent && p->bound) {
             // the persistent grid: resident waves of the device (the
             // largest of the per-order launches)
