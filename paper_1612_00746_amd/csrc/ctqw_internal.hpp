@@ -238,38 +238,9 @@ struct Obs3Args {
 hipError_t launch_obs3(const Obs3Args& a, int dtype, hipStream_t stream);
 
 // ---------------------------------------------------------------- adjoint
-// Backward sweeps: bands of kSweepOut output columns (a wave of 64 lanes
-// with one halo column on either side); a block of kSweepSegs waves splits
-// the band's rows into consecutive segments, each wave keeping the next
-// kSweepAhead rows of its inputs in flight.
-constexpr int kSweepOut = 62;
+// Backward passes: a block of kSweepSegs waves splits a band's rows into
+// consecutive segments, one wave each.
 constexpr int kSweepSegs = 4;
-constexpr int kSweepAhead = 4;
-struct AdjSweepArgs {
-    const void* x;       // input vector (never null)
-    double xs;           // scale of x (u = xs x)
-    const void* z;       // may be null
-    double cz;
-    int sign;            // +1: A = -i dt H; -1: A^dagger
-    void* y;             // output: cz z + s (-i) (dt H) u
-    const void* v;       // contraction partner of u; null: no contraction
-    const RealDev* reals;
-    const void* Jt;      // dt-scaled tables of the step kernel (dtype of the state)
-    const void* Et;
-    double dt;
-    const int64_t* site_off;
-    double* gJ;          // column parts (bond b / site b) per realisation
-    double* gE;
-    double* gV;          // row parts per band: [R][nb][row_stride]
-    double* gR;
-    int64_t R;
-    int nb;              // bands per realisation (ceil(max N / kSweepOut))
-    int row_stride;
-    int dtype;
-    int periodic;        // the batch's boundary (1: ring)
-    int layout;          // 0: one row (one particle), 1: full grid, 2: triangle (bosons)
-};
-hipError_t launch_adj_sweep(const AdjSweepArgs& a, hipStream_t stream);
 
 struct AdjWeightArgs {
     const void* psi;

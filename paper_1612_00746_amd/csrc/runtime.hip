@@ -27,6 +27,7 @@
 
 #include "../../include/ctqw.h"
 #include "ctqw_internal.hpp"
+#include "adjoint_pipe.hpp"
 #include "noise.hpp"
 #include "density.hpp"
 #include "graph.hpp"
@@ -2270,8 +2271,10 @@ GradLayout grad_layout(const ctqw_plan* p, int64_t n_steps, int64_t C) {
     auto dbl = [&](int64_t n) { const int64_t r = o; o += (n * 8 + 255) & ~int64_t(255); return r; };
     g.gJ = dbl(p->site_total);
     g.gE = dbl(p->site_total);
-    // row parts of the backward sweeps: one partial per band and row
-    g.nb = std::max(1, (p->max_N + kSweepOut - 1) / kSweepOut);
+    // row parts of the backward passes: one partial per band and row (the
+    // Horner passes' narrowest bands)
+    const int hw = pipe_band_width(pipe_max_levels(p->prob.dtype == CTQW_C128 ? 1 : 0, true));
+    g.nb = std::max(1, (p->max_N + hw - 1) / hw);
     g.gV = dbl((int64_t)p->prob.R * g.nb * p->max_N);
     g.gR = dbl((int64_t)p->prob.R * g.nb * p->max_N);
     g.row_loss = dbl(p->site_total);
@@ -2390,35 +2393,29 @@ ctqw_status ctqw_backward(ctqw_plan* p, int32_t kind, const double* site_w, void
     wa.dtype = dtype;
     HIP_TRY(p, launch_adj_weights(wa, s));
 
-    AdjSweepArgs sa{};
-    sa.reals = reals;
-    sa.Jt = dtype ? static_cast<const void*>(at<double>(p, p->lay.Jd)) : static_cast<const void*>(at<float>(p, p->lay.Jf));
-    sa.Et = dtype ? static_cast<const void*>(at<double>(p, p->lay.Ed)) : static_cast<const void*>(at<float>(p, p->lay.Ef));
-    sa.dt = pr.dt;
-    sa.site_off = site_off;
-    sa.gJ = reinterpret_cast<double*>(G + g.gJ);
-    sa.gE = reinterpret_cast<double*>(G + g.gE);
-    sa.gV = reinterpret_cast<double*>(G + g.gV);
-    sa.gR = reinterpret_cast<double*>(G + g.gR);
-    sa.R = pr.R;
-    sa.nb = g.nb;
-    sa.row_stride = p->max_N;
-    sa.dtype = dtype;
-    sa.periodic = pr.boundary == CTQW_PERIODIC ? 1 : 0;
-    sa.layout = pr.m == 1 ? 0 : (pr.statistics == CTQW_DISTINGUISHABLE ? 1 : 2);
-    // one sweep: y = cz z + s (-i)(dt H)(xs x), contracting xs x with v if given
-    auto sweep = [&](const void* x, double xs, const void* z, double cz, int sign, void* y,
-                     const void* v) -> ctqw_status {
-        AdjSweepArgs a = sa;
-        a.x = x;
-        a.xs = xs;
-        a.z = z;
-        a.cz = cz;
-        a.sign = sign;
-        a.y = y;
-        a.v = v;
-        HIP_TRY(p, launch_adj_sweep(a, s));
-        return CTQW_OK;
+    // K levels per pass (adjoint_pipe.hpp): forward vectors and Horner levels
+    AdjPipeArgs pa{};
+    pa.reals = reals;
+    pa.Jt = dtype ? static_cast<const void*>(at<double>(p, p->lay.Jd)) : static_cast<const void*>(at<float>(p, p->lay.Jf));
+    pa.Et = dtype ? static_cast<const void*>(at<double>(p, p->lay.Ed)) : static_cast<const void*>(at<float>(p, p->lay.Ef));
+    pa.dt = pr.dt;
+    pa.site_off = site_off;
+    pa.gJ = reinterpret_cast<double*>(G + g.gJ);
+    pa.gE = reinterpret_cast<double*>(G + g.gE);
+    pa.gV = reinterpret_cast<double*>(G + g.gV);
+    pa.gR = reinterpret_cast<double*>(G + g.gR);
+    pa.R = pr.R;
+    pa.nb = g.nb;
+    pa.max_n = p->max_N;
+    pa.row_stride = p->max_N;
+    pa.dtype = dtype;
+    pa.periodic = pr.boundary == CTQW_PERIODIC ? 1 : 0;
+    pa.layout = pr.m == 1 ? 0 : (pr.statistics == CTQW_DISTINGUISHABLE ? 1 : 2);
+    const int kf = pipe_max_levels(dtype, false), kh = pipe_max_levels(dtype, true);
+    // passes of at most kmax levels, as even as the count allows
+    auto pass_levels = [](int left, int kmax) {
+        const int passes = (left + kmax - 1) / kmax;
+        return (left + passes - 1) / passes;
     };
 
     int lc = 0;   // state(g.lam, lc) holds lambda_{k+1}
@@ -2433,34 +2430,56 @@ ctqw_status ctqw_backward(ctqw_plan* p, int32_t kind, const double* site_w, void
         }
         for (int64_t k = len - 1; k >= 0; --k) {
             const void* lam = state(g.lam, lc);
-            // v_i = A^i psi_k
+            // v_i = A^i psi_k, K levels per pass, every level stored
             vp[0] = segp[k];
-            for (int i = 1; i < n; ++i) {
-                vp[i] = state(g.v, i - 1);
-                if ((st = sweep(vp[i - 1], 1.0, nullptr, 0.0, +1, const_cast<void*>(vp[i]), nullptr)) != CTQW_OK)
-                    return st;
+            for (int i = 1; i < n; ++i) vp[i] = state(g.v, i - 1);
+            for (int i0 = 0; i0 < n - 1;) {
+                const int K = pass_levels(n - 1 - i0, kf);
+                AdjPipeArgs a = pa;
+                a.x = vp[i0];
+                a.xs = 1.0;
+                a.sign = +1;
+                a.levels = K;
+                for (int l = 1; l <= K; ++l) a.y[l - 1] = const_cast<void*>(vp[i0 + l]);
+                HIP_TRY(p, launch_adj_pipe(a, s));
+                i0 += K;
             }
             // Horner: level L contracts u_L with v_L and forms u_{L-1} = lambda / L! + A^dagger u_L
-            // (lambda_k at L = 0); u_{n-1} = lambda / n! is the first level's scaled input
+            // (lambda_k at L = 0); u_{n-1} = lambda / n! is the first pass's scaled input.  A pass
+            // of K levels runs L = Lhi .. Lhi - K + 1 and stores only its last level.
             int uc = 0;
             const void* u = lam;
             double us = inv_fact(n);
-            for (int L = n - 1; L >= 0; --L) {
-                void* y = L > 0 ? state(g.u, uc) : state(g.lam, 1 - lc);
-                if ((st = sweep(u, us, lam, inv_fact(L), -1, y, vp[L])) != CTQW_OK) return st;
+            for (int Lhi = n - 1; Lhi >= 0;) {
+                const int K = pass_levels(Lhi + 1, kh);
+                void* y = Lhi - K + 1 > 0 ? state(g.u, uc) : state(g.lam, 1 - lc);
+                AdjPipeArgs a = pa;
+                a.x = u;
+                a.xs = us;
+                a.z = lam;
+                a.sign = -1;
+                a.levels = K;
+                a.contract = 1;
+                for (int l = 1; l <= K; ++l) {
+                    a.v[l - 1] = vp[Lhi - l + 1];
+                    a.cz[l] = inv_fact(Lhi - l + 1);
+                }
+                a.y[K - 1] = y;
+                HIP_TRY(p, launch_adj_pipe(a, s));
                 u = y;
                 us = 1.0;
                 uc ^= 1;
+                Lhi -= K;
             }
             lc ^= 1;
         }
     }
 
     AdjReduceArgs ra{};
-    ra.gJ = sa.gJ;
-    ra.gE = sa.gE;
-    ra.gV = sa.gV;
-    ra.gR = sa.gR;
+    ra.gJ = pa.gJ;
+    ra.gE = pa.gE;
+    ra.gV = pa.gV;
+    ra.gR = pa.gR;
     ra.nb = g.nb;
     ra.row_stride = p->max_N;
     ra.row_loss = wa.row_loss;
