@@ -35,7 +35,7 @@ namespace ctqw {
 // would spill at two waves per SIMD).
 constexpr int kPipeMaxLevelsC64 = 8;
 constexpr int kPipeMaxLevelsC128 = 4;
-constexpr int kPipeMaxHornerC64 = 4;
+constexpr int kPipeMaxHornerC64 = 3;
 constexpr int kPipeMaxHornerC128 = 2;
 constexpr int kPipeMaxLevels = 8;
 

@@ -1455,6 +1455,8 @@ ctqw_status ctqw_groups(const ctqw_plan* p, int32_t* n_groups, int32_t* sizes) {
     return CTQW_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // Stored amplitudes of the realisations of group g (all equal).
 int64_t group_dim(const ctqw_plan* p, int32_t g) {
@@ -1462,6 +1464,8 @@ int64_t group_dim(const ctqw_plan* p, int32_t g) {
     return p->state_off[r + 1] - p->state_off[r];
 }
 }  // namespace
+
+extern "C" {
 
 ctqw_status ctqw_set_telegraph(ctqw_plan* p, double amplitude, double rate, uint64_t seed) {
     if (!p) return fail(nullptr, CTQW_ERR_INVALID_ARG, "NULL plan");
@@ -2028,6 +2032,8 @@ ctqw_status ctqw_propagate(ctqw_plan* p, int64_t n_steps, int64_t output_every, 
     return CTQW_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 std::string tune_key(ctqw_plan* p) {
@@ -2116,6 +2122,8 @@ ctqw_status time_steps(ctqw_plan* p, int32_t steps, double* ms) {
 }
 
 }  // namespace
+
+extern "C" {
 
 ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, ctqw_launch* best_out,
                           double* best_ms_out) {
@@ -2242,6 +2250,8 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
     return CTQW_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Gradient workspace: checkpoints, recomputed segment states, the Taylor
@@ -2291,6 +2301,8 @@ double inv_fact(int j) {
 }
 
 }  // namespace
+
+extern "C" {
 
 ctqw_status ctqw_gradient_workspace(const ctqw_plan* p, int64_t n_steps, int64_t ckpt_every, int64_t* bytes) {
     if (!p || !bytes) return fail(const_cast<ctqw_plan*>(p), CTQW_ERR_INVALID_ARG, "NULL argument");

@@ -136,7 +136,7 @@ def test_step_kernels_keep_their_register_budget(src):
 
 def test_adjoint_passes_do_not_spill():
     """The K-level adjoint passes (forward vectors up to 8 / 4 levels,
-    Horner passes up to 4 / 2 levels for complex64 / complex128) hold every
+    Horner passes up to 3 / 2 levels for complex64 / complex128) hold every
     level's rows in registers; none may spill to scratch."""
     asm = _assembly("adjoint_pipe.hip")
     found = 0
@@ -148,7 +148,7 @@ def test_adjoint_passes_do_not_spill():
         scratch = int(re.search(r"\.amdhsa_private_segment_fixed_size\s+(\d+)", body).group(1))
         vgpr = int(re.search(r"\.amdhsa_next_free_vgpr\s+(\d+)", body).group(1))
         assert scratch == 0 and vgpr <= 256, f"{name}: {vgpr} VGPRs, {scratch} bytes of scratch"
-    # five layouts (one row, full grid and ring, triangle) x (8 + 4 complex64
+    # five layouts (one row, full grid and ring, triangle) x (8 + 3 complex64
     # and 4 + 2 complex128 depths)
-    assert found == 5 * (8 + 4 + 4 + 2)
+    assert found == 5 * (8 + 3 + 4 + 2)
 
