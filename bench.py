@@ -728,7 +728,8 @@ def three_walkers(a):
     actually move (per amplitude: the first pass reads X and writes the
     partial sum and Psi_K, 24 B; a middle pass also reads the partial sum,
     32 B; the last reads X and the partial sum and writes the state, 24 B)
-    are reported beside it."""
+    are reported beside it.  --three-form 1: the product form (each pass
+    reads and writes one state, 16 B per amplitude and pass)."""
     import torch
     from paper_1612_00746_amd import Plan, make_problem
     from workloads import C5
@@ -743,7 +744,7 @@ def three_walkers(a):
                             dtype="c64", accumulation="kahan", taylor_tol=w.tol, observables=1)
     plan = Plan(pr)
     plan._keep.append(keep)
-    plan.set_launch(use_graph=1, terms_per_pass=a.terms_per_pass)
+    plan.set_launch(use_graph=1, terms_per_pass=a.terms_per_pass, three_form=a.three_form)
     plan.set_params(J, eps, U)
     plan.bind()
     plan.init_product_state(np.array([w.start_sites(int(n)) for n in sizes], dtype=np.int32))
@@ -752,7 +753,11 @@ def three_walkers(a):
     n = int(plan.orders().max())
     K = plan.get_launch().terms_per_pass or 3
     passes = -(-n // K)
-    impl_bytes = 16.0 if passes == 1 else 24.0 + 32.0 * (passes - 2) + 24.0
+    form = plan.get_launch().three_form
+    if passes == 1 or form == 1:
+        impl_bytes = 16.0 * passes
+    else:
+        impl_bytes = 24.0 + 32.0 * (passes - 2) + 24.0
     achieved = amps * 16.0 / (kern_ms * 1e-3) / 1e9
     st = plan.stats()
     print(json.dumps({
@@ -762,7 +767,8 @@ def three_walkers(a):
         "vs_baseline": None, "dtype": "c64", "data": "synthetic (seeded noise draws, no dataset)",
         "config": {"workload": w.name, "realisations": w.R, "sites": int(sizes[0]), "particles": 3,
                    "amplitudes": amps, "dt": w.dt, "taylor_tol": w.tol, "taylor_order": n,
-                   "terms_per_pass": K, "passes": passes},
+                   "terms_per_pass": K, "passes": passes,
+                   "pass_form": "product of root factors" if form == 1 else "chained Taylor sum"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "step3c_kernel",
                      "kernel_ms": round(kern_ms, 4), "bytes_per_update_algorithmic": 16,
@@ -878,6 +884,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time one gradient of the gradient workload (512 x two bosons, N = 256, 400 steps)")
     ap.add_argument("--adjoint-dtypes", default="c64,c128", help="--adjoint: comma-separated state types")
+    ap.add_argument("--three-form", type=int, default=1,
+                    help="three walkers: 0 chained Taylor sum per pass, 1 product of the polynomial's root factors")
     ap.add_argument("--terms-per-pass", type=int, default=0,
                     help="three walkers: Taylor terms chained per pass (0: the library's default)")
     a = ap.parse_args()

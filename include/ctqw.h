@@ -153,6 +153,20 @@ typedef struct {
                                 output ends on a 32-byte boundary (two bands
                                 then store parts of one line).  Other
                                 layouts ignore it.                         */
+    int32_t three_form;      /* three particles, steps of more than one pass:
+                                0 (default): each pass continues the Taylor sum
+                                (Eqs. 6-7) from the last term of the one
+                                before, carrying the partial sum and that
+                                term between passes; the truncation test
+                                sees the exact last term;
+                                1: product form -- the step's polynomial
+                                sum_k z^k / k! (z = -i dt H) factored over its
+                                roots, one group of at most terms_per_pass
+                                factors per pass, so a pass reads and writes
+                                one state; the last term's norm is bounded by
+                                (dt G)^(n - K) ||(dt H)^K psi|| from the first
+                                pass (G: the Gershgorin bound on ||H||).
+                                Ignored for m < 3.                         */
     int32_t row_segments;    /* two particles, all terms in one pass: a band's
                                 rows are swept in order by one wave, so a
                                 batch with few bands leaves most SIMDs

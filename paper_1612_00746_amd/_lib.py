@@ -78,6 +78,7 @@ class Launch(C.Structure):
         ("band_align", C.c_int32),
         ("terms_per_pass", C.c_int32),
         ("band_mode", C.c_int32),
+        ("three_form", C.c_int32),
         ("row_segments", C.c_int32),
     ]
 

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <new>
@@ -28,6 +29,7 @@
 #include "../../include/ctqw.h"
 #include "ctqw_internal.hpp"
 #include "adjoint_pipe.hpp"
+#include "step3c.hpp"
 #include "noise.hpp"
 #include "density.hpp"
 #include "graph.hpp"
@@ -82,6 +84,7 @@ struct ctqw_plan {
     std::vector<ItemDev> items;
     std::vector<Item3Dev> items3;    // three particles: plane tiles
     int k3 = 0;                      // three particles: terms per pass
+    std::vector<Step3cProd> prod3;   // three particles, product form: one entry per pass
     std::vector<int32_t> item_first, item_order;
     // fused steps: runs of item_order with one Taylor order each, largest
     // order first: {order, first, end}
@@ -241,6 +244,87 @@ int terms3(const ctqw_plan* p, int order) {
     return std::max(1, std::min(K, order));
 }
 
+// Product form of the three-particle step (step3c.hpp): the roots of
+// p_n(z) = sum_{k<=n} z^k / k! (Durand-Kerner iteration on n! p_n, which is
+// monic, in long double, then two Newton steps), grouped into passes of at
+// most K roots (conjugate pairs kept together where the sizes allow), and
+// per pass c_j = e_j (-i)^j, e_j the elementary symmetric polynomials of
+// -1/z_k over the pass's roots.  Fails if the passes' polynomials do not
+// multiply back to p_n to 1e-13.
+bool product_passes(int n, int K, std::vector<Step3cProd>& out) {
+    using cl = std::complex<long double>;
+    std::vector<long double> c(n + 1);   // c[k] = n! / k!
+    long double f = 1.0L;
+    for (int k = n; k >= 0; --k) {
+        c[k] = f;
+        f *= (k > 0 ? k : 1);
+    }
+    auto P = [&](cl z) { cl v = 0; for (int k = n; k >= 0; --k) v = v * z + c[k]; return v; };
+    auto dP = [&](cl z) { cl v = 0; for (int k = n; k >= 1; --k) v = v * z + (long double)k * c[k]; return v; };
+    const long double R = 1.0L + (long double)n / 2.718281828459045L;
+    std::vector<cl> z(n);
+    for (int k = 0; k < n; ++k) z[k] = std::polar(R, 0.4L + 6.283185307179586L * k / n);
+    for (int it = 0; it < 2000; ++it) {
+        long double step = 0;
+        for (int k = 0; k < n; ++k) {
+            cl den = 1;
+            for (int j = 0; j < n; ++j)
+                if (j != k) den *= z[k] - z[j];
+            const cl d = P(z[k]) / den;
+            z[k] -= d;
+            step = std::max(step, std::abs(d));
+        }
+        if (step < 1e-18L) break;
+    }
+    for (int k = 0; k < n; ++k)
+        for (int it = 0; it < 2; ++it) z[k] -= P(z[k]) / dP(z[k]);
+    // order: pairs (z, conj z) by increasing real part, a real root last
+    std::vector<cl> up, ordered;
+    cl real_root = 0;
+    bool has_real = false;
+    for (const cl& r : z) {
+        if (std::abs(r.imag()) < 1e-12L * std::abs(r)) { real_root = cl(r.real(), 0); has_real = true; }
+        else if (r.imag() > 0) up.push_back(r);
+    }
+    std::sort(up.begin(), up.end(), [](const cl& a, const cl& b) { return a.real() < b.real(); });
+    for (const cl& r : up) { ordered.push_back(r); ordered.push_back(std::conj(r)); }
+    if (has_real) ordered.push_back(real_root);
+    if ((int)ordered.size() != n) return false;
+    // passes of K roots (the last takes the rest)
+    out.clear();
+    std::vector<cl> total(1, cl(1));
+    for (int s0 = 0; s0 < n; s0 += K) {
+        const int Kq = std::min(K, n - s0);
+        std::vector<cl> e(Kq + 1, cl(0));
+        e[0] = 1;
+        for (int k = 0; k < Kq; ++k) {
+            const cl w = -1.0L / ordered[s0 + k];
+            for (int j = k + 1; j >= 1; --j) e[j] += w * e[j - 1];
+        }
+        Step3cProd pp{};
+        cl rot = 1;   // (-i)^j
+        for (int j = 1; j <= Kq; ++j) {
+            rot *= cl(0, -1);
+            const cl cj = e[j] * rot;
+            pp.cre[j - 1] = (double)cj.real();
+            pp.cim[j - 1] = (double)cj.imag();
+        }
+        pp.order = n;
+        pp.k_first = std::min(K, n);
+        out.push_back(pp);
+        std::vector<cl> nt(total.size() + Kq, cl(0));
+        for (size_t a = 0; a < total.size(); ++a)
+            for (int b = 0; b <= Kq; ++b) nt[a + b] += total[a] * e[b];
+        total.swap(nt);
+    }
+    long double inv = 1.0L;
+    for (int k = 0; k <= n; ++k) {
+        if (k > 0) inv /= k;
+        if (std::abs(total[k] - cl(inv)) > 1e-13L * inv) return false;
+    }
+    return true;
+}
+
 // Column bands of one realisation for halo h (= its Taylor order) and a
 // window of W columns.  A band computes its whole window and stores its
 // output columns [lo, hi), which lie at least h columns inside the window
@@ -340,6 +424,9 @@ ctqw_status build_tables(ctqw_plan* p) {
         // tiles of the (x2, x3) plane swept over x1, halo = terms per pass;
         // one norm partial per tile
         k3 = terms3(p, maxn);
+        p->prod3.clear();
+        if (p->launch.three_form == 1 && maxn > k3 && !product_passes(maxn, k3, p->prod3))
+            return fail(p, CTQW_ERR_UNSUPPORTED, "no product form of the order-%d Taylor polynomial", maxn);
         const int rows = step3c_rows_per_block(dtype, k3);
         if (rows <= 0) return fail(p, CTQW_ERR_UNSUPPORTED, "%d terms per pass are not compiled", k3);
         const bool periodic = pr.boundary == CTQW_PERIODIC;
@@ -847,6 +934,25 @@ ctqw_status enqueue_step3(ctqw_plan* p) {
     a.tail_coef = inv_fact(n);
     ctqw_status st;
     if (p->timing && (st = record_event(p, 0)) != CTQW_OK) return st;
+    if (!p->prod3.empty() && passes > 1) {
+        // product form: pass q maps its input to q_q(z) input; the passes
+        // alternate between two buffers and the last writes the new state
+        void* tmp[2] = {acc_tmp, seed_buf[0]};
+        const void* x = in;
+        for (int q = 0; q < passes; ++q) {
+            const int Kq = std::min(K, n - q * K);
+            a.x_in = x;
+            a.base_in = x;
+            a.sum_out = q == passes - 1 ? out : tmp[q & 1];
+            a.seed_out = nullptr;
+            for (int j = 0; j < 4; ++j) a.coef[j] = 0.0;
+            a.first = q == 0;
+            a.last = q == passes - 1;
+            a.tail_level = 0;
+            HIP_TRY(p, launch_step3c_prod(a, p->prod3[q], dtype, Kq, p->stream));
+            x = a.sum_out;
+        }
+    } else
     for (int q = 0; q < passes; ++q) {
         const int s0 = q * K;
         const int Kq = std::min(K, n - s0);
@@ -1308,6 +1414,7 @@ ctqw_status ctqw_plan_create(const ctqw_problem* pr, ctqw_plan** out) {
         p->launch.terms_per_pass = 0;
         p->launch.band_mode = 0;
         p->launch.row_segments = 0;
+        p->launch.three_form = 0;
         p->order.assign(R, 0);
         p->xbound.assign(R, 0.0);
     } catch (const std::bad_alloc&) {
@@ -1847,6 +1954,8 @@ ctqw_status ctqw_set_launch(ctqw_plan* p, const ctqw_launch* l) {
         return fail(p, CTQW_ERR_INVALID_ARG, "terms_per_pass must be 0 (default) or 1..3");
     if (l->band_mode != 0 && l->band_mode != 1)
         return fail(p, CTQW_ERR_INVALID_ARG, "band_mode must be 0 (output-aligned) or 1 (window-aligned)");
+    if (l->three_form != 0 && l->three_form != 1)
+        return fail(p, CTQW_ERR_INVALID_ARG, "three_form must be 0 (chained sum) or 1 (product form)");
     if (l->row_segments < 0 || l->row_segments > kMaxRowSegments)
         return fail(p, CTQW_ERR_INVALID_ARG, "row_segments must be 0 (auto), 1 (never split) or 2..%d", kMaxRowSegments);
     const ctqw_launch old = p->launch;
@@ -2078,6 +2187,7 @@ bool cache_lookup(const char* path, const std::string& key, ctqw_launch* out, do
             if (!parse_int_field(s, "terms_per_pass", &l.terms_per_pass)) l.terms_per_pass = 0;
             if (!parse_int_field(s, "band_mode", &l.band_mode)) l.band_mode = 0;
             if (!parse_int_field(s, "row_segments", &l.row_segments)) l.row_segments = 0;
+            if (!parse_int_field(s, "three_form", &l.three_form)) l.three_form = 0;
             *out = l;
             const size_t at = s.find("\"ms\": ");
             *ms = at == std::string::npos ? NAN : atof(s.c_str() + at + 6);
@@ -2094,9 +2204,9 @@ void cache_append(const char* path, const std::string& key, const ctqw_launch& l
     fprintf(f,
             "{\"key\": \"%s\", \"cols_per_lane\": %d, \"waves_per_block\": %d, \"persistent\": %d, "
             "\"waves_per_cu\": %d, \"chunked\": %d, \"band_align\": %d, \"terms_per_pass\": %d, "
-            "\"band_mode\": %d, \"row_segments\": %d, \"ms\": %.6f}\n",
+            "\"band_mode\": %d, \"row_segments\": %d, \"three_form\": %d, \"ms\": %.6f}\n",
             key.c_str(), l.cols_per_lane, l.waves_per_block, l.persistent, l.waves_per_cu, l.chunked, l.band_align,
-            l.terms_per_pass, l.band_mode, l.row_segments, ms);
+            l.terms_per_pass, l.band_mode, l.row_segments, l.three_form, ms);
     fclose(f);
 }
 
@@ -2154,12 +2264,14 @@ ctqw_status ctqw_autotune(ctqw_plan* p, const char* cache_path, int32_t steps, c
         }
     }
     if (!cached && p->prob.m == 3) {
-        // three particles: terms per pass and the x3 band alignment
+        // three particles: terms per pass, the x3 band alignment and the pass form
+        for (int form : {0, 1})
         for (int K : {3, 2, 1})
             for (int align : {128, 0}) {
                 ctqw_launch c = orig;
                 c.terms_per_pass = K;
                 c.band_align = align;
+                c.three_form = form;
                 p->launch = c;
                 if (build_tables(p) != CTQW_OK || p->lay.total > p->ws_bytes) continue;
                 if ((st = upload_tables(p)) != CTQW_OK) return st;

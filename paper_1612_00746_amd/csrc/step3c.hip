@@ -32,7 +32,7 @@
 // one read and one write per term.  The terms of a pass are summed apart
 // from the partial sum and added to it once, so the new state takes one
 // rounding per pass.
-#include "ctqw_internal.hpp"
+#include "step3c.hpp"
 
 namespace ctqw {
 namespace step3c_detail {
@@ -164,9 +164,11 @@ __device__ __forceinline__ double wave_sum3(double v) {
 // FIRST: X = psi times the realisation's load scale, and the partial sum
 // before the pass is X itself; LAST: the pass writes the new state, the
 // FP64 squared norm of it and of the order's last term (the kernel's last
-// level), and no Psi_{s+K}.
-template <typename T, int KT, int S, int W, bool FIRST, bool LAST>
-__global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
+// level), and no Psi_{s+K}.  PROD (step3c.hpp): the pass writes
+// X + sum_j c_j Y_j with complex c_j and no Psi_{s+K}; the first pass of a
+// step forms the squared norm of its last level, which bounds the last term.
+template <typename T, int KT, int S, int W, bool FIRST, bool LAST, bool PROD>
+__global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a, Step3cProd pp) {
     using C = typename Cplx3c<T>::type;
     static_assert(KT >= 1 && KT <= 3, "windows are indexed modulo 3");
     const int lane = threadIdx.x & 63;
@@ -203,7 +205,11 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
     const char* x_base = reinterpret_cast<const char*>(reinterpret_cast<const C*>(a.x_in) + rd.state_off);
     const char* b_base = reinterpret_cast<const char*>(reinterpret_cast<const C*>(a.base_in) + rd.state_off);
     char* s_base = reinterpret_cast<char*>(reinterpret_cast<C*>(a.sum_out) + rd.state_off);
-    char* q_base = LAST ? s_base : reinterpret_cast<char*>(reinterpret_cast<C*>(a.seed_out) + rd.state_off);
+    char* q_base = (LAST || PROD) ? s_base : reinterpret_cast<char*>(reinterpret_cast<C*>(a.seed_out) + rd.state_off);
+    // which FP64 partials this pass forms: the new state's squared norm
+    // (last pass) and the last term's (chained: last pass; product: first)
+    constexpr bool DO_NORM = LAST;
+    constexpr bool DO_TAIL = PROD ? FIRST : LAST;
     const T sc = FIRST ? static_cast<T>(((UPtr<double>)a.scale)[it.real]) : T(1);
     const int plane_bytes = (int)(NN * (int64_t)sizeof(C));
 
@@ -338,7 +344,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                 }
                 // partial sum of plane i - 1, used when it completes (step i - 1 + KT)
                 const int wb = m3(u - 1);
-                if constexpr (FIRST) {
+                if constexpr (FIRST || PROD) {
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         br[wb][s] = yr[0][wb][s];
@@ -365,10 +371,11 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                 const C dn_e = eb[(((j - 1) * (W + 2) + wv + 2) * 2 + 0) * 64 + lane];   // first row of wave w+1
                 const T cj = static_cast<T>(a.coef[j - 1]);
                 const T cr = static_cast<T>(rot_re(j)) * cj, ci = static_cast<T>(rot_im(j)) * cj;
+                const T pre_ = static_cast<T>(pp.cre[j - 1]), pim_ = static_cast<T>(pp.cim[j - 1]);
                 const int p = i - j;
                 const bool seed_ok = !LAST && j == KT && plane_out(p);
                 __amdgpu_buffer_rsrc_t rs_seed;
-                if constexpr (!LAST)
+                if constexpr (!LAST && !PROD)
                     if (j == KT) rs_seed = rsrc(q_base, shift(xc, -KT), seed_ok);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -403,23 +410,36 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                     }
                     // (-i)^j Y_j: odd j swaps the parts
                     const T xr = (j & 1) ? hi : hr, xi = (j & 1) ? hr : hi;
-                    if (j == 1) {
+                    if constexpr (PROD) {
+                        // c_j Y_j with complex c_j
+                        if (j == 1) {
+                            tr[sm][s] = fma3(pre_, hr, -(pim_ * hi));
+                            ti[sm][s] = fma3(pre_, hi, pim_ * hr);
+                        } else {
+                            tr[sm][s] = fma3(pre_, hr, fma3(-pim_, hi, tr[sm][s]));
+                            ti[sm][s] = fma3(pre_, hi, fma3(pim_, hr, ti[sm][s]));
+                        }
+                    } else if (j == 1) {
                         tr[sm][s] = cr * xr;
                         ti[sm][s] = ci * xi;
                     } else {
                         tr[sm][s] = fma3(cr, xr, tr[sm][s]);
                         ti[sm][s] = fma3(ci, xi, ti[sm][s]);
                     }
-                    if constexpr (LAST) {
-                        // |Y_K|^2 of this pass's last level (the order's last term)
+                    if constexpr (DO_TAIL) {
+                        // |Y_K|^2 of this pass's last level (chained: the
+                        // order's last term; product: the bound's base)
                         if (j == KT) {
                             const T m = (yout[s] && plane_out(p)) ? T(1) : T(0);
                             tail = fma3(m * hr, hr, fma3(m * hi, hi, tail));
                         }
-                    } else if (j == KT) {
-                        // Psi_{s+K} with its true phase, for the next pass
-                        store_c(static_cast<T>(rot_re(KT)) * xr, static_cast<T>(rot_im(KT)) * xi, rs_seed,
-                                voff_st[s]);
+                    }
+                    if constexpr (!LAST && !PROD) {
+                        if (j == KT) {
+                            // Psi_{s+K} with its true phase, for the next pass
+                            store_c(static_cast<T>(rot_re(KT)) * xr, static_cast<T>(rot_im(KT)) * xi, rs_seed,
+                                    voff_st[s]);
+                        }
                     }
                 }
             }
@@ -435,12 +455,12 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                     const T orr = br[w][s] + tr[w][s];
                     const T oi = bi[w][s] + ti[w][s];
                     store_c(orr, oi, rs, voff_st[s]);
-                    if constexpr (LAST) {
+                    if constexpr (DO_NORM) {
                         const double dr = orr, di = oi;
                         pn = __builtin_fma(yout[s] ? dr : 0.0, dr, __builtin_fma(yout[s] ? di : 0.0, di, pn));
                     }
                 }
-                if constexpr (LAST) {
+                if constexpr (DO_NORM) {
                     if (ok) nrm += pn;
                 }
             }
@@ -481,7 +501,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
     }
 
     // ---- FP64 partials of the item: squared norm and last term
-    if constexpr (LAST) {
+    if constexpr (DO_NORM || DO_TAIL) {
         __shared__ double red[2][W];
         const double n_w = wave_sum3(wz * nrm);
         const double t_w = wave_sum3(wz * (double)tail);
@@ -496,9 +516,19 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
                 sn += red[0][k];
                 st += red[1][k];
             }
-            const double f = a.tail_coef;
-            a.norm_part[home] = sn;
-            a.tail_part[home] = st * f * f;
+            double f = a.tail_coef;
+            if (PROD && !LAST) {
+                // ||(dt H)^n psi|| <= x^(n - K) ||(dt H)^K psi||, x = dt G, from
+                // the remainder factor r = (x / (n + 1)) / (1 - x / (n + 2))
+                const int n = pp.order;
+                const double r = rd.tail_factor_max;
+                const double x = r / (1.0 / (n + 1) + r / (n + 2));
+                double pw = 1.0;
+                for (int k = pp.k_first; k < n; ++k) pw *= x;
+                f = isfinite(r) ? f * pw : INFINITY;
+            }
+            if (DO_NORM) a.norm_part[home] = sn;
+            if (DO_TAIL) a.tail_part[home] = st * f * f;
         }
     }
 }
@@ -506,18 +536,19 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a) {
 }  // namespace step3c_detail
 
 namespace {
-using Step3cFn = void (*)(Step3cArgs);
+using Step3cFn = void (*)(Step3cArgs, Step3cProd);
 // Compiled shapes: (dtype, terms per pass) -> kernel, rows per wave, waves.
 struct Step3cShape {
     Step3cFn fn;
     int rows_per_wave;
     int waves;
 };
-Step3cShape select3c(int dtype, int K, bool first, bool last) {
+Step3cShape select3c(int dtype, int K, bool first, bool last, bool prod) {
     using namespace step3c_detail;
-#define CTQW_3C(T, KT, S, W)                                                            \
-    {first ? (last ? &step3c_kernel<T, KT, S, W, true, true> : &step3c_kernel<T, KT, S, W, true, false>) \
-           : (last ? &step3c_kernel<T, KT, S, W, false, true> : &step3c_kernel<T, KT, S, W, false, false>), S, W}
+#define CTQW_3C_P(T, KT, S, W, P)                                                                         \
+    (first ? (last ? &step3c_kernel<T, KT, S, W, true, true, P> : &step3c_kernel<T, KT, S, W, true, false, P>) \
+           : (last ? &step3c_kernel<T, KT, S, W, false, true, P> : &step3c_kernel<T, KT, S, W, false, false, P>))
+#define CTQW_3C(T, KT, S, W) {prod ? CTQW_3C_P(T, KT, S, W, true) : CTQW_3C_P(T, KT, S, W, false), S, W}
     if (dtype == 1) {
         switch (K) {
             case 1: return CTQW_3C(double, 1, 4, 8);
@@ -533,23 +564,34 @@ Step3cShape select3c(int dtype, int K, bool first, bool last) {
         default: return {nullptr, 0, 0};
     }
 #undef CTQW_3C
+#undef CTQW_3C_P
 }
 }  // namespace
 
 int step3c_rows_per_block(int dtype, int K) {
-    const Step3cShape sh = select3c(dtype, K, true, true);
+    const Step3cShape sh = select3c(dtype, K, true, true, false);
     return sh.fn ? sh.rows_per_wave * sh.waves : 0;
 }
 
-hipError_t launch_step3c(const Step3cArgs& a, int dtype, int K, hipStream_t stream) {
-    const Step3cShape sh = select3c(dtype, K, a.first != 0, a.last != 0);
+namespace {
+hipError_t launch3c(const Step3cArgs& a, const Step3cProd& pp, int dtype, int K, bool prod, hipStream_t stream) {
+    const Step3cShape sh = select3c(dtype, K, a.first != 0, a.last != 0, prod);
     if (!sh.fn) return hipErrorInvalidValue;
     if (a.n_items <= 0) return hipSuccess;
     const int64_t per = ((int64_t)a.n_items + 7) / 8;
     const int64_t blocks = per * 8;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(sh.fn, dim3((unsigned)blocks), dim3(64 * sh.waves), 0, stream, a);
+    hipLaunchKernelGGL(sh.fn, dim3((unsigned)blocks), dim3(64 * sh.waves), 0, stream, a, pp);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_step3c(const Step3cArgs& a, int dtype, int K, hipStream_t stream) {
+    return launch3c(a, Step3cProd{}, dtype, K, false, stream);
+}
+
+hipError_t launch_step3c_prod(const Step3cArgs& a, const Step3cProd& pp, int dtype, int K, hipStream_t stream) {
+    return launch3c(a, pp, dtype, K, true, stream);
 }
 
 }  // namespace ctqw

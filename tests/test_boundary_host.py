@@ -642,3 +642,21 @@ def test_fermion_plans_validate_and_use_the_triangle_layout():
         assert e.value.status == 2
     pr, _ = make_problem(1, 2, 9, 0.05, statistics="fermion", taylor_tol=1e-12)
     assert list(np.diff(Plan(pr).layout())) == [9, 9]
+
+
+def test_three_walker_product_form_builds_for_every_order():
+    """three_form = 1 factors the step's Taylor polynomial over its roots
+    (the library checks that the passes' polynomials multiply back to
+    sum z^k / k! to 1e-13): every order 2 .. 12 at 1, 2 and 3 terms per
+    pass builds; other values of the field are rejected."""
+    from paper_1612_00746_amd import CtqwError
+    N = 10
+    for order in range(2, 13):
+        for K in (1, 2, 3):
+            plan = make(m=3, R=1, n_sites=N, taylor_order=order, taylor_tol=0.0)
+            plan.set_launch(terms_per_pass=K, three_form=1)
+            plan.set_params(np.ones(N - 1), np.zeros(N), np.ones(1))
+            assert plan.get_launch().three_form == 1
+    plan = make(m=3, R=1, n_sites=N, taylor_order=6, taylor_tol=0.0)
+    with pytest.raises(CtqwError):
+        plan.set_launch(three_form=2)

@@ -226,3 +226,47 @@ def test_full_lattice_window_against_oracle():
     assert abs(occ.sum() - 3) < 1e-5
     assert np.max(np.abs(pair.sum(axis=1) - 2 * occ)) < 1e-5
     assert np.max(np.abs(pair - pair.T)) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("K,order,boundary", [(3, 6, "open"), (3, 7, "open"), (2, 5, "periodic"), (1, 3, "open")])
+def test_three_walkers_product_form(K, order, boundary, dtype):
+    """Product form of the step (the order-n Taylor polynomial factored over
+    its roots, at most K factors per pass, each pass reading and writing
+    one state): one step on a 70-site chain (several tiles, every lane) of
+    orders 3..7 against the oracle's Taylor map of the same order
+    (complex128 1e-12; complex64 5e-9), and against the chained passes to
+    rounding.  The truncation estimate is a bound on the last term, so it
+    is at least the chained passes' exact one."""
+    N, dt = 70 if boundary == "open" else 37, 0.02
+    reals = reals3(N, 1, 7, boundary)
+    say(f"case: m=3 product form N={N} {boundary} K={K} order={order} {dtype}")
+    g = np.random.default_rng(12)
+    D = N ** 3
+    psi0 = g.standard_normal(D) + 1j * g.standard_normal(D)
+    psi0 /= np.linalg.norm(psi0)
+
+    def run(form):
+        plan = gpu_plan(m=3, statistics="distinguishable", boundary=boundary, interaction="nearest", dtype=dtype,
+                        reals=reals, dt=dt, order=order, launch={"terms_per_pass": K, "three_form": form})
+        plan.set_state_numpy(psi0)
+        plan.propagate(1)
+        return plan.state_numpy(), plan.realization_norms()
+
+    psi, (n2, t2) = run(1)
+    psi_c, (n2_c, t2_c) = run(0)
+    _, J, eps, U = reals[0]
+    H = Hm.hamiltonian(N, 3, J, eps, U, B.DISTINGUISHABLE, boundary, "nearest")
+    ref, _, _ = P.evolve_taylor(H, psi0, dt, 1, order=order)
+    err = np.max(np.abs(psi - ref))
+    d = np.max(np.abs(psi.astype(np.complex128) - psi_c.astype(np.complex128)))
+    say(f"  max |psi - oracle map| = {err:.2e}, |product - chained| = {d:.2e}, "
+        f"tail^2 product {t2[0]:.3e} chained {t2_c[0]:.3e}")
+    bar = 1e-12 if dtype == "c128" else 5e-9
+    assert err <= bar
+    assert d <= 2 * bar
+    assert abs(n2[0] - n2_c[0]) <= (1e-12 if dtype == "c128" else 1e-6)
+    if order > K:
+        assert t2[0] >= t2_c[0] * (1 - 1e-6)
+    else:
+        assert abs(t2[0] - t2_c[0]) <= 1e-6 * t2_c[0]
