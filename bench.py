@@ -367,9 +367,10 @@ def time_plan(plan, steps, warmup):
 
 def run_copy_probe(mib):
     """A plain device-to-device copy of `mib` MiB (torch), timed with HIP
-    events: the practical HBM roof beside the 8 TB/s peak, and the kernel
-    whose FETCH_SIZE / WRITE_SIZE counters scale those of the step kernels
-    in a rocprofv3 counter run.  None when mib <= 0."""
+    events, whose FETCH_SIZE / WRITE_SIZE counters scale those of the step
+    kernels in a rocprofv3 counter run; beside it the library's flat copy
+    and band-sweep probes on the same buffers (practical roofs for a flat
+    stream and for the step kernel's access pattern).  None when mib <= 0."""
     if mib <= 0:
         return None
     import torch
@@ -386,6 +387,21 @@ def run_copy_probe(mib):
     dt_copy = e0.elapsed_time(e1) * 1e-3 / 5
     out = {"bytes_read": n * 4, "bytes_written": n * 4, "gbs": round(2 * n * 4 / dt_copy / 1e9, 1),
            "frac_of_peak": round(2 * n * 4 / dt_copy / 1e9 / HBM_PEAK_GBS, 4)}
+    # The library's probes on the same buffers: a flat copy of one 16-byte
+    # element per thread, and the step kernel's band row sweep (1 KiB bands
+    # of 1024 x 1024 complex64 grids, 8 resident waves per CU) with no
+    # arithmetic: the rate the step kernel's access pattern allows.
+    grid = 1024 * 1024 * 8
+    if (n * 4) % grid == 0:
+        from paper_1612_00746_amd import bandwidth_probe
+        for key, pattern in (("flat_copy_gbs", 0), ("band_sweep_gbs", 1)):
+            bandwidth_probe(src, dst, pattern)
+            e0.record()
+            for _ in range(5):
+                bandwidth_probe(src, dst, pattern)
+            e1.record()
+            torch.cuda.synchronize()
+            out[key] = round(2 * n * 4 / (e0.elapsed_time(e1) * 1e-3 / 5) / 1e9, 1)
     log(f"copy probe: {out}")
     del src, dst
     torch.cuda.empty_cache()
@@ -843,7 +859,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--copy-probe-mib", type=int, default=4096,
-                    help="a plain device copy of this size, timed as the practical HBM roof (0: skip)")
+                    help="device copies of this size (torch, and the library's flat and band-sweep probes), timed as practical HBM roofs (0: skip)")
     ap.add_argument("--regular", action="store_true", help="one block per item group instead of the persistent grid")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep --cols-per-lane, --waves-per-block and --waves-per-cu")

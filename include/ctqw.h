@@ -563,6 +563,26 @@ ctqw_status ctqw_autotune(ctqw_plan* plan, const char* cache_path, int32_t steps
 ctqw_status ctqw_set_timing(ctqw_plan* plan, int32_t enable);
 ctqw_status ctqw_get_timing(ctqw_plan* plan, double* step_kernel_ms, int64_t* launches);
 
+/* Memory-bandwidth probes, for reading the kernels' rates against what the
+ * memory system sustains (measurement only; no part of the method runs).
+ *   pattern 0: copy `bytes` from src to dst, one 16-byte element per thread
+ *              (the fastest plain copy form found on gfx950); n and
+ *              waves_per_cu are ignored.
+ *   pattern 1: the access pattern of the two-particle step kernel with its
+ *              arithmetic taken out: src and dst hold bytes / (8 n^2) grids
+ *              of n x n complex64 (rows of 8n bytes, n a multiple of 128),
+ *              and one wave per band of 128 columns (1 KiB of a row) copies
+ *              its band row by row with two rows of loads in flight, at most
+ *              waves_per_cu resident waves per CU (4..32; 0: 8, the step
+ *              kernel's occupancy at two columns per lane).
+ * src and dst are device buffers of `bytes` bytes that do not overlap;
+ * bytes is a multiple of 16 (pattern 0) or of 8 n^2 (pattern 1).
+ * Enqueued on hip_stream (hipStream_t, NULL = default); does not
+ * synchronise.  Errors: INVALID_ARG (NULL, overlap, sizes, pattern),
+ * DEVICE (launch failed).                                                  */
+ctqw_status ctqw_bandwidth_probe(const void* src, void* dst, int64_t bytes, int32_t pattern, int32_t n,
+                                 int32_t waves_per_cu, void* hip_stream);
+
 const char* ctqw_status_string(ctqw_status status);
 const char* ctqw_last_error(const ctqw_plan* plan);
 /* Library version string. */

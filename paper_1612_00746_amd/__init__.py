@@ -478,6 +478,22 @@ def graph_evolve_static(nbr, hop, onsite, psi, dt: float, order: int, n_steps: i
                                          C.c_void_p(stream)))
 
 
+def bandwidth_probe(src, dst, pattern: int, n: int = 1024, waves_per_cu: int = 0) -> None:
+    """ctqw_bandwidth_probe on two contiguous, non-overlapping device tensors
+    of the same byte size: pattern 0 copies src to dst flat, pattern 1 with
+    the step kernel's band row sweep over n x n complex64 grids (measurement
+    only).  Enqueued on the device's current stream."""
+    import torch
+    lib = L.load()
+    nbytes = src.numel() * src.element_size()
+    if (not src.is_contiguous() or not dst.is_contiguous() or dst.numel() * dst.element_size() != nbytes
+            or src.device != dst.device or src.device.type != "cuda"):
+        raise ValueError("src and dst must be contiguous device tensors of the same size on one device")
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    L.check(lib.ctqw_bandwidth_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, int(pattern),
+                                     int(n), int(waves_per_cu), C.c_void_p(stream)))
+
+
 def lattice_evolve(Jx, Jy, eps, psi, dt: float, order: int, n_steps: int, periodic=(False, False),
                    workspace=None, norms=None) -> None:
     """ctqw_lattice_evolve on device tensors: one particle on an Lx x Ly

@@ -137,6 +137,8 @@ SIGNATURES = {
     "ctqw_loss": (C.c_int, [PlanP, C.c_int32, dp, C.c_void_p, C.c_int64, dp]),
     "ctqw_set_timing": (C.c_int, [PlanP, C.c_int32]),
     "ctqw_get_timing": (C.c_int, [PlanP, dp, i64p]),
+    "ctqw_bandwidth_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_void_p]),
     "ctqw_status_string": (C.c_char_p, [C.c_int]),
     "ctqw_last_error": (C.c_char_p, [PlanP]),
     "ctqw_version": (C.c_char_p, []),

@@ -660,3 +660,27 @@ def test_three_walker_product_form_builds_for_every_order():
     plan = make(m=3, R=1, n_sites=N, taylor_order=6, taylor_tol=0.0)
     with pytest.raises(CtqwError):
         plan.set_launch(three_form=2)
+
+
+def test_bandwidth_probe_rejects_bad_arguments_before_any_launch():
+    """ctqw_bandwidth_probe validates on the host: NULL buffers, overlap,
+    sizes that are not whole elements or grids, bad n, occupancy or pattern
+    return INVALID_ARG without touching a device (the pointers here are
+    never dereferenced)."""
+    from paper_1612_00746_amd import _lib as L
+    lib = L.load()
+    a, b = C.c_void_p(1 << 20), C.c_void_p(1 << 30)
+    bad = [
+        (None, b, 1024, 0, 0, 0),
+        (a, None, 1024, 0, 0, 0),
+        (a, b, 0, 0, 0, 0),
+        (a, C.c_void_p((1 << 20) + 512), 1024, 0, 0, 0),      # overlap
+        (a, b, 1000, 0, 0, 0),                                 # not 16-byte elements
+        (a, b, 3 * 128 * 128 * 8, 1, 100, 0),                  # n not a multiple of 128
+        (a, b, 3 * 128 * 128 * 8 + 16, 1, 128, 0),             # not whole grids
+        (a, b, 3 * 128 * 128 * 8, 1, 128, 2),                  # waves per CU below 4
+        (a, b, 3 * 128 * 128 * 8, 1, 128, 33),                 # above 32
+        (a, b, 1024, 2, 128, 0),                               # pattern
+    ]
+    for args in bad:
+        assert lib.ctqw_bandwidth_probe(*args, None) == L.ERR_INVALID_ARG, args

@@ -70,7 +70,9 @@ def test_forced_passes_match_the_fused_kernel(dtype, acc, bar):
     assert d <= bar
     err = max_err_vs_taylor(chunked, reals, "distinguishable", [16, 17], 0.05, 60, 7)
     say(f"  chunked vs oracle map: {err:.2e}")
-    assert err <= (1e-12 if dtype == "c128" else 2e-5)
+    # complex64: FP32 rounding of the stored state, at most ~6e-8 per
+    # amplitude per step, as a random walk over 60 steps: 4.6e-7.
+    assert err <= (1e-12 if dtype == "c128" else 5e-7)
 
 
 def test_chunked_launch_forms_are_bitwise_identical():

@@ -173,6 +173,12 @@ def test_three_walker_autotune_picks_a_pass_depth():
 
 @pytest.mark.parametrize("acc", ["kahan", "plain"])
 def test_three_walkers_c64(acc):
+    """Complex64, 150 steps at tol 1e-7.  Against exact evolution the bar is
+    the truncation budget (at most tol per step, 150 steps: 1.5e-5) plus
+    rounding, held to 2e-5.  Against the oracle's Taylor map at the order
+    the plan applies, only the FP32 rounding of the stored state is left: at
+    most ~6e-8 per amplitude per step, accumulating as a random walk,
+    sqrt(150) * 6e-8 = 7.3e-7 for amplitudes of size <= 1, held to 1e-6."""
     say(f"case: m=3 N=12 c64 {acc}, 150 steps")
     N, R, dt, steps = 12, 2, 0.02, 150
     reals = reals3(N, R, 2)
@@ -189,6 +195,14 @@ def test_three_walkers_c64(acc):
     n2, _ = plan.realization_norms()
     say(f"  c64 {acc}: amplitude error {worst:.2e}, |norm - 1| {np.max(np.abs(np.sqrt(n2) - 1)):.1e}")
     assert worst <= 2e-5
+    order = int(plan.orders().max())   # three-particle steps apply the batch's largest order
+    map_err = 0.0
+    for r, (n, J, eps, U) in enumerate(reals):
+        H = Hm.hamiltonian(N, 3, J, eps, U, B.DISTINGUISHABLE, "open", "nearest")
+        ref, _, _ = P.evolve_taylor(H, B.product_state(N, sites), dt, steps, order=order)
+        map_err = max(map_err, float(np.max(np.abs(psi[r * N ** 3:(r + 1) * N ** 3] - ref))))
+    say(f"  c64 {acc}: against the oracle's map at order {order}: {map_err:.2e}")
+    assert map_err <= 1e-6
 
 
 def test_full_lattice_window_against_oracle():
