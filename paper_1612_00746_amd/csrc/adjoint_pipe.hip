@@ -1,6 +1,7 @@
 // Launcher of the K-level adjoint passes (kernel in adjoint_pipe_impl.hpp).
 #include "adjoint_pipe_impl.hpp"
 
+#include <climits>
 #include <utility>
 
 namespace ctqw {
@@ -38,6 +39,13 @@ hipError_t launch_adj_pipe(const AdjPipeArgs& a, hipStream_t s) {
     if (a.levels < 1 || a.levels > pipe_max_levels(a.dtype, a.contract != 0) || a.layout < 0 || a.layout > 2)
         return hipErrorInvalidValue;
     if (a.contract && (!a.gJ || !a.gE || !a.gV || !a.gR)) return hipErrorInvalidValue;
+    // the kernels store every level of a forward pass and only the last of a
+    // contracting (Horner) pass
+    for (int l = 0; l < a.levels; ++l)
+        if ((a.y[l] != nullptr) != (!a.contract || l == a.levels - 1)) return hipErrorInvalidValue;
+    // one buffer resource spans a realisation's amplitudes
+    const int64_t amps = a.layout == 0 ? (int64_t)a.max_n : (int64_t)a.max_n * a.max_n;
+    if (amps * (a.dtype == 1 ? 16 : 8) > INT32_MAX) return hipErrorInvalidValue;
     const PipeFn fn = a.dtype == 1 ? pick<double, kPipeMaxLevelsC128, kPipeMaxHornerC128>(a)
                                    : pick<float, kPipeMaxLevelsC64, kPipeMaxHornerC64>(a);
     if (!fn) return hipErrorInvalidValue;

@@ -99,32 +99,42 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
     const int nsweep = q1 > q0 ? s_hi - s_lo : 0;
     const int o_lo = q0 - s_lo, o_hi = q1 - s_lo;   // output rows, as sweep steps
 
-    const uint32_t row_bytes = (uint32_t)N * (uint32_t)sizeof(C);
     const uint32_t col_off = (uint32_t)cw * (uint32_t)sizeof(C);
     // grid row of sweep step s (wrapped on a ring)
     auto grid_row = [&](int s) { return rper ? wrapi(s_lo + s, rows) : s_lo + s; };
-    // Row of sweep step s through a buffer resource (length 0 outside the
-    // sweep): lanes without a stored amplitude read 0 and drop stores.
-    auto row_rsrc = [&](const void* base, int s, bool live, uint32_t& voff) {
+    // One buffer resource per array over this realisation's amplitudes (the
+    // launcher keeps them under 2^31 bytes), the row in the per-lane offset:
+    // a 32-bit offset per access instead of a resource per row.  Lanes
+    // without a stored amplitude, and rows outside the sweep, take an offset
+    // past the end: loads read 0 and stores are dropped.
+    const uint32_t real_bytes =
+        (uint32_t)(tri ? N * (N + 1) / 2 : rows * N) * (uint32_t)sizeof(C);
+    auto arr_rsrc = [&](const void* base) {
+        return __builtin_amdgcn_make_buffer_rsrc(const_cast<C*>(reinterpret_cast<const C*>(base)) + rd.state_off, 0,
+                                                 base ? (int)real_bytes : 0, kRawBufferWord3);
+    };
+    auto lane_off = [&](int s) -> uint32_t {
         int q = s_lo + s;
-        live = live && s >= 0 && s < nsweep;
+        const bool live = s >= 0 && s < nsweep;
         if (rper) q = wrapi(q, rows);
         q = live ? q : 0;
-        const int64_t rb = tri ? (int64_t)q * N - ((int64_t)q * (q + 1)) / 2 : (int64_t)q * N;
-        voff = stored(q) ? col_off : kPastEnd;
-        return __builtin_amdgcn_make_buffer_rsrc(const_cast<C*>(reinterpret_cast<const C*>(base)) + rd.state_off + rb,
-                                                 0, live ? (int)row_bytes : 0, kRawBufferWord3);
+        const uint32_t rowb = (uint32_t)(tri ? q * N - (q * (q + 1)) / 2 : q * N) * (uint32_t)sizeof(C);
+        return (live && stored(q)) ? rowb + col_off : kPastEnd;
     };
-    auto ldrow = [&](const void* base, int s) -> C {
-        uint32_t voff;
-        const __amdgpu_buffer_rsrc_t rs = row_rsrc(base, s, base != nullptr, voff);
-        return load_c(rs, voff, (C*)nullptr);
-    };
+    auto ldrow = [&](const __amdgpu_buffer_rsrc_t rs, int s) -> C { return load_c(rs, lane_off(s), (C*)nullptr); };
 
     // The Horner passes (CON) add Z to every level; the forward passes have none.
     const bool x_is_z = CON && a.x == a.z;
-    const void* X = x_is_z ? nullptr : a.x;
-    const void* Z = CON ? a.z : nullptr;
+    const __amdgpu_buffer_rsrc_t X = arr_rsrc(x_is_z ? nullptr : a.x);
+    const __amdgpu_buffer_rsrc_t Z = arr_rsrc(CON ? a.z : nullptr);
+    // stored levels: every level of a forward pass, the last of a Horner pass
+    __amdgpu_buffer_rsrc_t Y[K], V[CON ? K : 1];
+#pragma unroll
+    for (int l = 0; l < K; ++l) Y[l] = arr_rsrc((!CON || l == K - 1) ? a.y[l] : nullptr);
+    if constexpr (CON) {
+#pragma unroll
+        for (int l = 0; l < K; ++l) V[l] = arr_rsrc(a.v[l]);
+    }
 
     T yr[K][3], yi[K][3];          // levels 0 .. K - 1, rows modulo 3
     C xq[3], zq[3];                // X and Z rows i .. i + 2, modulo 3
@@ -177,7 +187,7 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
 #pragma unroll
         for (int l = 1; l <= K; ++l)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) vq[l - 1][k] = ldrow(a.v[l - 1], k - l);
+            for (int k = 0; k < 3; ++k) vq[l - 1][k] = ldrow(V[l - 1], k - l);
     }
     double bond_col = 0.0, site_col = 0.0;
     const double f = tri ? 2.0 : 1.0;
@@ -266,11 +276,7 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
                     yi[l][sm] = yi_;
                 }
                 const bool own = s >= o_lo && s < o_hi;
-                if (a.y[l - 1] != nullptr) {
-                    uint32_t voff;
-                    const __amdgpu_buffer_rsrc_t rs = row_rsrc(a.y[l - 1], s, true, voff);
-                    store_c(yr_, yi_, rs, (own && out) ? voff : kPastEnd);
-                }
+                if (!CON || l == K) store_c(yr_, yi_, Y[l - 1], (own && out) ? lane_off(s) : kPastEnd);
                 if constexpr (CON) {
                     // Im conj(u) v with u = level l's input, v = v[l - 1], per
                     // pair in the state's precision, summed in FP64
@@ -287,7 +293,7 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
                     // v[l - 1] advances one row
                     vq[l - 1][0] = vq[l - 1][1];
                     vq[l - 1][1] = vq[l - 1][2];
-                    vq[l - 1][2] = ldrow(a.v[l - 1], s + 3);
+                    vq[l - 1][2] = ldrow(V[l - 1], s + 3);
                 }
             }
             if constexpr (CON) {
