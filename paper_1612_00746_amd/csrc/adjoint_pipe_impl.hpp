@@ -148,6 +148,13 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
     C vq[CON ? K : 1][3];          // vq[l - 1][k]: v[l - 1] row i - l + k
     T rpv[CON ? K + 1 : 1], rps[CON ? K + 1 : 1];   // row parts of row i - l after level l
     double batch[8];               // three completed rows (bond, site), two zeros
+    // Lane offsets of the rows a step touches, formed once per row as it
+    // enters: after step i's shift ro[j] is the offset of row i + 3 - j
+    // (X and Z load row i + 3, level l loads v[l - 1] row i - l + 3 and
+    // stores row i - l).
+    uint32_t ro[K + 4];
+#pragma unroll
+    for (int j = 0; j < K + 4; ++j) ro[j] = lane_off(2 - j);
 #pragma unroll
     for (int l = 0; l < K; ++l)
 #pragma unroll
@@ -221,8 +228,11 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
                 for (int l = K; l >= 1; --l) pe[l] = pe[l - 1];
                 pjd[0] = qjd[u];
                 pe[0] = qe[u];
-                xq[u] = ldrow(X, i + 3);
-                if constexpr (CON) zq[u] = ldrow(Z, i + 3);
+#pragma unroll
+                for (int j = K + 3; j >= 1; --j) ro[j] = ro[j - 1];
+                ro[0] = lane_off(i + 3);
+                xq[u] = load_c(X, ro[0], (C*)nullptr);
+                if constexpr (CON) zq[u] = load_c(Z, ro[0], (C*)nullptr);
                 qjd[u] = row_jd(i + 3);
                 qe[u] = row_e(i + 3);
             }
@@ -276,7 +286,7 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
                     yi[l][sm] = yi_;
                 }
                 const bool own = s >= o_lo && s < o_hi;
-                if (!CON || l == K) store_c(yr_, yi_, Y[l - 1], (own && out) ? lane_off(s) : kPastEnd);
+                if (!CON || l == K) store_c(yr_, yi_, Y[l - 1], (own && out) ? ro[l + 3] : kPastEnd);
                 if constexpr (CON) {
                     // Im conj(u) v with u = level l's input, v = v[l - 1], per
                     // pair in the state's precision, summed in FP64
@@ -293,7 +303,7 @@ __global__ void __launch_bounds__(64 * kSweepSegs, 2) pipe_kernel(AdjPipeArgs a)
                     // v[l - 1] advances one row
                     vq[l - 1][0] = vq[l - 1][1];
                     vq[l - 1][1] = vq[l - 1][2];
-                    vq[l - 1][2] = ldrow(V[l - 1], s + 3);
+                    vq[l - 1][2] = load_c(V[l - 1], ro[l], (C*)nullptr);
                 }
             }
             if constexpr (CON) {
