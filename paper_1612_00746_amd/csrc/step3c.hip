@@ -62,20 +62,19 @@ constexpr int kStoreNT = 2;   // stores are read again only by the next pass
 constexpr uint32_t kPastRow = 0x80000000u;
 
 // Loads and stores of one amplitude per lane through a buffer resource over
-// one plane: loads take the row as soff (wave-uniform) and the column as off
-// (per lane); stores take row and column in off and a zero scalar offset.
+// one plane, row and column in the per-lane offset and a zero scalar offset.
 // An offset at or past the resource's length reads 0 and drops the store.
 // (A 16-byte store reads its data registers after it issues: a VALU write
 // of them must wait one cycle.  The compiler inserts that wait only for
 // stores whose scalar offset is not a register; with a register there the
 // store was seen to write the following instruction's results in some
 // lanes.  A zero scalar offset keeps the wait.)
-__device__ __forceinline__ float2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t off, int soff, float2*) {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, soff, 0);
+__device__ __forceinline__ float2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t off, float2*) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
     return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
 }
-__device__ __forceinline__ double2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t off, int soff, double2*) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, soff, 0);
+__device__ __forceinline__ double2 load_c(__amdgpu_buffer_rsrc_t rs, uint32_t off, double2*) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
     return make_double2(__hiloint2double((int)v.y, (int)v.x), __hiloint2double((int)v.w, (int)v.z));
 }
 __device__ __forceinline__ void store_c(float re, float im, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
@@ -224,16 +223,19 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a, Step3cP
     const T e3 = zin ? Et[zs] : T(0);
     const uint32_t voff_in = zin ? (uint32_t)zw * (uint32_t)sizeof(C) : kPastRow;
     const uint32_t voff_out = (zin && zout) ? (uint32_t)zw * (uint32_t)sizeof(C) : kPastRow;
+    // the planes x1 interacting with this lane's column (-1: none)
+    const int zta = zin ? (periodic ? wrap3(zw - want, N) : zw - want) : -1;
+    const int ztb = zin ? (periodic ? wrap3(zw + want, N) : zw + want) : -1;
 
     // ---- this wave's x2 rows (wave-uniform)
-    int soff[S];     // byte offset of the row in a plane (0 off the chain)
     bool yin[S];     // row on the chain: loads read it, else zero
     bool yout[S];    // output row: stores write it
-    uint32_t voff_ld[S];   // the lane's column offset, past the plane off the chain
+    uint32_t voff_ld[S];   // the lane's row and column offset, past the plane off the chain
     uint32_t voff_st[S];   // the lane's row and column offset, past the plane off the output
     T jrow[S + 1];   // jrow[s]: dt * bond between rows s-1 and s of the strip
     T drow[S];       // per lane: dt * (eps[x2] + eps[x3] + interaction of (x2, x3))
     int ywr[S];
+    int yta[S], ytb[S];   // planes x1 interacting with row s (-1: none)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int y = it.y0 + wv * S + s;
@@ -241,9 +243,13 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a, Step3cP
         yin[s] = periodic || (y >= 0 && y < N);
         yout[s] = y >= it.ylo && y < it.yhi;
         ywr[s] = yin[s] ? yw : 0;
-        soff[s] = ywr[s] * N * (int)sizeof(C);
-        voff_ld[s] = yin[s] ? voff_in : kPastRow;
-        voff_st[s] = (yout[s] && voff_out != kPastRow) ? voff_out + (uint32_t)soff[s] : kPastRow;
+        const uint32_t soff = (uint32_t)ywr[s] * (uint32_t)N * (uint32_t)sizeof(C);   // the row in a plane
+        voff_ld[s] = (yin[s] && voff_in != kPastRow) ? voff_in + soff : kPastRow;
+        voff_st[s] = (yout[s] && voff_out != kPastRow) ? voff_out + soff : kPastRow;
+        // the planes x1 whose interaction with this row counts (the chain
+        // distance |x1 - x2| equals `want`; none off the chain)
+        yta[s] = yin[s] ? (periodic ? wrap3(ywr[s] - want, N) : ywr[s] - want) : -1;
+        ytb[s] = yin[s] ? (periodic ? wrap3(ywr[s] + want, N) : ywr[s] + want) : -1;
     }
 #pragma unroll
     for (int s = 0; s <= S; ++s) {
@@ -297,7 +303,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a, Step3cP
     auto fetch = [&](const char* base, int xw, bool ok, C (&dst)[S]) {
         const __amdgpu_buffer_rsrc_t rs = rsrc(base, xw, ok);
 #pragma unroll
-        for (int s = 0; s < S; ++s) dst[s] = load_c(rs, voff_ld[s], soff[s], (C*)nullptr);
+        for (int s = 0; s < S; ++s) dst[s] = load_c(rs, voff_ld[s], (C*)nullptr);
     };
     // x1 of sweep position p + k, |k| <= 3, from x1 of p (wrapped once on a
     // ring, whose N >= 3)
@@ -354,7 +360,7 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a, Step3cP
                     const __amdgpu_buffer_rsrc_t rs = rsrc(b_base, shift(xc, -1), live(i - 1));
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        const C v = load_c(rs, voff_ld[s], soff[s], (C*)nullptr);
+                        const C v = load_c(rs, voff_ld[s], (C*)nullptr);
                         br[wb][s] = v.x;
                         bi[wb][s] = v.y;
                     }
@@ -473,10 +479,10 @@ __global__ void __launch_bounds__(64 * W, 1) step3c_kernel(Step3cArgs a, Step3cP
                 const int x1 = xin ? xc : 0;
                 const T e1v = Eu_t[x1];
                 const T e1 = xin ? e1v : T(0);
-                const T u13 = (xin & zin & related_u(x1, zw, N, periodic, want)) ? Udt : T(0);
+                const T u13 = (xin & ((x1 == zta) | (x1 == ztb))) ? Udt : T(0);
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const T u12 = (xin & yin[s] & related_u(x1, ywr[s], N, periodic, want)) ? Udt : T(0);
+                    const T u12 = (xin & ((x1 == yta[s]) | (x1 == ytb[s]))) ? Udt : T(0);
                     dg[w][s] = drow[s] + (e1 + u12) + u13;
                 }
             }
