@@ -508,8 +508,10 @@ ctqw_status ctqw_work_items(const ctqw_plan* plan, int64_t* items, int64_t* wave
  * steps, each segment is recomputed from its checkpoint, and the adjoint of
  * every step applies p(A)^dagger with A = -i dt H by a Horner recursion
  * (the same stencil with dt -> -dt) while FP64 kernels contract the bond
- * and site operators.  All realisations must share one lattice size;
- * renormalize must be 0.  grad_ws is caller-owned device memory of at
+ * and site operators.  All realisations must share one lattice size, whose
+ * state is under 2^31 bytes (two particles: N <= 16383 complex64, 11585
+ * complex128; UNSUPPORTED above); renormalize must be 0.  grad_ws is
+ * caller-owned device memory of at
  * least ctqw_gradient_workspace bytes (256-byte aligned).  On return the
  * current state is psi(T).                                                */
 #define CTQW_LOSS_ONE_BODY 0

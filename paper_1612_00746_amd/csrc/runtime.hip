@@ -2437,6 +2437,14 @@ ctqw_status ctqw_forward_ckpt(ctqw_plan* p, int64_t n_steps, int64_t ckpt_every,
     if (p->prob.m == 3) return fail(p, CTQW_ERR_UNSUPPORTED, "gradients are built for one and two particles");
     if (p->prob.m == 2 && p->prob.statistics == CTQW_FERMION)
         return fail(p, CTQW_ERR_UNSUPPORTED, "gradients are built for distinguishable particles and bosons");
+    {
+        // the adjoint passes address a realisation's amplitudes through one
+        // buffer resource, whose length is a 31-bit byte count
+        const int64_t amps = p->prob.m == 1 ? (int64_t)p->max_N : (int64_t)p->max_N * p->max_N;
+        if (amps * (p->prob.dtype == CTQW_C128 ? 16 : 8) > INT32_MAX)
+            return fail(p, CTQW_ERR_UNSUPPORTED, "gradients need each realisation's state under 2 GiB (N = %d)",
+                        p->max_N);
+    }
     ctqw_status st = ensure_ready(p);
     if (st != CTQW_OK) return st;
     const GradLayout g = grad_layout(p, n_steps, ckpt_every);

@@ -259,6 +259,13 @@ def test_gradient_entry_points_validate_on_host():
     renorm = make(R=2, n_sites=8, taylor_order=6, taylor_tol=0.0, renormalize=True)
     renorm.set_params(J, eps, U)
     assert lib.ctqw_forward_ckpt(renorm.h, 4, 2, C.c_void_p(256), 1 << 30) == L.ERR_UNSUPPORTED
+    # the adjoint passes address a realisation's state through one buffer
+    # resource: states of 2^31 bytes and more are refused before device work
+    for dtype, n in (("c64", 16384), ("c128", 11586)):
+        big = make(R=1, n_sites=n, taylor_order=6, taylor_tol=0.0, dtype=dtype)
+        big.set_params(np.ones(n - 1), np.zeros(n), np.zeros(1))
+        assert lib.ctqw_forward_ckpt(big.h, 4, 2, C.c_void_p(256), 1 << 40) == L.ERR_UNSUPPORTED, dtype
+        assert b"2 GiB" in lib.ctqw_last_error(big.h), dtype
 
 
 @pytest.mark.parametrize("boundary", ["open", "periodic"])
