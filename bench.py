@@ -960,24 +960,38 @@ def main():
     plan = build_plan(w, "c64", a.accumulation, launch, w.tol)
     tuned = None
     if not a.no_autotune:
-        # The autotuner times every launch shape on this batch; the batch's
+        # The autotuner times every launch shape on this batch.  The batch's
         # launch form stays persistent with the captured step loop (the
-        # workload is defined with one persistent launch per step), and the
-        # tuned columns per lane, waves per block, wave cap, chunking and
-        # band layout are kept.  The state is overwritten by tuning: start
-        # again after it.
+        # workload is defined with one persistent launch per step): the
+        # fastest persistent candidate of the autotuner's trace is taken
+        # (the fastest overall is reported beside it).  The state is
+        # overwritten by tuning: start again after it.
         import tempfile
+        keys = ("cols_per_lane", "waves_per_block", "persistent", "waves_per_cu", "chunked", "band_align",
+                "band_mode", "row_segments")
         with tempfile.TemporaryDirectory() as td:
-            best, best_ms = plan.autotune(os.path.join(td, "tune.jsonl"), steps=3)
-        tuned = {"cols_per_lane": best.cols_per_lane, "waves_per_block": best.waves_per_block,
-                 "persistent": best.persistent, "waves_per_cu": best.waves_per_cu, "chunked": best.chunked,
-                 "band_align": best.band_align, "band_mode": best.band_mode,
-                 "row_segments": best.row_segments, "ms": round(best_ms, 4)}
+            trace = os.path.join(td, "trace.jsonl")
+            old_trace = os.environ.get("CTQW_TUNE_TRACE")
+            os.environ["CTQW_TUNE_TRACE"] = trace
+            try:
+                best, best_ms = plan.autotune(os.path.join(td, "tune.jsonl"), steps=3)
+            finally:
+                if old_trace is None:
+                    del os.environ["CTQW_TUNE_TRACE"]
+                else:
+                    os.environ["CTQW_TUNE_TRACE"] = old_trace
+            cands = [json.loads(line) for line in open(trace)] if os.path.exists(trace) else []
+        tuned = {k: int(getattr(best, k)) for k in keys}
+        tuned["ms"] = round(best_ms, 4)
         log(f"autotune: {tuned}")
-        launch = {"cols_per_lane": best.cols_per_lane, "persistent": 0 if a.regular else 1,
-                  "waves_per_block": best.waves_per_block, "waves_per_cu": best.waves_per_cu,
-                  "chunked": best.chunked, "band_align": best.band_align, "band_mode": best.band_mode,
-                  "row_segments": best.row_segments, "use_graph": 1}
+        form = 0 if a.regular else 1
+        pick = min((c for c in cands if c["ms"] > 0 and c["persistent"] == form), key=lambda c: c["ms"], default=None)
+        if pick is None:
+            pick = dict(tuned, persistent=form)
+        log(f"launch form {'regular' if a.regular else 'persistent'}: fastest candidate "
+            f"{ {k: pick[k] for k in keys} } at {pick['ms']:.4f} ms")
+        launch = {k: int(pick[k]) for k in keys}
+        launch["use_graph"] = 1
         plan.set_launch(**launch)
         plan.bind()
         sizes0 = w.lattice_sizes()
