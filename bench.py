@@ -90,8 +90,8 @@ def cpu_baseline(w, budget_s: float = 10.0):
     each propagated step by step for `budget_s` seconds; the rate is the
     summed updates over the summed per-process seconds times the cores."""
     import multiprocessing as mp
-    # one process per core of the host's CPU share (the GPU box gives one GPU
-    # 16 cores, whatever the affinity mask shows)
+    # one process per core of the host's CPU share for one GPU (16 cores,
+    # whatever the affinity mask shows)
     available = host_cores()
     cores = min(available, 16)
     sizes = w.lattice_sizes()
