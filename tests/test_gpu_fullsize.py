@@ -203,3 +203,70 @@ def test_c4_full_lattice_gradient_against_the_oracle():
     say(f"  order {order}: loss {loss:.12e} (oracle {l0:.12e}); directional adjoint {ad:.10e} vs oracle FD {fd:.10e}")
     assert abs(loss - l0) <= 1e-12
     assert abs(ad - fd) <= 1e-6 * abs(fd)
+
+
+def test_c5_full_run_length_properties_and_sampled_realisations():
+    """The three-walker workload at its stated configuration: 64
+    realisations on N = 256 (16.8M amplitudes each, 1.07e9 in all),
+    nearest-neighbour U = 1, eps ~ U[-1, 1], J = 1, dt = 0.02, tolerance
+    1e-7, complex64, 500 steps to t = 10 with the ensemble occupation and
+    pair correlation every 50 steps, in the product form the benchmark
+    times.  No oracle evolves a 16.8M-amplitude state within a test, so the
+    whole batch is held to properties that hold at any size:
+      * at every output the ensemble occupation sums to m = 3 and the pair
+        correlation (ordered pairs a != b) to m(m - 1) = 6, within 1e-5;
+      * every realisation's FP64 norm stays within 5e-6 of 1 (FP32 rounding
+        of the state, one per pass, as a random walk over 1000 passes);
+      * the light cone: a walker started at 127..129 reaches a node d hops
+        away only through d of its own hops, each of norm 2J, so its
+        amplitude there is at most (2Jt)^d e^(2Jt) / d!, below 1e-19 for
+        d >= 100 at t = 10: the ensemble occupation of nodes 0..27 and
+        229..255 stays below 1e-12.
+    Two sampled realisations (the first and the last) are run alone in
+    complex128 with chained passes at the same order (that form is held to
+    1e-12 of the oracle on smaller lattices) and every complex64 amplitude
+    is within 2e-6 of them: the FP32 rounding of the state (6e-8 per
+    component and pass, a random walk over 1000 passes) plus the FP32
+    representation of the dt-scaled couplings (a Hamiltonian that differs
+    by about 6e-8 relative, acting for t = 10)."""
+    import torch
+    from workloads import C5
+    from _helpers import gpu_plan
+    w = C5()
+    say(f"case: C5 full configuration c64: R={w.R} N={w.N} {w.n_steps} steps, product form")
+    reals = w.all_realizations()
+    plan = gpu_plan(m=3, statistics="distinguishable", boundary="open", interaction="nearest", dtype="c64",
+                    reals=reals, dt=w.dt, tol=w.tol, observables=3, sites=list(w.start),
+                    launch={"three_form": 1})
+    out = plan.propagate(w.n_steps, w.output_every, 3)
+    N = w.N
+    assert out.shape == (w.n_steps // w.output_every + 1, N + N * N)
+    occ_sum = out[:, :N].sum(axis=1)
+    pair_sum = out[:, N:].sum(axis=1)
+    n2, _ = plan.realization_norms()
+    drift = float(np.max(np.abs(np.sqrt(n2) - 1.0)))
+    far = float(np.max(np.concatenate([out[:, :28], out[:, 229:N]], axis=1)))
+    order = int(plan.orders().max())
+    state_bytes, _ = plan.sizes()
+    dev = torch.empty(state_bytes, dtype=torch.uint8, device="cuda")
+    assert plan.lib.ctqw_get_state(plan.h, C.c_void_p(dev.data_ptr()), 1) == 0
+    psi = dev.view(torch.complex64)
+    off = plan.layout()
+    sample = [0, w.R - 1]
+    got = [psi[off[r]:off[r + 1]].cpu().numpy().astype(np.complex128) for r in sample]
+    del plan, dev, psi
+    torch.cuda.empty_cache()
+    ref_plan = gpu_plan(m=3, statistics="distinguishable", boundary="open", interaction="nearest",
+                        dtype="c128", reals=[reals[r] for r in sample], dt=w.dt, order=order,
+                        sites=list(w.start), launch={"three_form": 0})
+    ref_plan.propagate(w.n_steps)
+    ref = ref_plan.state_numpy()
+    D = N ** 3
+    diff = max(float(np.max(np.abs(got[k] - ref[k * D:(k + 1) * D]))) for k in range(len(sample)))
+    say(f"  order {order}: occupation sums {occ_sum.min():.7f}..{occ_sum.max():.7f}, pair sums "
+        f"{pair_sum.min():.7f}..{pair_sum.max():.7f}, max |norm - 1| {drift:.2e}, far occupation {far:.1e}, "
+        f"sample {sample} against complex128 {diff:.2e}")
+    assert np.allclose(occ_sum, 3.0, atol=1e-5) and np.allclose(pair_sum, 6.0, atol=1e-5)
+    assert drift <= 5e-6
+    assert far <= 1e-12
+    assert diff <= 2e-6
