@@ -1067,6 +1067,10 @@ def main():
         "norm_range": [st.min_norm, st.max_norm],
         "cpu_baseline": cpu,
         "copy_probe": copy_probe,
+        # the step kernel's rate against the band row sweep with no
+        # arithmetic, measured in this run (its access pattern's practical roof)
+        "frac_of_band_sweep": (round(achieved / copy_probe["band_sweep_gbs"], 4)
+                               if copy_probe and copy_probe.get("band_sweep_gbs") else None),
         "autotune": tuned,
     }
     print(json.dumps(line))
